@@ -1,0 +1,301 @@
+"""fp64 CPU oracle of the 3D Gaussian Splatting render path (test infrastructure).
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke entry point and the
+CPU-baseline leg of the benchmark use this package; the GPU library never
+does, and the two share no code.  The arithmetic lives in oracle.cpp (plain
+C++17, fp64, single-threaded); this module only marshals numpy arrays.
+
+Every input is widened from the caller's values to fp64 before the call, so a
+GPU run fed the same fp32 arrays sees exactly the same numbers.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.cpp")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+STATUS = {"visible": 0, "opacity": 1, "near": 2, "degenerate": 3, "viewport": 4}
+FLAG_FIXED_3SIGMA = 1
+FLAG_NO_VIEWPORT_CULL = 2
+
+
+def build(verbose=False):
+    """Compile oracle.cpp into liboracle.so with g++ (no GPU code involved)."""
+    cmd = ["g++", "-O2", "-std=c++17", "-Wall", "-Wextra", "-shared", "-fPIC", "-o", _LIB_PATH, _SRC]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.run(cmd, check=True)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+        build()
+    lib = C.CDLL(_LIB_PATH)
+    P = C.POINTER
+    d, i64, i32 = P(C.c_double), C.c_int64, C.c_int32
+    lib.orc_preprocess.argtypes = [i64, d, d, d, d, d, P(_Camera), P(_Options), P(_Projected)]
+    lib.orc_emit.argtypes = [i64, P(_Camera), P(_Options), d, d, d, d, d, i64, P(C.c_uint64), P(C.c_uint32), i64]
+    lib.orc_emit.restype = i64
+    lib.orc_stable_sort.argtypes = [i64, P(C.c_uint64), P(C.c_uint32), i32, i32]
+    lib.orc_tile_ranges.argtypes = [i64, P(C.c_uint64), i64, P(C.c_int64)]
+    lib.orc_composite.argtypes = [i64, d, d, d, d, P(C.c_int32), P(_Camera), P(_Options), i64, P(C.c_uint32),
+                                  P(C.c_int64), i64, P(C.c_uint8), P(_Image)]
+    lib.orc_render_brute.argtypes = [i64, d, d, d, d, d, P(_Camera), P(_Options), P(C.c_uint8), P(_Image)]
+    lib.orc_forward_backward.argtypes = [i64, d, d, d, d, d, P(_Camera), P(_Options), d, d, d, d, d, d, d, d]
+    lib.orc_forward_backward.restype = C.c_uint64
+    lib.orc_sh_basis.argtypes = [d, i32, d]
+    lib.orc_quat_to_rotmat.argtypes = [d, d]
+    _lib = lib
+    return lib
+
+
+class _Camera(C.Structure):
+    _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("fx", C.c_double), ("fy", C.c_double),
+                ("cx", C.c_double), ("cy", C.c_double), ("R", C.c_double * 9), ("t", C.c_double * 3),
+                ("C", C.c_double * 3)]
+
+
+class _Options(C.Structure):
+    _fields_ = [("tile_w", C.c_int32), ("tile_h", C.c_int32), ("sh_degree", C.c_int32), ("flags", C.c_int32),
+                ("near_z", C.c_double), ("lowpass", C.c_double), ("clamp_fov", C.c_double),
+                ("alpha_min", C.c_double), ("alpha_max", C.c_double), ("t_min", C.c_double),
+                ("bg", C.c_double * 3)]
+
+
+class _Projected(C.Structure):
+    _fields_ = [(name, C.c_void_p) for name in (
+        "status", "mean2d", "conic", "cov2d", "z", "depth32", "opacity", "rgb", "pix_rect", "tile_rect",
+        "tiles_touched", "clamp_bits", "bounds")]
+
+
+class _Image(C.Structure):
+    _fields_ = [(name, C.c_void_p) for name in ("rgb", "T", "n_eval", "n_contrib", "alpha_margin", "t_margin", "hash")]
+
+
+@dataclass
+class Options:
+    """Render options; the values are the readings of the paper used throughout."""
+    tile_w: int = 16
+    tile_h: int = 16
+    sh_degree: int = 0
+    flags: int = 0
+    near_z: float = 0.2
+    lowpass: float = 0.3
+    clamp_fov: float = 1.3
+    alpha_min: float = 1.0 / 255.0
+    alpha_max: float = 0.99
+    t_min: float = 1e-4
+    bg: tuple = (0.0, 0.0, 0.0)
+
+
+def _opts(o: Options) -> _Options:
+    s = _Options()
+    s.tile_w, s.tile_h, s.sh_degree, s.flags = o.tile_w, o.tile_h, o.sh_degree, o.flags
+    s.near_z, s.lowpass, s.clamp_fov = o.near_z, o.lowpass, o.clamp_fov
+    s.alpha_min, s.alpha_max, s.t_min = o.alpha_min, o.alpha_max, o.t_min
+    s.bg[:] = [float(b) for b in o.bg]
+    return s
+
+
+def _cam(cam) -> _Camera:
+    s = _Camera()
+    s.width, s.height = int(cam.width), int(cam.height)
+    s.fx, s.fy, s.cx, s.cy = float(cam.fx), float(cam.fy), float(cam.cx), float(cam.cy)
+    s.R[:] = [float(x) for x in np.asarray(cam.R, dtype=np.float64).reshape(9)]
+    s.t[:] = [float(x) for x in np.asarray(cam.t, dtype=np.float64).reshape(3)]
+    s.C[:] = [float(x) for x in np.asarray(cam.C, dtype=np.float64).reshape(3)]
+    return s
+
+
+def _dp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _scene64(scene):
+    return (_f64(scene.means), _f64(scene.log_scales), _f64(scene.quats), _f64(scene.opacity_logits),
+            _f64(scene.sh))
+
+
+def _check_opts(scene, opts: Options):
+    if opts.sh_degree != scene.sh_degree:
+        raise ValueError("opts.sh_degree must equal scene.sh_degree")
+
+
+def preprocess(scene, cam, opts: Options) -> dict:
+    """Per-Gaussian projection, colour and culling for one camera (all fp64)."""
+    _check_opts(scene, opts)
+    lib = _load()
+    n = scene.n
+    out = dict(
+        status=np.zeros(n, np.int8), mean2d=np.zeros((2, n)), conic=np.zeros((3, n)), cov2d=np.zeros((3, n)),
+        z=np.zeros(n), depth32=np.zeros(n, np.float32), opacity=np.zeros(n), rgb=np.zeros((3, n)),
+        pix_rect=np.zeros((4, n), np.int32), tile_rect=np.zeros((4, n), np.int32),
+        tiles_touched=np.zeros(n, np.int64), clamp_bits=np.zeros(n, np.uint8), bounds=np.zeros((4, n)))
+    P = _Projected(**{k: out[k].ctypes.data for k in out})
+    m, s, q, o, sh = _scene64(scene)
+    lib.orc_preprocess(n, _dp(m), _dp(s), _dp(q), _dp(o), _dp(sh), C.byref(_cam(cam)), C.byref(_opts(opts)),
+                       C.byref(P))
+    return out
+
+
+def tiles_xy(cam, opts: Options):
+    return (cam.width + opts.tile_w - 1) // opts.tile_w, (cam.height + opts.tile_h - 1) // opts.tile_h
+
+
+def emit(scene, cam, opts: Options, tile_offset=0):
+    """(tile | depth) keys and Gaussian-id values in emission order."""
+    _check_opts(scene, opts)
+    lib = _load()
+    m, s, q, o, sh = _scene64(scene)
+    cam_s, opt_s = _cam(cam), _opts(opts)
+    count = lib.orc_emit(scene.n, C.byref(cam_s), C.byref(opt_s), _dp(m), _dp(s), _dp(q), _dp(o), _dp(sh),
+                         tile_offset, None, None, 0)
+    keys = np.zeros(count, np.uint64)
+    vals = np.zeros(count, np.uint32)
+    lib.orc_emit(scene.n, C.byref(cam_s), C.byref(opt_s), _dp(m), _dp(s), _dp(q), _dp(o), _dp(sh), tile_offset,
+                 keys.ctypes.data_as(C.POINTER(C.c_uint64)), vals.ctypes.data_as(C.POINTER(C.c_uint32)), count)
+    return keys, vals
+
+
+def pair_count(scene, cam, opts: Options) -> int:
+    """Number of (tile, splat) pairs the view emits (the sum of tiles_touched)."""
+    _check_opts(scene, opts)
+    lib = _load()
+    m, s, q, o, sh = _scene64(scene)
+    return int(lib.orc_emit(scene.n, C.byref(_cam(cam)), C.byref(_opts(opts)), _dp(m), _dp(s), _dp(q), _dp(o),
+                            _dp(sh), 0, None, None, 0))
+
+
+def stable_sort(keys, vals, begin_bit=0, end_bit=64):
+    """std::stable_sort of the pairs on key bits [begin_bit, end_bit); returns sorted copies."""
+    lib = _load()
+    k = np.array(keys, dtype=np.uint64, copy=True)
+    v = np.array(vals, dtype=np.uint32, copy=True)
+    lib.orc_stable_sort(k.size, k.ctypes.data_as(C.POINTER(C.c_uint64)), v.ctypes.data_as(C.POINTER(C.c_uint32)),
+                        begin_bit, end_bit)
+    return k, v
+
+
+def tile_ranges(keys, n_tiles):
+    lib = _load()
+    k = np.ascontiguousarray(keys, dtype=np.uint64)
+    r = np.zeros((n_tiles, 2), np.int64)
+    lib.orc_tile_ranges(k.size, k.ctypes.data_as(C.POINTER(C.c_uint64)), n_tiles,
+                        r.ctypes.data_as(C.POINTER(C.c_int64)))
+    return r
+
+
+def _image_buffers(H, W):
+    return dict(rgb=np.zeros((3, H, W)), T=np.zeros((H, W)), n_eval=np.zeros((H, W), np.int64),
+                n_contrib=np.zeros((H, W), np.int64), alpha_margin=np.full((H, W), np.inf),
+                t_margin=np.full((H, W), np.inf), hash=np.zeros((H, W), np.uint64))
+
+
+def composite(mean2d, conic, opacity, rgb, pix_rect, cam, opts: Options, vals, ranges, tile_offset=0, mask=None):
+    """Tiled front-to-back compositing of given projected splats (fp64) and a sorted pair list."""
+    lib = _load()
+    n = int(np.asarray(opacity).shape[0])
+    mean2d, conic, opacity, rgb = _f64(mean2d), _f64(conic), _f64(opacity), _f64(rgb)
+    pr = np.ascontiguousarray(pix_rect, dtype=np.int32)
+    v = np.ascontiguousarray(vals, dtype=np.uint32)
+    rg = np.ascontiguousarray(ranges, dtype=np.int64)
+    out = _image_buffers(cam.height, cam.width)
+    img = _Image(**{k: out[k].ctypes.data for k in out})
+    mk = None
+    if mask is not None:
+        mk = np.ascontiguousarray(mask, dtype=np.uint8)
+    lib.orc_composite(n, _dp(mean2d), _dp(conic), _dp(opacity), _dp(rgb), pr.ctypes.data_as(C.POINTER(C.c_int32)),
+                      C.byref(_cam(cam)), C.byref(_opts(opts)), v.size, v.ctypes.data_as(C.POINTER(C.c_uint32)),
+                      rg.ctypes.data_as(C.POINTER(C.c_int64)), tile_offset,
+                      None if mk is None else mk.ctypes.data_as(C.POINTER(C.c_uint8)), C.byref(img))
+    return out
+
+
+def render(scene, cam, opts: Options, mode="tiled", mask=None) -> dict:
+    """Whole forward path for one view.
+
+    mode="tiled": preprocess, emit, stable sort, tile ranges, composite (the
+    pipeline's own steps).  mode="brute": every validly projected Gaussian at
+    every pixel in (fp32 depth bits, id) order, no culling (the definition).
+    """
+    _check_opts(scene, opts)
+    if mode == "brute":
+        lib = _load()
+        m, s, q, o, sh = _scene64(scene)
+        out = _image_buffers(cam.height, cam.width)
+        img = _Image(**{k: out[k].ctypes.data for k in out})
+        mk = None if mask is None else np.ascontiguousarray(mask, dtype=np.uint8)
+        lib.orc_render_brute(scene.n, _dp(m), _dp(s), _dp(q), _dp(o), _dp(sh), C.byref(_cam(cam)),
+                             C.byref(_opts(opts)), None if mk is None else mk.ctypes.data_as(C.POINTER(C.c_uint8)),
+                             C.byref(img))
+        return out
+    proj = preprocess(scene, cam, opts)
+    keys, vals = emit(scene, cam, opts)
+    skeys, svals = stable_sort(keys, vals)
+    tx, ty = tiles_xy(cam, opts)
+    ranges = tile_ranges(skeys, tx * ty)
+    out = composite(proj["mean2d"], proj["conic"], proj["opacity"], proj["rgb"], proj["pix_rect"], cam, opts,
+                    svals, ranges, 0, mask)
+    out.update(proj=proj, keys=keys, vals=vals, sorted_keys=skeys, sorted_vals=svals, ranges=ranges)
+    return out
+
+
+def forward_backward(scene, cam, opts: Options, dL_dimage=None):
+    """Forward of one view and, if dL_dimage [3,H,W] is given, its fp64 reverse mode.
+
+    Returns dict(image, grads={means, log_scales, quats, opacity_logits, sh},
+    splat_grad [n, 9] = dL/d(u, v, A, B, C, sigma, r, g, b), hash).
+    """
+    _check_opts(scene, opts)
+    lib = _load()
+    m, s, q, o, sh = _scene64(scene)
+    n = scene.n
+    H, W = cam.height, cam.width
+    image = np.zeros((3, H, W))
+    grads = dict(means=np.zeros((3, n)), log_scales=np.zeros((3, n)), quats=np.zeros((4, n)),
+                 opacity_logits=np.zeros(n), sh=np.zeros_like(sh))
+    splat_grad = np.zeros((n, 9))
+    g = None if dL_dimage is None else _f64(dL_dimage)
+    h = lib.orc_forward_backward(n, _dp(m), _dp(s), _dp(q), _dp(o), _dp(sh), C.byref(_cam(cam)),
+                                 C.byref(_opts(opts)), None if g is None else _dp(g), _dp(image),
+                                 _dp(grads["means"]), _dp(grads["log_scales"]), _dp(grads["quats"]),
+                                 _dp(grads["opacity_logits"]), _dp(grads["sh"]), _dp(splat_grad))
+    return dict(image=image, grads=grads, splat_grad=splat_grad, hash=int(h))
+
+
+def sh_basis(direction, degree=3):
+    lib = _load()
+    d = _f64(direction)
+    out = np.zeros(16)
+    lib.orc_sh_basis(_dp(d), degree, _dp(out))
+    return out[: (degree + 1) ** 2]
+
+
+def quat_to_rotmat(q):
+    lib = _load()
+    qq = _f64(q)
+    out = np.zeros(9)
+    lib.orc_quat_to_rotmat(_dp(qq), _dp(out))
+    return out.reshape(3, 3)
+
+
+def l1_loss_grad(image, target):
+    """L1 loss = mean |I - I*| over all elements; dL/dI = sign(I - I*) / numel with sign(0) = 0."""
+    diff = np.asarray(image, np.float64) - np.asarray(target, np.float64)
+    return np.abs(diff).mean(), np.sign(diff) / diff.size
