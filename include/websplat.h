@@ -1,0 +1,238 @@
+/*
+ * websplat.h -- C ABI of the MI355X (gfx950) 3D Gaussian Splatting render path.
+ *
+ * The library implements the per-frame path that WebSplatter (arXiv
+ * 2602.03207) accelerates, as a tile-based compute pipeline:
+ *
+ *   ws_preprocess       projection of each 3D Gaussian to a 2D splat (EWA,
+ *                       Sec. 2.1 Eq. 1-2), view-dependent SH colour (Eq. 3),
+ *                       opacity and bounding-box culling (Sec. 3.2, Sec. 3.4
+ *                       Eq. 7-8), then compaction into (tile | depth) keys.
+ *   ws_sort             stable LSD radix sort of the 64-bit keys with their
+ *                       32-bit values; each pass places an element at
+ *                       base_d + prefix_wg + rank_local (Sec. 3.3.2, Eq. 5-6).
+ *   ws_render           per-tile front-to-back alpha compositing (Eq. 2, Eq. 4).
+ *   ws_render_backward  reverse mode of ws_render and ws_preprocess.
+ *
+ * Conventions shared by every call
+ *   - Memory: every array argument is DEVICE memory owned by the caller unless
+ *     the argument says "host".  The library never allocates, frees or keeps a
+ *     pointer after a call returns.  Scratch memory comes from the caller
+ *     through (ws, ws_bytes); its size is given by the matching
+ *     ws_*_workspace_size() call.  ws must be 256-byte aligned.
+ *   - Streams: `stream` is a hipStream_t passed as void* (NULL = the null
+ *     stream).  Calls enqueue work and return without synchronising; they do
+ *     not call hipMemset or hipMalloc, so they may be captured in a HIP graph.
+ *   - Errors: argument errors are detected on the host before any work is
+ *     enqueued and returned as a ws_status; ws_last_error() then holds a
+ *     message (thread-local).  Conditions only the device can see (too many
+ *     pairs for the caller's capacity, an expired bounded wait) are written to
+ *     the caller's int32 device status word `d_status`; every later kernel
+ *     that receives the same d_status exits early without writing output.
+ *   - Layout: Gaussian parameters are fp32 structure-of-arrays, component
+ *     major: means[3][n], log_scales[3][n], quats[4][n] (w, x, y, z; need not
+ *     be normalised), opacity_logits[n], sh[3*K][n] with row k*3 + c holding
+ *     SH coefficient k of colour channel c, K = (sh_degree + 1)^2.
+ *     Images are fp32 planar [3][H][W] per view, views packed back to back in
+ *     view order.
+ *   - Multi-view: every call takes n_views cameras.  Tiles of all views share
+ *     one global id space: view v owns ids [tile_offset(v),
+ *     tile_offset(v) + tiles_x(v) * tiles_y(v)), tile_offset being the sum of
+ *     the tile counts of the views before it; tiles are row-major in a view.
+ *   - Determinism: preprocess, sort and render produce identical bits on
+ *     every run and for every launch configuration (tile size, radix width,
+ *     ordered or plain render).  The backward pass accumulates with
+ *     floating-point atomics and is reproducible only to rounding.
+ */
+#ifndef WEBSPLAT_H
+#define WEBSPLAT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum ws_status {
+    WS_OK = 0,
+    WS_ERR_INVALID_ARGUMENT = 1,   /* null pointer, negative size, bad option value */
+    WS_ERR_UNSUPPORTED = 2,        /* valid but not implemented (e.g. sh_degree > 3, tile size) */
+    WS_ERR_WORKSPACE_TOO_SMALL = 3,
+    WS_ERR_HIP = 4,                /* a HIP runtime call failed; message in ws_last_error() */
+    WS_ERR_CAPACITY = 5,           /* device status only: more pairs than the key buffers hold */
+    WS_ERR_SPIN_LIMIT = 6          /* device status only: a bounded inter-workgroup wait expired */
+} ws_status;
+
+/* Pinhole camera, OpenCV axes (x right, y down, z forward).  A world point X
+ * maps to camera space p = R X + t and to pixel (fx p.x/p.z + cx,
+ * fy p.y/p.z + cy); the centre of pixel (i, j) is (i + 0.5, j + 0.5).
+ * C is the world-space camera centre used for the SH view direction
+ * d = (X - C) / |X - C| (Sec. 2.1, Eq. 3).  width, height in [1, 32767]. */
+typedef struct ws_camera {
+    int32_t width, height;
+    float fx, fy, cx, cy;
+    float R[9];   /* row-major world -> camera rotation */
+    float t[3];
+    float C[3];
+    int32_t reserved;  /* must be 0 */
+} ws_camera;          /* 88 bytes */
+
+/* flags */
+#define WS_FLAG_FIXED_3SIGMA     1u  /* "-RADIUS" ablation (Sec. 4.4): 3-sigma extent for every splat */
+#define WS_FLAG_NO_VIEWPORT_CULL 2u  /* "-CULL" ablation (Sec. 4.4): keep splats whose AABB misses the view */
+#define WS_FLAG_ORDERED_RENDER   4u  /* render: persistent workgroups take tiles in descending pair count */
+
+typedef struct ws_options {
+    int32_t tile_w, tile_h;   /* 16x16 (default), 8x8, 16x8 or 32x16 pixels */
+    int32_t sh_degree;        /* 0..3 */
+    int32_t radix_bits;       /* ws_sort digit width 1..8; 0 = library default (8) */
+    uint32_t flags;           /* WS_FLAG_* */
+    float near_z;             /* cull p.z <= near_z (default 0.2) */
+    float lowpass;            /* added to both diagonal entries of the 2D covariance (0.3 px^2) */
+    float clamp_fov;          /* Jacobian uses x/z, y/z clamped to clamp_fov * half-FOV tangent (1.3) */
+    float alpha_min;          /* cull sigma < alpha_min; skip splats with alpha < alpha_min (1/255) */
+    float alpha_max;          /* alpha = min(alpha_max, sigma exp(power)) (0.99) */
+    float t_min;              /* stop before the transmittance falls below t_min (1e-4) */
+    float bg[3];              /* background colour, weighted by the final transmittance */
+} ws_options;
+
+typedef struct ws_gaussians {
+    int64_t n;                    /* number of Gaussians, 0 <= n < 2^31 */
+    const float* means;           /* [3][n] */
+    const float* log_scales;      /* [3][n] */
+    const float* quats;           /* [4][n] */
+    const float* opacity_logits;  /* [n] */
+    const float* sh;              /* [3*K][n] */
+} ws_gaussians;
+
+/* One projected splat (one per view and Gaussian), 48 bytes, 16-byte aligned.
+ * Valid only where tiles_touched != 0; otherwise the contents are unspecified. */
+typedef struct ws_splat {
+    float mean2d[2];     /* projected centre, pixels */
+    float conic[3];      /* A, B, C: inverse 2D covariance [[A, B], [B, C]] */
+    float opacity;       /* sigma = sigmoid(logit) */
+    float rgb[3];        /* max(0, SH + 0.5) */
+    float depth;         /* camera-space z, rounded to fp32 (its bits are the low key word) */
+    uint16_t rect[4];    /* inclusive pixel rectangle x0, x1, y0, y1 (the culling AABB, clipped) */
+} ws_splat;
+
+typedef struct ws_gaussian_grads {  /* same shapes as ws_gaussians; overwritten, not accumulated */
+    float* means;
+    float* log_scales;
+    float* quats;
+    float* opacity_logits;
+    float* sh;
+} ws_gaussian_grads;
+
+/* ------------------------------------------------------------------ sizes */
+
+/* Bytes of workspace for ws_preprocess with n Gaussians and n_views views. */
+size_t ws_preprocess_workspace_size(int64_t n, int32_t n_views);
+
+/* Bytes of workspace for ws_sort of up to `capacity` pairs on bits
+ * [begin_bit, end_bit) with digits of radix_bits (0 = default). */
+size_t ws_sort_workspace_size(int64_t capacity, int32_t begin_bit, int32_t end_bit, int32_t radix_bits);
+
+/* Bytes of workspace for ws_render over these host cameras. */
+size_t ws_render_workspace_size(const ws_camera* cams, int32_t n_views, const ws_options* opt);
+
+/* Bytes of workspace for ws_render_backward. */
+size_t ws_render_backward_workspace_size(int64_t n, int32_t n_views);
+
+/* Total tile count of the views (the length of the tile_ranges array / 2). */
+int64_t ws_total_tiles(const ws_camera* cams, int32_t n_views, const ws_options* opt);
+
+/* Total image floats of the views: sum of 3 * width * height. */
+int64_t ws_total_image_floats(const ws_camera* cams, int32_t n_views);
+
+/* ------------------------------------------------------------ the path */
+
+/* Pre-processing and key emission (Sec. 3.2; culling rules of Sec. 3.4).
+ *   g           Gaussians (device arrays, see the layout above)
+ *   cams        host array of n_views cameras (read during the call, for sizes)
+ *   d_cams      device copy of the same n_views cameras (read by the kernels)
+ *   splats      out [n_views][n] ws_splat
+ *   tiles_touched out [n_views][n] uint32: tiles covered by the splat, 0 if culled
+ *   keys, values out [capacity]: pair j = ((global tile id) << 32 | fp32 bits of
+ *               depth, Gaussian id), emitted for views in order, Gaussians in id
+ *               order and tiles row-major inside each splat's rectangle
+ *   d_num_pairs out device int64: the number of pairs M (also when M > capacity)
+ *   d_status    in/out device int32; set to WS_ERR_CAPACITY when M > capacity
+ *               (pairs beyond capacity are not written).  The caller zeroes it
+ *               before the first call of a frame.
+ * Culls (no pair): sigma < alpha_min, p.z <= near_z, non-finite parameters or
+ * zero quaternion, and a pixel rectangle that contains no pixel centre. */
+ws_status ws_preprocess(const ws_gaussians* g, const ws_camera* cams, const ws_camera* d_cams, int32_t n_views,
+                        const ws_options* opt, ws_splat* splats, uint32_t* tiles_touched, uint64_t* keys,
+                        uint32_t* values, int64_t capacity, int64_t* d_num_pairs, int32_t* d_status, void* ws,
+                        size_t ws_bytes, void* stream);
+
+/* Stable LSD radix sort of (key, value) pairs on key bits [begin_bit, end_bit)
+ * (Sec. 3.3.2): the result equals a stable sort by (key >> begin_bit) masked to
+ * end_bit - begin_bit bits; values move with their keys.
+ *   keys_in, values_in   input, not modified
+ *   keys_out, values_out output; must not overlap the inputs
+ *   n          number of pairs, or the capacity when d_n != NULL
+ *   d_n        optional device int64 count (clamped to n), for device-sized sorts
+ *   d_status   optional device status word: if non-zero on entry nothing is done
+ * 0 <= begin_bit < end_bit <= 64; n < 2^30.  With radix_bits r the sort runs
+ * ceil((end_bit - begin_bit) / r) passes. */
+ws_status ws_sort(const uint64_t* keys_in, const uint32_t* values_in, uint64_t* keys_out, uint32_t* values_out,
+                  int64_t n, const int64_t* d_n, const int32_t* d_status, int32_t begin_bit, int32_t end_bit,
+                  int32_t radix_bits, void* ws, size_t ws_bytes, void* stream);
+
+/* Tile ranges and front-to-back compositing (Eq. 2, Eq. 4).
+ *   splats        [n_views][n] from ws_preprocess
+ *   keys, values  tile-sorted pairs from ws_sort; count = min(*d_num_pairs, capacity)
+ *   tile_ranges   out [total_tiles][2] uint32: [start, end) of each tile's pairs
+ *   images        out: views packed back to back, each [3][H][W] fp32
+ * Per pixel, splats are taken in key order: a splat is skipped if the pixel is
+ * outside its rectangle or alpha < alpha_min; the pixel stops before a splat
+ * that would bring the transmittance below t_min; output = C + T * bg. */
+ws_status ws_render(const ws_splat* splats, int64_t n, const ws_camera* cams, const ws_camera* d_cams,
+                    int32_t n_views, const ws_options* opt, const uint64_t* keys, const uint32_t* values,
+                    int64_t capacity, const int64_t* d_num_pairs, const int32_t* d_status, uint32_t* tile_ranges,
+                    float* images, void* ws, size_t ws_bytes, void* stream);
+
+/* Reverse mode of ws_render and ws_preprocess.  Given dL/dimages (same
+ * layout as images), writes dL/d(parameters) summed over the views into
+ * `grads` (overwritten).  The compositing adjoint recomputes each tile front
+ * to back to find every pixel's final transmittance and last contributor,
+ * then walks back to front; no per-pixel state is stored by the forward.
+ * Discrete decisions (culls, skips, early stop, clamps) take the derivative
+ * of the branch taken. */
+ws_status ws_render_backward(const ws_gaussians* g, const ws_camera* cams, const ws_camera* d_cams,
+                             int32_t n_views, const ws_options* opt, const ws_splat* splats,
+                             const uint32_t* values, const uint32_t* tile_ranges, const float* dL_dimages,
+                             const int32_t* d_status, ws_gaussian_grads* grads, void* ws, size_t ws_bytes,
+                             void* stream);
+
+/* L1 photometric loss: *d_loss = mean |images - targets| over n floats and
+ * dL_dimages = sign(images - targets) / n (sign(0) = 0).  Deterministic. */
+ws_status ws_l1_loss(const float* images, const float* targets, int64_t n, float* dL_dimages, float* d_loss,
+                     void* ws, size_t ws_bytes, void* stream);
+size_t ws_l1_loss_workspace_size(int64_t n);
+
+/* ----------------------------------------------------------- HIP graphs */
+
+typedef struct ws_graph_s* ws_graph;
+
+/* Begin capturing the work enqueued on `stream` (thread-local capture mode). */
+ws_status ws_graph_begin(void* stream);
+/* End the capture and instantiate it; *out receives an executable graph. */
+ws_status ws_graph_end(void* stream, ws_graph* out);
+ws_status ws_graph_launch(ws_graph graph, void* stream);
+ws_status ws_graph_destroy(ws_graph graph);
+
+/* ------------------------------------------------------------ utilities */
+
+const char* ws_last_error(void);           /* thread-local message of the last failed call */
+const char* ws_status_string(int32_t status);
+int32_t ws_version(void);                  /* major * 10000 + minor * 100 + patch */
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WEBSPLAT_H */

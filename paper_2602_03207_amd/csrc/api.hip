@@ -1,0 +1,326 @@
+// C ABI of libwebsplat: argument validation, workspace sizing, error
+// reporting and HIP-graph helpers.  Every check here runs on the host before
+// any work is enqueued, so a rejected call leaves the stream untouched.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <string>
+
+#include "ws_internal.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+ws_status fail(ws_status s, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return s;
+}
+
+ws_status hip_status(hipError_t e, const char* where) {
+    if (e == hipSuccess) return WS_OK;
+    return fail(WS_ERR_HIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+constexpr int32_t kMaxViews = 4096;
+constexpr int64_t kMaxGaussians = (int64_t(1) << 31) - 1;
+constexpr int64_t kMaxSortN = (int64_t(1) << 30) - 1;
+
+bool finite_pos(float x) { return std::isfinite(x) && x > 0.f; }
+
+ws_status check_options(const ws_options* o) {
+    if (!o) return fail(WS_ERR_INVALID_ARGUMENT, "options is NULL");
+    const bool tile_ok = (o->tile_w == 16 && o->tile_h == 16) || (o->tile_w == 8 && o->tile_h == 8) ||
+                         (o->tile_w == 16 && o->tile_h == 8) || (o->tile_w == 32 && o->tile_h == 16);
+    if (!tile_ok) return fail(WS_ERR_UNSUPPORTED, "tile size %dx%d not supported (16x16, 8x8, 16x8, 32x16)",
+                              o->tile_w, o->tile_h);
+    if (o->sh_degree < 0 || o->sh_degree > 3)
+        return fail(WS_ERR_UNSUPPORTED, "sh_degree %d not supported (0..3)", o->sh_degree);
+    if (o->radix_bits < 0 || o->radix_bits > 8)
+        return fail(WS_ERR_INVALID_ARGUMENT, "radix_bits %d out of range (0..8)", o->radix_bits);
+    if (o->flags & ~(WS_FLAG_FIXED_3SIGMA | WS_FLAG_NO_VIEWPORT_CULL | WS_FLAG_ORDERED_RENDER))
+        return fail(WS_ERR_INVALID_ARGUMENT, "unknown flag bits 0x%x", o->flags);
+    if (!finite_pos(o->near_z)) return fail(WS_ERR_INVALID_ARGUMENT, "near_z must be finite and > 0");
+    if (!(std::isfinite(o->lowpass) && o->lowpass >= 0.f))
+        return fail(WS_ERR_INVALID_ARGUMENT, "lowpass must be finite and >= 0");
+    if (!finite_pos(o->clamp_fov)) return fail(WS_ERR_INVALID_ARGUMENT, "clamp_fov must be finite and > 0");
+    if (!(o->alpha_min > 0.f && o->alpha_min < 1.f))
+        return fail(WS_ERR_INVALID_ARGUMENT, "alpha_min must lie in (0, 1)");
+    if (!(o->alpha_max >= o->alpha_min && o->alpha_max < 1.f))
+        return fail(WS_ERR_INVALID_ARGUMENT, "alpha_max must lie in [alpha_min, 1)");
+    if (!(o->t_min > 0.f && o->t_min < 1.f)) return fail(WS_ERR_INVALID_ARGUMENT, "t_min must lie in (0, 1)");
+    for (int c = 0; c < 3; ++c)
+        if (!std::isfinite(o->bg[c])) return fail(WS_ERR_INVALID_ARGUMENT, "bg must be finite");
+    return WS_OK;
+}
+
+ws_status check_cameras(const ws_camera* cams, const ws_camera* d_cams, int32_t n_views) {
+    if (n_views < 1 || n_views > kMaxViews)
+        return fail(WS_ERR_INVALID_ARGUMENT, "n_views %d out of range (1..%d)", n_views, kMaxViews);
+    if (!cams) return fail(WS_ERR_INVALID_ARGUMENT, "cams (host) is NULL");
+    if (!d_cams) return fail(WS_ERR_INVALID_ARGUMENT, "d_cams (device) is NULL");
+    for (int32_t v = 0; v < n_views; ++v) {
+        const ws_camera& c = cams[v];
+        if (c.width < 1 || c.width > 32767 || c.height < 1 || c.height > 32767)
+            return fail(WS_ERR_INVALID_ARGUMENT, "camera %d: size %dx%d out of range", v, c.width, c.height);
+        if (!finite_pos(c.fx) || !finite_pos(c.fy) || !std::isfinite(c.cx) || !std::isfinite(c.cy))
+            return fail(WS_ERR_INVALID_ARGUMENT, "camera %d: intrinsics must be finite, fx and fy > 0", v);
+        for (int k = 0; k < 9; ++k)
+            if (!std::isfinite(c.R[k])) return fail(WS_ERR_INVALID_ARGUMENT, "camera %d: R not finite", v);
+        for (int k = 0; k < 3; ++k)
+            if (!std::isfinite(c.t[k]) || !std::isfinite(c.C[k]))
+                return fail(WS_ERR_INVALID_ARGUMENT, "camera %d: t or C not finite", v);
+    }
+    return WS_OK;
+}
+
+ws_status check_gaussians(const ws_gaussians* g) {
+    if (!g) return fail(WS_ERR_INVALID_ARGUMENT, "gaussians is NULL");
+    if (g->n < 0 || g->n > kMaxGaussians)
+        return fail(WS_ERR_INVALID_ARGUMENT, "n = %lld out of range (0..2^31-1)", (long long)g->n);
+    if (g->n > 0 && (!g->means || !g->log_scales || !g->quats || !g->opacity_logits || !g->sh))
+        return fail(WS_ERR_INVALID_ARGUMENT, "a Gaussian parameter array is NULL");
+    return WS_OK;
+}
+
+ws_status check_ws(const void* ws, size_t ws_bytes, size_t need) {
+    if (ws_bytes < need)
+        return fail(WS_ERR_WORKSPACE_TOO_SMALL, "workspace of %zu bytes, %zu needed", ws_bytes, need);
+    if (need > 0 && !ws) return fail(WS_ERR_INVALID_ARGUMENT, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(ws) % 256 != 0)
+        return fail(WS_ERR_INVALID_ARGUMENT, "workspace must be 256-byte aligned");
+    return WS_OK;
+}
+
+int64_t total_tiles_of(const ws_camera* cams, int32_t n_views, int32_t tw, int32_t th) {
+    int64_t t = 0;
+    for (int32_t v = 0; v < n_views; ++v) t += int64_t(ws::ceil_div(cams[v].width, tw)) * ws::ceil_div(cams[v].height, th);
+    return t;
+}
+
+ws::GaussPtrs gauss_ptrs(const ws_gaussians* g) {
+    ws::GaussPtrs p;
+    p.means = g->means;
+    p.log_scales = g->log_scales;
+    p.quats = g->quats;
+    p.logits = g->opacity_logits;
+    p.sh = g->sh;
+    p.n = g->n;
+    return p;
+}
+
+bool overlaps(const void* a, size_t an, const void* b, size_t bn) {
+    const uintptr_t x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
+    return x < y + bn && y < x + an;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t ws_version(void) { return 10000; }
+
+const char* ws_last_error(void) { return g_last_error.c_str(); }
+
+const char* ws_status_string(int32_t s) {
+    switch (s) {
+        case WS_OK: return "ok";
+        case WS_ERR_INVALID_ARGUMENT: return "invalid argument";
+        case WS_ERR_UNSUPPORTED: return "unsupported";
+        case WS_ERR_WORKSPACE_TOO_SMALL: return "workspace too small";
+        case WS_ERR_HIP: return "HIP error";
+        case WS_ERR_CAPACITY: return "pair capacity exceeded";
+        case WS_ERR_SPIN_LIMIT: return "bounded wait expired";
+        default: return "unknown status";
+    }
+}
+
+size_t ws_preprocess_workspace_size(int64_t n, int32_t n_views) {
+    if (n < 0 || n_views < 1) return 0;
+    return ws::preprocess_workspace(n, n_views);
+}
+
+size_t ws_sort_workspace_size(int64_t capacity, int32_t begin_bit, int32_t end_bit, int32_t radix_bits) {
+    if (capacity < 0 || begin_bit < 0 || end_bit > 64 || begin_bit >= end_bit || radix_bits < 0 || radix_bits > 8)
+        return 0;
+    return ws::sort_workspace(capacity, begin_bit, end_bit, radix_bits);
+}
+
+int64_t ws_total_tiles(const ws_camera* cams, int32_t n_views, const ws_options* opt) {
+    if (!cams || !opt || n_views < 1 || opt->tile_w < 1 || opt->tile_h < 1) return -1;
+    return total_tiles_of(cams, n_views, opt->tile_w, opt->tile_h);
+}
+
+int64_t ws_total_image_floats(const ws_camera* cams, int32_t n_views) {
+    if (!cams || n_views < 1) return -1;
+    int64_t f = 0;
+    for (int32_t v = 0; v < n_views; ++v) f += 3ll * cams[v].width * cams[v].height;
+    return f;
+}
+
+size_t ws_render_workspace_size(const ws_camera* cams, int32_t n_views, const ws_options* opt) {
+    if (!cams || !opt || n_views < 1 || opt->tile_w < 1 || opt->tile_h < 1) return 0;
+    return ws::render_workspace(total_tiles_of(cams, n_views, opt->tile_w, opt->tile_h), ws::to_kopts(*opt));
+}
+
+size_t ws_render_backward_workspace_size(int64_t n, int32_t n_views) {
+    if (n < 0 || n_views < 1) return 0;
+    return ws::render_backward_workspace(n, n_views);
+}
+
+size_t ws_l1_loss_workspace_size(int64_t n) {
+    if (n < 0) return 0;
+    return ws::l1_loss_workspace(n);
+}
+
+ws_status ws_preprocess(const ws_gaussians* g, const ws_camera* cams, const ws_camera* d_cams, int32_t n_views,
+                        const ws_options* opt, ws_splat* splats, uint32_t* tiles_touched, uint64_t* keys,
+                        uint32_t* values, int64_t capacity, int64_t* d_num_pairs, int32_t* d_status, void* ws,
+                        size_t ws_bytes, void* stream) {
+    ws_status s;
+    if ((s = check_gaussians(g)) != WS_OK) return s;
+    if ((s = check_cameras(cams, d_cams, n_views)) != WS_OK) return s;
+    if ((s = check_options(opt)) != WS_OK) return s;
+    if (g->n * int64_t(n_views) > kMaxGaussians)
+        return fail(WS_ERR_INVALID_ARGUMENT, "n * n_views must be < 2^31");
+    if (g->n > 0 && (!splats || !tiles_touched))
+        return fail(WS_ERR_INVALID_ARGUMENT, "splats / tiles_touched is NULL");
+    if (capacity < 0) return fail(WS_ERR_INVALID_ARGUMENT, "capacity < 0");
+    if (capacity > 0 && (!keys || !values)) return fail(WS_ERR_INVALID_ARGUMENT, "keys / values is NULL");
+    if (!d_num_pairs || !d_status) return fail(WS_ERR_INVALID_ARGUMENT, "d_num_pairs / d_status is NULL");
+    if (total_tiles_of(cams, n_views, opt->tile_w, opt->tile_h) > (int64_t(1) << 32))
+        return fail(WS_ERR_UNSUPPORTED, "more than 2^32 tiles");
+    if ((s = check_ws(ws, ws_bytes, ws::preprocess_workspace(g->n, n_views))) != WS_OK) return s;
+    if (reinterpret_cast<uintptr_t>(splats) % 16 != 0)
+        return fail(WS_ERR_INVALID_ARGUMENT, "splats must be 16-byte aligned");
+    const hipError_t e = ws::launch_preprocess(gauss_ptrs(g), d_cams, n_views, ws::to_kopts(*opt), splats,
+                                               tiles_touched, keys, values, capacity, d_num_pairs, d_status, ws,
+                                               static_cast<hipStream_t>(stream));
+    return hip_status(e, "ws_preprocess launch");
+}
+
+ws_status ws_sort(const uint64_t* keys_in, const uint32_t* values_in, uint64_t* keys_out, uint32_t* values_out,
+                  int64_t n, const int64_t* d_n, const int32_t* d_status, int32_t begin_bit, int32_t end_bit,
+                  int32_t radix_bits, void* ws, size_t ws_bytes, void* stream) {
+    if (n < 0 || n > kMaxSortN) return fail(WS_ERR_INVALID_ARGUMENT, "n = %lld out of range (0..2^30-1)", (long long)n);
+    if (begin_bit < 0 || end_bit > 64 || begin_bit >= end_bit)
+        return fail(WS_ERR_INVALID_ARGUMENT, "need 0 <= begin_bit < end_bit <= 64 (got %d, %d)", begin_bit, end_bit);
+    if (radix_bits < 0 || radix_bits > 8) return fail(WS_ERR_INVALID_ARGUMENT, "radix_bits %d out of range", radix_bits);
+    if (n == 0) return WS_OK;
+    if (!keys_in || !values_in || !keys_out || !values_out) return fail(WS_ERR_INVALID_ARGUMENT, "a key/value pointer is NULL");
+    if (overlaps(keys_in, size_t(n) * 8, keys_out, size_t(n) * 8) ||
+        overlaps(values_in, size_t(n) * 4, values_out, size_t(n) * 4))
+        return fail(WS_ERR_INVALID_ARGUMENT, "output buffers must not overlap the inputs");
+    ws_status s;
+    if ((s = check_ws(ws, ws_bytes, ws::sort_workspace(n, begin_bit, end_bit, radix_bits))) != WS_OK) return s;
+    const hipError_t e = ws::launch_sort(keys_in, values_in, keys_out, values_out, n, d_n, d_status, begin_bit,
+                                         end_bit, radix_bits, ws, static_cast<hipStream_t>(stream));
+    return hip_status(e, "ws_sort launch");
+}
+
+ws_status ws_render(const ws_splat* splats, int64_t n, const ws_camera* cams, const ws_camera* d_cams,
+                    int32_t n_views, const ws_options* opt, const uint64_t* keys, const uint32_t* values,
+                    int64_t capacity, const int64_t* d_num_pairs, const int32_t* d_status, uint32_t* tile_ranges,
+                    float* images, void* ws, size_t ws_bytes, void* stream) {
+    ws_status s;
+    if (n < 0 || n > kMaxGaussians) return fail(WS_ERR_INVALID_ARGUMENT, "n out of range");
+    if ((s = check_cameras(cams, d_cams, n_views)) != WS_OK) return s;
+    if ((s = check_options(opt)) != WS_OK) return s;
+    if (capacity < 0 || capacity > (int64_t(1) << 32) - 1) return fail(WS_ERR_INVALID_ARGUMENT, "capacity out of range");
+    if (capacity > 0 && (!keys || !values)) return fail(WS_ERR_INVALID_ARGUMENT, "keys / values is NULL");
+    if (n > 0 && !splats) return fail(WS_ERR_INVALID_ARGUMENT, "splats is NULL");
+    if (!d_num_pairs || !d_status || !tile_ranges || !images)
+        return fail(WS_ERR_INVALID_ARGUMENT, "d_num_pairs / d_status / tile_ranges / images is NULL");
+    const int64_t tiles = total_tiles_of(cams, n_views, opt->tile_w, opt->tile_h);
+    if (tiles > (int64_t(1) << 31)) return fail(WS_ERR_UNSUPPORTED, "more than 2^31 tiles");
+    const ws::KOpts ko = ws::to_kopts(*opt);
+    if ((s = check_ws(ws, ws_bytes, ws::render_workspace(tiles, ko))) != WS_OK) return s;
+    const hipError_t e = ws::launch_render(splats, n, d_cams, n_views, tiles, ko, keys, values, capacity, d_num_pairs,
+                                           d_status, tile_ranges, images, ws, static_cast<hipStream_t>(stream));
+    return hip_status(e, "ws_render launch");
+}
+
+ws_status ws_render_backward(const ws_gaussians* g, const ws_camera* cams, const ws_camera* d_cams,
+                             int32_t n_views, const ws_options* opt, const ws_splat* splats,
+                             const uint32_t* values, const uint32_t* tile_ranges, const float* dL_dimages,
+                             const int32_t* d_status, ws_gaussian_grads* grads, void* ws, size_t ws_bytes,
+                             void* stream) {
+    ws_status s;
+    if ((s = check_gaussians(g)) != WS_OK) return s;
+    if ((s = check_cameras(cams, d_cams, n_views)) != WS_OK) return s;
+    if ((s = check_options(opt)) != WS_OK) return s;
+    if (!grads || (g->n > 0 && (!grads->means || !grads->log_scales || !grads->quats || !grads->opacity_logits ||
+                                !grads->sh)))
+        return fail(WS_ERR_INVALID_ARGUMENT, "a gradient array is NULL");
+    if (!tile_ranges || !dL_dimages || !d_status) return fail(WS_ERR_INVALID_ARGUMENT, "tile_ranges / dL_dimages / d_status is NULL");
+    if (g->n > 0 && (!splats || !values)) return fail(WS_ERR_INVALID_ARGUMENT, "splats / values is NULL");
+    if (g->n * int64_t(n_views) > kMaxGaussians) return fail(WS_ERR_INVALID_ARGUMENT, "n * n_views must be < 2^31");
+    if ((s = check_ws(ws, ws_bytes, ws::render_backward_workspace(g->n, n_views))) != WS_OK) return s;
+    const int64_t tiles = total_tiles_of(cams, n_views, opt->tile_w, opt->tile_h);
+    ws::GradPtrs gp;
+    gp.means = grads->means;
+    gp.log_scales = grads->log_scales;
+    gp.quats = grads->quats;
+    gp.logits = grads->opacity_logits;
+    gp.sh = grads->sh;
+    const hipError_t e = ws::launch_render_backward(gauss_ptrs(g), d_cams, n_views, tiles, ws::to_kopts(*opt), splats,
+                                                    values, tile_ranges, dL_dimages, d_status, gp, ws,
+                                                    static_cast<hipStream_t>(stream));
+    return hip_status(e, "ws_render_backward launch");
+}
+
+ws_status ws_l1_loss(const float* images, const float* targets, int64_t n, float* dL_dimages, float* d_loss,
+                     void* ws, size_t ws_bytes, void* stream) {
+    if (n < 1) return fail(WS_ERR_INVALID_ARGUMENT, "n must be >= 1");
+    if (!images || !targets || !dL_dimages || !d_loss) return fail(WS_ERR_INVALID_ARGUMENT, "a pointer is NULL");
+    ws_status s;
+    if ((s = check_ws(ws, ws_bytes, ws::l1_loss_workspace(n))) != WS_OK) return s;
+    const hipError_t e = ws::launch_l1_loss(images, targets, n, dL_dimages, d_loss, ws, static_cast<hipStream_t>(stream));
+    return hip_status(e, "ws_l1_loss launch");
+}
+
+struct ws_graph_s {
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+};
+
+ws_status ws_graph_begin(void* stream) {
+    if (!stream) return fail(WS_ERR_INVALID_ARGUMENT, "graph capture needs a non-null stream");
+    return hip_status(hipStreamBeginCapture(static_cast<hipStream_t>(stream), hipStreamCaptureModeThreadLocal),
+                      "hipStreamBeginCapture");
+}
+
+ws_status ws_graph_end(void* stream, ws_graph* out) {
+    if (!stream || !out) return fail(WS_ERR_INVALID_ARGUMENT, "stream / out is NULL");
+    hipGraph_t g = nullptr;
+    ws_status s = hip_status(hipStreamEndCapture(static_cast<hipStream_t>(stream), &g), "hipStreamEndCapture");
+    if (s != WS_OK) return s;
+    hipGraphExec_t ex = nullptr;
+    s = hip_status(hipGraphInstantiate(&ex, g, nullptr, nullptr, 0), "hipGraphInstantiate");
+    if (s != WS_OK) {
+        (void)hipGraphDestroy(g);
+        return s;
+    }
+    *out = new ws_graph_s{g, ex};
+    return WS_OK;
+}
+
+ws_status ws_graph_launch(ws_graph graph, void* stream) {
+    if (!graph) return fail(WS_ERR_INVALID_ARGUMENT, "graph is NULL");
+    return hip_status(hipGraphLaunch(graph->exec, static_cast<hipStream_t>(stream)), "hipGraphLaunch");
+}
+
+ws_status ws_graph_destroy(ws_graph graph) {
+    if (!graph) return WS_OK;
+    (void)hipGraphExecDestroy(graph->exec);
+    (void)hipGraphDestroy(graph->graph);
+    delete graph;
+    return WS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,410 @@
+// Reverse mode of the render path.
+//
+// k_render_bwd<TW, TH>  per tile, no stored per-pixel state: pass 1 walks the
+//     tile's list front to back exactly as the forward does (same staged
+//     arithmetic, same decisions) to get each pixel's final transmittance and
+//     the list index of its last contributor; pass 2 walks back to front from
+//     there, recovering T_k = T_{k+1} / (1 - alpha_k) (alpha <= alpha_max < 1)
+//     and the suffix colour R_k = sum_{i>k} c_i alpha_i T_i + bg T_final, and
+//     forms for each contributor
+//        dL/dc_k     = alpha_k T_k dL/dC
+//        dL/dalpha_k = dL/dC . (c_k T_k - R_k / (1 - alpha_k))
+//     and, unless alpha was clamped, dL/dsigma = dL/dalpha exp(power) and
+//     dL/dpower = dL/dalpha * alpha with the derivatives of the power in the
+//     centre and the conic.  The nine per-splat sums of a staged batch are
+//     reduced across the wave (shuffles) and across the workgroup (LDS
+//     atomics), then added to device memory with one atomic per value.
+// k_bwd_clear           zeroes the per-(view, splat) gradient buffer.
+// k_preprocess_bwd      one thread per Gaussian, summing over the views: the
+//     chain through the conic inverse, the EWA covariance, the Jacobian
+//     (branch taken at the clamp), the rotation and scale, the mean
+//     projection, the SH colour (clamped channels give zero) and the sigmoid.
+#include "composite.h"
+#include "project.h"
+#include "ws_internal.h"
+
+namespace ws {
+namespace {
+
+constexpr int kNG = 9;  // u, v, A, B, C, sigma, r, g, b
+
+struct BwdWs {
+    float* sg;   // [kNG][V * n] per-(view, splat) gradients
+    int64_t vn;  // V * n
+};
+
+BwdWs carve_bwd(void* ws, int64_t n, int32_t n_views) {
+    BwdWs b;
+    b.vn = n * n_views;
+    b.sg = static_cast<float*>(ws);
+    return b;
+}
+
+__global__ void k_bwd_clear(float* p, int64_t count) {
+    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < count; i += stride) p[i] = 0.f;
+}
+
+struct BwdArgs {
+    const ws_splat* splats;
+    int64_t n;
+    const ws_camera* cams;
+    int32_t n_views;
+    const uint32_t* values;
+    const uint32_t* ranges;
+    const float* dL;
+    const int32_t* d_status;
+    BwdWs w;
+    KOpts o;
+};
+
+struct RawConic {
+    float A, B, C;
+};
+
+template <int TW, int TH>
+__global__ __launch_bounds__(TW * TH) void k_render_bwd(BwdArgs a) {
+    constexpr int NT = TW * TH;
+    __shared__ StagedSplat s_batch[NT];
+    __shared__ RawConic s_conic[NT];
+    __shared__ float s_acc[kNG][NT];
+    __shared__ int32_t s_maxlast;
+    if (*a.d_status != 0) return;
+    const int64_t g = blockIdx.x;
+    const TileInfo ti = locate_tile(a.cams, a.n_views, g, TW, TH);
+    const int px = ti.x0 + int(threadIdx.x % TW), py = ti.y0 + int(threadIdx.x / TW);
+    const bool inside = px < ti.W && py < ti.H;
+    const uint32_t start = a.ranges[2 * g], end = a.ranges[2 * g + 1];
+    const ws_splat* vsplats = a.splats + int64_t(ti.view) * a.n;
+    const int64_t vbase = int64_t(ti.view) * a.n;
+
+    // ---- pass 1: front to back, as in the forward
+    PixelState ps;
+    ps.init(px, py, !inside);
+    if (threadIdx.x == 0) s_maxlast = -1;
+    for (uint32_t b0 = start; b0 < end; b0 += NT) {
+        if (__syncthreads_count(ps.done) == NT) break;
+        const uint32_t idx = b0 + threadIdx.x;
+        if (idx < end) {
+            const uint32_t id = a.values[idx];
+            s_batch[threadIdx.x] = id < uint64_t(a.n) ? stage_splat(vsplats, id) : empty_splat();
+        }
+        __syncthreads();
+        const int cnt = int(min<uint32_t>(NT, end - b0));
+        if (!ps.done) {
+            for (int j = 0; j < cnt; ++j) {
+                if (ps.step(s_batch[j], a.o)) break;
+            }
+        }
+    }
+    __syncthreads();
+    if (ps.last >= 0) atomicMax(&s_maxlast, ps.last);
+    __syncthreads();
+    const int32_t maxlast = s_maxlast;
+    if (maxlast < 0) return;  // nothing composited in this tile
+
+    // ---- pass 2: back to front from the last contributor
+    float dLdC[3] = {0.f, 0.f, 0.f};
+    if (inside) {
+        const int64_t plane = int64_t(ti.W) * ti.H;
+        const int64_t p = ti.img_off + int64_t(py) * ti.W + px;
+        dLdC[0] = a.dL[p];
+        dLdC[1] = a.dL[p + plane];
+        dLdC[2] = a.dL[p + 2 * plane];
+    }
+    float T = ps.T;
+    float R[3] = {a.o.bg[0] * T, a.o.bg[1] * T, a.o.bg[2] * T};
+    const int32_t last = ps.last;
+    const float pcx = float(px) + 0.5f, pcy = float(py) + 0.5f;
+    for (int32_t bend = maxlast + 1; bend > 0; bend -= NT) {
+        const int32_t bstart = bend - NT > 0 ? bend - NT : 0;
+        __syncthreads();
+        {
+            const int32_t j = bstart + int32_t(threadIdx.x);
+            if (j < bend) {
+                const uint32_t id = a.values[start + uint32_t(j)];
+                StagedSplat s = id < uint64_t(a.n) ? stage_splat(vsplats, id) : empty_splat();
+                s_batch[threadIdx.x] = s;
+                const float* rec = reinterpret_cast<const float*>(vsplats + (id < uint64_t(a.n) ? id : 0));
+                s_conic[threadIdx.x] = RawConic{rec[2], rec[3], rec[4]};
+            }
+#pragma unroll
+            for (int k = 0; k < kNG; ++k) s_acc[k][threadIdx.x] = 0.f;
+        }
+        __syncthreads();
+        for (int32_t j = bend - 1; j >= bstart; --j) {
+            const StagedSplat& s = s_batch[j - bstart];
+            float gv[kNG];
+#pragma unroll
+            for (int k = 0; k < kNG; ++k) gv[k] = 0.f;
+            bool contrib = false;
+            if (j <= last && in_rect(s, px, py)) {
+                const float dx = s.u - pcx, dy = s.v - pcy;
+                float G;
+                const float araw = raw_alpha(s, dx, dy, &G);
+                const float alpha = fminf(a.o.alpha_max, araw);
+                if (alpha >= a.o.alpha_min) {
+                    contrib = true;
+                    const float one_m = 1.f - alpha;
+                    const float Tk = T / one_m;
+                    const float w = alpha * Tk;
+                    gv[6] = dLdC[0] * w;
+                    gv[7] = dLdC[1] * w;
+                    gv[8] = dLdC[2] * w;
+                    const float inv = 1.f / one_m;
+                    const float dLda = dLdC[0] * (s.r * Tk - R[0] * inv) + dLdC[1] * (s.g * Tk - R[1] * inv) +
+                                       dLdC[2] * (s.b * Tk - R[2] * inv);
+                    R[0] = fmaf(s.r, w, R[0]);
+                    R[1] = fmaf(s.g, w, R[1]);
+                    R[2] = fmaf(s.b, w, R[2]);
+                    T = Tk;
+                    if (!(araw > a.o.alpha_max)) {
+                        const RawConic& q = s_conic[j - bstart];
+                        const float gp = dLda * araw;  // dL/dpower
+                        gv[5] = dLda * G;
+                        gv[0] = -gp * (q.A * dx + q.B * dy);
+                        gv[1] = -gp * (q.C * dy + q.B * dx);
+                        gv[2] = -0.5f * gp * dx * dx;
+                        gv[3] = -gp * dx * dy;
+                        gv[4] = -0.5f * gp * dy * dy;
+                    }
+                }
+            }
+            if (__ballot(contrib) != 0) {
+#pragma unroll
+                for (int k = 0; k < kNG; ++k) {
+                    const float sum = wave_sum(gv[k]);
+                    if (lane_id() == 0 && sum != 0.f) atomicAdd(&s_acc[k][j - bstart], sum);
+                }
+            }
+        }
+        __syncthreads();
+        {
+            const int32_t j = bstart + int32_t(threadIdx.x);
+            if (j < bend) {
+                const uint32_t id = s_batch[threadIdx.x].id;
+                if (id < uint64_t(a.n)) {
+#pragma unroll
+                    for (int k = 0; k < kNG; ++k) {
+                        const float v = s_acc[k][threadIdx.x];
+                        if (v != 0.f) atomicAdd(&a.w.sg[int64_t(k) * a.w.vn + vbase + id], v);
+                    }
+                }
+            }
+        }
+    }
+}
+
+struct PreBwdArgs {
+    GaussPtrs g;
+    const ws_camera* cams;
+    int32_t n_views;
+    KOpts o;
+    BwdWs w;
+    GradPtrs out;
+};
+
+// Derivatives of the rotation matrix of a unit quaternion (w, x, y, z):
+// returns sum_ij G_ij dR_ij/dq_c for c = w, x, y, z.
+__device__ __forceinline__ void rotmat_vjp(const float* q, const float* G, float* gq) {
+    const float w = q[0], x = q[1], y = q[2], z = q[3];
+    // R = [[1-2(yy+zz), 2(xy-wz), 2(xz+wy)], [2(xy+wz), 1-2(xx+zz), 2(yz-wx)], [2(xz-wy), 2(yz+wx), 1-2(xx+yy)]]
+    gq[0] = 2.f * (-z * G[1] + y * G[2] + z * G[3] - x * G[5] - y * G[6] + x * G[7]);
+    gq[1] = 2.f * (y * G[1] + z * G[2] + y * G[3] - 2.f * x * G[4] - w * G[5] + z * G[6] + w * G[7] -
+                   2.f * x * G[8]);
+    gq[2] = 2.f * (-2.f * y * G[0] + x * G[1] + w * G[2] + x * G[3] + z * G[5] - w * G[6] + z * G[7] -
+                   2.f * y * G[8]);
+    gq[3] = 2.f * (-2.f * z * G[0] - w * G[1] + x * G[2] + w * G[3] - 2.f * z * G[4] + y * G[5] + x * G[6] +
+                   y * G[7]);
+}
+
+template <int DEG>
+__global__ __launch_bounds__(128) void k_preprocess_bwd(PreBwdArgs a) {
+    const int64_t i = int64_t(blockIdx.x) * 128 + threadIdx.x;
+    const int64_t n = a.g.n;
+    if (i >= n) return;
+    constexpr int K = (DEG + 1) * (DEG + 1);
+    float gm[3] = {0.f, 0.f, 0.f}, gls[3] = {0.f, 0.f, 0.f}, gq[4] = {0.f, 0.f, 0.f, 0.f}, glogit = 0.f;
+    float gsh[3 * K];
+#pragma unroll
+    for (int k = 0; k < 3 * K; ++k) gsh[k] = 0.f;
+    for (int32_t v = 0; v < a.n_views; ++v) {
+        const int64_t vi = int64_t(v) * n + i;
+        float gs[kNG];
+        bool any = false;
+#pragma unroll
+        for (int k = 0; k < kNG; ++k) {
+            gs[k] = a.w.sg[int64_t(k) * a.w.vn + vi];
+            any = any || gs[k] != 0.f;
+        }
+        if (!any) continue;
+        const ws_camera& cam = a.cams[v];
+        ProjState st;
+        if (!compute_projection<DEG>(a.g, i, cam, a.o, st, true)) continue;
+        // ---- colour
+        float Y[16];
+        sh_eval_basis(st.dir[0], st.dir[1], st.dir[2], DEG, Y);
+        float wsh[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) wsh[k] = 0.f;
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+            const float gc = (st.clamp & (1u << ch)) ? 0.f : gs[6 + ch];
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                gsh[k * 3 + ch] = fmaf(gc, Y[k], gsh[k * 3 + ch]);
+                wsh[k] = fmaf(gc, a.g.sh[(int64_t(k) * 3 + ch) * n + i], wsh[k]);
+            }
+        }
+        float gdx, gdy, gdz;
+        sh_basis_vjp(st.dir[0], st.dir[1], st.dir[2], DEG, wsh, &gdx, &gdy, &gdz);
+        {
+            const float dd = gdx * st.dir[0] + gdy * st.dir[1] + gdz * st.dir[2];
+            const float idn = 1.f / st.dir_norm;
+            gm[0] += (gdx - st.dir[0] * dd) * idn;
+            gm[1] += (gdy - st.dir[1] * dd) * idn;
+            gm[2] += (gdz - st.dir[2] * dd) * idn;
+        }
+        // ---- opacity
+        glogit += gs[5] * st.sigma * (1.f - st.sigma);
+        // ---- conic (A, B, C) = (c, -b, a) / det  ->  Sigma' entries (a, b, c)
+        const float ca = st.a, cb = st.b, cc = st.c;
+        const float idet = 1.f / st.det;
+        const float idet2 = idet * idet;
+        const float gA = gs[2], gB = gs[3], gC = gs[4];
+        const float ga = (-gA * cc * cc + gB * cb * cc - gC * cb * cb) * idet2;
+        const float gb = (2.f * gA * cb * cc - gB * (ca * cc + cb * cb) + 2.f * gC * ca * cb) * idet2;
+        const float gc2 = (-gA * cb * cb + gB * ca * cb - gC * ca * ca) * idet2;
+        // ---- Sigma' = M M^T + lowpass I
+        const float* M = st.M;
+        float gM[6];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            gM[j] = 2.f * ga * M[j] + gb * M[3 + j];
+            gM[3 + j] = gb * M[j] + 2.f * gc2 * M[3 + j];
+        }
+        // ---- M = J (T S), T = W Rq
+        const float iz = st.invz;
+        const float j00 = cam.fx * iz, j02 = -cam.fx * st.rxc * iz;
+        const float j11 = cam.fy * iz, j12 = -cam.fy * st.ryc * iz;
+        float gT[9];
+        float gj00 = 0.f, gj02 = 0.f, gj11 = 0.f, gj12 = 0.f;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) {
+            const float sj = st.s[j];
+            const float m0 = j00 * st.T[j] + j02 * st.T[6 + j];
+            const float m1 = j11 * st.T[3 + j] + j12 * st.T[6 + j];
+            gls[j] += (gM[j] * m0 + gM[3 + j] * m1) * sj;  // d/dlog s = s d/ds
+            gT[j] = gM[j] * j00 * sj;
+            gT[3 + j] = gM[3 + j] * j11 * sj;
+            gT[6 + j] = (gM[j] * j02 + gM[3 + j] * j12) * sj;
+            gj00 += gM[j] * st.T[j] * sj;
+            gj02 += gM[j] * st.T[6 + j] * sj;
+            gj11 += gM[3 + j] * st.T[3 + j] * sj;
+            gj12 += gM[3 + j] * st.T[6 + j] * sj;
+        }
+        // ---- T = W Rq  ->  dL/dRq = W^T dL/dT
+        float gR[9];
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+                gR[r * 3 + c] = cam.R[0 * 3 + r] * gT[0 * 3 + c] + cam.R[1 * 3 + r] * gT[1 * 3 + c] +
+                                cam.R[2 * 3 + r] * gT[2 * 3 + c];
+        float gqh[4];
+        rotmat_vjp(st.q, gR, gqh);
+        {
+            const float dq = gqh[0] * st.q[0] + gqh[1] * st.q[1] + gqh[2] * st.q[2] + gqh[3] * st.q[3];
+            const float iq = 1.f / st.qnorm;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) gq[c] += (gqh[c] - st.q[c] * dq) * iq;
+        }
+        // ---- Jacobian and mean projection -> camera-space centre p
+        const float iz2 = iz * iz;
+        const float rx = float(st.px / st.pz), ry = float(st.py / st.pz);
+        float gpx = gs[0] * cam.fx * iz, gpy = gs[1] * cam.fy * iz;
+        float gpz = -gs[0] * cam.fx * rx * iz - gs[1] * cam.fy * ry * iz;
+        gpz += -gj00 * cam.fx * iz2 - gj11 * cam.fy * iz2;
+        if (st.clamp & kClampJx) {
+            gpz += gj02 * cam.fx * st.rxc * iz2;  // j02 = -fx rxc / z with rxc fixed
+        } else {
+            gpx += -gj02 * cam.fx * iz2;  // j02 = -fx x / z^2
+            gpz += 2.f * gj02 * cam.fx * st.rxc * iz2;
+        }
+        if (st.clamp & kClampJy) {
+            gpz += gj12 * cam.fy * st.ryc * iz2;
+        } else {
+            gpy += -gj12 * cam.fy * iz2;
+            gpz += 2.f * gj12 * cam.fy * st.ryc * iz2;
+        }
+        // ---- p = W X + t
+#pragma unroll
+        for (int c = 0; c < 3; ++c) gm[c] += cam.R[0 * 3 + c] * gpx + cam.R[1 * 3 + c] * gpy + cam.R[2 * 3 + c] * gpz;
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        a.out.means[c * n + i] = gm[c];
+        a.out.log_scales[c * n + i] = gls[c];
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) a.out.quats[c * n + i] = gq[c];
+    a.out.logits[i] = glogit;
+#pragma unroll
+    for (int k = 0; k < 3 * K; ++k) a.out.sh[int64_t(k) * n + i] = gsh[k];
+}
+
+template <int TW, int TH>
+void launch_bwd_t(const BwdArgs& ba, int64_t tiles, hipStream_t stream) {
+    hipLaunchKernelGGL((k_render_bwd<TW, TH>), dim3(uint32_t(tiles)), dim3(TW * TH), 0, stream, ba);
+}
+
+}  // namespace
+
+size_t render_backward_workspace(int64_t n, int32_t n_views) {
+    return align_up(size_t(kNG) * size_t(std::max<int64_t>(n, 1)) * n_views * sizeof(float));
+}
+
+hipError_t launch_render_backward(const GaussPtrs& g, const ws_camera* d_cams, int32_t n_views,
+                                  int64_t total_tiles, const KOpts& o, const ws_splat* splats,
+                                  const uint32_t* values, const uint32_t* tile_ranges, const float* dL_dimages,
+                                  const int32_t* d_status, const GradPtrs& grads, void* ws, hipStream_t stream) {
+    BwdWs w = carve_bwd(ws, g.n, n_views);
+    const int64_t count = int64_t(kNG) * w.vn;
+    const uint32_t cgrid = uint32_t(std::min<int64_t>(std::max<int64_t>((count + 255) / 256, 1), 8192));
+    hipLaunchKernelGGL(k_bwd_clear, dim3(cgrid), dim3(256), 0, stream, w.sg, count);
+    if (g.n == 0) return hipGetLastError();
+    if (total_tiles > 0) {
+        BwdArgs ba;
+        ba.splats = splats;
+        ba.n = g.n;
+        ba.cams = d_cams;
+        ba.n_views = n_views;
+        ba.values = values;
+        ba.ranges = tile_ranges;
+        ba.dL = dL_dimages;
+        ba.d_status = d_status;
+        ba.w = w;
+        ba.o = o;
+        if (o.tile_w == 16 && o.tile_h == 16) launch_bwd_t<16, 16>(ba, total_tiles, stream);
+        else if (o.tile_w == 8 && o.tile_h == 8) launch_bwd_t<8, 8>(ba, total_tiles, stream);
+        else if (o.tile_w == 16 && o.tile_h == 8) launch_bwd_t<16, 8>(ba, total_tiles, stream);
+        else launch_bwd_t<32, 16>(ba, total_tiles, stream);
+    }
+    PreBwdArgs pa;
+    pa.g = g;
+    pa.cams = d_cams;
+    pa.n_views = n_views;
+    pa.o = o;
+    pa.w = w;
+    pa.out = grads;
+    const dim3 grid(uint32_t((g.n + 127) / 128));
+    switch (o.sh_degree) {
+        case 0: hipLaunchKernelGGL(k_preprocess_bwd<0>, grid, dim3(128), 0, stream, pa); break;
+        case 1: hipLaunchKernelGGL(k_preprocess_bwd<1>, grid, dim3(128), 0, stream, pa); break;
+        case 2: hipLaunchKernelGGL(k_preprocess_bwd<2>, grid, dim3(128), 0, stream, pa); break;
+        default: hipLaunchKernelGGL(k_preprocess_bwd<3>, grid, dim3(128), 0, stream, pa); break;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace ws

@@ -1,0 +1,64 @@
+// L1 photometric loss and its gradient, reduced in a fixed order so that the
+// loss value is identical on every run.
+#include "ws_internal.h"
+
+namespace ws {
+namespace {
+
+constexpr int kLossThreads = 256;
+constexpr int kLossBlocks = 1024;
+
+__global__ __launch_bounds__(kLossThreads) void k_l1_partial(const float* __restrict__ img,
+                                                             const float* __restrict__ tgt, int64_t n,
+                                                             float* __restrict__ dL, double* __restrict__ partial) {
+    __shared__ double s_part[kLossThreads / kWave];
+    const float inv_n = float(1.0 / double(n));
+    double acc = 0.0;
+    const int64_t stride = int64_t(gridDim.x) * kLossThreads;
+    for (int64_t i = int64_t(blockIdx.x) * kLossThreads + threadIdx.x; i < n; i += stride) {
+        const float d = img[i] - tgt[i];
+        dL[i] = d > 0.f ? inv_n : (d < 0.f ? -inv_n : 0.f);
+        acc += double(fabsf(d));
+    }
+    acc = wave_sum(acc);
+    if (lane_id() == 0) s_part[threadIdx.x / kWave] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int w = 0; w < kLossThreads / kWave; ++w) s += s_part[w];
+        partial[blockIdx.x] = s;
+    }
+}
+
+__global__ __launch_bounds__(kLossThreads) void k_l1_final(const double* __restrict__ partial, int nb, int64_t n,
+                                                           float* __restrict__ loss) {
+    __shared__ double s_part[kLossThreads / kWave];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < nb; i += kLossThreads) acc += partial[i];
+    acc = wave_sum(acc);
+    if (lane_id() == 0) s_part[threadIdx.x / kWave] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int w = 0; w < kLossThreads / kWave; ++w) s += s_part[w];
+        *loss = float(s / double(n));
+    }
+}
+
+}  // namespace
+
+size_t l1_loss_workspace(int64_t n) {
+    (void)n;
+    return align_up(kLossBlocks * sizeof(double));
+}
+
+hipError_t launch_l1_loss(const float* images, const float* targets, int64_t n, float* dL, float* d_loss, void* ws,
+                          hipStream_t stream) {
+    double* partial = static_cast<double*>(ws);
+    hipLaunchKernelGGL(k_l1_partial, dim3(kLossBlocks), dim3(kLossThreads), 0, stream, images, targets, n, dL,
+                       partial);
+    hipLaunchKernelGGL(k_l1_final, dim3(1), dim3(kLossThreads), 0, stream, partial, kLossBlocks, n, d_loss);
+    return hipGetLastError();
+}
+
+}  // namespace ws

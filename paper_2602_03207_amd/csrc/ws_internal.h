@@ -1,0 +1,176 @@
+// Internal declarations of the websplat HIP library (gfx950, wave64).
+// Device helpers shared by the kernels and the host-side launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/websplat.h"
+
+namespace ws {
+
+constexpr int kWave = 64;
+
+// ------------------------------------------------------------ wave helpers
+
+// Number of set bits of `mask` below the calling lane.
+__device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
+    return __builtin_amdgcn_mbcnt_hi(uint32_t(mask >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(mask), 0u));
+}
+
+__device__ __forceinline__ uint32_t lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)); }
+
+// Inclusive prefix sum across the 64 lanes of a wave.
+template <class T>
+__device__ __forceinline__ T wave_inclusive_scan(T v) {
+    const uint32_t lane = lane_id();
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        T o = __shfl_up(v, d, kWave);
+        if (lane >= uint32_t(d)) v += o;
+    }
+    return v;
+}
+
+template <class T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int d = kWave / 2; d >= 1; d >>= 1) v += __shfl_xor(v, d, kWave);
+    return v;
+}
+
+// Exclusive prefix sum over a workgroup of NT threads (NT a multiple of 64).
+// `scratch` holds NT/64 + 1 values; returns the exclusive prefix and the total.
+template <int NT, class T>
+__device__ __forceinline__ T block_exclusive_scan(T v, T* scratch, T* total) {
+    constexpr int NW = NT / kWave;
+    const int wave = threadIdx.x / kWave;
+    const uint32_t lane = lane_id();
+    T inc = wave_inclusive_scan(v);
+    if (lane == kWave - 1) scratch[wave] = inc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        T run = 0;
+        for (int w = 0; w < NW; ++w) {
+            T c = scratch[w];
+            scratch[w] = run;
+            run += c;
+        }
+        scratch[NW] = run;
+    }
+    __syncthreads();
+    T res = scratch[wave] + inc - v;
+    *total = scratch[NW];
+    __syncthreads();
+    return res;
+}
+
+// ------------------------------------------------ device-scope atomics
+
+__device__ __forceinline__ uint64_t load_agent(const uint64_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void store_agent(uint64_t* p, uint64_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t load_agent(const uint32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void store_agent(uint32_t* p, uint32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Bounded waits: a look-back that has not seen its predecessor after this
+// many polls gives up and reports WS_ERR_SPIN_LIMIT instead of hanging.
+constexpr uint32_t kSpinLimit = 1u << 22;
+
+// ------------------------------------------------------- shared data
+
+struct GaussPtrs {
+    const float* means;
+    const float* log_scales;
+    const float* quats;
+    const float* logits;
+    const float* sh;
+    int64_t n;
+};
+
+struct GradPtrs {
+    float* means;
+    float* log_scales;
+    float* quats;
+    float* logits;
+    float* sh;
+};
+
+// Options as the kernels see them.
+struct KOpts {
+    int32_t tile_w, tile_h, sh_degree;
+    uint32_t flags;
+    float near_z, lowpass, clamp_fov, alpha_min, alpha_max, t_min;
+    float bg[3];
+};
+
+inline KOpts to_kopts(const ws_options& o) {
+    KOpts k;
+    k.tile_w = o.tile_w; k.tile_h = o.tile_h; k.sh_degree = o.sh_degree; k.flags = o.flags;
+    k.near_z = o.near_z; k.lowpass = o.lowpass; k.clamp_fov = o.clamp_fov;
+    k.alpha_min = o.alpha_min; k.alpha_max = o.alpha_max; k.t_min = o.t_min;
+    k.bg[0] = o.bg[0]; k.bg[1] = o.bg[1]; k.bg[2] = o.bg[2];
+    return k;
+}
+
+__host__ __device__ inline int32_t ceil_div(int32_t a, int32_t b) { return (a + b - 1) / b; }
+
+// Tile id offset and image float offset of view v, from the device cameras
+// (n_views is small; a linear pass is cheaper than a table).
+__device__ __forceinline__ void view_offsets(const ws_camera* cams, int32_t v, int32_t tw, int32_t th,
+                                             int64_t* tile_off, int64_t* img_off) {
+    int64_t t = 0, f = 0;
+    for (int32_t u = 0; u < v; ++u) {
+        const int32_t W = cams[u].width, H = cams[u].height;
+        t += int64_t(ceil_div(W, tw)) * ceil_div(H, th);
+        f += 3ll * W * H;
+    }
+    *tile_off = t;
+    *img_off = f;
+}
+
+// ---------------------------------------------------- launchers (host)
+
+// preprocess.hip
+hipError_t launch_preprocess(const GaussPtrs& g, const ws_camera* d_cams, int32_t n_views, const KOpts& o,
+                             ws_splat* splats, uint32_t* tiles_touched, uint64_t* keys, uint32_t* values,
+                             int64_t capacity, int64_t* d_num_pairs, int32_t* d_status, void* ws,
+                             hipStream_t stream);
+size_t preprocess_workspace(int64_t n, int32_t n_views);
+
+// sort.hip
+hipError_t launch_sort(const uint64_t* kin, const uint32_t* vin, uint64_t* kout, uint32_t* vout, int64_t n,
+                       const int64_t* d_n, const int32_t* d_status, int32_t begin_bit, int32_t end_bit,
+                       int32_t radix_bits, void* ws, hipStream_t stream);
+size_t sort_workspace(int64_t capacity, int32_t begin_bit, int32_t end_bit, int32_t radix_bits);
+
+// render.hip
+hipError_t launch_render(const ws_splat* splats, int64_t n, const ws_camera* d_cams, int32_t n_views,
+                         int64_t total_tiles, const KOpts& o, const uint64_t* keys, const uint32_t* values,
+                         int64_t capacity, const int64_t* d_num_pairs, const int32_t* d_status,
+                         uint32_t* tile_ranges, float* images, void* ws, hipStream_t stream);
+size_t render_workspace(int64_t total_tiles, const KOpts& o);
+
+// backward.hip
+hipError_t launch_render_backward(const GaussPtrs& g, const ws_camera* d_cams, int32_t n_views,
+                                  int64_t total_tiles, const KOpts& o, const ws_splat* splats,
+                                  const uint32_t* values, const uint32_t* tile_ranges, const float* dL_dimages,
+                                  const int32_t* d_status, const GradPtrs& grads, void* ws, hipStream_t stream);
+size_t render_backward_workspace(int64_t n, int32_t n_views);
+
+// loss.hip
+hipError_t launch_l1_loss(const float* images, const float* targets, int64_t n, float* dL, float* d_loss, void* ws,
+                          hipStream_t stream);
+size_t l1_loss_workspace(int64_t n);
+
+// Round a byte count up to the workspace alignment.
+inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
+
+}  // namespace ws

@@ -1,0 +1,62 @@
+"""Shared helpers of the GPU parity tests (oracle side and GPU side kept apart)."""
+import numpy as np
+
+import oracle
+
+F32 = lambda x: float(np.float32(x))  # noqa: E731
+
+
+def oracle_options(tile_w=16, tile_h=16, sh_degree=0, flags=0, bg=(0.0, 0.0, 0.0)):
+    """Oracle options holding exactly the fp32 values the GPU library receives."""
+    return oracle.Options(tile_w=tile_w, tile_h=tile_h, sh_degree=sh_degree, flags=flags, near_z=F32(0.2),
+                          lowpass=F32(0.3), clamp_fov=F32(1.3), alpha_min=F32(1 / 255), alpha_max=F32(0.99),
+                          t_min=F32(1e-4), bg=tuple(F32(b) for b in bg))
+
+
+def gpu_options(tile_w=16, tile_h=16, sh_degree=0, flags=0, radix_bits=0, bg=(0.0, 0.0, 0.0)):
+    from paper_2602_03207_amd import binding as B
+    return B.make_options(tile_w=tile_w, tile_h=tile_h, sh_degree=sh_degree, flags=flags, radix_bits=radix_bits,
+                          bg=bg)
+
+
+def unpack_splats(splats_f32: np.ndarray):
+    """Fields of a [k, 12] float32 view of ws_splat records."""
+    s = np.ascontiguousarray(splats_f32, np.float32)
+    rect = s[:, 10:12].view(np.uint32)
+    return dict(mean2d=s[:, 0:2].T, conic=s[:, 2:5].T, opacity=s[:, 5], rgb=s[:, 6:9].T, depth=s[:, 9],
+                rect=np.stack([rect[:, 0] & 0xFFFF, rect[:, 0] >> 16, rect[:, 1] & 0xFFFF, rect[:, 1] >> 16]))
+
+
+def pack_splats(mean2d, conic, opacity, rgb, depth, pix_rect):
+    """[n, 12] float32 ws_splat records from per-component arrays (rect as inclusive x0, x1, y0, y1)."""
+    n = np.asarray(opacity).shape[0]
+    out = np.zeros((n, 12), np.float32)
+    out[:, 0:2] = np.asarray(mean2d, np.float32).T
+    out[:, 2:5] = np.asarray(conic, np.float32).T
+    out[:, 5] = np.asarray(opacity, np.float32)
+    out[:, 6:9] = np.asarray(rgb, np.float32).T
+    out[:, 9] = np.asarray(depth, np.float32)
+    r = np.asarray(pix_rect).astype(np.int64)
+    r = np.clip(r, 0, 65535).astype(np.uint32)
+    w = np.zeros((n, 2), np.uint32)
+    w[:, 0] = r[0] | (r[1] << 16)
+    w[:, 1] = r[2] | (r[3] << 16)
+    out[:, 10:12] = w.view(np.float32)
+    return out
+
+
+def pixel_flags(ref, margin_alpha=2e-5, margin_t=2e-5):
+    """Pixels whose result depends on a decision within fp32 reach of its threshold."""
+    return (ref["alpha_margin"] < margin_alpha) | (ref["t_margin"] < margin_t)
+
+
+def assert_image_parity(gpu, ref, tol=2e-4, max_flag_frac=2e-3, **margins):
+    """Max abs difference per channel <= tol on every unflagged pixel."""
+    flags = pixel_flags(ref, **margins)
+    ok = ~flags
+    err = np.abs(np.asarray(gpu, np.float64) - ref["rgb"])
+    worst = float(err[:, ok].max()) if ok.any() else 0.0
+    frac = float(flags.mean())
+    assert frac <= max_flag_frac, f"{frac:.2e} of pixels flagged"
+    assert worst <= tol, f"max |gpu - oracle| = {worst:.3e} on unflagged pixels (flagged {frac:.2e})"
+    return worst, frac

@@ -1,0 +1,131 @@
+"""ws_render on the GPU: per-component and end-to-end image parity with the oracle, and invariances."""
+import numpy as np
+import pytest
+
+import oracle
+import scenegen
+from _helpers import (assert_image_parity, gpu_options, oracle_options, pack_splats, pixel_flags)
+
+pytestmark = pytest.mark.gpu
+
+
+def _full(scene, cams, **kw):
+    import torch
+    from paper_2602_03207_amd.pipeline import GaussianTensors, Renderer
+    r = Renderer(cams, gpu_options(sh_degree=scene.sh_degree, **kw))
+    r.forward(GaussianTensors.from_scene(scene))
+    torch.cuda.synchronize()
+    return r
+
+
+def test_render_component_parity_c1():
+    """Render fed the oracle's fp32-rounded splats and sorted pairs vs the oracle compositing them."""
+    import torch
+    from paper_2602_03207_amd import binding as B
+    scene, cam = scenegen.c1()
+    ro = oracle_options()
+    ref = oracle.render(scene, cam, ro)
+    p = ref["proj"]
+    vis = p["status"] == 0
+    f32 = lambda a: np.asarray(a, np.float32)  # noqa: E731
+    rec = pack_splats(f32(p["mean2d"]), f32(p["conic"]), f32(p["opacity"]), f32(p["rgb"]), p["depth32"],
+                      np.where(vis, p["pix_rect"], 0))
+    comp = oracle.composite(f32(p["mean2d"]), f32(p["conic"]), f32(p["opacity"]), f32(p["rgb"]), p["pix_rect"], cam,
+                            ro, ref["sorted_vals"], ref["ranges"])
+    m = ref["sorted_keys"].size
+    opts = gpu_options()
+    cams = B.camera_array([cam])
+    d_cams = torch.as_tensor(B.camera_bytes(cams)).cuda()
+    splats = torch.as_tensor(rec).cuda()
+    keys = torch.as_tensor(ref["sorted_keys"].view(np.int64)).cuda()
+    vals = torch.as_tensor(ref["sorted_vals"].view(np.int32)).cuda()
+    d_n = torch.tensor([m], dtype=torch.int64, device="cuda")
+    d_status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    tiles = B.ws_total_tiles(cams, 1, opts)
+    ranges = torch.empty(2 * tiles, dtype=torch.int32, device="cuda")
+    images = torch.empty(3 * cam.width * cam.height, dtype=torch.float32, device="cuda")
+    ws = torch.empty(max(B.ws_render_workspace_size(cams, 1, opts), 256), dtype=torch.uint8, device="cuda")
+    B.ws_render(splats, scene.n, cams, d_cams, 1, opts, keys, vals, m, d_n, d_status, ranges, images, ws, ws.numel())
+    torch.cuda.synchronize()
+    rg = ranges.cpu().numpy().view(np.uint32).reshape(-1, 2).astype(np.int64)
+    assert np.array_equal(rg, ref["ranges"])
+    img = images.cpu().numpy().reshape(3, cam.height, cam.width)
+    worst, frac = assert_image_parity(img, comp)
+    assert worst < 2e-5
+
+
+@pytest.mark.parametrize("tile", [(16, 16), (8, 8), (16, 8), (32, 16)])
+def test_render_end_to_end_c1(tile):
+    scene, cam = scenegen.c1()
+    r = _full(scene, [cam], tile_w=tile[0], tile_h=tile[1])
+    ref = oracle.render(scene, cam, oracle_options(*tile))
+    assert r.num_pairs == ref["keys"].size
+    assert_image_parity(r.image(0).cpu().numpy(), ref)
+
+
+def test_render_end_to_end_tiny_near_plane_sh2():
+    scene = scenegen.random_scene(3000, 21, mean_lo=-1.5, mean_hi=1.5, log_scale_mu=-2.8, log_scale_sd=0.6,
+                                  logit_sd=2.5, sh_degree=2, dc_sd=0.5, rest_sd=0.2)
+    cam = scenegen.look_at([0.2, 0.1, -0.6], [0, 0, 1], 161, 97)  # ragged tiles in both directions
+    r = _full(scene, [cam])
+    ref = oracle.render(scene, cam, oracle_options(sh_degree=2))
+    assert_image_parity(r.image(0).cpu().numpy(), ref)
+
+
+def test_render_background_and_empty_scene():
+    scene = scenegen.random_scene(0, 1)
+    cam = scenegen.look_at([0, 0, -3], [0, 0, 0], 40, 24)
+    r = _full(scene, [cam], bg=(0.25, 0.5, 1.0))
+    img = r.image(0).cpu().numpy()
+    assert r.num_pairs == 0
+    for ch, b in enumerate((0.25, 0.5, 1.0)):
+        assert np.all(img[ch] == np.float32(b))
+    # every Gaussian culled (behind the camera)
+    scene = scenegen.random_scene(500, 2)
+    scene.means[2] = np.float32(-10.0)
+    r = _full(scene, [cam])
+    assert r.num_pairs == 0 and np.all(r.image(0).cpu().numpy() == 0)
+
+
+@pytest.mark.slow
+def test_render_end_to_end_c2():
+    scene, cam = scenegen.c2()
+    r = _full(scene, [cam])
+    ref = oracle.render(scene, cam, oracle_options(sh_degree=3))
+    worst, frac = assert_image_parity(r.image(0).cpu().numpy(), ref)
+    print(f"C2: worst {worst:.2e}, flagged {frac:.2e}, M gpu {r.num_pairs} oracle {ref['keys'].size}")
+
+
+def test_invariance_tile_size_and_radix_width():
+    scene, cam = scenegen.c1()
+    base = _full(scene, [cam]).image(0).cpu().numpy()
+    for tile in ((8, 8), (16, 8), (32, 16)):
+        for rb in (4, 8):
+            img = _full(scene, [cam], tile_w=tile[0], tile_h=tile[1], radix_bits=rb).image(0).cpu().numpy()
+            assert np.array_equal(img.view(np.uint32), base.view(np.uint32)), (tile, rb)
+
+
+def test_invariance_repeat_and_permutation():
+    scene, cam = scenegen.c1()
+    a = _full(scene, [cam]).image(0).cpu().numpy()
+    b = _full(scene, [cam]).image(0).cpu().numpy()
+    assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+    # keep the Gaussians whose fp32 depth is unique, so that the order cannot depend on ids
+    ref = oracle.preprocess(scene, cam, oracle_options())
+    _, first, counts = np.unique(ref["depth32"], return_index=True, return_counts=True)
+    keep = np.sort(first[counts == 1])
+    base = scene.subset(keep)
+    a = _full(base, [cam]).image(0).cpu().numpy()
+    perm = np.random.default_rng(0).permutation(base.n)
+    c = _full(base.subset(perm), [cam]).image(0).cpu().numpy()
+    assert np.array_equal(a.view(np.uint32), c.view(np.uint32))
+
+
+def test_batched_views_equal_single_views():
+    scene, _ = scenegen.c1()
+    cams = [scenegen.look_at([0, 0, -3], [0, 0, 0], 128, 96), scenegen.look_at([1.5, -0.5, -2.5], [0, 0, 0], 70, 130),
+            scenegen.look_at([-2.5, 0.3, -1.5], [0, 0, 0], 256, 64)]
+    rb = _full(scene, cams)
+    for v, cam in enumerate(cams):
+        single = _full(scene, [cam]).image(0).cpu().numpy()
+        assert np.array_equal(rb.image(v).cpu().numpy().view(np.uint32), single.view(np.uint32)), v

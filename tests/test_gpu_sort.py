@@ -1,0 +1,103 @@
+"""ws_sort on the GPU: bit-exact against the oracle's std::stable_sort, identical run to run."""
+import numpy as np
+import pytest
+
+import oracle
+import scenegen
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu_sort(keys, vals, begin_bit, end_bit, radix_bits=0, capacity=None, device_count=False):
+    import torch
+    from paper_2602_03207_amd import binding as B
+    n = keys.size
+    cap = capacity if capacity is not None else n
+    kin = torch.zeros(max(cap, 1), dtype=torch.int64, device="cuda")
+    vin = torch.zeros(max(cap, 1), dtype=torch.int32, device="cuda")
+    kin[:n] = torch.from_numpy(keys.view(np.int64))
+    vin[:n] = torch.from_numpy(vals.view(np.int32))
+    kout = torch.full((max(cap, 1),), -1, dtype=torch.int64, device="cuda")
+    vout = torch.full((max(cap, 1),), -1, dtype=torch.int32, device="cuda")
+    d_n = torch.tensor([n], dtype=torch.int64, device="cuda")
+    d_status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    need = B.ws_sort_workspace_size(max(cap, 1), begin_bit, end_bit, radix_bits)
+    ws = torch.empty(need + 256, dtype=torch.uint8, device="cuda")
+    B.ws_sort(kin, vin, kout, vout, cap if device_count else n, d_n if device_count else None, d_status, begin_bit,
+              end_bit, radix_bits, ws, ws.numel())
+    torch.cuda.synchronize()
+    assert int(d_status.item()) == 0
+    return kout[:n].cpu().numpy().view(np.uint64), vout[:n].cpu().numpy().view(np.uint32)
+
+
+def _cases():
+    rng = np.random.default_rng(5)
+    yield "n1", rng.integers(0, 2**63, 1, dtype=np.uint64)
+    for n in (63, 64, 65, 4095, 4096, 4097, 100_003):
+        yield f"rand{n}", rng.integers(0, 2**63, n, dtype=np.uint64) * np.uint64(2) + rng.integers(0, 2, n, dtype=np.uint64)
+    yield "equal", np.full(20_000, 7, np.uint64)
+    yield "sorted", np.arange(30_000, dtype=np.uint64) * np.uint64(977)
+    yield "reversed", (np.arange(30_000, dtype=np.uint64) * np.uint64(977))[::-1].copy()
+    yield "high32", rng.integers(0, 300, 50_000, dtype=np.uint64) << np.uint64(32)
+    yield "bit0", rng.integers(0, 2, 50_000, dtype=np.uint64)
+    yield "tiledepth", (rng.integers(0, 8160, 70_000, dtype=np.uint64) << np.uint64(32)) | \
+        rng.integers(0x3F000000, 0x41000000, 70_000, dtype=np.uint64)
+
+
+@pytest.mark.parametrize("bits", [(0, 64), (0, 45), (3, 17), (32, 64), (63, 64)])
+def test_sort_adversarial_bit_exact(bits):
+    b0, b1 = bits
+    for name, keys in _cases():
+        vals = np.arange(keys.size, dtype=np.uint32)
+        want_k, want_v = oracle.stable_sort(keys, vals, b0, b1)
+        got_k, got_v = _gpu_sort(keys, vals, b0, b1)
+        assert np.array_equal(got_v, want_v), (name, bits)
+        assert np.array_equal(got_k, want_k), (name, bits)
+
+
+@pytest.mark.parametrize("radix_bits", [1, 3, 4, 5, 6, 7, 8])
+def test_sort_every_radix_width(radix_bits):
+    rng = np.random.default_rng(radix_bits)
+    keys = (rng.integers(0, 5000, 60_001, dtype=np.uint64) << np.uint64(32)) | rng.integers(0, 2**31, 60_001, dtype=np.uint64)
+    vals = rng.integers(0, 2**32, keys.size, dtype=np.uint64).astype(np.uint32)
+    want_k, want_v = oracle.stable_sort(keys, vals, 0, 45)
+    got_k, got_v = _gpu_sort(keys, vals, 0, 45, radix_bits)
+    assert np.array_equal(got_k, want_k) and np.array_equal(got_v, want_v)
+
+
+def test_sort_device_count_and_repeatability():
+    rng = np.random.default_rng(9)
+    keys = rng.integers(0, 2**40, 123_457, dtype=np.uint64)
+    vals = np.arange(keys.size, dtype=np.uint32)
+    want_k, want_v = oracle.stable_sort(keys, vals, 0, 40)
+    outs = [_gpu_sort(keys, vals, 0, 40, capacity=300_000, device_count=True) for _ in range(3)]
+    for got_k, got_v in outs:
+        assert np.array_equal(got_k, want_k) and np.array_equal(got_v, want_v)
+
+
+def test_sort_respects_status_word():
+    import torch
+    from paper_2602_03207_amd import binding as B
+    n = 5000
+    kin = torch.arange(n, 0, -1, dtype=torch.int64, device="cuda")
+    vin = torch.arange(n, dtype=torch.int32, device="cuda")
+    kout = torch.full((n,), -1, dtype=torch.int64, device="cuda")
+    vout = torch.full((n,), -1, dtype=torch.int32, device="cuda")
+    d_status = torch.tensor([B.WS_ERR_CAPACITY], dtype=torch.int32, device="cuda")
+    need = B.ws_sort_workspace_size(n, 0, 32, 0)
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    B.ws_sort(kin, vin, kout, vout, n, None, d_status, 0, 32, 0, ws, ws.numel())
+    torch.cuda.synchronize()
+    assert bool((kout == -1).all()) and bool((vout == -1).all())
+
+
+def test_sort_oracle_key_buffer_1m_scene():
+    """The oracle's own (tile | depth) pair buffer of the 1M-Gaussian 1080p view."""
+    scene, cam = scenegen.c2()
+    keys, vals = oracle.emit(scene, cam, oracle.Options(sh_degree=3))
+    assert keys.size > 1_000_000
+    end_bit = 32 + int(np.ceil(np.log2(120 * 68)))
+    want_k, want_v = oracle.stable_sort(keys, vals, 0, end_bit)
+    for rb in (8, 6):
+        got_k, got_v = _gpu_sort(keys, vals, 0, end_bit, rb)
+        assert np.array_equal(got_k, want_k) and np.array_equal(got_v, want_v), rb
