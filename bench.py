@@ -1,0 +1,316 @@
+"""Benchmark of the MI355X 3D Gaussian Splatting render path.
+
+Default workload: 1,000,000 Gaussians (points on 20 random spheres and planes,
+bimodal opacity, SH degree 3), one 1920x1080 view from inside the scene.  One
+step = one frame of the plain path: preprocess, pair-count read-back, radix
+sort of the (tile | depth) pairs, tile ranges and compositing.
+
+Printed (one JSON line): frames/s (`value`), sorted keys/s of the frame's pair
+buffer, per-kernel launch times measured with HIP events, the roofline of the
+dominant kernel, batched (one graph replay for 8 views) vs plain (one view per
+launch) forward+backward views/s on 8 1080p views with an L1 loss, the
+preprocess+sort HBM fraction of the 6M-Gaussian 4K frame, and the fp64 CPU
+oracle timed on a bounded sample of the same frame.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+import argparse
+import json
+import math
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
+FP32_VALU_PEAK_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 (FMA) x 2.4 GHz; packed fp32 is not used
+STATS_FILE = os.path.join(ROOT, "tests", "golden", "c2_oracle_stats.json")
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_times(run_frame, kernels, frames=5):
+    """Average launch time (ms) and launches per frame of each kernel, from HIP events."""
+    import torch
+    from paper_2602_03207_amd import binding as B
+    out = {}
+    for k in kernels:
+        B.ws_timing_start(k)
+        for _ in range(frames):
+            run_frame()
+        torch.cuda.synchronize()
+        ms, n = B.ws_timing_stop()
+        out[k] = {"avg_ms": ms / max(n, 1), "launches_per_frame": n / frames, "ms_per_frame": ms / frames}
+    return out
+
+
+def c2_work(stats, m_pairs, passes):
+    """Algorithmic bytes (or flops) per launch of each kernel for the 1M-Gaussian 1080p frame."""
+    n = stats["n"]
+    vis, opac, near = stats["status_counts"][0], stats["status_counts"][1], stats["status_counts"][2]
+    n_o = n - opac - near          # read scales and rotations
+    k_sh = 16
+    e, c = stats["evaluations"], stats["contributions"]
+    return {
+        "preprocess": ("hbm", 16 * n + 28 * n_o + 12 * k_sh * vis + 4 * n + 48 * vis),
+        "scan_emit": ("hbm", 4 * n + 16 * vis + 12 * m_pairs),
+        "sort_hist": ("hbm", 8 * m_pairs),
+        "sort_pass": ("hbm", 24 * m_pairs),
+        # 13 fp32 operations for every evaluated entry (offsets, quadratic form, exp, opacity, clamp),
+        # 9 more for every composited one (transmittance, weight, three colour FMAs)
+        "render": ("alu", 13 * e + 9 * c),
+    }
+
+
+def bench_frames(args):
+    import numpy as np
+    import torch
+
+    import scenegen
+    from paper_2602_03207_amd import binding as B
+    from paper_2602_03207_amd.pipeline import GaussianTensors, Renderer
+
+    scene, cam = scenegen.c2()
+    opts = B.make_options(sh_degree=3)
+    g = GaussianTensors.from_scene(scene)
+    r = Renderer([cam], opts)
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        r.forward(g, stream)
+    torch.cuda.synchronize()
+    m = r.num_pairs
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        starts[i].record(stream)
+        r.forward(g, stream)
+        ends[i].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    frame_ms = [s.elapsed_time(e) for s, e in zip(starts, ends)]
+    log(f"frames: {args.steps} in {wall:.3f} s, M = {m}")
+    # per-kernel times
+    names = ["preprocess", "scan_emit", "sort_hist", "sort_pass", "ranges", "render"]
+    kt = kernel_times(lambda: r.forward(g, stream), names)
+    # sort alone on the frame's pair buffer
+    iters = max(10, args.steps)
+    se, ee = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    r.sort(m, stream=stream)
+    se.record(stream)
+    for _ in range(iters):
+        r.sort(m, stream=stream)
+    ee.record(stream)
+    torch.cuda.synchronize()
+    sort_ms = se.elapsed_time(ee) / iters
+    passes = math.ceil(r.end_bit / 8)
+    with open(STATS_FILE) as f:
+        stats = json.load(f)
+    if stats["pairs"] != m:
+        log(f"note: GPU pair count {m} differs from the oracle's {stats['pairs']} (rectangle bounds at a margin)")
+    work = c2_work(stats, m, passes)
+    return dict(r=r, m=m, wall=wall, frame_ms=frame_ms, kernels=kt, sort_ms=sort_ms, passes=passes, work=work,
+                stats=stats, end_bit=r.end_bit)
+
+
+def roofline(res):
+    """Roofline entry of the kernel with the largest time per frame."""
+    kt, work = res["kernels"], res["work"]
+    cands = {k: v for k, v in kt.items() if k in work}
+    dom = max(cands, key=lambda k: cands[k]["ms_per_frame"])
+    bound, amount = work[dom]
+    t = kt[dom]["avg_ms"] * 1e-3
+    if bound == "hbm":
+        achieved = amount / t / 1e9
+        return dom, {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None}
+    achieved = amount / t / 1e12
+    return dom, {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                 "frac": round(achieved / FP32_VALU_PEAK_TFLOPS, 4), "traffic": None}
+
+
+def bench_batched(args):
+    import torch
+
+    import scenegen
+    from paper_2602_03207_amd import binding as B
+    from paper_2602_03207_amd.batched import BatchedStep, PlainStep
+    from paper_2602_03207_amd.pipeline import GaussianTensors, Renderer
+
+    scene, cams, target_scene = scenegen.c5(n_views=args.views)
+    opts = B.make_options(sh_degree=3)
+    g = GaussianTensors.from_scene(scene)
+    tr = Renderer(cams, opts)
+    tr.forward(GaussianTensors.from_scene(target_scene))
+    targets = tr.images.clone()
+    del tr
+    plain = PlainStep(cams, opts, g, targets)
+    for _ in range(2):
+        plain.step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.batched_steps):
+        plain.step()
+    torch.cuda.synchronize()
+    t_plain = (time.perf_counter() - t0) / args.batched_steps
+    pimg = plain.images().clone()
+    pgrads = {k: v.clone() for k, v in plain.grads.items()}
+    bs = BatchedStep(cams, opts, g, targets)
+    bs.capture()
+    for _ in range(2):
+        bs.replay()
+    bs.check()
+    t0 = time.perf_counter()
+    for _ in range(args.batched_steps):
+        bs.replay()
+    bs.stream.synchronize()
+    t_batched = (time.perf_counter() - t0) / args.batched_steps
+    bs.check()
+    same_images = bool(torch.equal(bs.r.images, pimg))
+    rel = max((torch.linalg.norm(bs.grads[k].double() - pgrads[k].double()) /
+               torch.linalg.norm(pgrads[k].double())).item() for k in pgrads)
+    loss = float(bs.loss.item())
+    bs.close()
+    return {"views": args.views, "resolution": "1920x1080", "batched_views_per_s": round(args.views / t_batched, 2),
+            "plain_views_per_s": round(args.views / t_plain, 2), "batched_ms": round(t_batched * 1e3, 3),
+            "plain_ms": round(t_plain * 1e3, 3), "speedup": round(t_plain / t_batched, 3),
+            "images_bit_equal": same_images, "grad_max_rel_diff": rel, "l1_loss": loss}
+
+
+def bench_large(args):
+    """6M Gaussians at 3840x2160: preprocess + sort bytes over their time (HBM fraction)."""
+    import torch
+
+    import scenegen
+    from paper_2602_03207_amd import binding as B
+    from paper_2602_03207_amd.pipeline import GaussianTensors, Renderer
+
+    scene, cam = scenegen.c3()
+    opts = B.make_options(sh_degree=3)
+    g = GaussianTensors.from_scene(scene)
+    del scene
+    r = Renderer([cam], opts)
+    stream = torch.cuda.current_stream()
+    for _ in range(2):
+        r.forward(g, stream)
+    torch.cuda.synchronize()
+    m = r.num_pairs
+    names = ["preprocess", "scan_emit", "sort_hist", "sort_pass", "render"]
+    kt = kernel_times(lambda: r.forward(g, stream), names, frames=3)
+    tt = r.tiles_touched.cpu()
+    n_v = int((tt > 0).sum())
+    n = g.n
+    passes = math.ceil(r.end_bit / 8)
+    # culling counts that only the device knows cheaply: opacity test from the logits
+    sig = torch.sigmoid(g.opacity_logits.double()).cpu()
+    n_o_upper = int((sig >= 1.0 / 255.0).sum())  # opacity survivors (near-culled ones read no scales either)
+    pre_bytes = 16 * n + 28 * n_o_upper + 192 * n_v + 4 * n + 48 * n_v
+    emit_bytes = 4 * n + 16 * n_v + 12 * m
+    sort_bytes = 8 * m + 24 * m * passes
+    t_pre = kt["preprocess"]["ms_per_frame"] + kt["scan_emit"]["ms_per_frame"]
+    t_sort = kt["sort_hist"]["ms_per_frame"] + kt["sort_pass"]["ms_per_frame"]
+    total_bytes = pre_bytes + emit_bytes + sort_bytes
+    total_ms = t_pre + t_sort
+    gbs = total_bytes / (total_ms * 1e-3) / 1e9
+    return {"n": n, "pairs": m, "visible": n_v, "passes": passes, "preprocess_sort_bytes": total_bytes,
+            "preprocess_sort_ms": round(total_ms, 4), "achieved_GBs": round(gbs, 1),
+            "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+            "kernels_ms_per_frame": {k: round(v["ms_per_frame"], 4) for k, v in kt.items()},
+            "note": "opacity survivors counted as the scale/rotation readers (an upper bound on that term)"}
+
+
+def cpu_baseline(args):
+    """fp64 oracle (single thread) on a bounded sample: whole frames of the 1M-Gaussian 1080p view."""
+    import oracle
+    import scenegen
+    scene, cam = scenegen.c2()
+    opts = oracle.Options(sh_degree=3)
+    frames = 0
+    t0 = time.perf_counter()
+    while True:
+        oracle.render(scene, cam, opts)
+        frames += 1
+        if time.perf_counter() - t0 > args.cpu_seconds or frames >= 4:
+            break
+    dt = time.perf_counter() - t0
+    return {"value": round(frames / dt, 5), "unit": "frames/s", "cores": 1, "kind": "oracle",
+            "sample": f"{frames} full frame(s) of the 1M-Gaussian 1920x1080 view (preprocess, emission, "
+                      f"std::stable_sort, compositing), fp64, one thread, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--views", type=int, default=8)
+    ap.add_argument("--batched-steps", type=int, default=10)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-large", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the multi-GPU design is "
+              "described, not built)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    from paper_2602_03207_amd import binding as B
+    B.load()
+
+    log("leg: frames (1M Gaussians, 1920x1080)")
+    res = bench_frames(args)
+    dom, roof = roofline(res)
+    med = statistics.median(res["frame_ms"])
+    p99 = sorted(res["frame_ms"])[min(len(res["frame_ms"]) - 1, int(0.99 * len(res["frame_ms"])))]
+    fps = args.steps / res["wall"]
+    keys_per_s = res["m"] / (res["sort_ms"] * 1e-3)
+    line = {
+        "metric": "frames/s + sorted keys/s at 1M splats 1080p; batched fwd+bwd views/s vs plain",
+        "value": round(fps, 2),
+        "unit": "frames/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(res["wall"] / args.steps * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "1M Gaussians on 20 spheres/planes, bimodal opacity, SH degree 3, one 1920x1080 "
+                               "view, 16x16 tiles", "gaussians": 1_000_000, "width": 1920, "height": 1080,
+                   "sh_degree": 3, "tile": "16x16", "radix_bits": 8, "pairs": res["m"]},
+        "frame_ms_median": round(med, 4),
+        "frame_ms_p99": round(p99, 4),
+        "frame_ms_stdev": round(statistics.pstdev(res["frame_ms"]), 4),
+        "sorted_keys_per_s": round(keys_per_s, 1),
+        "sort_ms": round(res["sort_ms"], 4),
+        "sort_bits": res["end_bit"],
+        "kernels": {k: {kk: round(vv, 5) for kk, vv in v.items()} for k, v in res["kernels"].items()},
+        "dominant_kernel": dom,
+        "roofline": roof,
+    }
+    if not args.no_batched:
+        log("leg: batched vs plain fwd+bwd (8 views, 1920x1080)")
+        line["batched_fwd_bwd"] = bench_batched(args)
+    if not args.no_large:
+        log("leg: 6M Gaussians, 3840x2160")
+        line["large_scene_preprocess_sort"] = bench_large(args)
+    if not args.no_cpu:
+        log("leg: cpu baseline (oracle)")
+        line["cpu_baseline"] = cpu_baseline(args)
+    else:
+        line["cpu_baseline"] = None
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

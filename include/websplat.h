@@ -225,6 +225,26 @@ ws_status ws_graph_end(void* stream, ws_graph* out);
 ws_status ws_graph_launch(ws_graph graph, void* stream);
 ws_status ws_graph_destroy(ws_graph graph);
 
+/* ------------------------------------------------------- kernel timing */
+
+/* Kernels that ws_timing_start can time. */
+#define WS_KERNEL_PREPROCESS     0  /* projection, colour, culling */
+#define WS_KERNEL_SCAN_EMIT      1  /* prefix sum of tile counts and key emission */
+#define WS_KERNEL_SORT_HIST      2  /* digit histograms of all passes */
+#define WS_KERNEL_SORT_PASS      3  /* one digit pass of the radix sort */
+#define WS_KERNEL_RANGES         4  /* per-tile ranges (clear + boundaries) */
+#define WS_KERNEL_RENDER         5  /* tile compositing */
+#define WS_KERNEL_RENDER_BWD     6  /* compositing adjoint */
+#define WS_KERNEL_PREPROCESS_BWD 7  /* preprocess adjoint */
+
+/* While started, every launch of kernel `kernel` made by this process is
+ * bracketed by two HIP events recorded on the launch's stream (up to 4096
+ * launches).  ws_timing_stop waits for those events and returns the summed
+ * elapsed milliseconds and the number of launches, then stops timing.  Meant
+ * for benchmarks: not thread-safe, not for use under graph capture. */
+ws_status ws_timing_start(int32_t kernel);
+ws_status ws_timing_stop(double* total_ms, int64_t* launches);
+
 /* ------------------------------------------------------------ utilities */
 
 const char* ws_last_error(void);           /* thread-local message of the last failed call */

@@ -32,8 +32,12 @@ EXPORTED = [
     "ws_preprocess_workspace_size", "ws_sort_workspace_size", "ws_render_workspace_size",
     "ws_render_backward_workspace_size", "ws_total_tiles", "ws_total_image_floats", "ws_preprocess", "ws_sort",
     "ws_render", "ws_render_backward", "ws_l1_loss", "ws_l1_loss_workspace_size", "ws_graph_begin", "ws_graph_end",
-    "ws_graph_launch", "ws_graph_destroy", "ws_last_error", "ws_status_string", "ws_version",
+    "ws_graph_launch", "ws_graph_destroy", "ws_last_error", "ws_status_string", "ws_version", "ws_timing_start",
+    "ws_timing_stop",
 ]
+
+KERNELS = {"preprocess": 0, "scan_emit": 1, "sort_hist": 2, "sort_pass": 3, "ranges": 4, "render": 5,
+           "render_bwd": 6, "preprocess_bwd": 7}
 
 
 class WsError(RuntimeError):
@@ -110,7 +114,9 @@ def load():
     lib.ws_status_string.argtypes = [i32]
     lib.ws_status_string.restype = C.c_char_p
     lib.ws_version.restype = i32
-    for name in ("ws_preprocess", "ws_sort", "ws_render", "ws_render_backward", "ws_l1_loss", "ws_graph_begin",
+    lib.ws_timing_start.argtypes = [i32]
+    lib.ws_timing_stop.argtypes = [P(C.c_double), P(C.c_int64)]
+    for name in ("ws_timing_start", "ws_timing_stop", "ws_preprocess", "ws_sort", "ws_render", "ws_render_backward", "ws_l1_loss", "ws_graph_begin",
                  "ws_graph_end", "ws_graph_launch", "ws_graph_destroy"):
         getattr(lib, name).restype = i32
     _lib = lib
@@ -285,3 +291,15 @@ def ws_status_string(status):
 
 def ws_version():
     return load().ws_version()
+
+
+def ws_timing_start(kernel):
+    _check(load().ws_timing_start(KERNELS[kernel] if isinstance(kernel, str) else kernel))
+
+
+def ws_timing_stop():
+    """Returns (summed milliseconds, launches) of the kernel being timed."""
+    ms = C.c_double()
+    n = C.c_int64()
+    _check(load().ws_timing_stop(C.byref(ms), C.byref(n)))
+    return ms.value, n.value

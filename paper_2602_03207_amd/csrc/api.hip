@@ -5,6 +5,8 @@
 #include <cstdarg>
 #include <cstdio>
 #include <string>
+#include <utility>
+#include <vector>
 
 #include "ws_internal.h"
 
@@ -119,9 +121,71 @@ bool overlaps(const void* a, size_t an, const void* b, size_t bn) {
     return x < y + bn && y < x + an;
 }
 
+struct Timing {
+    int kernel = -1;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pool;
+    size_t used = 0;
+    bool open = false;
+};
+Timing g_timing;
+constexpr size_t kTimingSlots = 4096;
+
 }  // namespace
 
+namespace ws {
+
+void timing_begin(int kernel, hipStream_t stream) {
+    if (g_timing.kernel != kernel || g_timing.used >= g_timing.pool.size()) return;
+    (void)hipEventRecord(g_timing.pool[g_timing.used].first, stream);
+    g_timing.open = true;
+}
+
+void timing_end(int kernel, hipStream_t stream) {
+    if (g_timing.kernel != kernel || !g_timing.open) return;
+    (void)hipEventRecord(g_timing.pool[g_timing.used].second, stream);
+    g_timing.open = false;
+    ++g_timing.used;
+}
+
+}  // namespace ws
+
 extern "C" {
+
+ws_status ws_timing_start(int32_t kernel) {
+    if (kernel < WS_KERNEL_PREPROCESS || kernel > WS_KERNEL_PREPROCESS_BWD)
+        return fail(WS_ERR_INVALID_ARGUMENT, "unknown kernel id %d", kernel);
+    while (g_timing.pool.size() < kTimingSlots) {
+        hipEvent_t a = nullptr, b = nullptr;
+        ws_status s = hip_status(hipEventCreate(&a), "hipEventCreate");
+        if (s != WS_OK) return s;
+        s = hip_status(hipEventCreate(&b), "hipEventCreate");
+        if (s != WS_OK) return s;
+        g_timing.pool.emplace_back(a, b);
+    }
+    g_timing.kernel = kernel;
+    g_timing.used = 0;
+    g_timing.open = false;
+    return WS_OK;
+}
+
+ws_status ws_timing_stop(double* total_ms, int64_t* launches) {
+    if (!total_ms || !launches) return fail(WS_ERR_INVALID_ARGUMENT, "total_ms / launches is NULL");
+    double sum = 0.0;
+    for (size_t k = 0; k < g_timing.used; ++k) {
+        ws_status s = hip_status(hipEventSynchronize(g_timing.pool[k].second), "hipEventSynchronize");
+        if (s != WS_OK) return s;
+        float ms = 0.f;
+        s = hip_status(hipEventElapsedTime(&ms, g_timing.pool[k].first, g_timing.pool[k].second),
+                       "hipEventElapsedTime");
+        if (s != WS_OK) return s;
+        sum += ms;
+    }
+    *total_ms = sum;
+    *launches = int64_t(g_timing.used);
+    g_timing.kernel = -1;
+    g_timing.used = 0;
+    return WS_OK;
+}
 
 int32_t ws_version(void) { return 10000; }
 

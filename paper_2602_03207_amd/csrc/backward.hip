@@ -385,10 +385,12 @@ hipError_t launch_render_backward(const GaussPtrs& g, const ws_camera* d_cams, i
         ba.d_status = d_status;
         ba.w = w;
         ba.o = o;
+        timing_begin(WS_KERNEL_RENDER_BWD, stream);
         if (o.tile_w == 16 && o.tile_h == 16) launch_bwd_t<16, 16>(ba, total_tiles, stream);
         else if (o.tile_w == 8 && o.tile_h == 8) launch_bwd_t<8, 8>(ba, total_tiles, stream);
         else if (o.tile_w == 16 && o.tile_h == 8) launch_bwd_t<16, 8>(ba, total_tiles, stream);
         else launch_bwd_t<32, 16>(ba, total_tiles, stream);
+        timing_end(WS_KERNEL_RENDER_BWD, stream);
     }
     PreBwdArgs pa;
     pa.g = g;
@@ -398,12 +400,14 @@ hipError_t launch_render_backward(const GaussPtrs& g, const ws_camera* d_cams, i
     pa.w = w;
     pa.out = grads;
     const dim3 grid(uint32_t((g.n + 127) / 128));
+    timing_begin(WS_KERNEL_PREPROCESS_BWD, stream);
     switch (o.sh_degree) {
         case 0: hipLaunchKernelGGL(k_preprocess_bwd<0>, grid, dim3(128), 0, stream, pa); break;
         case 1: hipLaunchKernelGGL(k_preprocess_bwd<1>, grid, dim3(128), 0, stream, pa); break;
         case 2: hipLaunchKernelGGL(k_preprocess_bwd<2>, grid, dim3(128), 0, stream, pa); break;
         default: hipLaunchKernelGGL(k_preprocess_bwd<3>, grid, dim3(128), 0, stream, pa); break;
     }
+    timing_end(WS_KERNEL_PREPROCESS_BWD, stream);
     return hipGetLastError();
 }
 

@@ -215,6 +215,7 @@ hipError_t launch_preprocess(const GaussPtrs& g, const ws_camera* d_cams, int32_
     PreprocessWs pw = carve(ws, g.n, n_views);
     const int64_t total = g.n * n_views;
     const uint32_t gx = uint32_t(std::max<int64_t>((g.n + kPreThreads - 1) / kPreThreads, 1));
+    timing_begin(WS_KERNEL_PREPROCESS, stream);
     switch (o.sh_degree) {
         case 0: hipLaunchKernelGGL(k_preprocess<0>, dim3(gx, n_views), dim3(kPreThreads), 0, stream, g, d_cams, o,
                                    splats, tiles_touched, pw); break;
@@ -225,6 +226,7 @@ hipError_t launch_preprocess(const GaussPtrs& g, const ws_camera* d_cams, int32_
         default: hipLaunchKernelGGL(k_preprocess<3>, dim3(gx, n_views), dim3(kPreThreads), 0, stream, g, d_cams, o,
                                     splats, tiles_touched, pw); break;
     }
+    timing_end(WS_KERNEL_PREPROCESS, stream);
     EmitArgs a;
     a.tiles_touched = tiles_touched;
     a.splats = splats;
@@ -241,7 +243,9 @@ hipError_t launch_preprocess(const GaussPtrs& g, const ws_camera* d_cams, int32_
     a.d_status = d_status;
     const uint32_t blocks = uint32_t(std::max<int64_t>(pw.n_blocks, 1));
     a.n_launched = blocks;  // with no Gaussians one block still reports M = 0
+    timing_begin(WS_KERNEL_SCAN_EMIT, stream);
     hipLaunchKernelGGL(k_scan_emit, dim3(blocks), dim3(kScanThreads), 0, stream, a, pw);
+    timing_end(WS_KERNEL_SCAN_EMIT, stream);
     return hipGetLastError();
 }
 

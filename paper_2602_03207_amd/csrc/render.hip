@@ -108,9 +108,11 @@ hipError_t launch_render(const ws_splat* splats, int64_t n, const ws_camera* d_c
     (void)ws;
     const int64_t words = 2 * total_tiles;
     const uint32_t cgrid = uint32_t(std::min<int64_t>(std::max<int64_t>((words + 255) / 256, 1), 4096));
+    timing_begin(WS_KERNEL_RANGES, stream);
     hipLaunchKernelGGL(k_ranges_clear, dim3(cgrid), dim3(256), 0, stream, tile_ranges, words, (uint32_t*)nullptr);
     hipLaunchKernelGGL(k_ranges, dim3(2048), dim3(256), 0, stream, keys, capacity, d_num_pairs, d_status,
                        tile_ranges, total_tiles);
+    timing_end(WS_KERNEL_RANGES, stream);
     if (total_tiles == 0) return hipGetLastError();
     RenderArgs ra;
     ra.splats = splats;
@@ -123,10 +125,12 @@ hipError_t launch_render(const ws_splat* splats, int64_t n, const ws_camera* d_c
     ra.images = images;
     ra.d_status = d_status;
     ra.o = o;
+    timing_begin(WS_KERNEL_RENDER, stream);
     if (o.tile_w == 16 && o.tile_h == 16) launch_render_t<16, 16>(ra, stream);
     else if (o.tile_w == 8 && o.tile_h == 8) launch_render_t<8, 8>(ra, stream);
     else if (o.tile_w == 16 && o.tile_h == 8) launch_render_t<16, 8>(ra, stream);
     else launch_render_t<32, 16>(ra, stream);
+    timing_end(WS_KERNEL_RENDER, stream);
     return hipGetLastError();
 }
 

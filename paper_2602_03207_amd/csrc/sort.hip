@@ -309,7 +309,9 @@ hipError_t launch_sort(const uint64_t* kin, const uint32_t* vin, uint64_t* kout,
     h.status = L.status;
     h.max_tiles = L.max_tiles;
     const int64_t hist_blocks = std::min<int64_t>(std::max<int64_t>((n + 4095) / 4096, 1), 2048);
+    timing_begin(WS_KERNEL_SORT_HIST, stream);
     hipLaunchKernelGGL(k_sort_hist, dim3(uint32_t(hist_blocks)), dim3(kHistThreads), 0, stream, h);
+    timing_end(WS_KERNEL_SORT_HIST, stream);
     const uint32_t grid = uint32_t(L.max_tiles);
     for (int p = 0; p < L.passes; ++p) {
         PassArgs pa;
@@ -327,6 +329,7 @@ hipError_t launch_sort(const uint64_t* kin, const uint32_t* vin, uint64_t* kout,
         pa.hist = L.hist + p * L.radix;
         pa.status = L.status + int64_t(p) * L.max_tiles * L.radix;
         pa.ticket = L.tickets + p;
+        timing_begin(WS_KERNEL_SORT_PASS, stream);
         switch (L.r) {
             case 1: launch_pass<1>(pa, grid, stream); break;
             case 2: launch_pass<2>(pa, grid, stream); break;
@@ -337,6 +340,7 @@ hipError_t launch_sort(const uint64_t* kin, const uint32_t* vin, uint64_t* kout,
             case 7: launch_pass<7>(pa, grid, stream); break;
             default: launch_pass<8>(pa, grid, stream); break;
         }
+        timing_end(WS_KERNEL_SORT_PASS, stream);
     }
     return hipGetLastError();
 }

@@ -170,6 +170,11 @@ hipError_t launch_l1_loss(const float* images, const float* targets, int64_t n, 
                           hipStream_t stream);
 size_t l1_loss_workspace(int64_t n);
 
+// Benchmark timing hooks (defined in api.hip): no-ops unless ws_timing_start
+// selected this kernel.
+void timing_begin(int kernel, hipStream_t stream);
+void timing_end(int kernel, hipStream_t stream);
+
 // Round a byte count up to the workspace alignment.
 inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 

@@ -173,6 +173,22 @@ class Renderer:
         self.sort(self.capacity, device_count=True, stream=stream)
         self.render(self.capacity, stream)
 
+    def backward(self, g: GaussianTensors, dL_dimages: torch.Tensor, grads=None, stream=None):
+        """Parameter gradients of the last forward for dL/dimages (same layout as self.images).
+
+        Returns a dict of tensors shaped like the parameters; `grads` may supply them.
+        """
+        if grads is None:
+            grads = dict(means=torch.empty_like(g.means), log_scales=torch.empty_like(g.log_scales),
+                         quats=torch.empty_like(g.quats), opacity_logits=torch.empty_like(g.opacity_logits),
+                         sh=torch.empty_like(g.sh))
+        need = B.ws_render_backward_workspace_size(g.n, self.n_views)
+        ws = self.ws_bwd.get(need)
+        gs = B.make_grads(grads["means"], grads["log_scales"], grads["quats"], grads["opacity_logits"], grads["sh"])
+        B.ws_render_backward(g.struct(), self.cam_arr, self.d_cams, self.n_views, self.opts, self.splats, self.vals_b,
+                             self.tile_ranges, dL_dimages, self.d_status, gs, ws, ws.numel(), stream)
+        return grads
+
     def _check_status(self):
         st = int(self.d_status.item())
         if st != 0:

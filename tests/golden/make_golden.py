@@ -35,15 +35,19 @@ def main():
     out["C4_resolutions"] = [[c.width, c.height] for c in cams4]
     with open(os.path.join(HERE, "scenegen_sha256.json"), "w") as f:
         json.dump(out, f, indent=1)
-    # oracle statistics of the 1M-Gaussian 1080p workload (used as sanity bounds)
+    # oracle statistics of the 1M-Gaussian 1080p workload: the counts that fix its algorithmic work
     opts = oracle.Options(sh_degree=3)
-    p = oracle.preprocess(s2, cam2, opts)
+    r = oracle.render(s2, cam2, opts)
+    p = r["proj"]
     stats = {
         "n": int(s2.n),
         "status_counts": [int(x) for x in (p["status"][:, None] == range(5)).sum(0)],
         "pairs": int(p["tiles_touched"].sum()),
-        "note": "fp64 oracle preprocess of the 1M-Gaussian 1920x1080 scene; status order: visible, opacity, near, "
-                "degenerate, viewport",
+        "evaluations": int(r["n_eval"].sum()),
+        "contributions": int(r["n_contrib"].sum()),
+        "note": "fp64 oracle forward of the 1M-Gaussian 1920x1080 scene; status order: visible, opacity, near, "
+                "degenerate, viewport; evaluations = (pixel, splat) entries inside the splat rectangle visited "
+                "before the pixel stops; contributions = those composited",
     }
     with open(os.path.join(HERE, "c2_oracle_stats.json"), "w") as f:
         json.dump(stats, f, indent=1)

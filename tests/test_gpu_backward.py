@@ -1,0 +1,137 @@
+"""ws_render_backward on the GPU against the fp64 oracle's reverse mode; autograd and batched/graph paths."""
+import numpy as np
+import pytest
+
+import oracle
+import scenegen
+from _helpers import gpu_options, oracle_options
+
+pytestmark = pytest.mark.gpu
+
+NAMES = ("means", "log_scales", "quats", "opacity_logits", "sh")
+
+
+def _gpu_grads(scene, cams, dL_views, **kw):
+    import torch
+    from paper_2602_03207_amd.pipeline import GaussianTensors, Renderer
+    r = Renderer(cams, gpu_options(sh_degree=scene.sh_degree, **kw))
+    g = GaussianTensors.from_scene(scene)
+    r.forward(g)
+    dL = torch.as_tensor(np.concatenate([np.asarray(d, np.float32).reshape(-1) for d in dL_views])).cuda()
+    grads = r.backward(g, dL)
+    torch.cuda.synchronize()
+    assert r.status() == 0
+    return {k: grads[k].cpu().numpy().astype(np.float64) for k in NAMES}, r
+
+
+def _oracle_grads(scene, cams, dL_views, ropts):
+    tot = {k: 0.0 for k in NAMES}
+    for cam, dL in zip(cams, dL_views):
+        res = oracle.forward_backward(scene, cam, ropts, np.asarray(dL, np.float32).astype(np.float64))
+        for k in NAMES:
+            tot[k] = tot[k] + res["grads"][k]
+    return tot
+
+
+def _compare(got, want, rel=1e-3, elem_frac=0.999):
+    for k in NAMES:
+        g, w = got[k].reshape(-1), want[k].reshape(-1)
+        nrm = np.linalg.norm(w)
+        if nrm == 0:
+            assert np.linalg.norm(g) == 0, k
+            continue
+        err = np.linalg.norm(g - w) / nrm
+        assert err <= rel, f"{k}: relative error {err:.2e}"
+        scale = np.maximum(np.abs(w), np.sqrt(np.mean(w * w)))
+        ok = np.abs(g - w) <= rel * scale
+        assert ok.mean() >= elem_frac, f"{k}: {np.count_nonzero(~ok)} of {ok.size} elements off"
+
+
+def test_backward_fd_scene_matches_oracle():
+    scene, cam = scenegen.fd_scene()
+    rng = np.random.default_rng(3)
+    dL = rng.standard_normal((3, cam.height, cam.width)).astype(np.float32)
+    got, _ = _gpu_grads(scene, [cam], [dL])
+    want = _oracle_grads(scene, [cam], [dL], oracle_options(sh_degree=3))
+    _compare(got, want)
+
+
+@pytest.mark.parametrize("tile", [(16, 16), (8, 8), (32, 16)])
+def test_backward_multiview_matches_oracle(tile):
+    scene = scenegen.random_scene(2500, 8, log_scale_mu=-3.0, logit_sd=2.0, sh_degree=1, dc_sd=0.5, rest_sd=0.2)
+    cams = [scenegen.look_at([0.3, -0.2, -3.0], [0, 0, 0], 128, 96), scenegen.look_at([2.0, 0.5, -2.0], [0, 0, 0], 77, 61),
+            scenegen.look_at([-1.0, -1.5, -2.0], [0, 0, 0], 100, 100)]
+    rng = np.random.default_rng(4)
+    dLs = [rng.standard_normal((3, c.height, c.width)).astype(np.float32) for c in cams]
+    got, _ = _gpu_grads(scene, cams, dLs, tile_w=tile[0], tile_h=tile[1])
+    want = _oracle_grads(scene, cams, dLs, oracle_options(*tile, sh_degree=1))
+    _compare(got, want)
+
+
+@pytest.mark.slow
+def test_backward_1080p_l1_view_matches_oracle():
+    """One 1920x1080 view of the 1M-Gaussian scene with the L1 loss against a perturbed-scene target."""
+    scene, cams, target_scene = scenegen.c5(n_views=1)
+    cam = cams[0]
+    ro = oracle_options(sh_degree=3)
+    img = oracle.forward_backward(scene, cam, ro)["image"]
+    tgt = oracle.forward_backward(target_scene, cam, ro)["image"]
+    _, dL = oracle.l1_loss_grad(img, tgt)
+    dL = dL.astype(np.float32)
+    got, _ = _gpu_grads(scene, [cam], [dL])
+    want = _oracle_grads(scene, [cam], [dL], ro)
+    _compare(got, want)
+
+
+def test_autograd_function_matches_backward_call():
+    import torch
+    from paper_2602_03207_amd.autograd import render_gaussians
+    from paper_2602_03207_amd.pipeline import GaussianTensors, Renderer
+    scene = scenegen.random_scene(1500, 9, sh_degree=2, dc_sd=0.4, rest_sd=0.2)
+    cam = scenegen.look_at([0.1, 0.2, -3.0], [0, 0, 0], 96, 72)
+    g = GaussianTensors.from_scene(scene)
+    params = [getattr(g, k).clone().requires_grad_(True) for k in NAMES]
+    r = Renderer([cam], gpu_options(sh_degree=2))
+    img = render_gaussians(*params, r)
+    w = torch.randn_like(img)
+    (img * w).sum().backward()
+    r2 = Renderer([cam], gpu_options(sh_degree=2))
+    r2.forward(g)
+    assert torch.equal(r2.images, img.detach())
+    ref = r2.backward(g, w)
+    for k, p in zip(NAMES, params):
+        assert torch.allclose(p.grad, ref[k], rtol=1e-5, atol=1e-7), k
+
+
+def test_batched_graph_equals_plain_and_replays_consistently():
+    import torch
+    from paper_2602_03207_amd.batched import BatchedStep, PlainStep
+    from paper_2602_03207_amd.pipeline import GaussianTensors, Renderer
+    scene = scenegen.random_scene(4000, 10, log_scale_mu=-3.2, sh_degree=3, dc_sd=0.5, rest_sd=0.2)
+    target = scenegen.perturb(scene, 99)
+    rng = np.random.default_rng(1)
+    res = [(128, 128), (160, 90), (96, 120), (200, 64)]
+    cams = scenegen.orbit_cameras(rng, len(res), res)
+    opts = gpu_options(sh_degree=3)
+    g = GaussianTensors.from_scene(scene)
+    tr = Renderer(cams, opts)
+    tr.forward(GaussianTensors.from_scene(target))
+    targets = tr.images.clone()
+    plain = PlainStep(cams, opts, g, targets)
+    pg = {k: v.clone() for k, v in plain.step().items()}
+    pimg = plain.images().clone()
+    bs = BatchedStep(cams, opts, g, targets)
+    bs.capture()
+    for rep in range(3):
+        with torch.cuda.stream(bs.stream):  # eager work between replays; the graph must overwrite it
+            for k in bs.grads:
+                bs.grads[k].fill_(123.0)
+            bs.r.images.fill_(-1.0)
+        bs.replay()
+        bs.check()
+        assert torch.equal(bs.r.images, pimg), rep
+        for k in NAMES:
+            a, b = bs.grads[k].double(), pg[k].double()
+            err = (torch.linalg.norm(a - b) / torch.linalg.norm(b)).item()
+            assert err <= 1e-3, (rep, k, err)
+    bs.close()
