@@ -49,16 +49,24 @@ def kernel_times(run_frame, kernels, frames=5):
     return out
 
 
-def c2_work(stats, m_pairs, passes):
-    """Algorithmic bytes (or flops) per launch of each kernel for the 1M-Gaussian 1080p frame."""
+def c2_work(stats, m_pairs):
+    """Algorithmic bytes (or flops) per launch of each kernel for the 1M-Gaussian 1080p frame.
+
+    Pairs are emitted in depth order (the visible splats are compacted and
+    stably sorted by depth first), so the frame's sort covers the tile bits only.
+    """
     n = stats["n"]
     vis, opac, near = stats["status_counts"][0], stats["status_counts"][1], stats["status_counts"][2]
     n_o = n - opac - near          # read scales and rotations
     k_sh = 16
     e, c = stats["evaluations"], stats["contributions"]
+    # compaction: read 4n flags, write 12 per visible entry (+ its 4-byte depth read);
+    # depth sort of the visible entries (u64 key, u32 value): 8 for the histogram + 4 passes x 24;
+    # counts: list 4 + tile count 4 + offset 4; emission: offset 4 + list 4 + record 16 per entry, 12 per pair
+    scan_emit = 4 * n + (16 + 8 + 96 + 12 + 24) * vis + 12 * m_pairs
     return {
         "preprocess": ("hbm", 16 * n + 28 * n_o + 12 * k_sh * vis + 4 * n + 48 * vis),
-        "scan_emit": ("hbm", 4 * n + 16 * vis + 12 * m_pairs),
+        "scan_emit": ("hbm", scan_emit),
         "sort_hist": ("hbm", 8 * m_pairs),
         "sort_pass": ("hbm", 24 * m_pairs),
         # 13 fp32 operations for every evaluated entry (offsets, quadratic form, exp, opacity, clamp),
@@ -76,7 +84,7 @@ def bench_frames(args):
     from paper_2602_03207_amd.pipeline import GaussianTensors, Renderer
 
     scene, cam = scenegen.c2()
-    opts = B.make_options(sh_degree=3)
+    opts = B.make_options(sh_degree=3, flags=B.WS_FLAG_DEPTH_FIRST)
     g = GaussianTensors.from_scene(scene)
     r = Renderer([cam], opts)
     stream = torch.cuda.current_stream()
@@ -99,23 +107,32 @@ def bench_frames(args):
     # per-kernel times
     names = ["preprocess", "scan_emit", "sort_hist", "sort_pass", "ranges", "render"]
     kt = kernel_times(lambda: r.forward(g, stream), names)
-    # sort alone on the frame's pair buffer
     iters = max(10, args.steps)
-    se, ee = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    r.sort(m, stream=stream)
-    se.record(stream)
-    for _ in range(iters):
-        r.sort(m, stream=stream)
-    ee.record(stream)
+
+    def time_sort(rr):
+        se, ee = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        rr.sort(rr.num_pairs, stream=stream)
+        se.record(stream)
+        for _ in range(iters):
+            rr.sort(rr.num_pairs, stream=stream)
+        ee.record(stream)
+        torch.cuda.synchronize()
+        return se.elapsed_time(ee) / iters
+
+    # the frame's own sort: tile bits of depth-ordered pairs
+    frame_sort_ms = time_sort(r)
+    # the general sort: every key bit of the same pairs emitted in Gaussian order
+    rg = Renderer([cam], B.make_options(sh_degree=3))
+    rg.forward(g, stream)
     torch.cuda.synchronize()
-    sort_ms = se.elapsed_time(ee) / iters
-    passes = math.ceil(r.end_bit / 8)
+    sort_ms = time_sort(rg)
     with open(STATS_FILE) as f:
         stats = json.load(f)
     if stats["pairs"] != m:
         log(f"note: GPU pair count {m} differs from the oracle's {stats['pairs']} (rectangle bounds at a margin)")
-    work = c2_work(stats, m, passes)
-    return dict(r=r, m=m, wall=wall, frame_ms=frame_ms, kernels=kt, sort_ms=sort_ms, passes=passes, work=work,
+    work = c2_work(stats, m)
+    return dict(r=r, m=m, wall=wall, frame_ms=frame_ms, kernels=kt, sort_ms=sort_ms, frame_sort_ms=frame_sort_ms,
+                passes=math.ceil(rg.end_bit / 8), frame_passes=math.ceil((r.end_bit - r.begin_bit) / 8), work=work,
                 stats=stats, end_bit=r.end_bit)
 
 
@@ -144,7 +161,7 @@ def bench_batched(args):
     from paper_2602_03207_amd.pipeline import GaussianTensors, Renderer
 
     scene, cams, target_scene = scenegen.c5(n_views=args.views)
-    opts = B.make_options(sh_degree=3)
+    opts = B.make_options(sh_degree=3, flags=B.WS_FLAG_DEPTH_FIRST)
     g = GaussianTensors.from_scene(scene)
     tr = Renderer(cams, opts)
     tr.forward(GaussianTensors.from_scene(target_scene))
@@ -192,7 +209,7 @@ def bench_large(args):
     from paper_2602_03207_amd.pipeline import GaussianTensors, Renderer
 
     scene, cam = scenegen.c3()
-    opts = B.make_options(sh_degree=3)
+    opts = B.make_options(sh_degree=3, flags=B.WS_FLAG_DEPTH_FIRST)
     g = GaussianTensors.from_scene(scene)
     del scene
     r = Renderer([cam], opts)
@@ -206,12 +223,12 @@ def bench_large(args):
     tt = r.tiles_touched.cpu()
     n_v = int((tt > 0).sum())
     n = g.n
-    passes = math.ceil(r.end_bit / 8)
+    passes = math.ceil((r.end_bit - r.begin_bit) / 8)
     # culling counts that only the device knows cheaply: opacity test from the logits
     sig = torch.sigmoid(g.opacity_logits.double()).cpu()
     n_o_upper = int((sig >= 1.0 / 255.0).sum())  # opacity survivors (near-culled ones read no scales either)
     pre_bytes = 16 * n + 28 * n_o_upper + 192 * n_v + 4 * n + 48 * n_v
-    emit_bytes = 4 * n + 16 * n_v + 12 * m
+    emit_bytes = 4 * n + (16 + 8 + 96 + 12 + 24) * n_v + 12 * m
     sort_bytes = 8 * m + 24 * m * passes
     t_pre = kt["preprocess"]["ms_per_frame"] + kt["scan_emit"]["ms_per_frame"]
     t_sort = kt["sort_hist"]["ms_per_frame"] + kt["sort_pass"]["ms_per_frame"]
@@ -255,6 +272,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-large", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also copy a 256 MiB buffer 4 times (a plain copy kernel of known size, used to scale "
+                         "the HBM byte counters of a profiler run)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the multi-GPU design is "
@@ -264,6 +284,13 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     from paper_2602_03207_amd import binding as B
     B.load()
+    if args.copy_calibration:
+        src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(4):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: 4 x 268435456 bytes read and written")
 
     log("leg: frames (1M Gaussians, 1920x1080)")
     res = bench_frames(args)
@@ -287,13 +314,18 @@ def main():
         "data": "synthetic",
         "config": {"workload": "1M Gaussians on 20 spheres/planes, bimodal opacity, SH degree 3, one 1920x1080 "
                                "view, 16x16 tiles", "gaussians": 1_000_000, "width": 1920, "height": 1080,
-                   "sh_degree": 3, "tile": "16x16", "radix_bits": 8, "pairs": res["m"]},
+                   "sh_degree": 3, "tile": "16x16", "radix_bits": 8, "pairs": res["m"],
+                   "emission": "depth-first (tile bits sorted per frame)"},
         "frame_ms_median": round(med, 4),
         "frame_ms_p99": round(p99, 4),
         "frame_ms_stdev": round(statistics.pstdev(res["frame_ms"]), 4),
         "sorted_keys_per_s": round(keys_per_s, 1),
         "sort_ms": round(res["sort_ms"], 4),
         "sort_bits": res["end_bit"],
+        "sort_passes": res["passes"],
+        "frame_sort_keys_per_s": round(res["m"] / (res["frame_sort_ms"] * 1e-3), 1),
+        "frame_sort_ms": round(res["frame_sort_ms"], 4),
+        "frame_sort_passes": res["frame_passes"],
         "kernels": {k: {kk: round(vv, 5) for kk, vv in v.items()} for k, v in res["kernels"].items()},
         "dominant_kernel": dom,
         "roofline": roof,

@@ -82,6 +82,9 @@ typedef struct ws_camera {
 #define WS_FLAG_FIXED_3SIGMA     1u  /* "-RADIUS" ablation (Sec. 4.4): 3-sigma extent for every splat */
 #define WS_FLAG_NO_VIEWPORT_CULL 2u  /* "-CULL" ablation (Sec. 4.4): keep splats whose AABB misses the view */
 #define WS_FLAG_ORDERED_RENDER   4u  /* render: persistent workgroups take tiles in descending pair count */
+#define WS_FLAG_DEPTH_FIRST      8u  /* preprocess: emit pairs in (depth, view * n + id) order instead of
+                                        (view * n + id) order; a stable sort of the tile bits alone
+                                        [32, end_bit) then yields the full (tile, depth) order */
 
 typedef struct ws_options {
     int32_t tile_w, tile_h;   /* 16x16 (default), 8x8, 16x8 or 32x16 pixels */
@@ -127,8 +130,9 @@ typedef struct ws_gaussian_grads {  /* same shapes as ws_gaussians; overwritten,
 
 /* ------------------------------------------------------------------ sizes */
 
-/* Bytes of workspace for ws_preprocess with n Gaussians and n_views views. */
-size_t ws_preprocess_workspace_size(int64_t n, int32_t n_views);
+/* Bytes of workspace for ws_preprocess with n Gaussians, n_views views, key
+ * buffers of `capacity` pairs and the given option flags. */
+size_t ws_preprocess_workspace_size(int64_t n, int32_t n_views, int64_t capacity, uint32_t flags);
 
 /* Bytes of workspace for ws_sort of up to `capacity` pairs on bits
  * [begin_bit, end_bit) with digits of radix_bits (0 = default). */

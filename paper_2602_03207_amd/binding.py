@@ -27,6 +27,7 @@ WS_ERR_SPIN_LIMIT = 6
 WS_FLAG_FIXED_3SIGMA = 1
 WS_FLAG_NO_VIEWPORT_CULL = 2
 WS_FLAG_ORDERED_RENDER = 4
+WS_FLAG_DEPTH_FIRST = 8
 
 EXPORTED = [
     "ws_preprocess_workspace_size", "ws_sort_workspace_size", "ws_render_workspace_size",
@@ -84,7 +85,7 @@ def load():
                            "(or __graft_entry__.build()) first")
     lib = C.CDLL(LIB_PATH)
     P, vp, i64, i32, sz = C.POINTER, C.c_void_p, C.c_int64, C.c_int32, C.c_size_t
-    lib.ws_preprocess_workspace_size.argtypes = [i64, i32]
+    lib.ws_preprocess_workspace_size.argtypes = [i64, i32, i64, C.c_uint32]
     lib.ws_preprocess_workspace_size.restype = sz
     lib.ws_sort_workspace_size.argtypes = [i64, i32, i32, i32]
     lib.ws_sort_workspace_size.restype = sz
@@ -201,8 +202,8 @@ def make_grads(means, log_scales, quats, opacity_logits, sh) -> ws_gaussian_grad
 
 # -------------------------------------------------------------------- sizes
 
-def ws_preprocess_workspace_size(n, n_views):
-    return load().ws_preprocess_workspace_size(n, n_views)
+def ws_preprocess_workspace_size(n, n_views, capacity, flags=0):
+    return load().ws_preprocess_workspace_size(n, n_views, capacity, flags)
 
 
 def ws_sort_workspace_size(capacity, begin_bit, end_bit, radix_bits=0):

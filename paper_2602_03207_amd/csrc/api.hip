@@ -45,7 +45,7 @@ ws_status check_options(const ws_options* o) {
         return fail(WS_ERR_UNSUPPORTED, "sh_degree %d not supported (0..3)", o->sh_degree);
     if (o->radix_bits < 0 || o->radix_bits > 8)
         return fail(WS_ERR_INVALID_ARGUMENT, "radix_bits %d out of range (0..8)", o->radix_bits);
-    if (o->flags & ~(WS_FLAG_FIXED_3SIGMA | WS_FLAG_NO_VIEWPORT_CULL | WS_FLAG_ORDERED_RENDER))
+    if (o->flags & ~(WS_FLAG_FIXED_3SIGMA | WS_FLAG_NO_VIEWPORT_CULL | WS_FLAG_ORDERED_RENDER | WS_FLAG_DEPTH_FIRST))
         return fail(WS_ERR_INVALID_ARGUMENT, "unknown flag bits 0x%x", o->flags);
     if (!finite_pos(o->near_z)) return fail(WS_ERR_INVALID_ARGUMENT, "near_z must be finite and > 0");
     if (!(std::isfinite(o->lowpass) && o->lowpass >= 0.f))
@@ -204,9 +204,9 @@ const char* ws_status_string(int32_t s) {
     }
 }
 
-size_t ws_preprocess_workspace_size(int64_t n, int32_t n_views) {
+size_t ws_preprocess_workspace_size(int64_t n, int32_t n_views, int64_t capacity, uint32_t flags) {
     if (n < 0 || n_views < 1) return 0;
-    return ws::preprocess_workspace(n, n_views);
+    return ws::preprocess_workspace(n, n_views, capacity < 0 ? 0 : capacity, flags);
 }
 
 size_t ws_sort_workspace_size(int64_t capacity, int32_t begin_bit, int32_t end_bit, int32_t radix_bits) {
@@ -259,7 +259,7 @@ ws_status ws_preprocess(const ws_gaussians* g, const ws_camera* cams, const ws_c
     if (!d_num_pairs || !d_status) return fail(WS_ERR_INVALID_ARGUMENT, "d_num_pairs / d_status is NULL");
     if (total_tiles_of(cams, n_views, opt->tile_w, opt->tile_h) > (int64_t(1) << 32))
         return fail(WS_ERR_UNSUPPORTED, "more than 2^32 tiles");
-    if ((s = check_ws(ws, ws_bytes, ws::preprocess_workspace(g->n, n_views))) != WS_OK) return s;
+    if ((s = check_ws(ws, ws_bytes, ws::preprocess_workspace(g->n, n_views, capacity, opt->flags))) != WS_OK) return s;
     if (reinterpret_cast<uintptr_t>(splats) % 16 != 0)
         return fail(WS_ERR_INVALID_ARGUMENT, "splats must be 16-byte aligned");
     const hipError_t e = ws::launch_preprocess(gauss_ptrs(g), d_cams, n_views, ws::to_kopts(*opt), splats,

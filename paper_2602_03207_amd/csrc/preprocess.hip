@@ -1,55 +1,84 @@
 // Pre-processing stage (Sec. 3.2) and key emission.
 //
-// k_preprocess   one thread per (view, Gaussian): opacity cull, projection,
-//                bounding-box cull, SH colour; writes the 48-byte splat
-//                record of visible splats and tiles_touched of every splat.
-// k_scan_emit    one pass over tiles_touched: exclusive prefix sum across the
-//                device (decoupled look-back over workgroup aggregates, wait
-//                bounded), then each workgroup writes its own pairs
-//                (key = tile << 32 | depth bits, value = Gaussian id) with
-//                coalesced stores, load-balanced over the pairs rather than
-//                over the splats.
+// k_preprocess  one thread per (view, Gaussian): opacity cull, projection,
+//               bounding-box cull, SH colour; writes the 48-byte splat record
+//               of visible splats and tiles_touched of every splat.
+// compaction    list of the visible (view, Gaussian) entries in index order,
+//               the survivors "written into a buffer" of Sec. 3.2 (prefix sum
+//               of the visibility flags).  With WS_FLAG_DEPTH_FIRST each
+//               entry's fp32 depth bits are written too and the list is then
+//               stably sorted by depth.
+// counts        prefix sum of the listed entries' tile counts: each entry's
+//               first pair, the total M, and for every 1024-pair block of the
+//               output the entry that owns its first pair.
+// k_emit        one workgroup per 1024 pairs: loads the entries that cover
+//               its pairs, finds each pair's owner by marking the entry starts
+//               in LDS and taking a running maximum, and writes
+//               key = (tile << 32) | depth bits, value = Gaussian id with
+//               coalesced stores.  Work per workgroup is fixed, whatever the
+//               size of the splats.
+// Both prefix sums are the wait-free hierarchical scan of scan.h.
 #include "project.h"
+#include "scan.h"
 #include "ws_internal.h"
 
 namespace ws {
 namespace {
 
 constexpr int kPreThreads = 256;
-constexpr int kScanThreads = 256;
-constexpr int kScanItems = 4;
-constexpr int kScanTile = kScanThreads * kScanItems;  // entries per workgroup
-constexpr uint64_t kFlagAgg = 1ull << 62;
-constexpr uint64_t kFlagInc = 2ull << 62;
-constexpr uint64_t kValueMask = (1ull << 62) - 1;
+constexpr int kEmitThreads = 256;
+constexpr int kEmitItems = 4;
+constexpr int kEmitPairs = kEmitThreads * kEmitItems;  // pairs per emission workgroup
+constexpr int kEmitSlots = kEmitPairs + 1;             // entries one emission workgroup may need
 
 struct PreprocessWs {
-    uint64_t* scan_status;  // [n_blocks]
-    uint32_t* ticket;       // [1]
-    int64_t n_blocks;
+    uint32_t* list_a;       // [V n] visible entries in index order
+    uint32_t* list_b;       // [V n] the same, sorted by depth (depth-first mode)
+    uint64_t* dkey_a;       // [V n] fp32 depth bits of list_a (depth-first mode)
+    uint64_t* dkey_b;
+    uint32_t* offsets;      // [V n] first pair of each list entry
+    uint32_t* first_entry;  // [emit blocks] list entry owning each block's first pair
+    uint64_t* partials_a;   // scan block sums
+    uint64_t* partials_b;
+    int64_t* d_nvis;
+    void* sort_ws;
+    int64_t total, emit_blocks;
 };
 
-PreprocessWs carve(void* ws, int64_t n, int32_t n_views) {
-    PreprocessWs p;
-    const int64_t total = n * n_views;
-    p.n_blocks = (total + kScanTile - 1) / kScanTile;
+size_t layout(void* ws, int64_t n, int32_t n_views, int64_t capacity, bool depth_first, PreprocessWs* out) {
+    PreprocessWs p{};
+    p.total = n * n_views;
+    const int64_t ents = std::max<int64_t>(p.total, 1);
+    p.emit_blocks = std::max<int64_t>((capacity + kEmitPairs - 1) / kEmitPairs, 1);
     char* base = static_cast<char*>(ws);
-    p.scan_status = reinterpret_cast<uint64_t*>(base);
-    base += align_up(size_t(std::max<int64_t>(p.n_blocks, 1)) * sizeof(uint64_t));
-    p.ticket = reinterpret_cast<uint32_t*>(base);
-    return p;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        char* ptr = base ? base + off : nullptr;
+        off += align_up(bytes);
+        return ptr;
+    };
+    p.d_nvis = reinterpret_cast<int64_t*>(take(16));
+    p.partials_a = reinterpret_cast<uint64_t*>(take(size_t(scan_blocks(ents)) * 8));
+    p.partials_b = reinterpret_cast<uint64_t*>(take(size_t(scan_blocks(ents)) * 8));
+    p.list_a = reinterpret_cast<uint32_t*>(take(size_t(ents) * 4));
+    p.offsets = reinterpret_cast<uint32_t*>(take(size_t(ents) * 4));
+    p.first_entry = reinterpret_cast<uint32_t*>(take(size_t(p.emit_blocks) * 4));
+    if (depth_first) {
+        p.list_b = reinterpret_cast<uint32_t*>(take(size_t(ents) * 4));
+        p.dkey_a = reinterpret_cast<uint64_t*>(take(size_t(ents) * 8));
+        p.dkey_b = reinterpret_cast<uint64_t*>(take(size_t(ents) * 8));
+        p.sort_ws = take(sort_workspace(ents, 0, 31, 8));
+    }
+    if (out) *out = p;
+    return off;
 }
 
 template <int DEG>
 __global__ __launch_bounds__(kPreThreads) void k_preprocess(GaussPtrs g, const ws_camera* __restrict__ cams, KOpts o,
                                                            ws_splat* __restrict__ splats,
-                                                           uint32_t* __restrict__ tiles_touched, PreprocessWs pw) {
+                                                           uint32_t* __restrict__ tiles_touched) {
     const int32_t v = blockIdx.y;
     const int64_t i = int64_t(blockIdx.x) * kPreThreads + threadIdx.x;
-    // clear the emission look-back state for the kernel that follows
-    const int64_t flat = (int64_t(blockIdx.y) * gridDim.x + blockIdx.x) * kPreThreads + threadIdx.x;
-    if (flat < (pw.n_blocks > 0 ? pw.n_blocks : 1)) pw.scan_status[flat] = 0;
-    if (flat == 0) *pw.ticket = 0;
     if (i >= g.n) return;
     const ws_camera& cam = cams[v];
     ProjState st;
@@ -65,186 +94,211 @@ __global__ __launch_bounds__(kPreThreads) void k_preprocess(GaussPtrs g, const w
     rec[2] = make_float4(st.rgb[2], st.z32, __uint_as_float(r01), __uint_as_float(r23));
 }
 
-struct EmitArgs {
+// ---- compaction: prefix sum of the visibility flags
+struct FlagLoad {
     const uint32_t* tiles_touched;
+    __device__ uint64_t operator()(int64_t i) const { return tiles_touched[i] != 0u ? 1u : 0u; }
+};
+struct CompactStore {
+    const ws_splat* splats;
+    uint32_t* list;
+    uint64_t* dkeys;  // null unless depth-first
+    __device__ void operator()(int64_t i, uint64_t pos, uint64_t flag) const {
+        if (!flag) return;
+        list[pos] = uint32_t(i);
+        if (dkeys) dkeys[pos] = __float_as_uint(reinterpret_cast<const float*>(splats + i)[9]);
+    }
+};
+
+// ---- counts: prefix sum of the listed entries' tile counts
+struct CountLoad {
+    const uint32_t* tiles_touched;
+    const uint32_t* list;
+    __device__ uint64_t operator()(int64_t e) const { return tiles_touched[list[e]]; }
+};
+struct CountStore {
+    uint32_t* offsets;
+    uint32_t* first_entry;
+    int64_t emit_blocks;
+    __device__ void operator()(int64_t e, uint64_t s, uint64_t cnt) const {
+        offsets[e] = uint32_t(s);
+        if (cnt == 0) return;
+        // every output block whose first pair falls inside [s, s + cnt) starts in entry e
+        const uint64_t b_lo = (s + kEmitPairs - 1) / kEmitPairs;
+        const uint64_t b_hi = (s + cnt - 1) / kEmitPairs;
+        for (uint64_t b = b_lo; b <= b_hi && int64_t(b) < emit_blocks; ++b) first_entry[b] = uint32_t(e);
+    }
+};
+
+struct EmitArgs {
     const ws_splat* splats;
     const ws_camera* cams;
-    int32_t n_views;
+    const uint32_t* list;
+    const uint32_t* offsets;
+    const uint32_t* first_entry;
+    const int64_t* d_nvis;
+    const int64_t* d_num_pairs;
+    int32_t* d_status;
     int64_t n;
-    int64_t total;  // n * n_views
+    int64_t capacity;
     int32_t tile_w, tile_h;
     uint64_t* keys;
     uint32_t* values;
-    int64_t capacity;
-    int64_t* d_num_pairs;
-    int32_t* d_status;
-    int64_t n_launched;  // number of emission blocks launched (>= 1)
 };
 
-__global__ __launch_bounds__(kScanThreads) void k_scan_emit(EmitArgs a, PreprocessWs pw) {
-    __shared__ uint32_t s_block;
-    __shared__ uint64_t s_excl;
-    __shared__ uint32_t s_scan[kScanThreads / kWave + 1];
-    __shared__ uint32_t s_incl[kScanTile];   // inclusive prefix of pair counts inside the block
-    __shared__ uint32_t s_gid[kScanTile];    // Gaussian id
-    __shared__ uint32_t s_depth[kScanTile];  // fp32 depth bits
-    __shared__ uint32_t s_trect[kScanTile * 2];  // tile rect (tx0 | tx1 << 16, ty0 | ty1 << 16)
-    __shared__ uint32_t s_tbase[kScanTile];  // tile id offset of the entry's view
-    __shared__ uint32_t s_tilesx[kScanTile];
-
-    if (threadIdx.x == 0) s_block = atomicAdd(pw.ticket, 1u);
+__global__ __launch_bounds__(kEmitThreads) void k_emit(EmitArgs a) {
+    __shared__ uint32_t s_owner[kEmitPairs];
+    __shared__ uint32_t s_start[kEmitSlots];
+    __shared__ uint32_t s_gid[kEmitSlots];
+    __shared__ uint32_t s_depth[kEmitSlots];
+    __shared__ uint32_t s_trx[kEmitSlots];
+    __shared__ uint32_t s_try[kEmitSlots];
+    __shared__ uint32_t s_tbase[kEmitSlots];
+    __shared__ uint32_t s_tilesx[kEmitSlots];
+    __shared__ uint32_t s_scan[kEmitThreads / kWave + 1];
+    if (*a.d_status != 0) return;
+    const int64_t m = *a.d_num_pairs;
+    if (m > a.capacity) {  // the caller's buffers are too small: report, write nothing
+        if (blockIdx.x == 0 && threadIdx.x == 0) atomicMax(a.d_status, int32_t(WS_ERR_CAPACITY));
+        return;
+    }
+    const int64_t p0 = int64_t(blockIdx.x) * kEmitPairs;
+    if (p0 >= m) return;
+    const int64_t p1 = min(p0 + kEmitPairs, m);
+    const int64_t nvis = *a.d_nvis;
+    const int64_t e0 = a.first_entry[blockIdx.x];
+    for (int q = threadIdx.x; q < kEmitPairs; q += kEmitThreads) s_owner[q] = 0;
     __syncthreads();
-    const int64_t blk = s_block;
-    const int64_t base = blk * kScanTile;
-    // blocked arrangement: thread t owns entries base + 4t .. 4t + 3
-    uint32_t cnt[kScanItems];
-    uint32_t sum = 0;
-#pragma unroll
-    for (int j = 0; j < kScanItems; ++j) {
-        const int64_t idx = base + threadIdx.x * kScanItems + j;
-        cnt[j] = idx < a.total ? a.tiles_touched[idx] : 0u;
-        sum += cnt[j];
-    }
-    uint32_t block_total;
-    const uint32_t texcl = block_exclusive_scan<kScanThreads>(sum, s_scan, &block_total);
-
-    // ---- decoupled look-back over the preceding blocks (wave 0)
-    if (threadIdx.x < kWave) {
-        const uint32_t lane = threadIdx.x;
-        uint64_t excl = 0;
-        if (blk == 0) {
-            if (lane == 0) store_agent(&pw.scan_status[0], kFlagInc | block_total);
-        } else {
-            if (lane == 0) store_agent(&pw.scan_status[blk], kFlagAgg | block_total);
-            int64_t look = blk - 1;
-            uint32_t spins = 0;
-            bool failed = false;
-            while (true) {
-                const int64_t idx = look - int64_t(lane);
-                uint64_t s = idx >= 0 ? load_agent(&pw.scan_status[idx]) : kFlagInc;
-                while (__ballot((s >> 62) == 0) != 0) {
-                    if (++spins > kSpinLimit) { failed = true; break; }
-                    __builtin_amdgcn_s_sleep(1);
-                    if ((s >> 62) == 0) s = load_agent(&pw.scan_status[idx]);
-                }
-                if (failed) break;
-                const uint64_t inc_mask = __ballot((s >> 62) == 2);
-                if (inc_mask != 0) {
-                    const uint32_t first = __builtin_ctzll(inc_mask);
-                    const uint64_t part = lane <= first ? (s & kValueMask) : 0ull;
-                    excl += wave_sum(part);
-                    break;
-                }
-                excl += wave_sum(s & kValueMask);
-                look -= kWave;
-            }
-            if (failed) {
-                if (lane == 0) atomicExch(a.d_status, int32_t(WS_ERR_SPIN_LIMIT));
-                excl = 0;
-            }
-            if (lane == 0) store_agent(&pw.scan_status[blk], kFlagInc | (excl + block_total));
-        }
-        if (lane == 0) s_excl = excl;
-    }
-    // ---- per-entry data for the emission
-    uint32_t run = texcl;
-#pragma unroll
-    for (int j = 0; j < kScanItems; ++j) {
-        const int e = threadIdx.x * kScanItems + j;
-        const int64_t idx = base + e;
-        run += cnt[j];
-        s_incl[e] = run;
-        if (cnt[j] != 0) {
-            const int64_t view = idx / a.n;
-            const int64_t gid = idx - view * a.n;
+    // entries e0, e0 + 1, ... until one starts at or after p1
+    for (int chunk = 0; chunk * kEmitThreads < kEmitSlots; ++chunk) {
+        const int slot = chunk * kEmitThreads + threadIdx.x;
+        const int64_t e = e0 + slot;
+        const bool in = slot < kEmitSlots && e < nvis && int64_t(a.offsets[e]) < p1;
+        if (in) {
+            const uint32_t start = a.offsets[e];
+            const uint32_t idx = a.list[e];
+            const int64_t view = int64_t(idx) / a.n;
             const float4 r2 = reinterpret_cast<const float4*>(a.splats + idx)[2];
             const uint32_t r01 = __float_as_uint(r2.z), r23 = __float_as_uint(r2.w);
-            const uint32_t tx0 = (r01 & 0xffffu) / uint32_t(a.tile_w), tx1 = (r01 >> 16) / uint32_t(a.tile_w);
-            const uint32_t ty0 = (r23 & 0xffffu) / uint32_t(a.tile_h), ty1 = (r23 >> 16) / uint32_t(a.tile_h);
             int64_t toff, ioff;
             view_offsets(a.cams, int32_t(view), a.tile_w, a.tile_h, &toff, &ioff);
-            s_gid[e] = uint32_t(gid);
-            s_depth[e] = __float_as_uint(r2.y);
-            s_trect[2 * e] = tx0 | (tx1 << 16);
-            s_trect[2 * e + 1] = ty0 | (ty1 << 16);
-            s_tbase[e] = uint32_t(toff);
-            s_tilesx[e] = uint32_t(ceil_div(a.cams[view].width, a.tile_w));
+            s_start[slot] = start;
+            s_gid[slot] = uint32_t(int64_t(idx) - view * a.n);
+            s_depth[slot] = __float_as_uint(r2.y);
+            s_trx[slot] = ((r01 & 0xffffu) / uint32_t(a.tile_w)) | (((r01 >> 16) / uint32_t(a.tile_w)) << 16);
+            s_try[slot] = ((r23 & 0xffffu) / uint32_t(a.tile_h)) | (((r23 >> 16) / uint32_t(a.tile_h)) << 16);
+            s_tbase[slot] = uint32_t(toff);
+            s_tilesx[slot] = uint32_t(ceil_div(a.cams[view].width, a.tile_w));
+            if (slot > 0) s_owner[int64_t(start) - p0] = uint32_t(slot);
         }
+        // continue while the last slot of this chunk still starts before p1
+        const bool more = __syncthreads_or(in && threadIdx.x == kEmitThreads - 1);
+        if (!more) break;
     }
     __syncthreads();
-    const uint64_t excl = s_excl;
-    if (blk == a.n_launched - 1 && threadIdx.x == 0) {
-        const uint64_t m = excl + block_total;
-        *a.d_num_pairs = int64_t(m);
-        if (int64_t(m) > a.capacity) atomicMax(a.d_status, int32_t(WS_ERR_CAPACITY));
+    // owner of pair q = the largest slot that starts at or before q (slot 0 holds p0)
+    uint32_t own[kEmitItems];
+    uint32_t run = 0;
+#pragma unroll
+    for (int j = 0; j < kEmitItems; ++j) {
+        run = max(run, s_owner[threadIdx.x * kEmitItems + j]);
+        own[j] = run;
     }
-    // ---- emission: pair j of this block belongs to the first entry e with s_incl[e] > j
-    for (uint32_t j = threadIdx.x; j < block_total; j += kScanThreads) {
-        int lo = 0, hi = kScanTile - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if (s_incl[mid] > j) hi = mid; else lo = mid + 1;
+    // exclusive max-scan of the threads' last owners
+    {
+        uint32_t v = run;
+        const uint32_t lane = lane_id();
+#pragma unroll
+        for (int d = 1; d < kWave; d <<= 1) {
+            const uint32_t o = __shfl_up(v, d, kWave);
+            if (lane >= uint32_t(d)) v = max(v, o);
         }
-        const int e = lo;
-        const uint32_t start = e > 0 ? s_incl[e - 1] : 0u;
-        const uint32_t k = j - start;
-        const uint32_t xr = s_trect[2 * e], yr = s_trect[2 * e + 1];
-        const uint32_t tx0 = xr & 0xffffu, tx1 = xr >> 16, ty0 = yr & 0xffffu;
-        const uint32_t w = tx1 - tx0 + 1;
-        const uint32_t row = k / w, col = k - row * w;
-        const uint64_t tile = uint64_t(s_tbase[e]) + uint64_t(ty0 + row) * s_tilesx[e] + (tx0 + col);
-        const uint64_t pos = excl + j;
-        if (int64_t(pos) < a.capacity) {
-            a.keys[pos] = (tile << 32) | s_depth[e];
-            a.values[pos] = s_gid[e];
+        const int wave = threadIdx.x / kWave;
+        if (lane == kWave - 1) s_scan[wave] = v;
+        __syncthreads();
+        uint32_t before = 0;
+        for (int w = 0; w < wave; ++w) before = max(before, s_scan[w]);
+        const uint32_t prev = __shfl_up(v, 1, kWave);
+        if (lane > 0) before = max(before, prev);
+#pragma unroll
+        for (int j = 0; j < kEmitItems; ++j) own[j] = max(own[j], before);
+    }
+#pragma unroll
+    for (int j = 0; j < kEmitItems; ++j) {
+        const int64_t p = p0 + threadIdx.x * kEmitItems + j;
+        if (p < p1) {
+            const uint32_t s = own[j];
+            const uint32_t k = uint32_t(p - int64_t(s_start[s]));
+            const uint32_t xr = s_trx[s], yr = s_try[s];
+            const uint32_t tx0 = xr & 0xffffu, tx1 = xr >> 16, ty0 = yr & 0xffffu;
+            const uint32_t w = tx1 - tx0 + 1;
+            const uint32_t row = k / w, col = k - row * w;
+            const uint64_t tile = uint64_t(s_tbase[s]) + uint64_t(ty0 + row) * s_tilesx[s] + (tx0 + col);
+            a.keys[p] = (tile << 32) | s_depth[s];
+            a.values[p] = s_gid[s];
         }
     }
 }
 
 }  // namespace
 
-size_t preprocess_workspace(int64_t n, int32_t n_views) {
-    const int64_t blocks = std::max<int64_t>((n * n_views + kScanTile - 1) / kScanTile, 1);
-    return align_up(size_t(blocks) * sizeof(uint64_t)) + align_up(sizeof(uint32_t) * 4);
+size_t preprocess_workspace(int64_t n, int32_t n_views, int64_t capacity, uint32_t flags) {
+    return layout(nullptr, n, n_views, capacity, (flags & WS_FLAG_DEPTH_FIRST) != 0, nullptr);
 }
 
 hipError_t launch_preprocess(const GaussPtrs& g, const ws_camera* d_cams, int32_t n_views, const KOpts& o,
                              ws_splat* splats, uint32_t* tiles_touched, uint64_t* keys, uint32_t* values,
                              int64_t capacity, int64_t* d_num_pairs, int32_t* d_status, void* ws,
                              hipStream_t stream) {
-    PreprocessWs pw = carve(ws, g.n, n_views);
-    const int64_t total = g.n * n_views;
+    const bool depth_first = (o.flags & WS_FLAG_DEPTH_FIRST) != 0;
+    PreprocessWs pw;
+    layout(ws, g.n, n_views, capacity, depth_first, &pw);
     const uint32_t gx = uint32_t(std::max<int64_t>((g.n + kPreThreads - 1) / kPreThreads, 1));
     timing_begin(WS_KERNEL_PREPROCESS, stream);
     switch (o.sh_degree) {
         case 0: hipLaunchKernelGGL(k_preprocess<0>, dim3(gx, n_views), dim3(kPreThreads), 0, stream, g, d_cams, o,
-                                   splats, tiles_touched, pw); break;
+                                   splats, tiles_touched); break;
         case 1: hipLaunchKernelGGL(k_preprocess<1>, dim3(gx, n_views), dim3(kPreThreads), 0, stream, g, d_cams, o,
-                                   splats, tiles_touched, pw); break;
+                                   splats, tiles_touched); break;
         case 2: hipLaunchKernelGGL(k_preprocess<2>, dim3(gx, n_views), dim3(kPreThreads), 0, stream, g, d_cams, o,
-                                   splats, tiles_touched, pw); break;
+                                   splats, tiles_touched); break;
         default: hipLaunchKernelGGL(k_preprocess<3>, dim3(gx, n_views), dim3(kPreThreads), 0, stream, g, d_cams, o,
-                                    splats, tiles_touched, pw); break;
+                                    splats, tiles_touched); break;
     }
     timing_end(WS_KERNEL_PREPROCESS, stream);
-    EmitArgs a;
-    a.tiles_touched = tiles_touched;
-    a.splats = splats;
-    a.cams = d_cams;
-    a.n_views = n_views;
-    a.n = std::max<int64_t>(g.n, 1);
-    a.total = total;
-    a.tile_w = o.tile_w;
-    a.tile_h = o.tile_h;
-    a.keys = keys;
-    a.values = values;
-    a.capacity = capacity;
-    a.d_num_pairs = d_num_pairs;
-    a.d_status = d_status;
-    const uint32_t blocks = uint32_t(std::max<int64_t>(pw.n_blocks, 1));
-    a.n_launched = blocks;  // with no Gaussians one block still reports M = 0
+
     timing_begin(WS_KERNEL_SCAN_EMIT, stream);
-    hipLaunchKernelGGL(k_scan_emit, dim3(blocks), dim3(kScanThreads), 0, stream, a, pw);
+    // compaction of the visible entries (count to d_nvis)
+    launch_scan<uint64_t>(FlagLoad{tiles_touched}, CompactStore{splats, pw.list_a, depth_first ? pw.dkey_a : nullptr},
+                          pw.total, nullptr, d_status, pw.partials_a, reinterpret_cast<uint64_t*>(pw.d_nvis), stream);
+    const uint32_t* list = pw.list_a;
+    if (depth_first) {
+        // stable sort of the visible entries by depth: positive fp32 bits order like the values
+        const hipError_t e = launch_sort(pw.dkey_a, pw.list_a, pw.dkey_b, pw.list_b, std::max<int64_t>(pw.total, 1),
+                                         pw.d_nvis, d_status, 0, 31, 8, pw.sort_ws, stream, false);
+        if (e != hipSuccess) return e;
+        list = pw.list_b;
+    }
+    // pair offsets of the listed entries (total to d_num_pairs)
+    launch_scan<uint64_t>(CountLoad{tiles_touched, list}, CountStore{pw.offsets, pw.first_entry, pw.emit_blocks},
+                          std::max<int64_t>(pw.total, 1), pw.d_nvis, d_status, pw.partials_b,
+                          reinterpret_cast<uint64_t*>(d_num_pairs), stream);
+    EmitArgs ea;
+    ea.splats = splats;
+    ea.cams = d_cams;
+    ea.list = list;
+    ea.offsets = pw.offsets;
+    ea.first_entry = pw.first_entry;
+    ea.d_nvis = pw.d_nvis;
+    ea.d_num_pairs = d_num_pairs;
+    ea.d_status = d_status;
+    ea.n = std::max<int64_t>(g.n, 1);
+    ea.capacity = capacity;
+    ea.tile_w = o.tile_w;
+    ea.tile_h = o.tile_h;
+    ea.keys = keys;
+    ea.values = values;
+    hipLaunchKernelGGL(k_emit, dim3(uint32_t(pw.emit_blocks)), dim3(kEmitThreads), 0, stream, ea);
     timing_end(WS_KERNEL_SCAN_EMIT, stream);
     return hipGetLastError();
 }

@@ -143,12 +143,14 @@ hipError_t launch_preprocess(const GaussPtrs& g, const ws_camera* d_cams, int32_
                              ws_splat* splats, uint32_t* tiles_touched, uint64_t* keys, uint32_t* values,
                              int64_t capacity, int64_t* d_num_pairs, int32_t* d_status, void* ws,
                              hipStream_t stream);
-size_t preprocess_workspace(int64_t n, int32_t n_views);
+size_t preprocess_workspace(int64_t n, int32_t n_views, int64_t capacity, uint32_t flags);
 
 // sort.hip
+// `timed`: report the launches to the benchmark timing hooks (false for sorts
+// made inside another stage, which that stage's timing already covers).
 hipError_t launch_sort(const uint64_t* kin, const uint32_t* vin, uint64_t* kout, uint32_t* vout, int64_t n,
                        const int64_t* d_n, const int32_t* d_status, int32_t begin_bit, int32_t end_bit,
-                       int32_t radix_bits, void* ws, hipStream_t stream);
+                       int32_t radix_bits, void* ws, hipStream_t stream, bool timed = true);
 size_t sort_workspace(int64_t capacity, int32_t begin_bit, int32_t end_bit, int32_t radix_bits);
 
 // render.hip

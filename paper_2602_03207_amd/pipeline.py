@@ -128,7 +128,7 @@ class Renderer:
     # ----------------------------------------------------------- stages
     def preprocess(self, g: GaussianTensors, stream=None):
         self._ensure_n(g.n)
-        need = B.ws_preprocess_workspace_size(g.n, self.n_views)
+        need = B.ws_preprocess_workspace_size(g.n, self.n_views, self.capacity, self.opts.flags)
         ws = self.ws_pre.get(need)
         B.ws_preprocess(g.struct(), self.cam_arr, self.d_cams, self.n_views, self.opts, self.splats,
                         self.tiles_touched, self.keys_a, self.vals_a, self.capacity, self.d_num_pairs, self.d_status,
@@ -137,11 +137,17 @@ class Renderer:
     def sort(self, n_pairs, device_count=False, stream=None, radix_bits=None):
         rb = self.opts.radix_bits if radix_bits is None else radix_bits
         cap = self.capacity if device_count else n_pairs
-        need = B.ws_sort_workspace_size(max(cap, 1), 0, self.end_bit, rb)
+        begin = self.begin_bit
+        need = B.ws_sort_workspace_size(max(cap, 1), begin, self.end_bit, rb)
         ws = self.ws_sort.get(need)
         B.ws_sort(self.keys_a, self.vals_a, self.keys_b, self.vals_b, cap,
-                  self.d_num_pairs if device_count else None, self.d_status, 0, self.end_bit, rb, ws, ws.numel(),
+                  self.d_num_pairs if device_count else None, self.d_status, begin, self.end_bit, rb, ws, ws.numel(),
                   stream)
+
+    @property
+    def begin_bit(self) -> int:
+        """Pairs emitted in depth order only need their tile bits sorted (stable)."""
+        return 32 if (self.opts.flags & B.WS_FLAG_DEPTH_FIRST) else 0
 
     def render(self, cap, stream=None):
         need = B.ws_render_workspace_size(self.cam_arr, self.n_views, self.opts)

@@ -100,7 +100,9 @@ def test_autograd_function_matches_backward_call():
     assert torch.equal(r2.images, img.detach())
     ref = r2.backward(g, w)
     for k, p in zip(NAMES, params):
-        assert torch.allclose(p.grad, ref[k], rtol=1e-5, atol=1e-7), k
+        # the two backward calls differ only in the order of their floating-point atomic additions
+        rms = ref[k].double().pow(2).mean().sqrt().item()
+        assert torch.allclose(p.grad, ref[k], rtol=1e-4, atol=1e-5 * rms), k
 
 
 def test_batched_graph_equals_plain_and_replays_consistently():

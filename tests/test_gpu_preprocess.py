@@ -146,3 +146,46 @@ def test_multiview_tile_offsets():
     assert m == keys.size
     assert np.array_equal(r.keys_a[:m].cpu().numpy().view(np.uint64), keys)
     assert np.array_equal(r.vals_a[:m].cpu().numpy().view(np.uint32), np.concatenate(all_v))
+
+
+def _depth_first_reference(keys, vals, n_views_n=None):
+    """Oracle pairs regrouped per entry and ordered by (fp32 depth bits, entry order)."""
+    # pairs of one entry are contiguous in the oracle's emission; the entry's depth is the key's low word
+    starts = np.flatnonzero(np.r_[True, (vals[1:] != vals[:-1]) | ((keys[1:] >> np.uint64(32)) < (keys[:-1] >> np.uint64(32)))])
+    ends = np.r_[starts[1:], vals.size]
+    depth = (keys[starts] & np.uint64(0xFFFFFFFF)).astype(np.uint64)
+    order = np.argsort(depth, kind="stable")
+    idx = np.concatenate([np.arange(starts[o], ends[o]) for o in order]) if order.size else np.zeros(0, np.int64)
+    return keys[idx], vals[idx]
+
+
+def test_depth_first_emission_order_and_sorted_keys():
+    import torch
+    from paper_2602_03207_amd import binding as B
+    scene, cam = scenegen.c1()
+    r = _run(scene, [cam], flags=B.WS_FLAG_DEPTH_FIRST)
+    ropts = oracle_options()
+    keys, vals = oracle.emit(scene, cam, ropts)
+    m = r.num_pairs
+    assert m == keys.size
+    wk, wv = _depth_first_reference(keys, vals)
+    gk = r.keys_a[:m].cpu().numpy().view(np.uint64)
+    gv = r.vals_a[:m].cpu().numpy().view(np.uint32)
+    assert np.array_equal(gv, wv) and np.array_equal(gk, wk)
+    # sorting the tile bits alone gives the oracle's full stable sort
+    sk, sv = oracle.stable_sort(keys, vals)
+    assert np.array_equal(r.keys_b[:m].cpu().numpy().view(np.uint64), sk)
+    assert np.array_equal(r.vals_b[:m].cpu().numpy().view(np.uint32), sv)
+
+
+def test_depth_first_multiview_sorted_keys_match():
+    from paper_2602_03207_amd import binding as B
+    scene = scenegen.random_scene(6000, 12, log_scale_mu=-3.2, sh_degree=1, dc_sd=0.4, rest_sd=0.2)
+    cams = [scenegen.look_at([0, 0, -3], [0, 0, 0], 100, 80), scenegen.look_at([2, -1, -2], [0, 0, 0], 64, 120)]
+    a = _run(scene, cams)
+    b = _run(scene, cams, flags=B.WS_FLAG_DEPTH_FIRST)
+    assert a.num_pairs == b.num_pairs
+    m = a.num_pairs
+    assert np.array_equal(a.keys_b[:m].cpu().numpy(), b.keys_b[:m].cpu().numpy())
+    assert np.array_equal(a.vals_b[:m].cpu().numpy(), b.vals_b[:m].cpu().numpy())
+    assert np.array_equal(a.images.cpu().numpy().view(np.uint32), b.images.cpu().numpy().view(np.uint32))

@@ -88,21 +88,26 @@ def test_render_background_and_empty_scene():
 
 
 @pytest.mark.slow
-def test_render_end_to_end_c2():
+@pytest.mark.parametrize("depth_first", [False, True])
+def test_render_end_to_end_c2(depth_first):
+    from paper_2602_03207_amd import binding as B
     scene, cam = scenegen.c2()
-    r = _full(scene, [cam])
+    r = _full(scene, [cam], flags=B.WS_FLAG_DEPTH_FIRST if depth_first else 0)
     ref = oracle.render(scene, cam, oracle_options(sh_degree=3))
     worst, frac = assert_image_parity(r.image(0).cpu().numpy(), ref)
     print(f"C2: worst {worst:.2e}, flagged {frac:.2e}, M gpu {r.num_pairs} oracle {ref['keys'].size}")
 
 
-def test_invariance_tile_size_and_radix_width():
+def test_invariance_tile_size_radix_width_and_emission_order():
+    from paper_2602_03207_amd import binding as B
     scene, cam = scenegen.c1()
     base = _full(scene, [cam]).image(0).cpu().numpy()
-    for tile in ((8, 8), (16, 8), (32, 16)):
+    for tile in ((8, 8), (16, 8), (16, 16), (32, 16)):
         for rb in (4, 8):
-            img = _full(scene, [cam], tile_w=tile[0], tile_h=tile[1], radix_bits=rb).image(0).cpu().numpy()
-            assert np.array_equal(img.view(np.uint32), base.view(np.uint32)), (tile, rb)
+            for flags in (0, B.WS_FLAG_DEPTH_FIRST):
+                img = _full(scene, [cam], tile_w=tile[0], tile_h=tile[1], radix_bits=rb,
+                            flags=flags).image(0).cpu().numpy()
+                assert np.array_equal(img.view(np.uint32), base.view(np.uint32)), (tile, rb, flags)
 
 
 def test_invariance_repeat_and_permutation():
