@@ -90,12 +90,7 @@ __global__ __launch_bounds__(TW * TH) void k_render_bwd(BwdArgs a) {
             s_batch[threadIdx.x] = id < uint64_t(a.n) ? stage_splat(vsplats, id) : empty_splat();
         }
         __syncthreads();
-        const int cnt = int(min<uint32_t>(NT, end - b0));
-        if (!ps.done) {
-            for (int j = 0; j < cnt; ++j) {
-                if (ps.step(s_batch[j], a.o)) break;
-            }
-        }
+        composite_batch(ps, s_batch, int(min<uint32_t>(NT, end - b0)), int32_t(b0 - start), a.o);
     }
     __syncthreads();
     if (ps.last >= 0) atomicMax(&s_maxlast, ps.last);
@@ -138,7 +133,7 @@ __global__ __launch_bounds__(TW * TH) void k_render_bwd(BwdArgs a) {
 #pragma unroll
             for (int k = 0; k < kNG; ++k) gv[k] = 0.f;
             bool contrib = false;
-            if (j <= last && in_rect(s, px, py)) {
+            if (j <= last && in_rect(s, ps.pxy)) {
                 const float dx = s.u - pcx, dy = s.v - pcy;
                 float G;
                 const float araw = raw_alpha(s, dx, dy, &G);

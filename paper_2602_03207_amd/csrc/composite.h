@@ -20,9 +20,15 @@ struct StagedSplat {
     float u, v, qa, qb;    // qa = -log2(e)/2 * A, qb = -log2(e) * B
     float qc, sigma, r, g; // qc = -log2(e)/2 * C
     float b;
-    uint32_t rx, ry;       // x0 | x1 << 16, y0 | y1 << 16 (inclusive pixel rectangle)
+    uint32_t rxy;          // x0 | y0 << 16: first pixel of the inclusive rectangle
+    uint32_t rwh;          // (x1 - x0) | (y1 - y0) << 16
     uint32_t id;           // Gaussian id
 };
+
+// Two 16-bit lanes packed in one register (pixel or rectangle coordinates).
+typedef uint16_t u16x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ uint32_t pack_xy(int x, int y) { return uint32_t(x) | (uint32_t(y) << 16); }
 
 __device__ __forceinline__ StagedSplat stage_splat(const ws_splat* __restrict__ vsplats, uint32_t id) {
     const float4* rec = reinterpret_cast<const float4*>(vsplats + id);
@@ -37,23 +43,33 @@ __device__ __forceinline__ StagedSplat stage_splat(const ws_splat* __restrict__ 
     s.r = r1.z;
     s.g = r1.w;
     s.b = r2.x;
-    s.rx = __float_as_uint(r2.z);
-    s.ry = __float_as_uint(r2.w);
+    const uint32_t rx = __float_as_uint(r2.z), ry = __float_as_uint(r2.w);  // x0 | x1 << 16, y0 | y1 << 16
+    const uint32_t x0 = rx & 0xffffu, x1 = rx >> 16, y0 = ry & 0xffffu, y1 = ry >> 16;
+    if (x1 >= x0 && y1 >= y0) {
+        s.rxy = pack_xy(int(x0), int(y0));
+        s.rwh = pack_xy(int(x1 - x0), int(y1 - y0));
+    } else {
+        s.rxy = 0xffffffffu;  // holds no pixel (coordinates stay below 32768)
+        s.rwh = 0u;
+    }
     s.id = id;
     return s;
 }
 
-// A splat that covers no pixel (x0 > x1): used for out-of-range ids.
+// A splat that covers no pixel: used for out-of-range ids.
 __device__ __forceinline__ StagedSplat empty_splat() {
     StagedSplat s{};
-    s.rx = 1u;  // x0 = 1, x1 = 0
-    s.ry = 1u;
+    s.rxy = 0xffffffffu;
+    s.rwh = 0u;
     return s;
 }
 
-__device__ __forceinline__ bool in_rect(const StagedSplat& s, int px, int py) {
-    const uint32_t x0 = s.rx & 0xffffu, x1 = s.rx >> 16, y0 = s.ry & 0xffffu, y1 = s.ry >> 16;
-    return uint32_t(px - int(x0)) <= x1 - x0 && uint32_t(py - int(y0)) <= y1 - y0;
+// Pixel pxy = x | y << 16 inside the splat's rectangle: per 16-bit lane,
+// (p - first) mod 2^16 <= extent; both tests in two packed integer ops.
+__device__ __forceinline__ bool in_rect(const StagedSplat& s, uint32_t pxy) {
+    const u16x2 d = __builtin_bit_cast(u16x2, pxy) - __builtin_bit_cast(u16x2, s.rxy);
+    const u16x2 m = __builtin_elementwise_min(d, __builtin_bit_cast(u16x2, s.rwh));
+    return __builtin_bit_cast(uint32_t, m) == __builtin_bit_cast(uint32_t, d);
 }
 
 // exp(power) for the staged conic; returns sigma * exp(power) (before the clamp).
@@ -96,47 +112,62 @@ __device__ __forceinline__ TileInfo locate_tile(const ws_camera* cams, int32_t n
 }
 
 struct PixelState {
-    int px, py;
+    uint32_t pxy;  // x | y << 16
     float pcx, pcy;
     float T;
     float c[3];
     bool done;
-    int32_t last;   // index (in the tile's list) of the last splat composited, -1 if none
-    int32_t count;  // list entries consumed so far
+    int32_t last;  // index (in the tile's list) of the last splat composited, -1 if none
 
     __device__ __forceinline__ void init(int x, int y, bool finished) {
-        px = x;
-        py = y;
+        pxy = pack_xy(x, y);
         pcx = float(x) + 0.5f;
         pcy = float(y) + 0.5f;
         T = 1.f;
         c[0] = c[1] = c[2] = 0.f;
         done = finished;
         last = -1;
-        count = 0;
-    }
-
-    // Composite one splat; returns true once the pixel has stopped.
-    __device__ __forceinline__ bool step(const StagedSplat& s, const KOpts& o) {
-        const int32_t idx = count++;
-        if (!in_rect(s, px, py)) return false;
-        const float dx = s.u - pcx, dy = s.v - pcy;
-        float G;
-        const float alpha = fminf(o.alpha_max, raw_alpha(s, dx, dy, &G));
-        if (alpha < o.alpha_min) return false;
-        const float Tn = T * (1.f - alpha);
-        if (Tn < o.t_min) {
-            done = true;
-            return true;
-        }
-        const float w = alpha * T;
-        c[0] = fmaf(s.r, w, c[0]);
-        c[1] = fmaf(s.g, w, c[1]);
-        c[2] = fmaf(s.b, w, c[2]);
-        T = Tn;
-        last = idx;
-        return false;
     }
 };
+
+// One splat of the list into one pixel, with the decisions of the rule above.
+// Returns true once no lane of the wave is left active.
+__device__ __forceinline__ bool blend_one(PixelState& ps, const StagedSplat& s, int32_t idx, const KOpts& o) {
+    const bool inr = in_rect(s, ps.pxy) & !ps.done;
+    if (__ballot(inr) == 0) return false;  // the whole wave skips this splat
+    const float dx = s.u - ps.pcx, dy = s.v - ps.pcy;
+    float G;
+    const float alpha = fminf(o.alpha_max, raw_alpha(s, dx, dy, &G));
+    const float Tn = ps.T * (1.f - alpha);
+    const bool hit = inr & !(alpha < o.alpha_min);
+    const bool stop = hit & (Tn < o.t_min);
+    const bool take = hit & !stop;
+    const float w = alpha * ps.T;
+    ps.c[0] = take ? fmaf(s.r, w, ps.c[0]) : ps.c[0];
+    ps.c[1] = take ? fmaf(s.g, w, ps.c[1]) : ps.c[1];
+    ps.c[2] = take ? fmaf(s.b, w, ps.c[2]) : ps.c[2];
+    ps.T = take ? Tn : ps.T;
+    ps.last = take ? idx : ps.last;
+    if (__ballot(stop) == 0) return false;
+    ps.done = ps.done | stop;
+    return __ballot(!ps.done) == 0;
+}
+
+// Composites the staged splats batch[0, cnt) (cnt >= 1), whose first entry has
+// index idx0 in the tile's list, front to back.  Two records alternate in
+// registers so that the next one is read from LDS while the current one is
+// blended; the wave leaves once all its lanes have stopped.
+__device__ __forceinline__ void composite_batch(PixelState& ps, const StagedSplat* batch, int cnt, int32_t idx0,
+                                                const KOpts& o) {
+    if (__ballot(!ps.done) == 0) return;
+    StagedSplat s0 = batch[0], s1;
+    int j = 0;
+    while (true) {
+        s1 = batch[j + 1 < cnt ? j + 1 : j];
+        if (blend_one(ps, s0, idx0 + j, o) || ++j >= cnt) return;
+        s0 = batch[j + 1 < cnt ? j + 1 : j];
+        if (blend_one(ps, s1, idx0 + j, o) || ++j >= cnt) return;
+    }
+}
 
 }  // namespace ws

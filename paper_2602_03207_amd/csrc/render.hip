@@ -71,12 +71,7 @@ __global__ __launch_bounds__(TW * TH) void k_render(RenderArgs a) {
             s_batch[threadIdx.x] = id < uint64_t(a.n) ? stage_splat(vsplats, id) : empty_splat();
         }
         __syncthreads();
-        const int cnt = int(min<uint32_t>(NT, end - b0));
-        if (!ps.done) {
-            for (int j = 0; j < cnt; ++j) {
-                if (ps.step(s_batch[j], a.o)) break;
-            }
-        }
+        composite_batch(ps, s_batch, int(min<uint32_t>(NT, end - b0)), int32_t(b0 - start), a.o);
     }
     if (inside) {
         float* img = a.images + ti.img_off;

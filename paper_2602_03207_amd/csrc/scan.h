@@ -80,30 +80,43 @@ __global__ __launch_bounds__(kPartialThreads) void k_scan_partials(T* partials, 
     if (threadIdx.x == 0 && total_out) *total_out = s_carry;
 }
 
+// Wave-striped: wave w owns items base + w*1024 + j*64 + lane (j < 16), so
+// every load and store of the wave covers 64 consecutive items.
 template <class T, class Loader, class Writer>
 __global__ __launch_bounds__(kScanThreads) void k_scan_down(Loader ld, Writer wr, int64_t cap, const int64_t* d_n,
                                                             const int32_t* d_status, const T* partials) {
-    __shared__ T s_scan[kScanThreads / kWave + 1];
+    constexpr int kPerWave = kScanItemsPerThread * kWave;
+    __shared__ T s_wave[kScanThreads / kWave];
     if (d_status && *d_status != 0) return;
     const int64_t n = scan_count(cap, d_n);
     const int64_t base = int64_t(blockIdx.x) * kScanBlock;
     if (base >= n) return;
-    // blocked: thread t owns items base + 16 t .. base + 16 t + 15 (consecutive)
+    const int wave = threadIdx.x / kWave;
+    const uint32_t lane = lane_id();
+    const int64_t wbase = base + int64_t(wave) * kPerWave + lane;
     T v[kScanItemsPerThread];
-    T sum = 0;
 #pragma unroll
     for (int j = 0; j < kScanItemsPerThread; ++j) {
-        const int64_t i = base + int64_t(threadIdx.x) * kScanItemsPerThread + j;
+        const int64_t i = wbase + j * kWave;
         v[j] = i < n ? ld(i) : T(0);
-        sum += v[j];
     }
-    T tot;
-    T run = block_exclusive_scan<kScanThreads>(sum, s_scan, &tot) + partials[blockIdx.x];
+    // exclusive prefix of each item inside the wave's run of 1024
+    T ex[kScanItemsPerThread];
+    T carry = 0;
 #pragma unroll
     for (int j = 0; j < kScanItemsPerThread; ++j) {
-        const int64_t i = base + int64_t(threadIdx.x) * kScanItemsPerThread + j;
-        if (i < n) wr(i, run, v[j]);
-        run += v[j];
+        const T inc = wave_inclusive_scan(v[j]);
+        ex[j] = carry + inc - v[j];
+        carry += __shfl(inc, kWave - 1, kWave);
+    }
+    if (lane == 0) s_wave[wave] = carry;
+    __syncthreads();
+    T off = partials[blockIdx.x];
+    for (int w = 0; w < wave; ++w) off += s_wave[w];
+#pragma unroll
+    for (int j = 0; j < kScanItemsPerThread; ++j) {
+        const int64_t i = wbase + j * kWave;
+        if (i < n) wr(i, off + ex[j], v[j]);
     }
 }
 

@@ -6,24 +6,28 @@
 //   rank_local  rank among equal digits inside the tile, in input order,
 //               which makes the sort stable.
 // rank_local comes from wave64 ballots (a wave matches its lanes' digits bit
-// by bit) and per-wave digit counters in LDS; the tile is reordered by digit
-// in LDS so that global writes are runs of consecutive addresses.  A tile is
-// 4096 pairs (256 threads x 16).
+// by bit, the bit count of the pass fixed at compile time) and per-wave digit
+// counters in LDS; the tile is reordered by digit in LDS, keys first and then
+// values through the same buffer, so that global writes are runs of
+// consecutive addresses.  A tile is 256 threads x ITEMS pairs: 4096 pairs for
+// large inputs, 1024 for small ones so that they still spread over the CUs.
 //
 // Two schedules compute base_d + prefix_wg; they give identical bits:
-//  * wait-free (large inputs): per pass, k_upsweep counts each tile's digits
-//    into a digit-major table [digit][tile]; one exclusive scan of that table
-//    (the hierarchical scan of scan.h, one dispatch per level) yields
-//    base_d + prefix_wg for every (digit, tile) at once; k_downsweep ranks and
-//    scatters.  No workgroup waits for another: this is the paper's
-//    structure, with the table read as the "indicator stream" of all digits.
-//  * look-back (small inputs, up to kLookbackMaxTiles tiles): base_d from one
+//  * look-back (small inputs, up to kSmallSortMax pairs): base_d from one
 //    histogram of all passes (k_sort_hist), prefix_wg by a decoupled look-back
 //    over per-tile counts published in device memory.  Tiles take an atomic
-//    ticket, so a tile only waits for tiles that have started, and the wait
-//    is bounded (WS_ERR_SPIN_LIMIT on expiry).  One read and one write per
-//    pair and pass, but the ticket serialises at about 12 ns per tile, which
-//    is why large inputs use the wait-free schedule.
+//    ticket, so a tile only waits for tiles that have started, and the wait is
+//    bounded (WS_ERR_SPIN_LIMIT on expiry).  One read and one write per pair
+//    and pass, and one launch per pass.
+//  * wait-free (large inputs, where the ticket's round trip in front of every
+//    tile's loads and the histogram's extra read cost more than they save):
+//    per pass, k_upsweep counts each tile's digits into a digit-major table
+//    [digit][tile]; one exclusive scan of that table (the hierarchical scan of
+//    scan.h) yields base_d + prefix_wg for every (digit, tile) at once;
+//    k_downsweep ranks and scatters.  No workgroup waits for another.  Tiles
+//    are laid out XCD-contiguously, so the table's entries of neighbouring
+//    tiles, and the partly written lines where their digit runs meet, stay in
+//    one L2.
 #include "scan.h"
 #include "ws_internal.h"
 
@@ -32,12 +36,12 @@ namespace {
 
 constexpr int kSortThreads = 256;
 constexpr int kSortWaves = kSortThreads / kWave;
-constexpr int kSortItems = 16;
-constexpr int kSortTile = kSortThreads * kSortItems;  // 4096 pairs per tile
+constexpr int kItemsLarge = 16;              // 4096-pair tiles
+constexpr int kItemsSmall = 4;               // 1024-pair tiles
+constexpr int64_t kSmallSortMax = 1 << 20;   // capacities up to this use small tiles
 constexpr int kHistThreads = 256;
 constexpr int kMaxBins = 2048;  // passes * radix over every radix width
 constexpr int kLook = 16;       // predecessor tiles read at once by the look-back
-constexpr int64_t kLookbackMaxTiles = 256;
 constexpr uint32_t kStAgg = 1u << 30;
 constexpr uint32_t kStInc = 2u << 30;
 constexpr uint32_t kStMask = (1u << 30) - 1;
@@ -51,7 +55,7 @@ struct SortLayout {
     uint32_t* table;     // wait-free: [radix][max_tiles]
     uint32_t* partials;  // wait-free: scan block sums of the table
     int64_t max_tiles;
-    int passes, r, radix;
+    int passes, r, radix, items;
     bool wait_free;
 };
 
@@ -62,8 +66,10 @@ size_t plan(void* ws, int64_t capacity, int begin_bit, int end_bit, int radix_bi
     L.r = default_radix(radix_bits);
     L.radix = 1 << L.r;
     L.passes = (end_bit - begin_bit + L.r - 1) / L.r;
-    L.max_tiles = std::max<int64_t>((capacity + kSortTile - 1) / kSortTile, 1);
-    L.wait_free = L.max_tiles > kLookbackMaxTiles;
+    L.items = capacity <= kSmallSortMax ? kItemsSmall : kItemsLarge;
+    const int64_t tile = int64_t(kSortThreads) * L.items;
+    L.max_tiles = std::max<int64_t>((capacity + tile - 1) / tile, 1);
+    L.wait_free = capacity > kSmallSortMax;
     char* base = static_cast<char*>(ws);
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -96,50 +102,54 @@ __device__ __forceinline__ int64_t device_count(int64_t cap, const int64_t* d_n)
 
 // ------------------------------------------------------- tile ranking
 //
-// Loads tile `tile` (wave-striped: item j of lane l is element
-// base + j*64 + l, so each wave's items are in input order) and computes, for
-// every item, its rank among the equal digits of its wave.  On return
-// s_whist[w][d] holds the exclusive prefix over waves of digit d's count and
-// *cnt_out (threads t < RADIX) the tile's count of digit t.
+// B: digit bits of the pass; ITEMS: pairs per thread.  Item j of lane l in
+// wave w is element tile*TILE + w*ITEMS*64 + j*64 + l, so each wave's items
+// are in input order.
 
-template <int RADIX>
+template <int B, int ITEMS>
 struct TileSmem {
-    uint64_t keys[kSortTile];
-    uint32_t vals[kSortTile];
-    uint32_t whist[kSortWaves][RADIX];
-    uint32_t tile_off[RADIX];
-    uint32_t global[RADIX];
+    static constexpr int kTile = kSortThreads * ITEMS;
+    static constexpr int kRadix = 1 << B;
+    uint64_t buf[kTile];  // reorder buffer: keys, then values (as u32)
+    uint32_t whist[kSortWaves][kRadix];
+    uint32_t tile_off[kRadix];
+    uint32_t global[kRadix];
     uint32_t scan[kSortWaves + 1];
     uint32_t tile;
 };
 
-template <int R>
-__device__ __forceinline__ void load_and_rank(TileSmem<1 << R>& sm, const uint64_t* kin, const uint32_t* vin,
-                                              int64_t n, int64_t tile, int shift, int bits, uint64_t* key,
-                                              uint32_t* val, uint32_t* rank, uint32_t* cnt_out) {
-    constexpr int RADIX = 1 << R;
+template <int B>
+__device__ __forceinline__ uint32_t digit_of(uint64_t k, int shift) {
+    return uint32_t(k >> shift) & ((1u << B) - 1u);
+}
+
+// Loads the tile and computes, for every item, its rank among the equal
+// digits of its wave.  On return whist[w][d] holds the exclusive prefix over
+// waves of digit d's count and *cnt_out (threads t < 2^B) the tile's count of
+// digit t.  whist must be zero on entry.
+template <int B, int ITEMS>
+__device__ __forceinline__ void load_and_rank(TileSmem<B, ITEMS>& sm, const uint64_t* kin, int64_t n, int64_t tile,
+                                              int shift, uint64_t* key, uint32_t* rank, uint32_t* cnt_out) {
+    constexpr int kTile = kSortThreads * ITEMS;
     const int wave = threadIdx.x / kWave;
     const uint32_t lane = lane_id();
-    const uint32_t dmask = (1u << bits) - 1u;
-    const int64_t wbase = tile * kSortTile + int64_t(wave) * (kSortItems * kWave);
+    const int64_t wbase = tile * kTile + int64_t(wave) * (ITEMS * kWave);
 #pragma unroll
-    for (int j = 0; j < kSortItems; ++j) {
+    for (int j = 0; j < ITEMS; ++j) {
         const int64_t idx = wbase + j * kWave + lane;
-        const bool valid = idx < n;
-        key[j] = valid ? kin[idx] : 0ull;
-        val[j] = valid ? vin[idx] : 0u;
+        key[j] = idx < n ? kin[idx] : 0ull;
     }
     // Phase 1: lanes of the wave holding the same digit (matched bit by bit),
     // this lane's rank among them and the group's leader (lowest lane).
     // packed = below | leader << 8 | count << 16.
-    uint32_t packed[kSortItems];
+    uint32_t packed[ITEMS];
 #pragma unroll
-    for (int j = 0; j < kSortItems; ++j) {
-        const int64_t idx = wbase + j * kWave + lane;
-        const bool valid = idx < n;
-        const uint32_t d = uint32_t(key[j] >> shift) & dmask;
+    for (int j = 0; j < ITEMS; ++j) {
+        const bool valid = wbase + j * kWave + lane < n;
+        const uint32_t d = digit_of<B>(key[j], shift);
         uint64_t peers = __ballot(valid);
-        for (int b = 0; b < bits; ++b) {
+#pragma unroll
+        for (int b = 0; b < B; ++b) {
             const bool bit = (d >> b) & 1u;
             const uint64_t m = __ballot(bit);
             peers &= bit ? m : ~m;
@@ -152,16 +162,15 @@ __device__ __forceinline__ void load_and_rank(TileSmem<1 << R>& sm, const uint64
     // Phase 2: each group's leader adds the group size to the wave's digit
     // counter; LDS executes a wave's atomics in issue order, so item j sees the
     // counts of items 0..j-1 and the atomics need not wait for each other.
-    uint32_t old[kSortItems];
+    uint32_t old[ITEMS];
 #pragma unroll
-    for (int j = 0; j < kSortItems; ++j) {
+    for (int j = 0; j < ITEMS; ++j) {
         const uint32_t cnt = packed[j] >> 16;
-        const uint32_t d = uint32_t(key[j] >> shift) & dmask;
-        old[j] = cnt ? atomicAdd(&sm.whist[wave][d], cnt) : 0u;
+        old[j] = cnt ? atomicAdd(&sm.whist[wave][digit_of<B>(key[j], shift)], cnt) : 0u;
     }
     // Phase 3: every lane takes its group's base from the leader.
 #pragma unroll
-    for (int j = 0; j < kSortItems; ++j) {
+    for (int j = 0; j < ITEMS; ++j) {
         const uint32_t leader = (packed[j] >> 8) & 0xffu;
         const uint32_t base = uint32_t(__shfl(int(old[j]), int(leader), kWave));
         rank[j] = base + (packed[j] & 0xffu);
@@ -170,7 +179,7 @@ __device__ __forceinline__ void load_and_rank(TileSmem<1 << R>& sm, const uint64
     // per digit: exclusive prefix over the waves, and the tile's count
     const int t = threadIdx.x;
     uint32_t c = 0;
-    if (t < RADIX) {
+    if (t < (1 << B)) {
 #pragma unroll
         for (int w = 0; w < kSortWaves; ++w) {
             const uint32_t x = sm.whist[w][t];
@@ -181,37 +190,78 @@ __device__ __forceinline__ void load_and_rank(TileSmem<1 << R>& sm, const uint64
     *cnt_out = c;
 }
 
-// Reorders the ranked tile by digit in LDS and writes runs of equal digits
-// to out positions global[d] + (position inside the digit's run).
-template <int R>
-__device__ __forceinline__ void scatter_tile(TileSmem<1 << R>& sm, int64_t n, int64_t tile, int shift, int bits,
-                                             const uint64_t* key, const uint32_t* val, const uint32_t* rank,
-                                             uint64_t* kout, uint32_t* vout) {
+// Reordering of a ranked tile by digit through LDS, so that global writes are
+// runs of consecutive addresses: stage_keys puts each key at its position in
+// the reordered tile (rank becomes that position), flush_tile writes runs of
+// equal digits to global[d] + (position inside the digit's run), keys first
+// and values second through the same buffer.  The values are read only after
+// the keys are staged, which keeps them out of registers during the ranking.
+// Requires tile_off (and for flush_tile global) visible to the workgroup.
+template <int B, int ITEMS>
+__device__ __forceinline__ void stage_keys(TileSmem<B, ITEMS>& sm, int64_t n, int64_t tile, int shift,
+                                           const uint64_t* key, uint32_t* rank) {
+    constexpr int kTile = kSortThreads * ITEMS;
     const int wave = threadIdx.x / kWave;
     const uint32_t lane = lane_id();
-    const uint32_t dmask = (1u << bits) - 1u;
-    const int64_t wbase = tile * kSortTile + int64_t(wave) * (kSortItems * kWave);
+    const int64_t wbase = tile * kTile + int64_t(wave) * (ITEMS * kWave);
 #pragma unroll
-    for (int j = 0; j < kSortItems; ++j) {
+    for (int j = 0; j < ITEMS; ++j) {
+        const uint32_t d = digit_of<B>(key[j], shift);
+        rank[j] += sm.tile_off[d] + sm.whist[wave][d];
+        if (wbase + j * kWave + lane < n) sm.buf[rank[j]] = key[j];
+    }
+}
+
+template <int ITEMS>
+__device__ __forceinline__ void load_vals(const uint32_t* vin, int64_t n, int64_t tile, uint32_t* val) {
+    constexpr int kTile = kSortThreads * ITEMS;
+    const int64_t wbase = tile * kTile + int64_t(threadIdx.x / kWave) * (ITEMS * kWave);
+    const uint32_t lane = lane_id();
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
         const int64_t idx = wbase + j * kWave + lane;
-        if (idx < n) {
-            const uint32_t d = uint32_t(key[j] >> shift) & dmask;
-            const uint32_t pos = sm.tile_off[d] + sm.whist[wave][d] + rank[j];
-            sm.keys[pos] = key[j];
-            sm.vals[pos] = val[j];
+        val[j] = idx < n ? vin[idx] : 0u;
+    }
+}
+
+// Caller synchronises the workgroup between stage_keys and this call.
+template <int B, int ITEMS>
+__device__ __forceinline__ void flush_tile(TileSmem<B, ITEMS>& sm, int64_t n, int64_t tile, int shift,
+                                           const uint32_t* pos, const uint32_t* val, uint64_t* kout,
+                                           uint32_t* vout) {
+    constexpr int kTile = kSortThreads * ITEMS;
+    const int wave = threadIdx.x / kWave;
+    const uint32_t lane = lane_id();
+    const int64_t wbase = tile * kTile + int64_t(wave) * (ITEMS * kWave);
+    const int tile_n = int(min<int64_t>(kTile, n - tile * kTile));
+    uint32_t out[ITEMS];
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+        const int i = threadIdx.x + k * kSortThreads;
+        out[k] = 0xffffffffu;
+        if (i < tile_n) {
+            const uint64_t kk = sm.buf[i];
+            const uint32_t d = digit_of<B>(kk, shift);
+            out[k] = sm.global[d] + uint32_t(i) - sm.tile_off[d];
+            if (int64_t(out[k]) < n) kout[out[k]] = kk;  // always true for consistent counts; guards the write
         }
     }
     __syncthreads();
-    const int tile_n = int(min<int64_t>(kSortTile, n - tile * kSortTile));
-    for (int i = threadIdx.x; i < tile_n; i += kSortThreads) {
-        const uint64_t k = sm.keys[i];
-        const uint32_t d = uint32_t(k >> shift) & dmask;
-        const uint32_t out = sm.global[d] + uint32_t(i) - sm.tile_off[d];
-        if (int64_t(out) < n) {  // always true for consistent counts; guards the write
-            kout[out] = k;
-            vout[out] = sm.vals[i];
-        }
+    uint32_t* vbuf = reinterpret_cast<uint32_t*>(sm.buf);
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j)
+        if (wbase + j * kWave + lane < n) vbuf[pos[j]] = val[j];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < ITEMS; ++k) {
+        const int i = threadIdx.x + k * kSortThreads;
+        if (i < tile_n && int64_t(out[k]) < n) vout[out[k]] = vbuf[i];
     }
+}
+
+template <int B, int ITEMS>
+__device__ __forceinline__ void clear_whist(TileSmem<B, ITEMS>& sm) {
+    for (int i = threadIdx.x; i < kSortWaves * (1 << B); i += kSortThreads) (&sm.whist[0][0])[i] = 0;
 }
 
 // ------------------------------------------------ wait-free schedule
@@ -221,30 +271,38 @@ struct UpArgs {
     int64_t cap;
     const int64_t* d_n;
     const int32_t* d_status;
-    int shift, bits;
+    int shift;
     uint32_t* table;
     int64_t max_tiles;
 };
 
 // Digit counts of one tile into table[d][tile] (zeros for tiles past the end).
-template <int R>
+template <int B, int ITEMS>
 __global__ __launch_bounds__(kSortThreads) void k_upsweep(UpArgs a) {
-    constexpr int RADIX = 1 << R;
+    constexpr int RADIX = 1 << B;
+    constexpr int kTile = kSortThreads * ITEMS;
     __shared__ uint32_t s_h[kSortWaves][RADIX];
     if (a.d_status && *a.d_status != 0) return;
     const int64_t n = device_count(a.cap, a.d_n);
-    const int64_t tile = blockIdx.x;
+    const int64_t ntiles = (n + kTile - 1) / kTile;
+    // live tiles in XCD-contiguous order; the others write their zero counts
+    const int64_t tile = int64_t(blockIdx.x) < ntiles ? int64_t(xcd_contiguous(blockIdx.x, uint32_t(ntiles)))
+                                                       : int64_t(blockIdx.x);
     const int wave = threadIdx.x / kWave;
     for (int i = threadIdx.x; i < kSortWaves * RADIX; i += kSortThreads) (&s_h[0][0])[i] = 0;
     __syncthreads();
-    const uint32_t dmask = (1u << a.bits) - 1u;
-    const int64_t base = tile * kSortTile;
-    const uint32_t lane = lane_id();
-#pragma unroll 4
-    for (int j = 0; j < kSortItems; ++j) {
-        const int64_t idx = base + int64_t(wave) * (kSortItems * kWave) + j * kWave + lane;
-        const bool valid = idx < n;
-        const uint32_t d = valid ? uint32_t(a.kin[idx] >> a.shift) & dmask : 0u;
+    const int64_t wbase = tile * kTile + int64_t(wave) * (ITEMS * kWave) + lane_id();
+    // all of the tile's loads in flight before the first use
+    uint64_t k[ITEMS];
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+        const int64_t idx = wbase + j * kWave;
+        k[j] = idx < n ? a.kin[idx] : 0ull;
+    }
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+        const bool valid = wbase + j * kWave < n;
+        const uint32_t d = digit_of<B>(k[j], a.shift);
         const uint64_t active = __ballot(valid);
         if (active == 0) continue;
         const uint32_t d0 = __builtin_amdgcn_readfirstlane(valid ? d : 0xffffffffu);
@@ -273,34 +331,39 @@ struct DownArgs {
     int64_t cap;
     const int64_t* d_n;
     const int32_t* d_status;
-    int shift, bits;
+    int shift;
     const uint32_t* table;  // scanned: base_d + prefix_wg per (digit, tile)
     int64_t max_tiles;
 };
 
-template <int R>
+template <int B, int ITEMS>
 __global__ __launch_bounds__(kSortThreads) void k_downsweep(DownArgs a) {
-    constexpr int RADIX = 1 << R;
-    __shared__ TileSmem<RADIX> sm;
+    constexpr int kTile = kSortThreads * ITEMS;
+    __shared__ TileSmem<B, ITEMS> sm;
     if (a.d_status && *a.d_status != 0) return;
     const int64_t n = device_count(a.cap, a.d_n);
-    const int64_t tile = blockIdx.x;
-    if (tile * kSortTile >= n) return;
-    for (int i = threadIdx.x; i < kSortWaves * RADIX; i += kSortThreads) (&sm.whist[0][0])[i] = 0;
+    const int64_t ntiles = (n + kTile - 1) / kTile;
+    if (int64_t(blockIdx.x) >= ntiles) return;
+    const int64_t tile = xcd_contiguous(blockIdx.x, uint32_t(ntiles));
+    clear_whist(sm);
     __syncthreads();
-    uint64_t key[kSortItems];
-    uint32_t val[kSortItems];
-    uint32_t rank[kSortItems];
+    uint64_t key[ITEMS];
+    uint32_t rank[ITEMS];
     uint32_t cnt;
-    load_and_rank<R>(sm, a.kin, a.vin, n, tile, a.shift, a.bits, key, val, rank, &cnt);
+    load_and_rank<B, ITEMS>(sm, a.kin, n, tile, a.shift, key, rank, &cnt);
+    // the values are in flight during the scan and the staging of the keys
+    uint32_t val[ITEMS];
+    load_vals<ITEMS>(a.vin, n, tile, val);
     uint32_t total;
     const uint32_t toff = block_exclusive_scan<kSortThreads>(cnt, sm.scan, &total);
-    if (threadIdx.x < RADIX) {
+    if (threadIdx.x < (1 << B)) {
         sm.tile_off[threadIdx.x] = toff;
         sm.global[threadIdx.x] = a.table[int64_t(threadIdx.x) * a.max_tiles + tile];
     }
     __syncthreads();
-    scatter_tile<R>(sm, n, tile, a.shift, a.bits, key, val, rank, a.kout, a.vout);
+    stage_keys<B, ITEMS>(sm, n, tile, a.shift, key, rank);
+    __syncthreads();
+    flush_tile<B, ITEMS>(sm, n, tile, a.shift, rank, val, a.kout, a.vout);
 }
 
 struct TableLoad {
@@ -325,6 +388,7 @@ struct HistArgs {
     const int64_t* d_n;
     const int32_t* d_status;
     int begin, end, r, passes;
+    int tile;  // pairs per sort tile
     uint32_t* hist;
     uint32_t* status;
     int64_t max_tiles;
@@ -343,7 +407,7 @@ __global__ __launch_bounds__(kHistThreads) void k_sort_hist(HistArgs a) {
 #pragma unroll
         for (int w = 0; w < kHistThreads / kWave; ++w) s_h[w][i] = 0;
     }
-    const int64_t tiles = (n + kSortTile - 1) / kSortTile;
+    const int64_t tiles = (n + a.tile - 1) / a.tile;
     const int64_t words = tiles * radix;
     const int64_t gsize = int64_t(gridDim.x) * kHistThreads;
     for (int p = 0; p < a.passes; ++p) {
@@ -387,37 +451,45 @@ struct PassArgs {
     const int64_t* d_n;
     int32_t* d_status_rw;  // may be null
     const int32_t* d_status;
-    int shift, bits;
+    int shift;
     const uint32_t* hist;  // [radix] of this pass
-    uint32_t* status;      // [max_tiles][radix] of this pass
+    uint32_t* status;      // [max_tiles][2^B] of this pass
     uint32_t* ticket;
 };
 
-template <int R>
+template <int B, int ITEMS>
 __global__ __launch_bounds__(kSortThreads) void k_sort_pass(PassArgs a) {
-    constexpr int RADIX = 1 << R;
-    __shared__ TileSmem<RADIX> sm;
+    constexpr int RADIX = 1 << B;
+    constexpr int kTile = kSortThreads * ITEMS;
+    __shared__ TileSmem<B, ITEMS> sm;
     if (a.d_status && *a.d_status != 0) return;
     const int64_t n = device_count(a.cap, a.d_n);
+    const int64_t ntiles = (n + kTile - 1) / kTile;
+    // Workgroups past the live tiles leave before taking a ticket: tickets
+    // 0..ntiles-1 then all go to the ntiles workgroups below, each of which
+    // takes exactly one.
+    if (int64_t(blockIdx.x) >= ntiles) return;
     if (threadIdx.x == 0) sm.tile = atomicAdd(a.ticket, 1u);
-    for (int i = threadIdx.x; i < kSortWaves * RADIX; i += kSortThreads) (&sm.whist[0][0])[i] = 0;
+    clear_whist(sm);
     __syncthreads();
     const int64_t tile = sm.tile;
-    const int64_t ntiles = (n + kSortTile - 1) / kSortTile;
-    if (tile >= ntiles) return;
-    uint64_t key[kSortItems];
-    uint32_t val[kSortItems];
-    uint32_t rank[kSortItems];
+    uint64_t key[ITEMS];
+    uint32_t rank[ITEMS];
     uint32_t cnt;
-    load_and_rank<R>(sm, a.kin, a.vin, n, tile, a.shift, a.bits, key, val, rank, &cnt);
+    load_and_rank<B, ITEMS>(sm, a.kin, n, tile, a.shift, key, rank, &cnt);
     const int t = threadIdx.x;
     if (t < RADIX) store_agent(&a.status[tile * RADIX + t], (tile == 0 ? kStInc : kStAgg) | cnt);
     uint32_t total;
     const uint32_t toff = block_exclusive_scan<kSortThreads>(cnt, sm.scan, &total);
     const uint32_t hv = t < RADIX ? a.hist[t] : 0u;
     const uint32_t dbase = block_exclusive_scan<kSortThreads>(hv, sm.scan, &total);
+    if (t < RADIX) sm.tile_off[t] = toff;
+    __syncthreads();
+    // the keys wait in LDS (and the values are in flight) during the look-back
+    stage_keys<B, ITEMS>(sm, n, tile, a.shift, key, rank);
+    uint32_t val[ITEMS];
+    load_vals<ITEMS>(a.vin, n, tile, val);
     if (t < RADIX) {
-        sm.tile_off[t] = toff;
         uint32_t excl = 0;
         if (tile > 0) {
             // Look back over windows of kLook predecessors with all loads in
@@ -468,22 +540,46 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_pass(PassArgs a) {
         sm.global[t] = dbase + excl;
     }
     __syncthreads();
-    scatter_tile<R>(sm, n, tile, a.shift, a.bits, key, val, rank, a.kout, a.vout);
+    flush_tile<B, ITEMS>(sm, n, tile, a.shift, rank, val, a.kout, a.vout);
 }
 
-template <int R>
-void launch_pass_lookback(const PassArgs& pa, uint32_t grid, hipStream_t stream) {
-    hipLaunchKernelGGL(k_sort_pass<R>, dim3(grid), dim3(kSortThreads), 0, stream, pa);
+// ------------------------------------------------ dispatch
+
+struct PassLaunch {
+    const SortLayout* L;
+    UpArgs ua;
+    DownArgs da;
+    PassArgs pa;
+    const int32_t* d_status;
+    hipStream_t stream;
+};
+
+template <int B, int ITEMS>
+void run_pass(const PassLaunch& c) {
+    const uint32_t grid = uint32_t(c.L->max_tiles);
+    if (c.L->wait_free) {
+        hipLaunchKernelGGL((k_upsweep<B, ITEMS>), dim3(grid), dim3(kSortThreads), 0, c.stream, c.ua);
+        const int64_t entries = int64_t(1 << B) * c.L->max_tiles;
+        launch_scan<uint32_t>(TableLoad{c.ua.table}, TableStore{c.ua.table}, entries, nullptr, c.d_status,
+                              c.L->partials, static_cast<uint32_t*>(nullptr), c.stream);
+        hipLaunchKernelGGL((k_downsweep<B, ITEMS>), dim3(grid), dim3(kSortThreads), 0, c.stream, c.da);
+    } else {
+        hipLaunchKernelGGL((k_sort_pass<B, ITEMS>), dim3(grid), dim3(kSortThreads), 0, c.stream, c.pa);
+    }
 }
 
-template <int R>
-void launch_pass_wait_free(const UpArgs& ua, const DownArgs& da, uint32_t grid, uint32_t* partials,
-                           const int32_t* d_status, hipStream_t stream) {
-    hipLaunchKernelGGL(k_upsweep<R>, dim3(grid), dim3(kSortThreads), 0, stream, ua);
-    const int64_t entries = int64_t(1 << R) * ua.max_tiles;
-    launch_scan<uint32_t>(TableLoad{ua.table}, TableStore{ua.table}, entries, nullptr, d_status, partials,
-                          static_cast<uint32_t*>(nullptr), stream);
-    hipLaunchKernelGGL(k_downsweep<R>, dim3(grid), dim3(kSortThreads), 0, stream, da);
+template <int ITEMS>
+void run_pass_bits(const PassLaunch& c, int bits) {
+    switch (bits) {
+        case 1: run_pass<1, ITEMS>(c); break;
+        case 2: run_pass<2, ITEMS>(c); break;
+        case 3: run_pass<3, ITEMS>(c); break;
+        case 4: run_pass<4, ITEMS>(c); break;
+        case 5: run_pass<5, ITEMS>(c); break;
+        case 6: run_pass<6, ITEMS>(c); break;
+        case 7: run_pass<7, ITEMS>(c); break;
+        default: run_pass<8, ITEMS>(c); break;
+    }
 }
 
 }  // namespace
@@ -498,7 +594,6 @@ hipError_t launch_sort(const uint64_t* kin, const uint32_t* vin, uint64_t* kout,
     SortLayout L;
     plan(ws, n, begin_bit, end_bit, radix_bits, &L);
     const int hist_id = timed ? WS_KERNEL_SORT_HIST : -1, pass_id = timed ? WS_KERNEL_SORT_PASS : -1;
-    const uint32_t grid = uint32_t(L.max_tiles);
     if (!L.wait_free) {
         hipLaunchKernelGGL(k_sort_init, dim3(1), dim3(256), 0, stream, L.hist, L.passes * L.radix, L.tickets,
                            L.passes);
@@ -511,6 +606,7 @@ hipError_t launch_sort(const uint64_t* kin, const uint32_t* vin, uint64_t* kout,
         h.end = end_bit;
         h.r = L.r;
         h.passes = L.passes;
+        h.tile = kSortThreads * L.items;
         h.hist = L.hist;
         h.status = L.status;
         h.max_tiles = L.max_tiles;
@@ -527,46 +623,27 @@ hipError_t launch_sort(const uint64_t* kin, const uint32_t* vin, uint64_t* kout,
         uint32_t* ov = to_out ? vout : L.alt_vals;
         const int shift = begin_bit + p * L.r;
         const int bits = std::min(L.r, end_bit - shift);
+        PassLaunch c;
+        c.L = &L;
+        c.d_status = d_status;
+        c.stream = stream;
+        c.ua = UpArgs{pk, n, d_n, d_status, shift, L.table, L.max_tiles};
+        c.da = DownArgs{pk, pv, ok, ov, n, d_n, d_status, shift, L.table, L.max_tiles};
+        c.pa.kin = pk;
+        c.pa.vin = pv;
+        c.pa.kout = ok;
+        c.pa.vout = ov;
+        c.pa.cap = n;
+        c.pa.d_n = d_n;
+        c.pa.d_status_rw = const_cast<int32_t*>(d_status);
+        c.pa.d_status = d_status;
+        c.pa.shift = shift;
+        c.pa.hist = L.wait_free ? nullptr : L.hist + p * L.radix;
+        c.pa.status = L.wait_free ? nullptr : L.status + int64_t(p) * L.max_tiles * L.radix;
+        c.pa.ticket = L.wait_free ? nullptr : L.tickets + p;
         timing_begin(pass_id, stream);
-        if (L.wait_free) {
-            UpArgs ua{pk, n, d_n, d_status, shift, bits, L.table, L.max_tiles};
-            DownArgs da{pk, pv, ok, ov, n, d_n, d_status, shift, bits, L.table, L.max_tiles};
-            switch (L.r) {
-                case 1: launch_pass_wait_free<1>(ua, da, grid, L.partials, d_status, stream); break;
-                case 2: launch_pass_wait_free<2>(ua, da, grid, L.partials, d_status, stream); break;
-                case 3: launch_pass_wait_free<3>(ua, da, grid, L.partials, d_status, stream); break;
-                case 4: launch_pass_wait_free<4>(ua, da, grid, L.partials, d_status, stream); break;
-                case 5: launch_pass_wait_free<5>(ua, da, grid, L.partials, d_status, stream); break;
-                case 6: launch_pass_wait_free<6>(ua, da, grid, L.partials, d_status, stream); break;
-                case 7: launch_pass_wait_free<7>(ua, da, grid, L.partials, d_status, stream); break;
-                default: launch_pass_wait_free<8>(ua, da, grid, L.partials, d_status, stream); break;
-            }
-        } else {
-            PassArgs pa;
-            pa.kin = pk;
-            pa.vin = pv;
-            pa.kout = ok;
-            pa.vout = ov;
-            pa.cap = n;
-            pa.d_n = d_n;
-            pa.d_status_rw = const_cast<int32_t*>(d_status);
-            pa.d_status = d_status;
-            pa.shift = shift;
-            pa.bits = bits;
-            pa.hist = L.hist + p * L.radix;
-            pa.status = L.status + int64_t(p) * L.max_tiles * L.radix;
-            pa.ticket = L.tickets + p;
-            switch (L.r) {
-                case 1: launch_pass_lookback<1>(pa, grid, stream); break;
-                case 2: launch_pass_lookback<2>(pa, grid, stream); break;
-                case 3: launch_pass_lookback<3>(pa, grid, stream); break;
-                case 4: launch_pass_lookback<4>(pa, grid, stream); break;
-                case 5: launch_pass_lookback<5>(pa, grid, stream); break;
-                case 6: launch_pass_lookback<6>(pa, grid, stream); break;
-                case 7: launch_pass_lookback<7>(pa, grid, stream); break;
-                default: launch_pass_lookback<8>(pa, grid, stream); break;
-            }
-        }
+        if (L.items == kItemsSmall) run_pass_bits<kItemsSmall>(c, bits);
+        else run_pass_bits<kItemsLarge>(c, bits);
         timing_end(pass_id, stream);
     }
     return hipGetLastError();

@@ -39,6 +39,16 @@ __device__ __forceinline__ T wave_sum(T v) {
     return v;
 }
 
+// Workgroups of a 1-D grid are dealt to the 8 XCDs round-robin by blockIdx.
+// This maps block b < count to a work item so that each XCD receives one
+// contiguous range of items (a bijection on [0, count)): neighbouring items
+// then share that XCD's L2, and lines they write in part are merged there.
+constexpr uint32_t kXcds = 8;
+__device__ __forceinline__ uint32_t xcd_contiguous(uint32_t b, uint32_t count) {
+    const uint32_t x = b % kXcds, q = count / kXcds, r = count % kXcds;
+    return x * q + (x < r ? x : r) + b / kXcds;
+}
+
 // Exclusive prefix sum over a workgroup of NT threads (NT a multiple of 64).
 // `scratch` holds NT/64 + 1 values; returns the exclusive prefix and the total.
 template <int NT, class T>
