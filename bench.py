@@ -8,7 +8,9 @@ sort of the (tile | depth) pairs, tile ranges and compositing.
 Printed (one JSON line): frames/s (`value`), sorted keys/s of the frame's pair
 buffer, per-kernel launch times measured with HIP events, the roofline of the
 dominant kernel, batched (one graph replay for 8 views) vs plain (one view per
-launch) forward+backward views/s on 8 1080p views with an L1 loss, the
+launch) forward+backward views/s on 8 1080p views with an L1 loss, batched vs
+plain forward views/s on 64 views of uneven resolution (tile size and radix
+width from the autotuner, persistent ordered render), the
 preprocess+sort HBM fraction of the 6M-Gaussian 4K frame, and the fp64 CPU
 oracle timed on a bounded sample of the same frame.
 
@@ -203,6 +205,56 @@ def bench_batched(args):
             "images_bit_equal": same_images, "grad_max_rel_diff": rel, "l1_loss": loss}
 
 
+def bench_multiview(args):
+    """64 orbit views of uneven resolution: one graph replay (persistent ordered render, autotuned tile
+    size and radix width) vs one view per launch sequence; forward only."""
+    import torch
+
+    import scenegen
+    from paper_2602_03207_amd import binding as B
+    from paper_2602_03207_amd.autotune import autotune
+    from paper_2602_03207_amd.batched import BatchedForward, PlainForward
+    from paper_2602_03207_amd.pipeline import GaussianTensors
+
+    scene, cams = scenegen.c4(n_views=args.mv_views)
+    g = GaussianTensors.from_scene(scene)
+    del scene
+    base = B.make_options(sh_degree=3, flags=B.WS_FLAG_DEPTH_FIRST | B.WS_FLAG_ORDERED_RENDER)
+    tune = autotune(g, cams, base, radix_bits=(6, 7, 8), reps=3, log=log)
+    opts = tune.apply(base)
+    bf = BatchedForward(cams, opts, g)
+    bf.capture()
+    for _ in range(2):
+        bf.replay()
+    bf.check()
+    reps = max(3, args.batched_steps)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        bf.replay()
+    bf.stream.synchronize()
+    t_batched = (time.perf_counter() - t0) / reps
+    bf.check()
+    pairs = int(bf.r.d_num_pairs.item())
+    plain = PlainForward(cams, opts, g)
+    plain.step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        plain.step()
+    torch.cuda.synchronize()
+    t_plain = (time.perf_counter() - t0) / reps
+    same = bool(torch.equal(bf.r.images.view(torch.int32), plain.images().view(torch.int32)))
+    res = sorted({(c.width, c.height) for c in cams})
+    bf.close()
+    return {"views": len(cams), "resolutions": {f"{w}x{h}": sum(1 for c in cams if (c.width, c.height) == (w, h))
+                                                for w, h in res},
+            "pairs": pairs, "tuned": {"tile": f"{tune.tile_w}x{tune.tile_h}", "radix_bits": tune.radix_bits,
+                                      "candidates": len(tune.table)},
+            "batched_views_per_s": round(len(cams) / t_batched, 2), "plain_views_per_s": round(len(cams) / t_plain, 2),
+            "batched_ms": round(t_batched * 1e3, 3), "plain_ms": round(t_plain * 1e3, 3),
+            "speedup": round(t_plain / t_batched, 3), "images_bit_equal": same}
+
+
 def bench_large(args):
     """6M Gaussians at 3840x2160: preprocess + sort bytes over their time (HBM fraction)."""
     import torch
@@ -275,6 +327,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-large", action="store_true")
+    ap.add_argument("--no-multiview", action="store_true")
+    ap.add_argument("--mv-views", type=int, default=64)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also copy a 256 MiB buffer 4 times (a plain copy kernel of known size, used to scale "
                          "the HBM byte counters of a profiler run)")
@@ -336,6 +390,9 @@ def main():
     if not args.no_batched:
         log("leg: batched vs plain fwd+bwd (8 views, 1920x1080)")
         line["batched_fwd_bwd"] = bench_batched(args)
+    if not args.no_multiview:
+        log(f"leg: batched vs plain forward ({args.mv_views} views of uneven resolution)")
+        line["multiview_forward"] = bench_multiview(args)
     if not args.no_large:
         log("leg: 6M Gaussians, 3840x2160")
         line["large_scene_preprocess_sort"] = bench_large(args)

@@ -81,7 +81,8 @@ typedef struct ws_camera {
 /* flags */
 #define WS_FLAG_FIXED_3SIGMA     1u  /* "-RADIUS" ablation (Sec. 4.4): 3-sigma extent for every splat */
 #define WS_FLAG_NO_VIEWPORT_CULL 2u  /* "-CULL" ablation (Sec. 4.4): keep splats whose AABB misses the view */
-#define WS_FLAG_ORDERED_RENDER   4u  /* render: persistent workgroups take tiles in descending pair count */
+#define WS_FLAG_ORDERED_RENDER   4u  /* render: persistent workgroups take tiles from a queue, longest first
+                                          (grouped by the power of two of the pair count); same images */
 #define WS_FLAG_DEPTH_FIRST      8u  /* preprocess: emit pairs in (depth, view * n + id) order instead of
                                         (view * n + id) order; a stable sort of the tile bits alone
                                         [32, end_bit) then yields the full (tile, depth) order */

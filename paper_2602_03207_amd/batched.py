@@ -12,6 +12,9 @@ sets the device status word (checked by `check()`), never writes out of bounds.
 `PlainStep` is the reference sequence it is compared with: a host loop over
 views, each a single-view forward (with its pair-count read-back), loss and
 backward, gradients accumulated on the device.
+
+`BatchedForward` / `PlainForward` are the forward-only counterparts (many
+views rendered by one captured graph vs one view per launch sequence).
 """
 from __future__ import annotations
 
@@ -115,6 +118,64 @@ class PlainStep:
             for k in self.grads:
                 self.grads[k].add_(self.view_grads[k])
         return self.grads
+
+    def images(self):
+        return torch.cat([r.images for r in self.renderers])
+
+
+class BatchedForward:
+    """All views' forward (preprocess, device-sized sort, render) as one graph replay."""
+
+    def __init__(self, cams, opts: B.ws_options, g: GaussianTensors, headroom=1.1, device="cuda"):
+        self.g = g
+        self.stream = torch.cuda.Stream(device=device)  # default priority
+        self.r = Renderer(cams, opts, device=device)
+        with torch.cuda.stream(self.stream):
+            m = self.r.forward(g, stream=self.stream)
+            self.r._ensure_capacity(int(m * headroom) + 4096)
+            self.r.forward_capacity(g, stream=self.stream)  # sizes the workspaces at this capacity
+        self.stream.synchronize()
+        self.graph = None
+
+    def capture(self):
+        s = self.stream
+        s.synchronize()
+        B.ws_graph_begin(s)
+        try:
+            with torch.cuda.stream(s):
+                self.r.forward_capacity(self.g, stream=s)
+        except Exception:
+            B.ws_graph_end(s)
+            raise
+        self.graph = B.ws_graph_end(s)
+
+    def replay(self):
+        if self.graph is None:
+            self.capture()
+        B.ws_graph_launch(self.graph, self.stream)
+
+    def check(self):
+        self.stream.synchronize()
+        st = self.r.status()
+        if st != 0:
+            raise B.WsError(st, B.ws_status_string(st))
+
+    def close(self):
+        if self.graph is not None:
+            B.ws_graph_destroy(self.graph)
+            self.graph = None
+
+
+class PlainForward:
+    """One view per launch sequence, each with its pair-count read-back."""
+
+    def __init__(self, cams, opts: B.ws_options, g: GaussianTensors, device="cuda"):
+        self.g = g
+        self.renderers = [Renderer([c], opts, device=device) for c in cams]
+
+    def step(self, stream=None):
+        for r in self.renderers:
+            r.forward(self.g, stream=stream)
 
     def images(self):
         return torch.cat([r.images for r in self.renderers])

@@ -9,6 +9,15 @@
 //                             gathers one 48-byte record); every lane then
 //                             walks the batch front to back.  The workgroup
 //                             leaves as soon as all its pixels have stopped.
+// k_tile_classes / k_tile_order  (WS_FLAG_ORDERED_RENDER) group the tiles by
+//                             the power of two of their pair count and list
+//                             them longest first;
+// k_render_queue<TW, TH>      persistent workgroups (as many as are resident
+//                             at once) take tiles from that list through an
+//                             atomic counter until it is exhausted, so the
+//                             longest tiles start first and no workgroup
+//                             waits for another.  The order in which tiles are
+//                             processed does not change any pixel.
 // The per-(pixel, splat) arithmetic lives in composite.h and is shared with
 // the backward pass, so both take exactly the same skip / stop decisions.
 #include "composite.h"
@@ -50,13 +59,11 @@ struct RenderArgs {
     KOpts o;
 };
 
+// Composites global tile g into the images.  s_batch: NT staged records.
 template <int TW, int TH>
-__global__ __launch_bounds__(TW * TH) void k_render(RenderArgs a) {
+__device__ __forceinline__ void render_tile(const RenderArgs& a, int64_t g, StagedSplat* s_batch) {
     constexpr int NT = TW * TH;
-    __shared__ StagedSplat s_batch[NT];
-    if (*a.d_status != 0) return;
-    const int64_t g = blockIdx.x;
-    TileInfo ti = locate_tile(a.cams, a.n_views, g, TW, TH);
+    const TileInfo ti = locate_tile(a.cams, a.n_views, g, TW, TH);
     const int px = ti.x0 + int(threadIdx.x % TW), py = ti.y0 + int(threadIdx.x / TW);
     const bool inside = px < ti.W && py < ti.H;
     const uint32_t start = a.ranges[2 * g], end = a.ranges[2 * g + 1];
@@ -84,15 +91,135 @@ __global__ __launch_bounds__(TW * TH) void k_render(RenderArgs a) {
 }
 
 template <int TW, int TH>
-void launch_render_t(const RenderArgs& ra, hipStream_t stream) {
-    hipLaunchKernelGGL((k_render<TW, TH>), dim3(uint32_t(ra.total_tiles)), dim3(TW * TH), 0, stream, ra);
+__global__ __launch_bounds__(TW * TH) void k_render(RenderArgs a) {
+    __shared__ StagedSplat s_batch[TW * TH];
+    if (*a.d_status != 0) return;
+    render_tile<TW, TH>(a, blockIdx.x, s_batch);
+}
+
+// ---- ordered, persistent render
+
+constexpr int kClasses = 33;  // 0: empty tile; c >= 1: pair count in [2^(c-1), 2^c)
+
+__device__ __forceinline__ int tile_class(const uint32_t* ranges, int64_t t) {
+    const uint32_t len = ranges[2 * t + 1] - ranges[2 * t];
+    return len ? 32 - __builtin_clz(len) : 0;
+}
+
+// Tile counts per class (counters zeroed beforehand).
+__global__ __launch_bounds__(256) void k_tile_classes(const uint32_t* ranges, int64_t total_tiles,
+                                                      const int32_t* d_status, uint32_t* hist) {
+    __shared__ uint32_t s_h[kClasses];
+    if (*d_status != 0) return;
+    for (int i = threadIdx.x; i < kClasses; i += 256) s_h[i] = 0;
+    __syncthreads();
+    const int64_t stride = int64_t(gridDim.x) * 256;
+    for (int64_t t = int64_t(blockIdx.x) * 256 + threadIdx.x; t < total_tiles; t += stride)
+        atomicAdd(&s_h[tile_class(ranges, t)], 1u);
+    __syncthreads();
+    for (int i = threadIdx.x; i < kClasses; i += 256)
+        if (s_h[i]) atomicAdd(&hist[i], s_h[i]);
+}
+
+// order[] lists the tiles by descending class (any order inside a class).
+__global__ __launch_bounds__(256) void k_tile_order(const uint32_t* ranges, int64_t total_tiles,
+                                                    const int32_t* d_status, const uint32_t* hist,
+                                                    uint32_t* cursor, uint32_t* order) {
+    __shared__ uint32_t s_base[kClasses];
+    if (*d_status != 0) return;
+    if (threadIdx.x == 0) {
+        uint32_t run = 0;
+        for (int c = kClasses - 1; c >= 0; --c) {
+            s_base[c] = run;
+            run += hist[c];
+        }
+    }
+    __syncthreads();
+    const int64_t stride = int64_t(gridDim.x) * 256;
+    for (int64_t t = int64_t(blockIdx.x) * 256 + threadIdx.x; t < total_tiles; t += stride) {
+        const int c = tile_class(ranges, t);
+        const uint32_t pos = s_base[c] + atomicAdd(&cursor[c], 1u);
+        if (int64_t(pos) < total_tiles) order[pos] = uint32_t(t);  // always true for consistent counts
+    }
+}
+
+// Every workgroup takes list positions from *queue until they run past the
+// end; each take advances the counter, so every workgroup leaves.
+template <int TW, int TH>
+__global__ __launch_bounds__(TW * TH) void k_render_queue(RenderArgs a, const uint32_t* order, uint32_t* queue) {
+    __shared__ StagedSplat s_batch[TW * TH];
+    __shared__ uint32_t s_q;
+    if (*a.d_status != 0) return;
+    while (true) {
+        if (threadIdx.x == 0) s_q = atomicAdd(queue, 1u);
+        __syncthreads();
+        const uint32_t q = s_q;
+        __syncthreads();
+        if (int64_t(q) >= a.total_tiles) break;
+        render_tile<TW, TH>(a, order[q], s_batch);
+    }
+}
+
+struct OrderWs {
+    uint32_t* order;   // [total_tiles]
+    uint32_t* hist;    // [kClasses]
+    uint32_t* cursor;  // [kClasses]
+    uint32_t* queue;   // [1]
+};
+
+size_t order_ws(void* ws, int64_t total_tiles, OrderWs* out) {
+    char* base = static_cast<char*>(ws);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        char* ptr = base ? base + off : nullptr;
+        off += align_up(bytes);
+        return ptr;
+    };
+    OrderWs w;
+    w.order = reinterpret_cast<uint32_t*>(take(size_t(std::max<int64_t>(total_tiles, 1)) * 4));
+    w.hist = reinterpret_cast<uint32_t*>(take((2 * kClasses + 1) * 4));
+    w.cursor = w.hist ? w.hist + kClasses : nullptr;
+    w.queue = w.hist ? w.hist + 2 * kClasses : nullptr;
+    if (out) *out = w;
+    return off;
+}
+
+__global__ void k_order_clear(uint32_t* words, int count) {
+    for (int i = threadIdx.x; i < count; i += blockDim.x) words[i] = 0;
+}
+
+// Resident workgroups of k_render_queue on the current device (cached per device).
+template <int TW, int TH>
+uint32_t persistent_grid() {
+    static int cached[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
+    if (cached[dev] == 0) {
+        int per_cu = 0, cus = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_render_queue<TW, TH>, TW * TH, 0) != hipSuccess ||
+            per_cu < 1)
+            per_cu = 1;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 1;
+        cached[dev] = per_cu * cus;
+    }
+    return uint32_t(cached[dev]);
+}
+
+template <int TW, int TH>
+void launch_render_t(const RenderArgs& ra, const OrderWs* ow, hipStream_t stream) {
+    if (!ow) {
+        hipLaunchKernelGGL((k_render<TW, TH>), dim3(uint32_t(ra.total_tiles)), dim3(TW * TH), 0, stream, ra);
+        return;
+    }
+    const uint32_t grid = uint32_t(std::min<int64_t>(persistent_grid<TW, TH>(), ra.total_tiles));
+    hipLaunchKernelGGL((k_render_queue<TW, TH>), dim3(grid), dim3(TW * TH), 0, stream, ra,
+                       static_cast<const uint32_t*>(ow->order), ow->queue);
 }
 
 }  // namespace
 
 size_t render_workspace(int64_t total_tiles, const KOpts& o) {
-    (void)total_tiles;
-    (void)o;
+    if (o.flags & WS_FLAG_ORDERED_RENDER) return order_ws(nullptr, total_tiles, nullptr);
     return align_up(64);
 }
 
@@ -100,7 +227,6 @@ hipError_t launch_render(const ws_splat* splats, int64_t n, const ws_camera* d_c
                          int64_t total_tiles, const KOpts& o, const uint64_t* keys, const uint32_t* values,
                          int64_t capacity, const int64_t* d_num_pairs, const int32_t* d_status,
                          uint32_t* tile_ranges, float* images, void* ws, hipStream_t stream) {
-    (void)ws;
     const int64_t words = 2 * total_tiles;
     const uint32_t cgrid = uint32_t(std::min<int64_t>(std::max<int64_t>((words + 255) / 256, 1), 4096));
     timing_begin(WS_KERNEL_RANGES, stream);
@@ -120,11 +246,23 @@ hipError_t launch_render(const ws_splat* splats, int64_t n, const ws_camera* d_c
     ra.images = images;
     ra.d_status = d_status;
     ra.o = o;
+    OrderWs ow;
+    const bool ordered = (o.flags & WS_FLAG_ORDERED_RENDER) != 0;
     timing_begin(WS_KERNEL_RENDER, stream);
-    if (o.tile_w == 16 && o.tile_h == 16) launch_render_t<16, 16>(ra, stream);
-    else if (o.tile_w == 8 && o.tile_h == 8) launch_render_t<8, 8>(ra, stream);
-    else if (o.tile_w == 16 && o.tile_h == 8) launch_render_t<16, 8>(ra, stream);
-    else launch_render_t<32, 16>(ra, stream);
+    if (ordered) {
+        order_ws(ws, total_tiles, &ow);
+        const uint32_t ogrid = uint32_t(std::min<int64_t>((total_tiles + 255) / 256, 1024));
+        hipLaunchKernelGGL(k_order_clear, dim3(1), dim3(128), 0, stream, ow.hist, 2 * kClasses + 1);
+        hipLaunchKernelGGL(k_tile_classes, dim3(ogrid), dim3(256), 0, stream, static_cast<const uint32_t*>(tile_ranges),
+                           total_tiles, d_status, ow.hist);
+        hipLaunchKernelGGL(k_tile_order, dim3(ogrid), dim3(256), 0, stream, static_cast<const uint32_t*>(tile_ranges),
+                           total_tiles, d_status, static_cast<const uint32_t*>(ow.hist), ow.cursor, ow.order);
+    }
+    const OrderWs* owp = ordered ? &ow : nullptr;
+    if (o.tile_w == 16 && o.tile_h == 16) launch_render_t<16, 16>(ra, owp, stream);
+    else if (o.tile_w == 8 && o.tile_h == 8) launch_render_t<8, 8>(ra, owp, stream);
+    else if (o.tile_w == 16 && o.tile_h == 8) launch_render_t<16, 8>(ra, owp, stream);
+    else launch_render_t<32, 16>(ra, owp, stream);
     timing_end(WS_KERNEL_RENDER, stream);
     return hipGetLastError();
 }

@@ -134,3 +134,32 @@ def test_batched_views_equal_single_views():
     for v, cam in enumerate(cams):
         single = _full(scene, [cam]).image(0).cpu().numpy()
         assert np.array_equal(rb.image(v).cpu().numpy().view(np.uint32), single.view(np.uint32)), v
+
+
+@pytest.mark.parametrize("tile", [(16, 16), (8, 8), (32, 16)])
+def test_ordered_persistent_render_equals_plain(tile):
+    """WS_FLAG_ORDERED_RENDER (persistent workgroups, longest tiles first) changes no pixel."""
+    from paper_2602_03207_amd import binding as B
+    scene, _ = scenegen.c1()
+    cams = [scenegen.look_at([0, 0, -3], [0, 0, 0], 256, 256), scenegen.look_at([1.5, -0.5, -2.5], [0, 0, 0], 70, 130),
+            scenegen.look_at([-0.4, 0.3, -1.2], [0, 0, 0], 333, 97)]
+    kw = dict(tile_w=tile[0], tile_h=tile[1])
+    plain = _full(scene, cams, **kw)
+    ordered = _full(scene, cams, flags=B.WS_FLAG_ORDERED_RENDER, **kw)
+    assert ordered.status() == 0
+    assert np.array_equal(ordered.images.cpu().numpy().view(np.uint32), plain.images.cpu().numpy().view(np.uint32))
+    # and against the oracle on the first view
+    ref = oracle.render(scene, cams[0], oracle_options(*tile))
+    assert_image_parity(ordered.image(0).cpu().numpy(), ref)
+
+
+@pytest.mark.parametrize("flags", [1, 2, 3])
+def test_ablation_flags_match_oracle(flags):
+    """Fixed 3-sigma extent (1) and no viewport cull (2), the ablations of Sec. 4.4, against the oracle."""
+    scene = scenegen.random_scene(4000, 31, mean_lo=-1.5, mean_hi=1.5, log_scale_mu=-3.0, log_scale_sd=0.6,
+                                  logit_sd=2.5, sh_degree=1, dc_sd=0.5, rest_sd=0.2)
+    cam = scenegen.look_at([0.3, 0.2, -1.4], [0, 0, 0.5], 150, 110)
+    r = _full(scene, [cam], flags=flags)
+    ref = oracle.render(scene, cam, oracle_options(sh_degree=1, flags=flags))
+    assert r.num_pairs == ref["keys"].size
+    assert_image_parity(r.image(0).cpu().numpy(), ref)
