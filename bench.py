@@ -141,6 +141,33 @@ def bench_frames(args):
                 stats=stats, end_bit=r.end_bit)
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "c2_frame_hbm_traffic.md")
+TRAFFIC_KERNEL = {"render": "k_render<16, 16>"}
+
+
+def measured_traffic(dom):
+    """HBM bytes per launch of the dominant kernel from the committed counter summary, or None when the
+    summary covers another kernel or the kernel's sources changed since the counters were taken."""
+    import hashlib
+    if dom not in TRAFFIC_KERNEL or not os.path.exists(TRAFFIC_FILE):
+        return None
+    fields = {}
+    with open(TRAFFIC_FILE) as f:
+        for line in f:
+            if ":" in line and not line.startswith(("|", "#", " ")):
+                k, v = line.split(":", 1)
+                fields[k.strip()] = v.strip()
+    if fields.get("kernel") != TRAFFIC_KERNEL[dom] or "sources" not in fields:
+        return None
+    h = hashlib.sha256()
+    for src in fields["sources"].split():
+        with open(os.path.join(ROOT, src), "rb") as f:
+            h.update(f.read())
+    if h.hexdigest() != fields.get("source_sha256"):
+        return None
+    return int(fields["traffic_bytes_per_launch"])
+
+
 def roofline(res):
     """Roofline entry of the kernel with the largest time per frame."""
     kt, work = res["kernels"], res["work"]
@@ -151,10 +178,10 @@ def roofline(res):
     if bound == "hbm":
         achieved = amount / t / 1e9
         return dom, {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None}
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom)}
     achieved = amount / t / 1e12
     return dom, {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                 "frac": round(achieved / FP32_VALU_PEAK_TFLOPS, 4), "traffic": None}
+                 "frac": round(achieved / FP32_VALU_PEAK_TFLOPS, 4), "traffic": measured_traffic(dom)}
 
 
 def bench_batched(args):
