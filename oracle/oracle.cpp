@@ -298,7 +298,9 @@ Projected<T> project(const T* mean, const T* log_scale, const T* quat, const T& 
     }
 
     // Culling, in order: opacity (Sec. 3.4), near plane, degenerate, viewport (Sec. 3.2).
-    const bool det_ok = val(det) > 0.0 && finite(val(det)) && finite(val(P.u)) && finite(val(P.v));
+    // Degenerate also covers a non-finite colour (a non-finite SH coefficient).
+    const bool colour_ok = finite(val(P.rgb[0])) && finite(val(P.rgb[1])) && finite(val(P.rgb[2]));
+    const bool det_ok = val(det) > 0.0 && finite(val(det)) && finite(val(P.u)) && finite(val(P.v)) && colour_ok;
     P.valid = near_ok && det_ok;
     if (!(sig >= opt.alpha_min)) { P.status = CULL_OPACITY; return P; }
     if (!near_ok) { P.status = CULL_NEAR; return P; }

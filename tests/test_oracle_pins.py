@@ -587,3 +587,20 @@ def test_p3c_single_anisotropic_image_from_numeric_covariance():
         safe = np.abs(np.log(255 * alpha)) > 1e-4  # away from the skip threshold (FD Jacobian error)
         expect = np.where(alpha >= 1 / 255, alpha, 0.0)
         assert np.allclose(img[:, safe], col[:, None] * expect[safe][None], rtol=1e-5, atol=1e-7), trial
+
+
+def test_p17_non_finite_colour_culls_as_degenerate():
+    """A non-finite SH coefficient makes the colour non-finite: the splat is culled as degenerate
+    (reading of the non-finite-input rule) and contributes nowhere, in either compositing mode."""
+    mu = np.array([[0.0, 0.05], [0.0, 0.0], [3.0, 3.2]])
+    sc = _scene(mu, np.full((3, 2), -2.5), np.tile([[1.0], [0.0], [0.0], [0.0]], (1, 2)), [2.0, 2.0],
+                np.array([[0.4, np.nan], [0.1, 0.2], [0.3, np.inf]]))
+    cam = _cam(48, 40)
+    opts = oracle.Options()
+    pre = oracle.preprocess(sc, cam, opts)
+    assert list(pre["status"]) == [oracle.STATUS["visible"], oracle.STATUS["degenerate"]]
+    alone = _single(mu[:, 0], [-2.5] * 3, [1.0, 0, 0, 0], 2.0, [0.4, 0.1, 0.3])
+    for mode in ("tiled", "brute"):
+        img = oracle.render(sc, cam, opts, mode=mode)["rgb"]
+        ref = oracle.render(alone, cam, opts, mode=mode)["rgb"]
+        assert np.all(np.isfinite(img)) and np.array_equal(img, ref), mode
