@@ -59,38 +59,50 @@ struct BwdArgs {
 };
 
 struct RawConic {
-    float A, B, C;
+    float A, B, C, sigma;
 };
 
 template <int TW, int TH>
 __global__ __launch_bounds__(TW * TH) void k_render_bwd(BwdArgs a) {
-    constexpr int NT = TW * TH;
+    constexpr int NT = TW * TH, NW = NT / kWave;
     __shared__ StagedSplat s_batch[NT];
     __shared__ RawConic s_conic[NT];
     __shared__ float s_acc[kNG][NT];
+    __shared__ uint64_t s_masks[NW * NW];
     __shared__ int32_t s_maxlast;
     if (*a.d_status != 0) return;
     const int64_t g = blockIdx.x;
     const TileInfo ti = locate_tile(a.cams, a.n_views, g, TW, TH);
-    const int px = ti.x0 + int(threadIdx.x % TW), py = ti.y0 + int(threadIdx.x / TW);
+    int px, py;
+    quadrant_pixel<TW>(ti.x0, ti.y0, &px, &py);
     const bool inside = px < ti.W && py < ti.H;
+    const uint64_t* my_masks = s_masks + (threadIdx.x / kWave) * NW;
     const uint32_t start = a.ranges[2 * g], end = a.ranges[2 * g + 1];
     const ws_splat* vsplats = a.splats + int64_t(ti.view) * a.n;
     const int64_t vbase = int64_t(ti.view) * a.n;
 
     // ---- pass 1: front to back, as in the forward
     PixelState ps;
-    ps.init(px, py, !inside);
+    ps.init(px, py);
+    uint64_t active = wave_ballot(inside);  // lanes whose pixel is still compositing
+    const BlendConsts bk(a.o);
     if (threadIdx.x == 0) s_maxlast = -1;
     for (uint32_t b0 = start; b0 < end; b0 += NT) {
-        if (__syncthreads_count(ps.done) == NT) break;
+        if (__syncthreads_count(!lane_in(active)) == NT) break;
         const uint32_t idx = b0 + threadIdx.x;
+        StagedSplat s = empty_splat();
+        bool valid = false;
         if (idx < end) {
             const uint32_t id = a.values[idx];
-            s_batch[threadIdx.x] = id < uint64_t(a.n) ? stage_splat(vsplats, id) : empty_splat();
+            if (id < uint64_t(a.n)) {
+                s = stage_splat(vsplats, id);
+                valid = true;
+            }
+            s_batch[threadIdx.x] = s;
         }
+        stage_quadrant_masks<TW, TH>(s, valid, ti.x0, ti.y0, s_masks);
         __syncthreads();
-        composite_batch(ps, s_batch, int(min<uint32_t>(NT, end - b0)), int32_t(b0 - start), a.o);
+        composite_batch<NW>(ps, active, s_batch, my_masks, int32_t(b0 - start), bk);
     }
     __syncthreads();
     if (ps.last >= 0) atomicMax(&s_maxlast, ps.last);
@@ -111,34 +123,43 @@ __global__ __launch_bounds__(TW * TH) void k_render_bwd(BwdArgs a) {
     float R[3] = {a.o.bg[0] * T, a.o.bg[1] * T, a.o.bg[2] * T};
     const int32_t last = ps.last;
     const float pcx = float(px) + 0.5f, pcy = float(py) + 0.5f;
+    const uint32_t pix = inside ? pack_xy(px, py) : kNoPixel;
     for (int32_t bend = maxlast + 1; bend > 0; bend -= NT) {
         const int32_t bstart = bend - NT > 0 ? bend - NT : 0;
         __syncthreads();
         {
             const int32_t j = bstart + int32_t(threadIdx.x);
+            StagedSplat s = empty_splat();
+            bool valid = false;
             if (j < bend) {
                 const uint32_t id = a.values[start + uint32_t(j)];
-                StagedSplat s = id < uint64_t(a.n) ? stage_splat(vsplats, id) : empty_splat();
+                valid = id < uint64_t(a.n);
+                if (valid) s = stage_splat(vsplats, id);
                 s_batch[threadIdx.x] = s;
-                const float* rec = reinterpret_cast<const float*>(vsplats + (id < uint64_t(a.n) ? id : 0));
-                s_conic[threadIdx.x] = RawConic{rec[2], rec[3], rec[4]};
+                const float* rec = reinterpret_cast<const float*>(vsplats + (valid ? id : 0));
+                s_conic[threadIdx.x] = RawConic{rec[2], rec[3], rec[4], rec[5]};
             }
 #pragma unroll
             for (int k = 0; k < kNG; ++k) s_acc[k][threadIdx.x] = 0.f;
+            stage_quadrant_masks<TW, TH>(s, valid, ti.x0, ti.y0, s_masks);
         }
         __syncthreads();
-        for (int32_t j = bend - 1; j >= bstart; --j) {
-            const StagedSplat& s = s_batch[j - bstart];
+        // back to front over the staged splats that meet this wave's quadrant
+        MaskWalk<NW, false> walk;
+        walk.init(my_masks);
+        for (int t = walk.next(); t >= 0; t = walk.next()) {
+            const int32_t j = bstart + t;
+            const StagedSplat& s = s_batch[t];
             float gv[kNG];
 #pragma unroll
             for (int k = 0; k < kNG; ++k) gv[k] = 0.f;
             bool contrib = false;
-            if (j <= last && in_rect(s, ps.pxy)) {
+            if (j <= last && in_rect(s, pix)) {
                 const float dx = s.u - pcx, dy = s.v - pcy;
-                float G;
-                const float araw = raw_alpha(s, dx, dy, &G);
-                const float alpha = fminf(a.o.alpha_max, araw);
-                if (alpha >= a.o.alpha_min) {
+                // the forward's alpha (same evaluation, same skip decision)
+                const float araw = raw_alpha(s, dx, dy);
+                const float alpha = __builtin_amdgcn_fmed3f(araw, 0.f, bk.alpha_max);
+                if (!(alpha < bk.alpha_min)) {
                     contrib = true;
                     const float one_m = 1.f - alpha;
                     const float Tk = T / one_m;
@@ -153,10 +174,10 @@ __global__ __launch_bounds__(TW * TH) void k_render_bwd(BwdArgs a) {
                     R[1] = fmaf(s.g, w, R[1]);
                     R[2] = fmaf(s.b, w, R[2]);
                     T = Tk;
-                    if (!(araw > a.o.alpha_max)) {
-                        const RawConic& q = s_conic[j - bstart];
+                    if (!(araw > bk.alpha_max)) {
+                        const RawConic& q = s_conic[t];
                         const float gp = dLda * araw;  // dL/dpower
-                        gv[5] = dLda * G;
+                        gv[5] = dLda * (araw / q.sigma);  // dL/dsigma = dL/dalpha exp(power)
                         gv[0] = -gp * (q.A * dx + q.B * dy);
                         gv[1] = -gp * (q.C * dy + q.B * dx);
                         gv[2] = -0.5f * gp * dx * dx;
@@ -169,7 +190,7 @@ __global__ __launch_bounds__(TW * TH) void k_render_bwd(BwdArgs a) {
 #pragma unroll
                 for (int k = 0; k < kNG; ++k) {
                     const float sum = wave_sum(gv[k]);
-                    if (lane_id() == 0 && sum != 0.f) atomicAdd(&s_acc[k][j - bstart], sum);
+                    if (lane_id() == 0 && sum != 0.f) atomicAdd(&s_acc[k][t], sum);
                 }
             }
         }
@@ -235,7 +256,7 @@ __global__ __launch_bounds__(128) void k_preprocess_bwd(PreBwdArgs a) {
         if (!any) continue;
         const ws_camera& cam = a.cams[v];
         ProjState st;
-        if (!compute_projection<DEG>(a.g, i, cam, a.o, st, true)) continue;
+        if (!compute_projection<DEG>(a.g, i, cam, a.o, st)) continue;
         // ---- colour
         float Y[16];
         sh_eval_basis(st.dir[0], st.dir[1], st.dir[2], DEG, Y);

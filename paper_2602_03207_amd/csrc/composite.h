@@ -5,8 +5,11 @@
 //   a splat is skipped where the pixel is outside its rectangle or
 //   alpha < alpha_min; the pixel stops before a splat whose compositing would
 //   bring the transmittance below t_min; otherwise C += c alpha T, T *= 1 - alpha.
-// The exponential is evaluated as exp2 with the conic pre-scaled by log2(e)
-// when the splat is staged, which folds one multiply out of the inner loop.
+// Evaluation: sigma * exp(power) = 2^(power log2(e) + log2(sigma)), with the
+// conic pre-scaled by log2(e) and log2(sigma) computed once when the splat is
+// staged, so a (pixel, splat) pair costs one quadratic form and one exp2.
+// The transmittance step is T' = fma(-T, alpha, T) and the colour weight is
+// T - T' (= alpha T), so the weights of a pixel sum exactly to 1 - T_final.
 #pragma once
 
 #include "ws_internal.h"
@@ -18,7 +21,7 @@ constexpr float kLog2e = 1.4426950408889634f;
 // A splat staged in LDS for compositing: 48 bytes.
 struct StagedSplat {
     float u, v, qa, qb;    // qa = -log2(e)/2 * A, qb = -log2(e) * B
-    float qc, sigma, r, g; // qc = -log2(e)/2 * C
+    float qc, ls, r, g;    // qc = -log2(e)/2 * C, ls = log2(sigma)
     float b;
     uint32_t rxy;          // x0 | y0 << 16: first pixel of the inclusive rectangle
     uint32_t rwh;          // (x1 - x0) | (y1 - y0) << 16
@@ -39,7 +42,7 @@ __device__ __forceinline__ StagedSplat stage_splat(const ws_splat* __restrict__ 
     s.qa = -0.5f * kLog2e * r0.z;
     s.qb = -kLog2e * r0.w;
     s.qc = -0.5f * kLog2e * r1.x;
-    s.sigma = r1.y;
+    s.ls = __log2f(r1.y);
     s.r = r1.z;
     s.g = r1.w;
     s.b = r2.x;
@@ -72,12 +75,12 @@ __device__ __forceinline__ bool in_rect(const StagedSplat& s, uint32_t pxy) {
     return __builtin_bit_cast(uint32_t, m) == __builtin_bit_cast(uint32_t, d);
 }
 
-// exp(power) for the staged conic; returns sigma * exp(power) (before the clamp).
-__device__ __forceinline__ float raw_alpha(const StagedSplat& s, float dx, float dy, float* G) {
-    const float p2 = fmaf(s.qa * dx, dx, fmaf(s.qc * dy, dy, s.qb * dx * dy));
-    const float e = __builtin_amdgcn_exp2f(p2);
-    *G = e;
-    return s.sigma * e;
+// sigma * exp(power) for the staged splat (alpha before the clamp):
+// 2^(qa dx^2 + dy (qb dx + qc dy) + log2 sigma).
+__device__ __forceinline__ float raw_alpha(const StagedSplat& s, float dx, float dy) {
+    const float cross = fmaf(s.qb, dx, s.qc * dy);
+    const float p2 = fmaf(dy, cross, fmaf(s.qa * dx, dx, s.ls));
+    return __builtin_amdgcn_exp2f(p2);
 }
 
 struct TileInfo {
@@ -111,62 +114,182 @@ __device__ __forceinline__ TileInfo locate_tile(const ws_camera* cams, int32_t n
     return t;
 }
 
+// A packed coordinate that lies in no rectangle (real coordinates stay below
+// 32768), for lanes without a pixel.
+constexpr uint32_t kNoPixel = 0xffffffffu;
+
 struct PixelState {
     uint32_t pxy;  // x | y << 16
     float pcx, pcy;
     float T;
     float c[3];
-    bool done;
     int32_t last;  // index (in the tile's list) of the last splat composited, -1 if none
 
-    __device__ __forceinline__ void init(int x, int y, bool finished) {
+    __device__ __forceinline__ void init(int x, int y) {
         pxy = pack_xy(x, y);
         pcx = float(x) + 0.5f;
         pcy = float(y) + 0.5f;
         T = 1.f;
         c[0] = c[1] = c[2] = 0.f;
-        done = finished;
         last = -1;
     }
 };
 
-// One splat of the list into one pixel, with the decisions of the rule above.
-// Returns true once no lane of the wave is left active.
-__device__ __forceinline__ bool blend_one(PixelState& ps, const StagedSplat& s, int32_t idx, const KOpts& o) {
-    const bool inr = in_rect(s, ps.pxy) & !ps.done;
-    if (__ballot(inr) == 0) return false;  // the whole wave skips this splat
+// Thresholds of the compositing rule, canonicalised once so that the clamp in
+// the inner loop needs no per-iteration canonicalisation.
+struct BlendConsts {
+    float alpha_min, alpha_max, t_min;
+    __device__ __forceinline__ explicit BlendConsts(const KOpts& o)
+        : alpha_min(__builtin_canonicalizef(o.alpha_min)),
+          alpha_max(__builtin_canonicalizef(o.alpha_max)),
+          t_min(__builtin_canonicalizef(o.t_min)) {}
+};
+
+__device__ __forceinline__ uint64_t wave_ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+__device__ __forceinline__ bool lane_in(uint64_t mask) { return __builtin_amdgcn_inverse_ballot_w64(mask); }
+
+// One splat of the list into the pixels of a wave, with the decisions of the
+// rule above.  `active` is the wave's set of lanes whose pixel has not stopped
+// (a lane mask in scalar registers); the per-lane decisions are formed as lane
+// masks too (ballots of the comparisons) and applied with lane_in().  Returns
+// true once no lane is left active.
+__device__ __forceinline__ bool blend_one(PixelState& ps, uint64_t& active, const StagedSplat& s, int32_t idx,
+                                          const BlendConsts& k) {
+    const uint64_t inr = active & wave_ballot(in_rect(s, ps.pxy));
+    if (inr == 0) return false;  // the whole wave skips this splat
     const float dx = s.u - ps.pcx, dy = s.v - ps.pcy;
-    float G;
-    const float alpha = fminf(o.alpha_max, raw_alpha(s, dx, dy, &G));
-    const float Tn = ps.T * (1.f - alpha);
-    const bool hit = inr & !(alpha < o.alpha_min);
-    const bool stop = hit & (Tn < o.t_min);
-    const bool take = hit & !stop;
-    const float w = alpha * ps.T;
-    ps.c[0] = take ? fmaf(s.r, w, ps.c[0]) : ps.c[0];
-    ps.c[1] = take ? fmaf(s.g, w, ps.c[1]) : ps.c[1];
-    ps.c[2] = take ? fmaf(s.b, w, ps.c[2]) : ps.c[2];
-    ps.T = take ? Tn : ps.T;
+    // min(alpha_max, sigma e^power) as one clamp: the raw value is never negative
+    const float alpha = __builtin_amdgcn_fmed3f(raw_alpha(s, dx, dy), 0.f, k.alpha_max);
+    const float Tn = fmaf(-ps.T, alpha, ps.T);
+    const uint64_t hit = inr & wave_ballot(!(alpha < k.alpha_min));
+    const uint64_t stop = hit & wave_ballot(Tn < k.t_min);
+    const bool take = lane_in(hit & ~stop);
+    // weight T - T': alpha T where the splat is taken, exactly +0 elsewhere
+    // (colours are finite and >= 0, so adding r * 0 leaves the sums unchanged)
+    const float T1 = take ? Tn : ps.T;
+    const float w = ps.T - T1;
+    ps.c[0] = fmaf(s.r, w, ps.c[0]);
+    ps.c[1] = fmaf(s.g, w, ps.c[1]);
+    ps.c[2] = fmaf(s.b, w, ps.c[2]);
+    ps.T = T1;
     ps.last = take ? idx : ps.last;
-    if (__ballot(stop) == 0) return false;
-    ps.done = ps.done | stop;
-    return __ballot(!ps.done) == 0;
+    if (stop == 0) return false;
+    active &= ~stop;
+    return active == 0;
 }
 
-// Composites the staged splats batch[0, cnt) (cnt >= 1), whose first entry has
-// index idx0 in the tile's list, front to back.  Two records alternate in
-// registers so that the next one is read from LDS while the current one is
-// blended; the wave leaves once all its lanes have stopped.
-__device__ __forceinline__ void composite_batch(PixelState& ps, const StagedSplat* batch, int cnt, int32_t idx0,
-                                                const KOpts& o) {
-    if (__ballot(!ps.done) == 0) return;
-    StagedSplat s0 = batch[0], s1;
-    int j = 0;
-    while (true) {
-        s1 = batch[j + 1 < cnt ? j + 1 : j];
-        if (blend_one(ps, s0, idx0 + j, o) || ++j >= cnt) return;
-        s0 = batch[j + 1 < cnt ? j + 1 : j];
-        if (blend_one(ps, s1, idx0 + j, o) || ++j >= cnt) return;
+// ---- pixel layout and per-wave splat lists
+//
+// A TW x TH tile (both multiples of 8) is split into 8x8 quadrants, one per
+// wave: wave w owns quadrant (w % (TW/8), w / (TW/8)) and its lane l the
+// pixel (l % 8, l / 8) inside it.  When a batch is staged, every staged splat
+// is tested against each quadrant's pixel block; the wave-wide ballots of
+// those tests (one 64-bit mask per staging wave and quadrant) let each wave
+// walk only the splats whose rectangle meets its quadrant, in list order.
+
+template <int TW>
+__device__ __forceinline__ void quadrant_pixel(int x0, int y0, int* px, int* py) {
+    const int w = threadIdx.x / kWave, l = int(lane_id());
+    *px = x0 + (w % (TW / 8)) * 8 + (l & 7);
+    *py = y0 + (w / (TW / 8)) * 8 + (l >> 3);
+}
+
+// Ballots of "this staged splat meets quadrant q" into masks[q * NW + staging wave].
+template <int TW, int TH>
+__device__ __forceinline__ void stage_quadrant_masks(const StagedSplat& s, bool valid, int x0, int y0,
+                                                     uint64_t* masks) {
+    constexpr int QX = TW / 8, NQ = (TW / 8) * (TH / 8), NW = TW * TH / kWave;
+    const int rx0 = int(s.rxy & 0xffffu), ry0 = int(s.rxy >> 16);
+    const int rx1 = rx0 + int(s.rwh & 0xffffu), ry1 = ry0 + int(s.rwh >> 16);
+    const int w = threadIdx.x / kWave;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const int qx0 = x0 + (q % QX) * 8, qy0 = y0 + (q / QX) * 8;
+        const bool meets = valid && rx0 <= qx0 + 7 && rx1 >= qx0 && ry0 <= qy0 + 7 && ry1 >= qy0;
+        const uint64_t b = wave_ballot(meets);
+        if (lane_id() == 0) masks[q * NW + w] = b;
+    }
+}
+
+// The value of lane 0, as a wave-uniform (scalar) value.  readfirstlane
+// returns a signed int: each half goes through uint32_t so that the low word
+// is not sign-extended into the high one.
+__device__ __forceinline__ uint64_t uniform_u64(uint64_t v) {
+    const uint32_t lo = uint32_t(__builtin_amdgcn_readfirstlane(int(uint32_t(v))));
+    const uint32_t hi = uint32_t(__builtin_amdgcn_readfirstlane(int(uint32_t(v >> 32))));
+    return uint64_t(lo) | (uint64_t(hi) << 32);
+}
+
+// The set bits of a wave's NW quadrant masks (held in scalar registers), in
+// increasing order (Forward) or decreasing order; next() returns -1 at the end.
+template <int NW, bool Forward>
+struct MaskWalk {
+    uint64_t mk[NW];
+    uint64_t m;
+    int sw;
+
+    __device__ __forceinline__ void init(const uint64_t* quadrant_masks) {
+#pragma unroll
+        for (int w = 0; w < NW; ++w) mk[w] = uniform_u64(quadrant_masks[w]);
+        sw = Forward ? 0 : NW - 1;
+        m = mk[sw];
+    }
+    __device__ __forceinline__ uint64_t pick(int w) const {
+        uint64_t r = mk[0];
+#pragma unroll
+        for (int i = 1; i < NW; ++i) r = (w == i) ? mk[i] : r;
+        return r;
+    }
+    __device__ __forceinline__ int next() {
+        while (m == 0) {
+            sw += Forward ? 1 : -1;
+            if (sw < 0 || sw >= NW) return -1;
+            m = pick(sw);
+        }
+        const int j = Forward ? __builtin_ctzll(m) : 63 - __builtin_clzll(m);
+        m &= ~(uint64_t(1) << j);
+        return sw * kWave + j;
+    }
+};
+
+// Composites, front to back, the staged splats of the batch that meet this
+// wave's quadrant (entry j of the batch has index idx0 + j in the tile's
+// list): the set bits of the wave's masks, in order.  Inside a mask word two
+// records alternate in registers, so the next one is read from LDS while the
+// current one is blended.  The wave leaves once all its lanes have stopped
+// (`active` empty).
+template <int NW>
+__device__ __forceinline__ void composite_batch(PixelState& ps, uint64_t& active, const StagedSplat* batch,
+                                                const uint64_t* quadrant_masks, int32_t idx0, const BlendConsts& k) {
+    if (active == 0) return;
+    uint64_t mk[NW];
+#pragma unroll
+    for (int w = 0; w < NW; ++w) mk[w] = uniform_u64(quadrant_masks[w]);
+#pragma unroll
+    for (int sw = 0; sw < NW; ++sw) {
+        uint64_t m = mk[sw];
+        if (m == 0) continue;
+        const StagedSplat* wb = batch + sw * kWave;
+        const int32_t wi = idx0 + sw * kWave;
+        int j0 = __builtin_ctzll(m), j1;
+        m &= m - 1;
+        StagedSplat s0 = wb[j0], s1;
+        // the read ahead is unconditional (the last record is read again) so
+        // that no branch separates it from its use
+        while (true) {
+            const bool more1 = m != 0;
+            j1 = more1 ? __builtin_ctzll(m) : j0;
+            m &= m - 1;
+            s1 = wb[j1];
+            if (blend_one(ps, active, s0, wi + j0, k)) return;
+            if (!more1) break;
+            const bool more0 = m != 0;
+            j0 = more0 ? __builtin_ctzll(m) : j1;
+            m &= m - 1;
+            s0 = wb[j0];
+            if (blend_one(ps, active, s1, wi + j1, k)) return;
+            if (!more0) break;
+        }
     }
 }
 

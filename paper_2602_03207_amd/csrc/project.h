@@ -138,11 +138,10 @@ struct ProjState {
 __device__ __forceinline__ bool finitef(float x) { return __builtin_isfinite(x); }
 
 // Geometry and colour of Gaussian i for camera `cam`, SH degree DEG (equal to
-// o.sh_degree).  Returns st.visible.  When `need_color` is false the SH
-// coefficients are not read.
+// o.sh_degree).  Returns st.visible.
 template <int DEG>
 __device__ __forceinline__ bool compute_projection(const GaussPtrs& g, int64_t i, const ws_camera& cam,
-                                                   const KOpts& o, ProjState& st, bool need_color = true) {
+                                                   const KOpts& o, ProjState& st) {
     const int64_t n = g.n;
     st.alive = false;
     st.visible = false;
@@ -248,7 +247,6 @@ __device__ __forceinline__ bool compute_projection(const GaussPtrs& g, int64_t i
     st.tiles = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
     st.visible = true;
 
-    if (!need_color) return true;
     // View-dependent colour
     float dx = mx - cam.C[0], dy = my - cam.C[1], dz = mz - cam.C[2];
     st.dir_norm = sqrtf(dx * dx + dy * dy + dz * dz);
@@ -263,6 +261,13 @@ __device__ __forceinline__ bool compute_projection(const GaussPtrs& g, int64_t i
     for (int k = 0; k < K; ++k) {
 #pragma unroll
         for (int ch = 0; ch < 3; ++ch) col[ch] = fmaf(g.sh[(int64_t(k) * 3 + ch) * n + i], Y[k], col[ch]);
+    }
+    // a non-finite colour (non-finite SH coefficient) culls the splat as degenerate
+    if (!(finitef(col[0]) && finitef(col[1]) && finitef(col[2]))) {
+        st.alive = false;
+        st.visible = false;
+        st.tiles = 0;
+        return false;
     }
 #pragma unroll
     for (int ch = 0; ch < 3; ++ch) {

@@ -4,11 +4,14 @@
 //                             tile-sorted key list (boundary where key >> 32
 //                             changes); tiles without pairs keep [0, 0).
 // k_render<TW, TH>            one workgroup of TW*TH threads per tile, one
-//                             pixel per thread.  The tile's splats are staged
-//                             in LDS in batches of TW*TH records (each thread
-//                             gathers one 48-byte record); every lane then
-//                             walks the batch front to back.  The workgroup
-//                             leaves as soon as all its pixels have stopped.
+//                             pixel per thread, one 8x8 quadrant per wave.
+//                             The tile's splats are staged in LDS in batches
+//                             of TW*TH records (each thread gathers one
+//                             48-byte record) together with per-quadrant
+//                             ballot masks; every wave then walks, front to
+//                             back, the staged splats that meet its quadrant.
+//                             The workgroup leaves as soon as all its pixels
+//                             have stopped.
 // k_tile_classes / k_tile_order  (WS_FLAG_ORDERED_RENDER) group the tiles by
 //                             the power of two of their pair count and list
 //                             them longest first;
@@ -59,26 +62,45 @@ struct RenderArgs {
     KOpts o;
 };
 
-// Composites global tile g into the images.  s_batch: NT staged records.
+// Staging of one batch: thread t stages list entry b0 + t (if any) and the
+// quadrant masks of the batch are formed; the caller synchronises afterwards.
 template <int TW, int TH>
-__device__ __forceinline__ void render_tile(const RenderArgs& a, int64_t g, StagedSplat* s_batch) {
-    constexpr int NT = TW * TH;
+__device__ __forceinline__ void stage_batch(const RenderArgs& a, const ws_splat* vsplats, uint32_t b0, uint32_t end,
+                                            int x0, int y0, StagedSplat* s_batch, uint64_t* s_masks) {
+    const uint32_t idx = b0 + threadIdx.x;
+    StagedSplat s = empty_splat();
+    bool valid = false;
+    if (idx < end) {
+        const uint32_t id = a.values[idx];
+        if (id < uint64_t(a.n)) {
+            s = stage_splat(vsplats, id);
+            valid = true;
+        }
+        s_batch[threadIdx.x] = s;
+    }
+    stage_quadrant_masks<TW, TH>(s, valid, x0, y0, s_masks);
+}
+
+// Composites global tile g into the images.
+template <int TW, int TH>
+__device__ __forceinline__ void render_tile(const RenderArgs& a, int64_t g, StagedSplat* s_batch, uint64_t* s_masks) {
+    constexpr int NT = TW * TH, NW = NT / kWave;
     const TileInfo ti = locate_tile(a.cams, a.n_views, g, TW, TH);
-    const int px = ti.x0 + int(threadIdx.x % TW), py = ti.y0 + int(threadIdx.x / TW);
+    int px, py;
+    quadrant_pixel<TW>(ti.x0, ti.y0, &px, &py);
     const bool inside = px < ti.W && py < ti.H;
     const uint32_t start = a.ranges[2 * g], end = a.ranges[2 * g + 1];
     const ws_splat* vsplats = a.splats + int64_t(ti.view) * a.n;
+    const uint64_t* my_masks = s_masks + (threadIdx.x / kWave) * NW;
     PixelState ps;
-    ps.init(px, py, !inside);
+    ps.init(px, py);
+    uint64_t active = wave_ballot(inside);  // lanes whose pixel is still compositing
+    const BlendConsts bk(a.o);
     for (uint32_t b0 = start; b0 < end; b0 += NT) {
-        if (__syncthreads_count(ps.done) == NT) break;
-        const uint32_t idx = b0 + threadIdx.x;
-        if (idx < end) {
-            const uint32_t id = a.values[idx];
-            s_batch[threadIdx.x] = id < uint64_t(a.n) ? stage_splat(vsplats, id) : empty_splat();
-        }
+        if (__syncthreads_count(!lane_in(active)) == NT) break;
+        stage_batch<TW, TH>(a, vsplats, b0, end, ti.x0, ti.y0, s_batch, s_masks);
         __syncthreads();
-        composite_batch(ps, s_batch, int(min<uint32_t>(NT, end - b0)), int32_t(b0 - start), a.o);
+        composite_batch<NW>(ps, active, s_batch, my_masks, int32_t(b0 - start), bk);
     }
     if (inside) {
         float* img = a.images + ti.img_off;
@@ -92,9 +114,11 @@ __device__ __forceinline__ void render_tile(const RenderArgs& a, int64_t g, Stag
 
 template <int TW, int TH>
 __global__ __launch_bounds__(TW * TH) void k_render(RenderArgs a) {
+    constexpr int NW = TW * TH / kWave;
     __shared__ StagedSplat s_batch[TW * TH];
+    __shared__ uint64_t s_masks[NW * NW];
     if (*a.d_status != 0) return;
-    render_tile<TW, TH>(a, blockIdx.x, s_batch);
+    render_tile<TW, TH>(a, blockIdx.x, s_batch, s_masks);
 }
 
 // ---- ordered, persistent render
@@ -147,7 +171,9 @@ __global__ __launch_bounds__(256) void k_tile_order(const uint32_t* ranges, int6
 // end; each take advances the counter, so every workgroup leaves.
 template <int TW, int TH>
 __global__ __launch_bounds__(TW * TH) void k_render_queue(RenderArgs a, const uint32_t* order, uint32_t* queue) {
+    constexpr int NW = TW * TH / kWave;
     __shared__ StagedSplat s_batch[TW * TH];
+    __shared__ uint64_t s_masks[NW * NW];
     __shared__ uint32_t s_q;
     if (*a.d_status != 0) return;
     while (true) {
@@ -156,7 +182,7 @@ __global__ __launch_bounds__(TW * TH) void k_render_queue(RenderArgs a, const ui
         const uint32_t q = s_q;
         __syncthreads();
         if (int64_t(q) >= a.total_tiles) break;
-        render_tile<TW, TH>(a, order[q], s_batch);
+        render_tile<TW, TH>(a, order[q], s_batch, s_masks);
     }
 }
 
