@@ -317,9 +317,22 @@ def bench_large(args):
     total_bytes = pre_bytes + emit_bytes + sort_bytes
     total_ms = t_pre + t_sort
     gbs = total_bytes / (total_ms * 1e-3) / 1e9
+    # context: a plain device-to-device copy of 1 GiB (read + write) on the same GPU
+    src = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    c0.record()
+    for _ in range(5):
+        dst.copy_(src)
+    c1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 2 * src.numel() * 4 * 5 / (c0.elapsed_time(c1) * 1e-3) / 1e9
+    del src, dst
     return {"n": n, "pairs": m, "visible": n_v, "passes": passes, "preprocess_sort_bytes": total_bytes,
             "preprocess_sort_ms": round(total_ms, 4), "achieved_GBs": round(gbs, 1),
-            "hbm_frac": round(gbs / HBM_PEAK_GBS, 4),
+            "hbm_frac": round(gbs / HBM_PEAK_GBS, 4), "copy_1GiB_GBs": round(copy_gbs, 1),
+            "frac_of_copy": round(gbs / copy_gbs, 4),
             "kernels_ms_per_frame": {k: round(v["ms_per_frame"], 4) for k, v in kt.items()},
             "note": "opacity survivors counted as the scale/rotation readers (an upper bound on that term)"}
 

@@ -9,14 +9,14 @@
 //               entry's fp32 depth bits are written too and the list is then
 //               stably sorted by depth.
 // counts        prefix sum of the listed entries' tile counts: each entry's
-//               first pair, the total M, and for every 1024-pair block of the
+//               first pair, the total M, and for every 2048-pair block of the
 //               output the entry that owns its first pair.
-// k_emit        one workgroup per 1024 pairs: loads the entries that cover
-//               its pairs, finds each pair's owner by marking the entry starts
-//               in LDS and taking a running maximum, and writes
-//               key = (tile << 32) | depth bits, value = Gaussian id with
-//               coalesced stores.  Work per workgroup is fixed, whatever the
-//               size of the splats.
+// k_emit        one workgroup per 2048 pairs, in rounds of up to 256 entries:
+//               loads the entries that cover the round's pairs, finds each
+//               pair's owner by marking the entry starts in LDS and taking a
+//               running maximum, and writes key = (tile << 32) | depth bits,
+//               value = Gaussian id with coalesced stores.  Work per
+//               workgroup is fixed, whatever the size of the splats.
 // Both prefix sums are the wait-free hierarchical scan of scan.h.
 #include "project.h"
 #include "scan.h"
@@ -27,9 +27,9 @@ namespace {
 
 constexpr int kPreThreads = 256;
 constexpr int kEmitThreads = 256;
-constexpr int kEmitItems = 4;
+constexpr int kEmitItems = 8;
 constexpr int kEmitPairs = kEmitThreads * kEmitItems;  // pairs per emission workgroup
-constexpr int kEmitSlots = kEmitPairs + 1;             // entries one emission workgroup may need
+constexpr int kEmitSlots = kEmitThreads;               // entries loaded per round
 
 struct PreprocessWs {
     uint32_t* list_a;       // [V n] visible entries in index order
@@ -67,7 +67,7 @@ size_t layout(void* ws, int64_t n, int32_t n_views, int64_t capacity, bool depth
         p.list_b = reinterpret_cast<uint32_t*>(take(size_t(ents) * 4));
         p.dkey_a = reinterpret_cast<uint64_t*>(take(size_t(ents) * 8));
         p.dkey_b = reinterpret_cast<uint64_t*>(take(size_t(ents) * 8));
-        p.sort_ws = take(sort_workspace(ents, 0, 31, 8));
+        p.sort_ws = take(sort_workspace(ents, 0, 31, 8, true));
     }
     if (out) *out = p;
     return off;
@@ -156,6 +156,7 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(EmitArgs a) {
     __shared__ uint32_t s_tbase[kEmitSlots];
     __shared__ uint32_t s_tilesx[kEmitSlots];
     __shared__ uint32_t s_scan[kEmitThreads / kWave + 1];
+    __shared__ int64_t s_hi;
     if (*a.d_status != 0) return;
     const int64_t m = *a.d_num_pairs;
     if (m > a.capacity) {  // the caller's buffers are too small: report, write nothing
@@ -166,17 +167,20 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(EmitArgs a) {
     if (p0 >= m) return;
     const int64_t p1 = min(p0 + kEmitPairs, m);
     const int64_t nvis = *a.d_nvis;
-    const int64_t e0 = a.first_entry[blockIdx.x];
-    for (int q = threadIdx.x; q < kEmitPairs; q += kEmitThreads) s_owner[q] = 0;
-    __syncthreads();
-    // entries e0, e0 + 1, ... until one starts at or after p1
-    for (int chunk = 0; chunk * kEmitThreads < kEmitSlots; ++chunk) {
-        const int slot = chunk * kEmitThreads + threadIdx.x;
-        const int64_t e = e0 + slot;
-        const bool in = slot < kEmitSlots && e < nvis && int64_t(a.offsets[e]) < p1;
+    // Rounds: entries e, e + 1, ..., e + kEmitSlots - 1 (entry e owns pair lo)
+    // cover the pairs [lo, hi), hi = the first pair of entry e + kEmitSlots
+    // (or p1).  Entry starts strictly increase: every listed entry has pairs.
+    int64_t e = a.first_entry[blockIdx.x];
+    int64_t lo = p0;
+    while (lo < p1) {
+        for (int q = threadIdx.x; q < kEmitPairs; q += kEmitThreads) s_owner[q] = 0;
+        __syncthreads();
+        const int slot = threadIdx.x;
+        const int64_t ent = e + slot;
+        const bool in = ent < nvis && int64_t(a.offsets[ent]) < p1;
         if (in) {
-            const uint32_t start = a.offsets[e];
-            const uint32_t idx = a.list[e];
+            const uint32_t start = a.offsets[ent];
+            const uint32_t idx = a.list[ent];
             const int64_t view = int64_t(idx) / a.n;
             const float4 r2 = reinterpret_cast<const float4*>(a.splats + idx)[2];
             const uint32_t r01 = __float_as_uint(r2.z), r23 = __float_as_uint(r2.w);
@@ -191,52 +195,65 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(EmitArgs a) {
             s_tilesx[slot] = uint32_t(ceil_div(a.cams[view].width, a.tile_w));
             if (slot > 0) s_owner[int64_t(start) - p0] = uint32_t(slot);
         }
-        // continue while the last slot of this chunk still starts before p1
-        const bool more = __syncthreads_or(in && threadIdx.x == kEmitThreads - 1);
-        if (!more) break;
-    }
-    __syncthreads();
-    // owner of pair q = the largest slot that starts at or before q (slot 0 holds p0)
-    uint32_t own[kEmitItems];
-    uint32_t run = 0;
-#pragma unroll
-    for (int j = 0; j < kEmitItems; ++j) {
-        run = max(run, s_owner[threadIdx.x * kEmitItems + j]);
-        own[j] = run;
-    }
-    // exclusive max-scan of the threads' last owners
-    {
-        uint32_t v = run;
-        const uint32_t lane = lane_id();
-#pragma unroll
-        for (int d = 1; d < kWave; d <<= 1) {
-            const uint32_t o = __shfl_up(v, d, kWave);
-            if (lane >= uint32_t(d)) v = max(v, o);
+        if (threadIdx.x == 0) {
+            const int64_t next = e + kEmitSlots;
+            s_hi = next < nvis ? min(p1, int64_t(a.offsets[next])) : p1;
         }
-        const int wave = threadIdx.x / kWave;
-        if (lane == kWave - 1) s_scan[wave] = v;
         __syncthreads();
-        uint32_t before = 0;
-        for (int w = 0; w < wave; ++w) before = max(before, s_scan[w]);
-        const uint32_t prev = __shfl_up(v, 1, kWave);
-        if (lane > 0) before = max(before, prev);
+        const int64_t hi = s_hi;
+        // owner of pair q = the largest slot that starts at or before q (slot 0
+        // owns lo; marks before lo were cleared)
+        uint32_t own[kEmitItems];
+        uint32_t run = 0;
 #pragma unroll
-        for (int j = 0; j < kEmitItems; ++j) own[j] = max(own[j], before);
-    }
-#pragma unroll
-    for (int j = 0; j < kEmitItems; ++j) {
-        const int64_t p = p0 + threadIdx.x * kEmitItems + j;
-        if (p < p1) {
-            const uint32_t s = own[j];
-            const uint32_t k = uint32_t(p - int64_t(s_start[s]));
-            const uint32_t xr = s_trx[s], yr = s_try[s];
-            const uint32_t tx0 = xr & 0xffffu, tx1 = xr >> 16, ty0 = yr & 0xffffu;
-            const uint32_t w = tx1 - tx0 + 1;
-            const uint32_t row = k / w, col = k - row * w;
-            const uint64_t tile = uint64_t(s_tbase[s]) + uint64_t(ty0 + row) * s_tilesx[s] + (tx0 + col);
-            a.keys[p] = (tile << 32) | s_depth[s];
-            a.values[p] = s_gid[s];
+        for (int j = 0; j < kEmitItems; ++j) {
+            run = max(run, s_owner[threadIdx.x * kEmitItems + j]);
+            own[j] = run;
         }
+        // exclusive max-scan of the threads' last owners
+        {
+            uint32_t v = run;
+            const uint32_t lane = lane_id();
+#pragma unroll
+            for (int d = 1; d < kWave; d <<= 1) {
+                const uint32_t o = __shfl_up(v, d, kWave);
+                if (lane >= uint32_t(d)) v = max(v, o);
+            }
+            const int wave = threadIdx.x / kWave;
+            if (lane == kWave - 1) s_scan[wave] = v;
+            __syncthreads();
+            uint32_t before = 0;
+            for (int w = 0; w < wave; ++w) before = max(before, s_scan[w]);
+            const uint32_t prev = __shfl_up(v, 1, kWave);
+            if (lane > 0) before = max(before, prev);
+#pragma unroll
+            for (int j = 0; j < kEmitItems; ++j) own[j] = max(own[j], before);
+        }
+        // hand the owners over through LDS so that consecutive lanes write
+        // consecutive pairs (the scan above runs on consecutive pairs per thread)
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kEmitItems; ++j) s_owner[threadIdx.x * kEmitItems + j] = own[j];
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < kEmitItems; ++j) {
+            const int q = j * kEmitThreads + threadIdx.x;
+            const int64_t p = p0 + q;
+            if (p >= lo && p < hi) {
+                const uint32_t s = s_owner[q];
+                const uint32_t k = uint32_t(p - int64_t(s_start[s]));
+                const uint32_t xr = s_trx[s], yr = s_try[s];
+                const uint32_t tx0 = xr & 0xffffu, tx1 = xr >> 16, ty0 = yr & 0xffffu;
+                const uint32_t w = tx1 - tx0 + 1;
+                const uint32_t row = k / w, col = k - row * w;
+                const uint64_t tile = uint64_t(s_tbase[s]) + uint64_t(ty0 + row) * s_tilesx[s] + (tx0 + col);
+                a.keys[p] = (tile << 32) | s_depth[s];
+                a.values[p] = s_gid[s];
+            }
+        }
+        e += kEmitSlots;
+        lo = hi;
+        __syncthreads();  // the next round reuses the LDS
     }
 }
 
@@ -274,8 +291,9 @@ hipError_t launch_preprocess(const GaussPtrs& g, const ws_camera* d_cams, int32_
     const uint32_t* list = pw.list_a;
     if (depth_first) {
         // stable sort of the visible entries by depth: positive fp32 bits order like the values
+        // the visible entries are typically a small fraction of all (view, Gaussian) entries
         const hipError_t e = launch_sort(pw.dkey_a, pw.list_a, pw.dkey_b, pw.list_b, std::max<int64_t>(pw.total, 1),
-                                         pw.d_nvis, d_status, 0, 31, 8, pw.sort_ws, stream, false);
+                                         pw.d_nvis, d_status, 0, 31, 8, pw.sort_ws, stream, false, true);
         if (e != hipSuccess) return e;
         list = pw.list_b;
     }

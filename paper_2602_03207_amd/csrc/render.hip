@@ -35,17 +35,46 @@ __global__ void k_ranges_clear(uint32_t* ranges, int64_t words, uint32_t* counte
     if (counter && blockIdx.x == 0 && threadIdx.x == 0) *counter = 0;
 }
 
-__global__ void k_ranges(const uint64_t* __restrict__ keys, int64_t cap, const int64_t* d_n,
-                         const int32_t* d_status, uint32_t* __restrict__ ranges, int64_t total_tiles) {
+// Grid-stride over chunks of 8 x 256 consecutive pairs: every key is loaded
+// once (coalesced, all 8 loads of a thread in flight together), its
+// predecessor and successor come from the neighbouring lanes (the wave's end
+// lanes load theirs), and a tile's start / end is written where the tile id
+// changes.
+constexpr int kRangeThreads = 256;
+constexpr int kRangeItems = 8;
+
+__global__ __launch_bounds__(kRangeThreads) void k_ranges(const uint64_t* __restrict__ keys, int64_t cap,
+                                                          const int64_t* d_n, const int32_t* d_status,
+                                                          uint32_t* __restrict__ ranges, int64_t total_tiles) {
     if (*d_status != 0) return;
     int64_t m = *d_n;
     m = m < cap ? m : cap;
-    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
-    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < m; i += stride) {
-        const uint32_t t = uint32_t(keys[i] >> 32);
-        if (int64_t(t) >= total_tiles) continue;  // keys from ws_preprocess never exceed it
-        if (i == 0 || uint32_t(keys[i - 1] >> 32) != t) ranges[2 * int64_t(t)] = uint32_t(i);
-        if (i == m - 1 || uint32_t(keys[i + 1] >> 32) != t) ranges[2 * int64_t(t) + 1] = uint32_t(i + 1);
+    const uint32_t lane = lane_id();
+    constexpr int64_t kChunk = int64_t(kRangeThreads) * kRangeItems;
+    const int64_t stride = int64_t(gridDim.x) * kChunk;
+    for (int64_t base = int64_t(blockIdx.x) * kChunk; base < m; base += stride) {
+        // the wave's end lanes also load the neighbour outside the wave
+        const int64_t off = lane == 0 ? -1 : (lane == kWave - 1 ? 1 : 0);
+        uint32_t t[kRangeItems], edge[kRangeItems];
+#pragma unroll
+        for (int j = 0; j < kRangeItems; ++j) {
+            const int64_t i = base + j * kRangeThreads + threadIdx.x;
+            t[j] = i < m ? uint32_t(keys[i] >> 32) : 0xffffffffu;
+            const int64_t ie = i + off;
+            edge[j] = (off != 0 && ie >= 0 && ie < m) ? uint32_t(keys[ie] >> 32) : 0xffffffffu;
+        }
+#pragma unroll
+        for (int j = 0; j < kRangeItems; ++j) {
+            const int64_t i = base + j * kRangeThreads + threadIdx.x;
+            uint32_t prev = uint32_t(__shfl_up(int(t[j]), 1, kWave));
+            if (lane == 0) prev = edge[j];
+            uint32_t next = uint32_t(__shfl_down(int(t[j]), 1, kWave));
+            if (lane == kWave - 1) next = edge[j];
+            if (i < m && int64_t(t[j]) < total_tiles) {  // keys from ws_preprocess never exceed it
+                if (i == 0 || prev != t[j]) ranges[2 * int64_t(t[j])] = uint32_t(i);
+                if (i == m - 1 || next != t[j]) ranges[2 * int64_t(t[j]) + 1] = uint32_t(i + 1);
+            }
+        }
     }
 }
 
@@ -257,7 +286,9 @@ hipError_t launch_render(const ws_splat* splats, int64_t n, const ws_camera* d_c
     const uint32_t cgrid = uint32_t(std::min<int64_t>(std::max<int64_t>((words + 255) / 256, 1), 4096));
     timing_begin(WS_KERNEL_RANGES, stream);
     hipLaunchKernelGGL(k_ranges_clear, dim3(cgrid), dim3(256), 0, stream, tile_ranges, words, (uint32_t*)nullptr);
-    hipLaunchKernelGGL(k_ranges, dim3(2048), dim3(256), 0, stream, keys, capacity, d_num_pairs, d_status,
+    const int64_t rchunk = int64_t(kRangeThreads) * kRangeItems;
+    const uint32_t rgrid = uint32_t(std::min<int64_t>(std::max<int64_t>((capacity + rchunk - 1) / rchunk, 1), 4096));
+    hipLaunchKernelGGL(k_ranges, dim3(rgrid), dim3(kRangeThreads), 0, stream, keys, capacity, d_num_pairs, d_status,
                        tile_ranges, total_tiles);
     timing_end(WS_KERNEL_RANGES, stream);
     if (total_tiles == 0) return hipGetLastError();

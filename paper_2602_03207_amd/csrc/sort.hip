@@ -13,7 +13,8 @@
 // large inputs, 1024 for small ones so that they still spread over the CUs.
 //
 // Two schedules compute base_d + prefix_wg; they give identical bits:
-//  * look-back (small inputs, up to kSmallSortMax pairs): base_d from one
+//  * look-back (small inputs, up to kSmallSortMax pairs, or inputs whose
+//    device count is known to be far below the capacity): base_d from one
 //    histogram of all passes (k_sort_hist), prefix_wg by a decoupled look-back
 //    over per-tile counts published in device memory.  Tiles take an atomic
 //    ticket, so a tile only waits for tiles that have started, and the wait is
@@ -42,6 +43,7 @@ constexpr int64_t kSmallSortMax = 1 << 20;   // capacities up to this use small 
 constexpr int kHistThreads = 256;
 constexpr int kMaxBins = 2048;  // passes * radix over every radix width
 constexpr int kLook = 16;       // predecessor tiles read at once by the look-back
+constexpr int64_t kLookbackGrid = 1024;  // workgroups of a look-back pass at most
 constexpr uint32_t kStAgg = 1u << 30;
 constexpr uint32_t kStInc = 2u << 30;
 constexpr uint32_t kStMask = (1u << 30) - 1;
@@ -61,15 +63,16 @@ struct SortLayout {
 
 int default_radix(int r) { return r <= 0 ? 8 : r; }
 
-size_t plan(void* ws, int64_t capacity, int begin_bit, int end_bit, int radix_bits, SortLayout* out) {
+size_t plan(void* ws, int64_t capacity, int begin_bit, int end_bit, int radix_bits, bool sparse, SortLayout* out) {
     SortLayout L{};
     L.r = default_radix(radix_bits);
     L.radix = 1 << L.r;
     L.passes = (end_bit - begin_bit + L.r - 1) / L.r;
-    L.items = capacity <= kSmallSortMax ? kItemsSmall : kItemsLarge;
+    const bool small = sparse || capacity <= kSmallSortMax;
+    L.items = small ? kItemsSmall : kItemsLarge;
     const int64_t tile = int64_t(kSortThreads) * L.items;
     L.max_tiles = std::max<int64_t>((capacity + tile - 1) / tile, 1);
-    L.wait_free = capacity > kSmallSortMax;
+    L.wait_free = !small;
     char* base = static_cast<char*>(ws);
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -458,21 +461,9 @@ struct PassArgs {
 };
 
 template <int B, int ITEMS>
-__global__ __launch_bounds__(kSortThreads) void k_sort_pass(PassArgs a) {
+__device__ __forceinline__ void sort_tile_lookback(TileSmem<B, ITEMS>& sm, const PassArgs& a, int64_t n,
+                                                   int64_t tile) {
     constexpr int RADIX = 1 << B;
-    constexpr int kTile = kSortThreads * ITEMS;
-    __shared__ TileSmem<B, ITEMS> sm;
-    if (a.d_status && *a.d_status != 0) return;
-    const int64_t n = device_count(a.cap, a.d_n);
-    const int64_t ntiles = (n + kTile - 1) / kTile;
-    // Workgroups past the live tiles leave before taking a ticket: tickets
-    // 0..ntiles-1 then all go to the ntiles workgroups below, each of which
-    // takes exactly one.
-    if (int64_t(blockIdx.x) >= ntiles) return;
-    if (threadIdx.x == 0) sm.tile = atomicAdd(a.ticket, 1u);
-    clear_whist(sm);
-    __syncthreads();
-    const int64_t tile = sm.tile;
     uint64_t key[ITEMS];
     uint32_t rank[ITEMS];
     uint32_t cnt;
@@ -543,6 +534,29 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_pass(PassArgs a) {
     flush_tile<B, ITEMS>(sm, n, tile, a.shift, rank, val, a.kout, a.vout);
 }
 
+template <int B, int ITEMS>
+__global__ __launch_bounds__(kSortThreads) void k_sort_pass(PassArgs a) {
+    constexpr int kTile = kSortThreads * ITEMS;
+    __shared__ TileSmem<B, ITEMS> sm;
+    if (a.d_status && *a.d_status != 0) return;
+    const int64_t n = device_count(a.cap, a.d_n);
+    const int64_t ntiles = (n + kTile - 1) / kTile;
+    // Workgroups past the live tiles leave before taking a ticket.  The others
+    // take tickets until they run past the live tiles; each tile goes to one
+    // workgroup, and a workgroup only ever waits for tiles with smaller
+    // tickets, which running workgroups hold.
+    if (int64_t(blockIdx.x) >= ntiles) return;
+    while (true) {
+        if (threadIdx.x == 0) sm.tile = atomicAdd(a.ticket, 1u);
+        clear_whist(sm);
+        __syncthreads();
+        const int64_t tile = sm.tile;
+        if (tile >= ntiles) return;
+        sort_tile_lookback<B, ITEMS>(sm, a, n, tile);
+        __syncthreads();  // the tile's LDS is reused by the next ticket
+    }
+}
+
 // ------------------------------------------------ dispatch
 
 struct PassLaunch {
@@ -564,7 +578,9 @@ void run_pass(const PassLaunch& c) {
                               c.L->partials, static_cast<uint32_t*>(nullptr), c.stream);
         hipLaunchKernelGGL((k_downsweep<B, ITEMS>), dim3(grid), dim3(kSortThreads), 0, c.stream, c.da);
     } else {
-        hipLaunchKernelGGL((k_sort_pass<B, ITEMS>), dim3(grid), dim3(kSortThreads), 0, c.stream, c.pa);
+        // workgroups loop over tickets, so the grid need not cover every tile
+        const uint32_t lgrid = uint32_t(std::min<int64_t>(c.L->max_tiles, kLookbackGrid));
+        hipLaunchKernelGGL((k_sort_pass<B, ITEMS>), dim3(lgrid), dim3(kSortThreads), 0, c.stream, c.pa);
     }
 }
 
@@ -584,15 +600,15 @@ void run_pass_bits(const PassLaunch& c, int bits) {
 
 }  // namespace
 
-size_t sort_workspace(int64_t capacity, int32_t begin_bit, int32_t end_bit, int32_t radix_bits) {
-    return plan(nullptr, capacity, begin_bit, end_bit, radix_bits, nullptr);
+size_t sort_workspace(int64_t capacity, int32_t begin_bit, int32_t end_bit, int32_t radix_bits, bool sparse) {
+    return plan(nullptr, capacity, begin_bit, end_bit, radix_bits, sparse, nullptr);
 }
 
 hipError_t launch_sort(const uint64_t* kin, const uint32_t* vin, uint64_t* kout, uint32_t* vout, int64_t n,
                        const int64_t* d_n, const int32_t* d_status, int32_t begin_bit, int32_t end_bit,
-                       int32_t radix_bits, void* ws, hipStream_t stream, bool timed) {
+                       int32_t radix_bits, void* ws, hipStream_t stream, bool timed, bool sparse) {
     SortLayout L;
-    plan(ws, n, begin_bit, end_bit, radix_bits, &L);
+    plan(ws, n, begin_bit, end_bit, radix_bits, sparse, &L);
     const int hist_id = timed ? WS_KERNEL_SORT_HIST : -1, pass_id = timed ? WS_KERNEL_SORT_PASS : -1;
     if (!L.wait_free) {
         hipLaunchKernelGGL(k_sort_init, dim3(1), dim3(256), 0, stream, L.hist, L.passes * L.radix, L.tickets,
@@ -610,7 +626,8 @@ hipError_t launch_sort(const uint64_t* kin, const uint32_t* vin, uint64_t* kout,
         h.hist = L.hist;
         h.status = L.status;
         h.max_tiles = L.max_tiles;
-        const int64_t hist_blocks = std::min<int64_t>(std::max<int64_t>((n + 4095) / 4096, 1), 2048);
+        // few workgroups: each adds its bins to the global histogram once
+        const int64_t hist_blocks = std::min<int64_t>(std::max<int64_t>((n + 4095) / 4096, 1), 256);
         timing_begin(hist_id, stream);
         hipLaunchKernelGGL(k_sort_hist, dim3(uint32_t(hist_blocks)), dim3(kHistThreads), 0, stream, h);
         timing_end(hist_id, stream);

@@ -158,10 +158,13 @@ size_t preprocess_workspace(int64_t n, int32_t n_views, int64_t capacity, uint32
 // sort.hip
 // `timed`: report the launches to the benchmark timing hooks (false for sorts
 // made inside another stage, which that stage's timing already covers).
+// `sparse`: the device count is expected to be far below the capacity; the
+// sort then always takes the small-tile look-back schedule, whose cost follows
+// the live count (workgroups past it leave at once) rather than the capacity.
 hipError_t launch_sort(const uint64_t* kin, const uint32_t* vin, uint64_t* kout, uint32_t* vout, int64_t n,
                        const int64_t* d_n, const int32_t* d_status, int32_t begin_bit, int32_t end_bit,
-                       int32_t radix_bits, void* ws, hipStream_t stream, bool timed = true);
-size_t sort_workspace(int64_t capacity, int32_t begin_bit, int32_t end_bit, int32_t radix_bits);
+                       int32_t radix_bits, void* ws, hipStream_t stream, bool timed = true, bool sparse = false);
+size_t sort_workspace(int64_t capacity, int32_t begin_bit, int32_t end_bit, int32_t radix_bits, bool sparse = false);
 
 // render.hip
 hipError_t launch_render(const ws_splat* splats, int64_t n, const ws_camera* d_cams, int32_t n_views,
