@@ -151,12 +151,12 @@ __device__ __forceinline__ bool lane_in(uint64_t mask) { return __builtin_amdgcn
 // One splat of the list into the pixels of a wave, with the decisions of the
 // rule above.  `active` is the wave's set of lanes whose pixel has not stopped
 // (a lane mask in scalar registers); the per-lane decisions are formed as lane
-// masks too (ballots of the comparisons) and applied with lane_in().  Returns
-// true once no lane is left active.
-__device__ __forceinline__ bool blend_one(PixelState& ps, uint64_t& active, const StagedSplat& s, int32_t idx,
+// masks too (ballots of the comparisons) and applied with lane_in().  A splat
+// that no active lane's rectangle holds changes nothing (all its masks are
+// empty), so it needs no separate test.
+__device__ __forceinline__ void blend_one(PixelState& ps, uint64_t& active, const StagedSplat& s, int32_t idx,
                                           const BlendConsts& k) {
     const uint64_t inr = active & wave_ballot(in_rect(s, ps.pxy));
-    if (inr == 0) return false;  // the whole wave skips this splat
     const float dx = s.u - ps.pcx, dy = s.v - ps.pcy;
     // min(alpha_max, sigma e^power) as one clamp: the raw value is never negative
     const float alpha = __builtin_amdgcn_fmed3f(raw_alpha(s, dx, dy), 0.f, k.alpha_max);
@@ -173,9 +173,7 @@ __device__ __forceinline__ bool blend_one(PixelState& ps, uint64_t& active, cons
     ps.c[2] = fmaf(s.b, w, ps.c[2]);
     ps.T = T1;
     ps.last = take ? idx : ps.last;
-    if (stop == 0) return false;
     active &= ~stop;
-    return active == 0;
 }
 
 // ---- pixel layout and per-wave splat lists
@@ -254,10 +252,10 @@ struct MaskWalk {
 
 // Composites, front to back, the staged splats of the batch that meet this
 // wave's quadrant (entry j of the batch has index idx0 + j in the tile's
-// list): the set bits of the wave's masks, in order.  Inside a mask word two
-// records alternate in registers, so the next one is read from LDS while the
-// current one is blended.  The wave leaves once all its lanes have stopped
-// (`active` empty).
+// list): the set bits of the wave's masks, in order, two per step with both
+// records read from LDS before the first is blended.  The wave leaves once all
+// its lanes have stopped (`active` empty); a splat blended after that changes
+// nothing.
 template <int NW>
 __device__ __forceinline__ void composite_batch(PixelState& ps, uint64_t& active, const StagedSplat* batch,
                                                 const uint64_t* quadrant_masks, int32_t idx0, const BlendConsts& k) {
@@ -268,27 +266,22 @@ __device__ __forceinline__ void composite_batch(PixelState& ps, uint64_t& active
 #pragma unroll
     for (int sw = 0; sw < NW; ++sw) {
         uint64_t m = mk[sw];
-        if (m == 0) continue;
         const StagedSplat* wb = batch + sw * kWave;
         const int32_t wi = idx0 + sw * kWave;
-        int j0 = __builtin_ctzll(m), j1;
-        m &= m - 1;
-        StagedSplat s0 = wb[j0], s1;
-        // the read ahead is unconditional (the last record is read again) so
-        // that no branch separates it from its use
-        while (true) {
-            const bool more1 = m != 0;
-            j1 = more1 ? __builtin_ctzll(m) : j0;
+        while (m != 0) {
+            const int j0 = __builtin_ctzll(m);
             m &= m - 1;
-            s1 = wb[j1];
-            if (blend_one(ps, active, s0, wi + j0, k)) return;
-            if (!more1) break;
-            const bool more0 = m != 0;
-            j0 = more0 ? __builtin_ctzll(m) : j1;
-            m &= m - 1;
-            s0 = wb[j0];
-            if (blend_one(ps, active, s1, wi + j1, k)) return;
-            if (!more0) break;
+            const StagedSplat s0 = wb[j0];
+            if (m != 0) {
+                const int j1 = __builtin_ctzll(m);
+                m &= m - 1;
+                const StagedSplat s1 = wb[j1];
+                blend_one(ps, active, s0, wi + j0, k);
+                blend_one(ps, active, s1, wi + j1, k);
+            } else {
+                blend_one(ps, active, s0, wi + j0, k);
+            }
+            if (active == 0) return;
         }
     }
 }
