@@ -252,8 +252,8 @@ struct MaskWalk {
 
 // Composites, front to back, the staged splats of the batch that meet this
 // wave's quadrant (entry j of the batch has index idx0 + j in the tile's
-// list): the set bits of the wave's masks, in order, two per step with both
-// records read from LDS before the first is blended.  The wave leaves once all
+// list): the set bits of the wave's masks, in order, up to four per step with
+// all records read from LDS before the first is blended.  The wave leaves once all
 // its lanes have stopped (`active` empty); a splat blended after that changes
 // nothing.
 template <int NW>
@@ -269,10 +269,23 @@ __device__ __forceinline__ void composite_batch(PixelState& ps, uint64_t& active
         const StagedSplat* wb = batch + sw * kWave;
         const int32_t wi = idx0 + sw * kWave;
         while (m != 0) {
+            const int left = __builtin_popcountll(m);
             const int j0 = __builtin_ctzll(m);
             m &= m - 1;
             const StagedSplat s0 = wb[j0];
-            if (m != 0) {
+            if (left >= 4) {
+                const int j1 = __builtin_ctzll(m);
+                m &= m - 1;
+                const int j2 = __builtin_ctzll(m);
+                m &= m - 1;
+                const int j3 = __builtin_ctzll(m);
+                m &= m - 1;
+                const StagedSplat s1 = wb[j1], s2 = wb[j2], s3 = wb[j3];
+                blend_one(ps, active, s0, wi + j0, k);
+                blend_one(ps, active, s1, wi + j1, k);
+                blend_one(ps, active, s2, wi + j2, k);
+                blend_one(ps, active, s3, wi + j3, k);
+            } else if (left >= 2) {
                 const int j1 = __builtin_ctzll(m);
                 m &= m - 1;
                 const StagedSplat s1 = wb[j1];

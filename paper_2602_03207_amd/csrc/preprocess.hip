@@ -38,8 +38,8 @@ struct PreprocessWs {
     uint64_t* dkey_b;
     uint32_t* offsets;      // [V n] first pair of each list entry
     uint32_t* first_entry;  // [emit blocks] list entry owning each block's first pair
-    uint64_t* partials_a;   // scan block sums
-    uint64_t* partials_b;
+    void* scan_a;           // workspaces of the two prefix sums
+    void* scan_b;
     int64_t* d_nvis;
     void* sort_ws;
     int64_t total, emit_blocks;
@@ -58,8 +58,8 @@ size_t layout(void* ws, int64_t n, int32_t n_views, int64_t capacity, bool depth
         return ptr;
     };
     p.d_nvis = reinterpret_cast<int64_t*>(take(16));
-    p.partials_a = reinterpret_cast<uint64_t*>(take(size_t(scan_blocks(ents)) * 8));
-    p.partials_b = reinterpret_cast<uint64_t*>(take(size_t(scan_blocks(ents)) * 8));
+    p.scan_a = take(scan_workspace(ents));
+    p.scan_b = take(scan_workspace(ents));
     p.list_a = reinterpret_cast<uint32_t*>(take(size_t(ents) * 4));
     p.offsets = reinterpret_cast<uint32_t*>(take(size_t(ents) * 4));
     p.first_entry = reinterpret_cast<uint32_t*>(take(size_t(p.emit_blocks) * 4));
@@ -287,7 +287,7 @@ hipError_t launch_preprocess(const GaussPtrs& g, const ws_camera* d_cams, int32_
     timing_begin(WS_KERNEL_SCAN_EMIT, stream);
     // compaction of the visible entries (count to d_nvis)
     launch_scan<uint64_t>(FlagLoad{tiles_touched}, CompactStore{splats, pw.list_a, depth_first ? pw.dkey_a : nullptr},
-                          pw.total, nullptr, d_status, pw.partials_a, reinterpret_cast<uint64_t*>(pw.d_nvis), stream);
+                          pw.total, nullptr, d_status, pw.scan_a, reinterpret_cast<uint64_t*>(pw.d_nvis), stream);
     const uint32_t* list = pw.list_a;
     if (depth_first) {
         // stable sort of the visible entries by depth: positive fp32 bits order like the values
@@ -299,7 +299,7 @@ hipError_t launch_preprocess(const GaussPtrs& g, const ws_camera* d_cams, int32_
     }
     // pair offsets of the listed entries (total to d_num_pairs)
     launch_scan<uint64_t>(CountLoad{tiles_touched, list}, CountStore{pw.offsets, pw.first_entry, pw.emit_blocks},
-                          std::max<int64_t>(pw.total, 1), pw.d_nvis, d_status, pw.partials_b,
+                          std::max<int64_t>(pw.total, 1), pw.d_nvis, d_status, pw.scan_b,
                           reinterpret_cast<uint64_t*>(d_num_pairs), stream);
     EmitArgs ea;
     ea.splats = splats;

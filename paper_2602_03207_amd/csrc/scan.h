@@ -1,12 +1,16 @@
-// Wait-free device-wide exclusive prefix sum (reduce, scan of the block sums,
-// down-sweep): the hierarchical scheme of the paper's sort stage (Sec. 3.3.2),
-// each level one dispatch, no workgroup ever waits for another.
+// Device-wide exclusive prefix sums.
 //
-//   k_scan_reduce<T, Loader>     block b sums items [b*kScanBlock, (b+1)*kScanBlock)
-//   k_scan_partials<T>           one workgroup scans the block sums in place
-//                                (exclusive) and optionally stores the total
-//   k_scan_down<T, Loader, Writer>  block b re-reads its items, scans them and
-//                                calls writer(i, exclusive_prefix, value)
+// Two schedules, chosen by the number of 4096-item blocks:
+//  * one pass (up to kOnePassMaxBlocks blocks): every block scans its items in
+//    registers, publishes its sum, reads its predecessors' published sums
+//    (a decoupled look-back: one wave reads 64 predecessors per round trip
+//    and stops at the first inclusive prefix) and writes its results.  Blocks
+//    take an atomic ticket, so a block only waits for blocks that have
+//    started, and the wait is bounded (WS_ERR_SPIN_LIMIT on expiry).  One
+//    read of the items, two launches (clearing the published sums, the pass).
+//  * wait-free (larger inputs): the hierarchical scan of the paper's sort stage
+//    (Sec. 3.3.2) -- reduce, one-workgroup scan of the block sums, down-sweep
+//    -- each level one dispatch, no workgroup ever waits for another.
 //
 // Loader:  __device__ T operator()(int64_t i) const   (i < n)
 // Writer:  __device__ void operator()(int64_t i, T prefix, T value) const
@@ -122,11 +126,133 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_down(Loader ld, Writer wr
 
 inline int64_t scan_blocks(int64_t cap) { return std::max<int64_t>((cap + kScanBlock - 1) / kScanBlock, 1); }
 
-// Launch the three levels.  partials must hold scan_blocks(cap) values of T.
+// ---------------------------------------------------------- one pass
+
+constexpr int64_t kOnePassMaxBlocks = 1024;
+constexpr uint64_t kScanAgg = uint64_t(1) << 62;
+constexpr uint64_t kScanInc = uint64_t(2) << 62;
+constexpr uint64_t kScanVal = (uint64_t(1) << 62) - 1;
+
+template <int Threads>
+__global__ __launch_bounds__(Threads) void k_scan_clear(uint64_t* status, int64_t nb, uint32_t* ticket) {
+    for (int64_t i = threadIdx.x; i < nb; i += Threads) status[i] = 0;
+    if (threadIdx.x == 0) *ticket = 0;
+}
+
+template <class T, class Loader, class Writer>
+__global__ __launch_bounds__(kScanThreads) void k_scan_onepass(Loader ld, Writer wr, int64_t cap, const int64_t* d_n,
+                                                               const int32_t* d_status, uint64_t* status,
+                                                               uint32_t* ticket, T* total_out) {
+    constexpr int kPerWave = kScanItemsPerThread * kWave;
+    __shared__ T s_wave[kScanThreads / kWave];
+    __shared__ T s_excl;
+    __shared__ uint32_t s_block;
+    if (d_status && *d_status != 0) return;
+    const int64_t n = scan_count(cap, d_n);
+    const int64_t nb = (n + kScanBlock - 1) / kScanBlock;
+    if (nb == 0) {
+        if (blockIdx.x == 0 && threadIdx.x == 0 && total_out) *total_out = T(0);
+        return;
+    }
+    // blocks past the live ones leave before taking a ticket
+    if (int64_t(blockIdx.x) >= nb) return;
+    if (threadIdx.x == 0) s_block = atomicAdd(ticket, 1u);
+    __syncthreads();
+    const int64_t b = s_block;
+    const int wave = threadIdx.x / kWave;
+    const uint32_t lane = lane_id();
+    const int64_t wbase = b * kScanBlock + int64_t(wave) * kPerWave + lane;
+    T v[kScanItemsPerThread];
+#pragma unroll
+    for (int j = 0; j < kScanItemsPerThread; ++j) {
+        const int64_t i = wbase + j * kWave;
+        v[j] = i < n ? ld(i) : T(0);
+    }
+    T ex[kScanItemsPerThread];
+    T carry = 0;
+#pragma unroll
+    for (int j = 0; j < kScanItemsPerThread; ++j) {
+        const T inc = wave_inclusive_scan(v[j]);
+        ex[j] = carry + inc - v[j];
+        carry += __shfl(inc, kWave - 1, kWave);
+    }
+    if (lane == 0) s_wave[wave] = carry;
+    __syncthreads();
+    T block_sum = 0, woff = 0;
+#pragma unroll
+    for (int w = 0; w < kScanThreads / kWave; ++w) {
+        if (w < wave) woff += s_wave[w];
+        block_sum += s_wave[w];
+    }
+    if (wave == 0) {
+        if (lane == 0) store_agent(&status[b], (b == 0 ? kScanInc : kScanAgg) | uint64_t(block_sum));
+        T excl = 0;
+        if (b > 0) {
+            int64_t k = b - 1;  // lane l reads predecessor k - l
+            uint32_t spins = 0;
+            while (true) {
+                const int64_t kk = k - int64_t(lane);
+                uint64_t st = kk >= 0 ? load_agent(&status[kk]) : kScanInc;
+                uint64_t need = 0, incm = 0;
+                while (true) {
+                    incm = __ballot((st >> 62) == 2);
+                    const uint64_t zero = __ballot((st >> 62) == 0);
+                    // lanes up to and including the first inclusive prefix
+                    need = incm ? ((incm & (~incm + 1)) << 1) - 1 : ~uint64_t(0);
+                    if ((zero & need) == 0) break;
+                    if (++spins > kSpinLimit) {
+                        if (lane == 0) atomicExch(const_cast<int32_t*>(d_status), int32_t(WS_ERR_SPIN_LIMIT));
+                        need = 0;
+                        incm = 1;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                    if ((st >> 62) == 0) st = load_agent(&status[kk]);
+                }
+                const T part = ((need >> lane) & 1) ? T(st & kScanVal) : T(0);
+                excl += wave_sum(part);
+                if (incm) break;
+                k -= kWave;
+            }
+            if (lane == 0) store_agent(&status[b], kScanInc | uint64_t(excl + block_sum));
+        }
+        if (lane == 0) {
+            s_excl = excl;
+            if (b == nb - 1 && total_out) *total_out = excl + block_sum;
+        }
+    }
+    __syncthreads();
+    const T off = s_excl + woff;
+#pragma unroll
+    for (int j = 0; j < kScanItemsPerThread; ++j) {
+        const int64_t i = wbase + j * kWave;
+        if (i < n) wr(i, off + ex[j], v[j]);
+    }
+}
+
+// Workspace of one scan over up to `cap` items (either schedule), bytes.
+inline size_t scan_workspace(int64_t cap) {
+    const int64_t nb = scan_blocks(cap);
+    return align_up(size_t(nb) * 8) + align_up(8);
+}
+
+// Scans up to `cap` items (the count read from d_n when given).  `ws` holds
+// scan_workspace(cap) bytes; `d_status` (may be null) is also the word a
+// bounded wait that expires reports into.
 template <class T, class Loader, class Writer>
 void launch_scan(const Loader& ld, const Writer& wr, int64_t cap, const int64_t* d_n, const int32_t* d_status,
-                 T* partials, T* total_out, hipStream_t stream) {
+                 void* ws, T* total_out, hipStream_t stream) {
     const int64_t nb = scan_blocks(cap);
+    char* base = static_cast<char*>(ws);
+    if (nb <= kOnePassMaxBlocks && d_status) {
+        uint64_t* status = reinterpret_cast<uint64_t*>(base);
+        uint32_t* ticket = reinterpret_cast<uint32_t*>(base + align_up(size_t(nb) * 8));
+        hipLaunchKernelGGL(k_scan_clear<256>, dim3(1), dim3(256), 0, stream, status, nb, ticket);
+        hipLaunchKernelGGL((k_scan_onepass<T, Loader, Writer>), dim3(uint32_t(nb)), dim3(kScanThreads), 0, stream, ld,
+                           wr, cap, d_n, d_status, status, ticket, total_out);
+        return;
+    }
+    T* partials = reinterpret_cast<T*>(base);
     hipLaunchKernelGGL((k_scan_reduce<T, Loader>), dim3(uint32_t(nb)), dim3(kScanThreads), 0, stream, ld, cap, d_n,
                        d_status, partials);
     hipLaunchKernelGGL((k_scan_partials<T>), dim3(1), dim3(kPartialThreads), 0, stream, partials, nb, d_n, d_status,

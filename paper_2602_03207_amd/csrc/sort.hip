@@ -55,7 +55,7 @@ struct SortLayout {
     uint32_t* status;    // look-back: [passes][max_tiles][radix]
     uint32_t* tickets;   // look-back: [passes]
     uint32_t* table;     // wait-free: [radix][max_tiles]
-    uint32_t* partials;  // wait-free: scan block sums of the table
+    void* table_scan;    // wait-free: workspace of the table's prefix sum
     int64_t max_tiles;
     int passes, r, radix, items;
     bool wait_free;
@@ -87,7 +87,7 @@ size_t plan(void* ws, int64_t capacity, int begin_bit, int end_bit, int radix_bi
     if (L.wait_free) {
         const int64_t entries = int64_t(L.radix) * L.max_tiles;
         L.table = reinterpret_cast<uint32_t*>(take(size_t(entries) * 4));
-        L.partials = reinterpret_cast<uint32_t*>(take(size_t(scan_blocks(entries)) * 4));
+        L.table_scan = take(scan_workspace(entries));
     } else {
         L.hist = reinterpret_cast<uint32_t*>(take(size_t(L.passes) * L.radix * 4));
         L.status = reinterpret_cast<uint32_t*>(take(size_t(L.passes) * L.max_tiles * L.radix * 4));
@@ -575,7 +575,7 @@ void run_pass(const PassLaunch& c) {
         hipLaunchKernelGGL((k_upsweep<B, ITEMS>), dim3(grid), dim3(kSortThreads), 0, c.stream, c.ua);
         const int64_t entries = int64_t(1 << B) * c.L->max_tiles;
         launch_scan<uint32_t>(TableLoad{c.ua.table}, TableStore{c.ua.table}, entries, nullptr, c.d_status,
-                              c.L->partials, static_cast<uint32_t*>(nullptr), c.stream);
+                              c.L->table_scan, static_cast<uint32_t*>(nullptr), c.stream);
         hipLaunchKernelGGL((k_downsweep<B, ITEMS>), dim3(grid), dim3(kSortThreads), 0, c.stream, c.da);
     } else {
         // workgroups loop over tickets, so the grid need not cover every tile
