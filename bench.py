@@ -91,11 +91,41 @@ def bench_frames(args):
     from paper_2602_03207_amd import binding as B
     from paper_2602_03207_amd.pipeline import GaussianTensors, Renderer
 
+    from paper_2602_03207_amd.autotune import autotune
+    from paper_2602_03207_amd.batched import BatchedForward
+
     scene, cam = scenegen.c2()
-    opts = B.make_options(sh_degree=3, flags=B.WS_FLAG_DEPTH_FIRST)
+    base = B.make_options(sh_degree=3, flags=B.WS_FLAG_DEPTH_FIRST)
     g = GaussianTensors.from_scene(scene)
-    r = Renderer([cam], opts)
     stream = torch.cuda.current_stream()
+    # tile size and radix width from the autotuner (neither changes a pixel; the tuner checks it)
+    tune = autotune(g, [cam], base, reps=3, log=log)
+    opts = tune.apply(base)
+    log(f"tuned: tile {tune.tile_w}x{tune.tile_h}, radix {tune.radix_bits}")
+
+    def graph_frames(o):
+        bf = BatchedForward([cam], o, g)
+        bf.capture()
+        for _ in range(args.warmup):
+            bf.replay()
+        bf.check()
+        st = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+        en = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            st[i].record(bf.stream)
+            bf.replay()
+            en[i].record(bf.stream)
+        bf.stream.synchronize()
+        w = time.perf_counter() - t0
+        bf.check()
+        ms = [a.elapsed_time(b) for a, b in zip(st, en)]
+        img = bf.r.images.clone()
+        bf.close()
+        return w, ms, img
+
+    r = Renderer([cam], opts)
     for _ in range(args.warmup):
         r.forward(g, stream)
     torch.cuda.synchronize()
@@ -114,27 +144,14 @@ def bench_frames(args):
     log(f"frames (plain): {args.steps} in {wall:.3f} s, M = {m}")
     # the same frame as one graph replay: device-sized sort and render (capacity from the measured
     # frame plus 10 %, overflow reported in the status word), no host synchronisation inside
-    from paper_2602_03207_amd.batched import BatchedForward
-    bf = BatchedForward([cam], opts, g)
-    bf.capture()
-    for _ in range(args.warmup):
-        bf.replay()
-    bf.check()
-    gstarts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    gends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        gstarts[i].record(bf.stream)
-        bf.replay()
-        gends[i].record(bf.stream)
-    bf.stream.synchronize()
-    graph_wall = time.perf_counter() - t0
-    bf.check()
-    graph_ms = [s.elapsed_time(e) for s, e in zip(gstarts, gends)]
-    graph_same = bool(torch.equal(bf.r.images.view(torch.int32), r.images.view(torch.int32)))
-    bf.close()
+    graph_wall, graph_ms, gimg = graph_frames(opts)
+    graph_same = bool(torch.equal(gimg.view(torch.int32), r.images.view(torch.int32)))
     log(f"frames (graph): {args.steps} in {graph_wall:.3f} s, images equal to the plain path: {graph_same}")
+    # reference: the same graph frame with 16x16 tiles and 8-bit digits
+    ref_opts = B.make_options(sh_degree=3, flags=B.WS_FLAG_DEPTH_FIRST)
+    w16, ms16, img16 = graph_frames(ref_opts)
+    same16 = bool(torch.equal(img16.view(torch.int32), r.images.view(torch.int32)))
+    del gimg, img16
     # per-kernel times
     names = ["preprocess", "scan_emit", "sort_hist", "sort_pass", "ranges", "render"]
     kt = kernel_times(lambda: r.forward(g, stream), names)
@@ -163,9 +180,11 @@ def bench_frames(args):
         log(f"note: GPU pair count {m} differs from the oracle's {stats['pairs']} (rectangle bounds at a margin)")
     work = c2_work(stats, m)
     return dict(r=r, m=m, wall=wall, frame_ms=frame_ms, graph_wall=graph_wall, graph_ms=graph_ms,
-                graph_same=graph_same, kernels=kt, sort_ms=sort_ms, frame_sort_ms=frame_sort_ms,
-                passes=math.ceil(rg.end_bit / 8), frame_passes=math.ceil((r.end_bit - r.begin_bit) / 8), work=work,
-                stats=stats, end_bit=r.end_bit)
+                graph_same=graph_same, tune=tune, w16=w16, ms16=ms16, same16=same16, m16=rg.num_pairs,
+                kernels=kt, sort_ms=sort_ms, frame_sort_ms=frame_sort_ms,
+                passes=math.ceil(rg.end_bit / 8),
+                frame_passes=math.ceil((r.end_bit - r.begin_bit) / (tune.radix_bits or 8)), work=work,
+                stats=stats, end_bit=r.end_bit, end_bit16=rg.end_bit)
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "c2_frame_hbm_traffic.md")
@@ -423,7 +442,8 @@ def main():
     p99 = sorted(res["graph_ms"])[min(len(res["graph_ms"]) - 1, int(0.99 * len(res["graph_ms"])))]
     fps = args.steps / res["graph_wall"]
     plain_med = statistics.median(res["frame_ms"])
-    keys_per_s = res["m"] / (res["sort_ms"] * 1e-3)
+    keys_per_s = res["m16"] / (res["sort_ms"] * 1e-3)
+    tune = res["tune"]
     line = {
         "metric": "frames/s + sorted keys/s at 1M splats 1080p; batched fwd+bwd views/s vs plain",
         "value": round(fps, 2),
@@ -438,20 +458,28 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "1M Gaussians on 20 spheres/planes, bimodal opacity, SH degree 3, one 1920x1080 "
-                               "view, 16x16 tiles", "gaussians": 1_000_000, "width": 1920, "height": 1080,
-                   "sh_degree": 3, "tile": "16x16", "radix_bits": 8, "pairs": res["m"],
+                               "view", "gaussians": 1_000_000, "width": 1920, "height": 1080,
+                   "sh_degree": 3, "tile": f"{tune.tile_w}x{tune.tile_h}", "radix_bits": tune.radix_bits,
+                   "tuned_by": "autotuner (tile size x radix width, images checked bit-identical)",
+                   "pairs": res["m"],
                    "emission": "depth-first (tile bits sorted per frame)",
                    "frame": "one graph replay (preprocess, device-sized sort and render)"},
         "frame_ms_median": round(med, 4),
         "frame_ms_p99": round(p99, 4),
         "frame_ms_stdev": round(statistics.pstdev(res["graph_ms"]), 4),
         "graph_images_equal_plain": res["graph_same"],
+        "frames_per_s_16x16": round(args.steps / res["w16"], 2),
+        "frame_ms_median_16x16": round(statistics.median(res["ms16"]), 4),
+        "images_equal_16x16": res["same16"],
         "plain_frames_per_s": round(args.steps / res["wall"], 2),
         "plain_frame_ms_median": round(plain_med, 4),
         "sorted_keys_per_s": round(keys_per_s, 1),
+        "sorted_keys": res["m16"],
         "sort_ms": round(res["sort_ms"], 4),
-        "sort_bits": res["end_bit"],
+        "sort_bits": res["end_bit16"],
         "sort_passes": res["passes"],
+        "sort_workload": "the 16x16-tile (tile | depth) pair buffer of the frame, emitted in Gaussian order, "
+                         "all key bits, 8-bit digits",
         "frame_sort_keys_per_s": round(res["m"] / (res["frame_sort_ms"] * 1e-3), 1),
         "frame_sort_ms": round(res["frame_sort_ms"], 4),
         "frame_sort_passes": res["frame_passes"],
