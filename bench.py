@@ -184,18 +184,18 @@ def bench_frames(args):
                 kernels=kt, sort_ms=sort_ms, frame_sort_ms=frame_sort_ms,
                 passes=math.ceil(rg.end_bit / 8),
                 frame_passes=math.ceil((r.end_bit - r.begin_bit) / (tune.radix_bits or 8)), work=work,
-                stats=stats, end_bit=r.end_bit, end_bit16=rg.end_bit)
+                stats=stats, end_bit=r.end_bit, end_bit16=rg.end_bit, tile=(tune.tile_w, tune.tile_h))
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "c2_frame_hbm_traffic.md")
-TRAFFIC_KERNEL = {"render": "k_render<16, 16>"}
 
 
-def measured_traffic(dom):
+def measured_traffic(dom, tile):
     """HBM bytes per launch of the dominant kernel from the committed counter summary, or None when the
     summary covers another kernel or the kernel's sources changed since the counters were taken."""
     import hashlib
-    if dom not in TRAFFIC_KERNEL or not os.path.exists(TRAFFIC_FILE):
+    names = {"render": f"k_render<{tile[0]}, {tile[1]}>"}
+    if dom not in names or not os.path.exists(TRAFFIC_FILE):
         return None
     fields = {}
     with open(TRAFFIC_FILE) as f:
@@ -203,7 +203,7 @@ def measured_traffic(dom):
             if ":" in line and not line.startswith(("|", "#", " ")):
                 k, v = line.split(":", 1)
                 fields[k.strip()] = v.strip()
-    if fields.get("kernel") != TRAFFIC_KERNEL[dom] or "sources" not in fields:
+    if fields.get("kernel") != names[dom] or "sources" not in fields:
         return None
     h = hashlib.sha256()
     for src in fields["sources"].split():
@@ -224,10 +224,10 @@ def roofline(res):
     if bound == "hbm":
         achieved = amount / t / 1e9
         return dom, {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom)}
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom, res["tile"])}
     achieved = amount / t / 1e12
     return dom, {"bound": "alu", "achieved": round(achieved, 3), "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                 "frac": round(achieved / FP32_VALU_PEAK_TFLOPS, 4), "traffic": measured_traffic(dom)}
+                 "frac": round(achieved / FP32_VALU_PEAK_TFLOPS, 4), "traffic": measured_traffic(dom, res["tile"])}
 
 
 def bench_batched(args):
