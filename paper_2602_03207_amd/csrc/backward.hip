@@ -100,7 +100,7 @@ __global__ __launch_bounds__(TW * TH) void k_render_bwd(BwdArgs a) {
             }
             s_batch[threadIdx.x] = s;
         }
-        stage_quadrant_masks<TW, TH>(s, valid, ti.x0, ti.y0, s_masks);
+        stage_quadrant_masks<TW, TH>(s, valid, ti.x0, ti.y0, bk.log2_amin, s_masks);
         __syncthreads();
         composite_batch<NW>(ps, active, s_batch, my_masks, int32_t(b0 - start), bk);
     }
@@ -141,7 +141,7 @@ __global__ __launch_bounds__(TW * TH) void k_render_bwd(BwdArgs a) {
             }
 #pragma unroll
             for (int k = 0; k < kNG; ++k) s_acc[k][threadIdx.x] = 0.f;
-            stage_quadrant_masks<TW, TH>(s, valid, ti.x0, ti.y0, s_masks);
+            stage_quadrant_masks<TW, TH>(s, valid, ti.x0, ti.y0, bk.log2_amin, s_masks);
         }
         __syncthreads();
         // back to front over the staged splats that meet this wave's quadrant

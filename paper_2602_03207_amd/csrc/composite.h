@@ -139,10 +139,12 @@ struct PixelState {
 // the inner loop needs no per-iteration canonicalisation.
 struct BlendConsts {
     float alpha_min, alpha_max, t_min;
+    float log2_amin;  // for the quadrant culling bound only
     __device__ __forceinline__ explicit BlendConsts(const KOpts& o)
         : alpha_min(__builtin_canonicalizef(o.alpha_min)),
           alpha_max(__builtin_canonicalizef(o.alpha_max)),
-          t_min(__builtin_canonicalizef(o.t_min)) {}
+          t_min(__builtin_canonicalizef(o.t_min)),
+          log2_amin(__log2f(o.alpha_min)) {}
 };
 
 __device__ __forceinline__ uint64_t wave_ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
@@ -192,18 +194,62 @@ __device__ __forceinline__ void quadrant_pixel(int x0, int y0, int* px, int* py)
     *py = y0 + (w / (TW / 8)) * 8 + (l >> 3);
 }
 
-// Ballots of "this staged splat meets quadrant q" into masks[q * NW + staging wave].
+// Can the splat reach alpha >= alpha_min at any pixel centre of the block
+// [bx0, bx1] x [by0, by1] (inclusive pixel indices)?  With Q(d) = -(qa dx^2 +
+// qb dx dy + qc dy^2) >= 0 the pixel test passes only where Q <= ls -
+// log2(alpha_min) =: R.  Q is convex, so its minimum over the box of offsets
+// d = mean - pixel centre is 0 when the mean lies in the box and otherwise lies
+// on one of the four edges, where it is a one-dimensional quadratic minimised
+// in closed form (clamped to the edge).  The answer is "no" only when that
+// minimum exceeds R by a margin far above the fp32 rounding of this bound and
+// of the per-pixel evaluation (relative to the sizes of the terms involved),
+// so a block it rules out holds no pixel whose fp32 alpha reaches alpha_min:
+// dropping the splat there changes no pixel and no skip decision.  Non-finite
+// values answer "yes".
+struct EllipseCull {
+    float a, b, c, kx, ky, R, scale;  // Q = a dx^2 + b dx dy + c dy^2
+    __device__ __forceinline__ EllipseCull(const StagedSplat& s, float log2_amin) {
+        a = -s.qa;
+        b = -s.qb;
+        c = -s.qc;
+        kx = b / (2.f * c);  // edge dx = const: dy* = -kx dx
+        ky = b / (2.f * a);  // edge dy = const: dx* = -ky dy
+        R = s.ls - log2_amin;
+        scale = fabsf(s.ls) + fabsf(log2_amin);
+    }
+    __device__ __forceinline__ float q(float dx, float dy) const { return fmaf(a * dx, dx, dy * fmaf(b, dx, c * dy)); }
+    __device__ __forceinline__ bool meets(const StagedSplat& s, int bx0, int bx1, int by0, int by1) const {
+        const float lx0 = s.u - (float(bx1) + 0.5f), lx1 = s.u - (float(bx0) + 0.5f);
+        const float ly0 = s.v - (float(by1) + 0.5f), ly1 = s.v - (float(by0) + 0.5f);
+        if (lx0 <= 0.f && lx1 >= 0.f && ly0 <= 0.f && ly1 >= 0.f) return true;
+        const float q0 = q(lx0, __builtin_amdgcn_fmed3f(-kx * lx0, ly0, ly1));
+        const float q1 = q(lx1, __builtin_amdgcn_fmed3f(-kx * lx1, ly0, ly1));
+        const float q2 = q(__builtin_amdgcn_fmed3f(-ky * ly0, lx0, lx1), ly0);
+        const float q3 = q(__builtin_amdgcn_fmed3f(-ky * ly1, lx0, lx1), ly1);
+        const float qmin = fminf(fminf(q0, q1), fminf(q2, q3));
+        const float mx = fmaxf(fabsf(lx0), fabsf(lx1)), my = fmaxf(fabsf(ly0), fabsf(ly1));
+        const float size = fmaf(a * mx, mx, my * fmaf(fabsf(b), mx, c * my)) + scale;
+        const bool finite = __builtin_isfinite(qmin) && __builtin_isfinite(size) && a > 0.f && c > 0.f;
+        return !(finite && qmin > R + 1e-4f * size + 1e-4f);
+    }
+};
+
+// Ballots of "this staged splat meets quadrant q" into masks[q * NW + staging
+// wave]: its rectangle meets the quadrant's pixel block and, on the part they
+// share, the splat can reach alpha_min (EllipseCull).
 template <int TW, int TH>
 __device__ __forceinline__ void stage_quadrant_masks(const StagedSplat& s, bool valid, int x0, int y0,
-                                                     uint64_t* masks) {
+                                                     float log2_amin, uint64_t* masks) {
     constexpr int QX = TW / 8, NQ = (TW / 8) * (TH / 8), NW = TW * TH / kWave;
     const int rx0 = int(s.rxy & 0xffffu), ry0 = int(s.rxy >> 16);
     const int rx1 = rx0 + int(s.rwh & 0xffffu), ry1 = ry0 + int(s.rwh >> 16);
     const int w = threadIdx.x / kWave;
+    const EllipseCull ec(s, log2_amin);
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
         const int qx0 = x0 + (q % QX) * 8, qy0 = y0 + (q / QX) * 8;
-        const bool meets = valid && rx0 <= qx0 + 7 && rx1 >= qx0 && ry0 <= qy0 + 7 && ry1 >= qy0;
+        bool meets = valid && rx0 <= qx0 + 7 && rx1 >= qx0 && ry0 <= qy0 + 7 && ry1 >= qy0;
+        if (meets) meets = ec.meets(s, max(rx0, qx0), min(rx1, qx0 + 7), max(ry0, qy0), min(ry1, qy0 + 7));
         const uint64_t b = wave_ballot(meets);
         if (lane_id() == 0) masks[q * NW + w] = b;
     }

@@ -17,7 +17,10 @@
 //               running maximum, and writes key = (tile << 32) | depth bits,
 //               value = Gaussian id with coalesced stores.  Work per
 //               workgroup is fixed, whatever the size of the splats.
-// Both prefix sums are the wait-free hierarchical scan of scan.h.
+// Both prefix sums are those of scan.h (one pass with look-back up to 1024
+// workgroups, else the wait-free three-level scan).  k_preprocess zeroes the
+// look-back words of both scans and of the depth sort on its way, so none of
+// them needs a clearing launch.
 #include "project.h"
 #include "scan.h"
 #include "ws_internal.h"
@@ -30,10 +33,17 @@ constexpr int kEmitThreads = 256;
 constexpr int kEmitItems = 8;
 constexpr int kEmitPairs = kEmitThreads * kEmitItems;  // pairs per emission workgroup
 constexpr int kEmitSlots = kEmitThreads;               // entries loaded per round
+// Items per thread of the two prefix sums: the visibility flags of every
+// entry (large blocks, a short look-back) and the tile counts of the listed
+// entries (smaller blocks: few entries are listed and each count takes two
+// dependent loads).
+constexpr int kCompactItems = 16;
+constexpr int kCountItems = 8;
 
 struct PreprocessWs {
     uint32_t* list_a;       // [V n] visible entries in index order
     uint32_t* list_b;       // [V n] the same, sorted by depth (depth-first mode)
+    uint32_t* depth;        // [V n] fp32 depth bits of every visible entry (depth-first mode)
     uint64_t* dkey_a;       // [V n] fp32 depth bits of list_a (depth-first mode)
     uint64_t* dkey_b;
     uint32_t* offsets;      // [V n] first pair of each list entry
@@ -58,13 +68,14 @@ size_t layout(void* ws, int64_t n, int32_t n_views, int64_t capacity, bool depth
         return ptr;
     };
     p.d_nvis = reinterpret_cast<int64_t*>(take(16));
-    p.scan_a = take(scan_workspace(ents));
-    p.scan_b = take(scan_workspace(ents));
+    p.scan_a = take(scan_workspace(ents, kCompactItems));
+    p.scan_b = take(scan_workspace(ents, kCountItems));
     p.list_a = reinterpret_cast<uint32_t*>(take(size_t(ents) * 4));
     p.offsets = reinterpret_cast<uint32_t*>(take(size_t(ents) * 4));
     p.first_entry = reinterpret_cast<uint32_t*>(take(size_t(p.emit_blocks) * 4));
     if (depth_first) {
         p.list_b = reinterpret_cast<uint32_t*>(take(size_t(ents) * 4));
+        p.depth = reinterpret_cast<uint32_t*>(take(size_t(ents) * 4));
         p.dkey_a = reinterpret_cast<uint64_t*>(take(size_t(ents) * 8));
         p.dkey_b = reinterpret_cast<uint64_t*>(take(size_t(ents) * 8));
         p.sort_ws = take(sort_workspace(ents, 0, 31, 8, true));
@@ -76,9 +87,12 @@ size_t layout(void* ws, int64_t n, int32_t n_views, int64_t capacity, bool depth
 template <int DEG>
 __global__ __launch_bounds__(kPreThreads) void k_preprocess(GaussPtrs g, const ws_camera* __restrict__ cams, KOpts o,
                                                            ws_splat* __restrict__ splats,
-                                                           uint32_t* __restrict__ tiles_touched) {
+                                                           uint32_t* __restrict__ tiles_touched,
+                                                           uint32_t* __restrict__ depth, ClearList clr) {
     const int32_t v = blockIdx.y;
     const int64_t i = int64_t(blockIdx.x) * kPreThreads + threadIdx.x;
+    // the look-back words of the scans and of the depth sort that follow
+    clear_words(clr, int64_t(v) * gridDim.x * kPreThreads + i, int64_t(gridDim.x) * gridDim.y * kPreThreads);
     if (i >= g.n) return;
     const ws_camera& cam = cams[v];
     ProjState st;
@@ -92,29 +106,39 @@ __global__ __launch_bounds__(kPreThreads) void k_preprocess(GaussPtrs g, const w
     rec[0] = make_float4(st.u, st.v, st.A, st.B);
     rec[1] = make_float4(st.C, st.sigma, st.rgb[0], st.rgb[1]);
     rec[2] = make_float4(st.rgb[2], st.z32, __uint_as_float(r01), __uint_as_float(r23));
+    // a dense copy of the depth, so that the compaction reads it coalesced
+    // rather than one word out of every 48-byte record
+    if (depth) depth[vi] = __float_as_uint(st.z32);
 }
 
 // ---- compaction: prefix sum of the visibility flags
+struct FlagItem {
+    uint32_t tiles, depth;  // depth bits are read only for visible entries (depth-first mode)
+};
 struct FlagLoad {
+    using Item = FlagItem;
     const uint32_t* tiles_touched;
-    __device__ uint64_t operator()(int64_t i) const { return tiles_touched[i] != 0u ? 1u : 0u; }
+    const uint32_t* depth;  // null unless depth-first
+    __device__ FlagItem operator()(int64_t i) const { return FlagItem{tiles_touched[i], depth ? depth[i] : 0u}; }
+    __device__ static uint64_t value(const FlagItem& it) { return it.tiles != 0u ? 1u : 0u; }
 };
 struct CompactStore {
-    const ws_splat* splats;
     uint32_t* list;
     uint64_t* dkeys;  // null unless depth-first
-    __device__ void operator()(int64_t i, uint64_t pos, uint64_t flag) const {
-        if (!flag) return;
+    __device__ void operator()(int64_t i, uint64_t pos, const FlagItem& it) const {
+        if (it.tiles == 0u) return;
         list[pos] = uint32_t(i);
-        if (dkeys) dkeys[pos] = __float_as_uint(reinterpret_cast<const float*>(splats + i)[9]);
+        if (dkeys) dkeys[pos] = it.depth;
     }
 };
 
 // ---- counts: prefix sum of the listed entries' tile counts
 struct CountLoad {
+    using Item = uint64_t;
     const uint32_t* tiles_touched;
     const uint32_t* list;
     __device__ uint64_t operator()(int64_t e) const { return tiles_touched[list[e]]; }
+    __device__ static uint64_t value(uint64_t c) { return c; }
 };
 struct CountStore {
     uint32_t* offsets;
@@ -271,36 +295,41 @@ hipError_t launch_preprocess(const GaussPtrs& g, const ws_camera* d_cams, int32_
     PreprocessWs pw;
     layout(ws, g.n, n_views, capacity, depth_first, &pw);
     const uint32_t gx = uint32_t(std::max<int64_t>((g.n + kPreThreads - 1) / kPreThreads, 1));
+    const int64_t ents = std::max<int64_t>(pw.total, 1);
+    ClearList clr;
+    clr.add(pw.scan_a, scan_sync_words(pw.total, kCompactItems));
+    if (depth_first) sort_sync_words(pw.sort_ws, ents, 0, 31, 8, true, &clr);
+    clr.add(pw.scan_b, scan_sync_words(ents, kCountItems));
     timing_begin(WS_KERNEL_PREPROCESS, stream);
     switch (o.sh_degree) {
         case 0: hipLaunchKernelGGL(k_preprocess<0>, dim3(gx, n_views), dim3(kPreThreads), 0, stream, g, d_cams, o,
-                                   splats, tiles_touched); break;
+                                   splats, tiles_touched, pw.depth, clr); break;
         case 1: hipLaunchKernelGGL(k_preprocess<1>, dim3(gx, n_views), dim3(kPreThreads), 0, stream, g, d_cams, o,
-                                   splats, tiles_touched); break;
+                                   splats, tiles_touched, pw.depth, clr); break;
         case 2: hipLaunchKernelGGL(k_preprocess<2>, dim3(gx, n_views), dim3(kPreThreads), 0, stream, g, d_cams, o,
-                                   splats, tiles_touched); break;
+                                   splats, tiles_touched, pw.depth, clr); break;
         default: hipLaunchKernelGGL(k_preprocess<3>, dim3(gx, n_views), dim3(kPreThreads), 0, stream, g, d_cams, o,
-                                    splats, tiles_touched); break;
+                                    splats, tiles_touched, pw.depth, clr); break;
     }
     timing_end(WS_KERNEL_PREPROCESS, stream);
 
     timing_begin(WS_KERNEL_SCAN_EMIT, stream);
     // compaction of the visible entries (count to d_nvis)
-    launch_scan<uint64_t>(FlagLoad{tiles_touched}, CompactStore{splats, pw.list_a, depth_first ? pw.dkey_a : nullptr},
-                          pw.total, nullptr, d_status, pw.scan_a, reinterpret_cast<uint64_t*>(pw.d_nvis), stream);
+    launch_scan<uint64_t, kCompactItems>(FlagLoad{tiles_touched, pw.depth}, CompactStore{pw.list_a, depth_first ? pw.dkey_a : nullptr},
+                          pw.total, nullptr, d_status, pw.scan_a, reinterpret_cast<uint64_t*>(pw.d_nvis), stream,
+                          true);
     const uint32_t* list = pw.list_a;
     if (depth_first) {
         // stable sort of the visible entries by depth: positive fp32 bits order like the values
         // the visible entries are typically a small fraction of all (view, Gaussian) entries
-        const hipError_t e = launch_sort(pw.dkey_a, pw.list_a, pw.dkey_b, pw.list_b, std::max<int64_t>(pw.total, 1),
-                                         pw.d_nvis, d_status, 0, 31, 8, pw.sort_ws, stream, false, true);
+        const hipError_t e = launch_sort(pw.dkey_a, pw.list_a, pw.dkey_b, pw.list_b, ents, pw.d_nvis, d_status, 0, 31,
+                                         8, pw.sort_ws, stream, false, true, true);
         if (e != hipSuccess) return e;
         list = pw.list_b;
     }
     // pair offsets of the listed entries (total to d_num_pairs)
-    launch_scan<uint64_t>(CountLoad{tiles_touched, list}, CountStore{pw.offsets, pw.first_entry, pw.emit_blocks},
-                          std::max<int64_t>(pw.total, 1), pw.d_nvis, d_status, pw.scan_b,
-                          reinterpret_cast<uint64_t*>(d_num_pairs), stream);
+    launch_scan<uint64_t, kCountItems>(CountLoad{tiles_touched, list}, CountStore{pw.offsets, pw.first_entry, pw.emit_blocks},
+                          ents, pw.d_nvis, d_status, pw.scan_b, reinterpret_cast<uint64_t*>(d_num_pairs), stream, true);
     EmitArgs ea;
     ea.splats = splats;
     ea.cams = d_cams;

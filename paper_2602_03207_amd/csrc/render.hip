@@ -1,8 +1,11 @@
 // Tile ranges and front-to-back compositing (Eq. 2, Eq. 4).
 //
-// k_ranges_clear / k_ranges   [start, end) of every tile's run of pairs in the
-//                             tile-sorted key list (boundary where key >> 32
-//                             changes); tiles without pairs keep [0, 0).
+// k_ranges                    [start, end) of every tile's run of pairs in the
+//                             tile-sorted key list, written where key >> 32
+//                             changes; the tiles without pairs between two
+//                             runs get an empty range at that boundary, so
+//                             every tile is written once and no clearing
+//                             launch is needed.
 // k_render<TW, TH>            one workgroup of TW*TH threads per tile, one
 //                             pixel per thread, one 8x8 quadrant per wave.
 //                             The tile's splats are staged in LDS in batches
@@ -29,19 +32,23 @@
 namespace ws {
 namespace {
 
-__global__ void k_ranges_clear(uint32_t* ranges, int64_t words, uint32_t* counter) {
-    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
-    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < words; i += stride) ranges[i] = 0;
-    if (counter && blockIdx.x == 0 && threadIdx.x == 0) *counter = 0;
-}
-
 // Grid-stride over chunks of 8 x 256 consecutive pairs: every key is loaded
 // once (coalesced, all 8 loads of a thread in flight together), its
 // predecessor and successor come from the neighbouring lanes (the wave's end
-// lanes load theirs), and a tile's start / end is written where the tile id
-// changes.
+// lanes load theirs).  Tile t's range is [first pair with tile >= t, first
+// pair with tile > t): a run's first pair writes its start, its last pair its
+// end, and the last pair of a run also writes the empty ranges of the tiles
+// between its tile and the next run's (the whole wave writes each such gap,
+// so a long gap costs few stores per lane).  Tiles before the first run are
+// written by workgroup 0; an empty key list makes every range [0, 0).
 constexpr int kRangeThreads = 256;
 constexpr int kRangeItems = 8;
+
+__device__ __forceinline__ void fill_empty(uint32_t* ranges, uint32_t lo, uint32_t hi, uint32_t pos, uint32_t first,
+                                           uint32_t step) {
+    uint2* r = reinterpret_cast<uint2*>(ranges);
+    for (uint32_t t = lo + first; t < hi; t += step) r[t] = make_uint2(pos, pos);
+}
 
 __global__ __launch_bounds__(kRangeThreads) void k_ranges(const uint64_t* __restrict__ keys, int64_t cap,
                                                           const int64_t* d_n, const int32_t* d_status,
@@ -49,6 +56,15 @@ __global__ __launch_bounds__(kRangeThreads) void k_ranges(const uint64_t* __rest
     if (*d_status != 0) return;
     int64_t m = *d_n;
     m = m < cap ? m : cap;
+    const uint32_t T = uint32_t(total_tiles);
+    if (m == 0) {
+        fill_empty(ranges, 0, T, 0, blockIdx.x * kRangeThreads + threadIdx.x, gridDim.x * kRangeThreads);
+        return;
+    }
+    if (blockIdx.x == 0) {  // tiles before the first run
+        const uint64_t t0 = keys[0] >> 32;
+        fill_empty(ranges, 0, uint32_t(t0 < T ? t0 : T), 0, threadIdx.x, kRangeThreads);
+    }
     const uint32_t lane = lane_id();
     constexpr int64_t kChunk = int64_t(kRangeThreads) * kRangeItems;
     const int64_t stride = int64_t(gridDim.x) * kChunk;
@@ -70,9 +86,29 @@ __global__ __launch_bounds__(kRangeThreads) void k_ranges(const uint64_t* __rest
             if (lane == 0) prev = edge[j];
             uint32_t next = uint32_t(__shfl_down(int(t[j]), 1, kWave));
             if (lane == kWave - 1) next = edge[j];
-            if (i < m && int64_t(t[j]) < total_tiles) {  // keys from ws_preprocess never exceed it
-                if (i == 0 || prev != t[j]) ranges[2 * int64_t(t[j])] = uint32_t(i);
-                if (i == m - 1 || next != t[j]) ranges[2 * int64_t(t[j]) + 1] = uint32_t(i + 1);
+            // empty tiles (t, min(next tile, T)) after the last pair of a run
+            uint32_t glo = 0, ghi = 0;
+            if (i < m) {
+                const uint32_t cur = t[j];
+                const bool first = i == 0 || prev != cur;
+                const bool last = i == m - 1 || next != cur;
+                if (cur < T) {  // keys from ws_preprocess never exceed it
+                    if (first) ranges[2 * int64_t(cur)] = uint32_t(i);
+                    if (last) ranges[2 * int64_t(cur) + 1] = uint32_t(i + 1);
+                }
+                if (last && cur < T && cur + 1 < T) {
+                    glo = cur + 1;
+                    ghi = i == m - 1 ? T : (next < T ? next : T);
+                }
+            }
+            uint64_t gaps = __ballot(ghi > glo);
+            while (gaps) {
+                const int l = __builtin_ctzll(gaps);
+                const uint32_t lo = uint32_t(__shfl(int(glo), l, kWave));
+                const uint32_t hi = uint32_t(__shfl(int(ghi), l, kWave));
+                const uint32_t pos = uint32_t(__shfl(int(uint32_t(i + 1)), l, kWave));
+                fill_empty(ranges, lo, hi, pos, lane, kWave);
+                gaps &= gaps - 1;
             }
         }
     }
@@ -95,7 +131,8 @@ struct RenderArgs {
 // quadrant masks of the batch are formed; the caller synchronises afterwards.
 template <int TW, int TH>
 __device__ __forceinline__ void stage_batch(const RenderArgs& a, const ws_splat* vsplats, uint32_t b0, uint32_t end,
-                                            int x0, int y0, StagedSplat* s_batch, uint64_t* s_masks) {
+                                            int x0, int y0, float log2_amin, StagedSplat* s_batch,
+                                            uint64_t* s_masks) {
     const uint32_t idx = b0 + threadIdx.x;
     StagedSplat s = empty_splat();
     bool valid = false;
@@ -107,7 +144,7 @@ __device__ __forceinline__ void stage_batch(const RenderArgs& a, const ws_splat*
         }
         s_batch[threadIdx.x] = s;
     }
-    stage_quadrant_masks<TW, TH>(s, valid, x0, y0, s_masks);
+    stage_quadrant_masks<TW, TH>(s, valid, x0, y0, log2_amin, s_masks);
 }
 
 // Composites global tile g into the images.
@@ -127,7 +164,7 @@ __device__ __forceinline__ void render_tile(const RenderArgs& a, int64_t g, Stag
     const BlendConsts bk(a.o);
     for (uint32_t b0 = start; b0 < end; b0 += NT) {
         if (__syncthreads_count(!lane_in(active)) == NT) break;
-        stage_batch<TW, TH>(a, vsplats, b0, end, ti.x0, ti.y0, s_batch, s_masks);
+        stage_batch<TW, TH>(a, vsplats, b0, end, ti.x0, ti.y0, bk.log2_amin, s_batch, s_masks);
         __syncthreads();
         composite_batch<NW>(ps, active, s_batch, my_masks, int32_t(b0 - start), bk);
     }
@@ -282,10 +319,7 @@ hipError_t launch_render(const ws_splat* splats, int64_t n, const ws_camera* d_c
                          int64_t total_tiles, const KOpts& o, const uint64_t* keys, const uint32_t* values,
                          int64_t capacity, const int64_t* d_num_pairs, const int32_t* d_status,
                          uint32_t* tile_ranges, float* images, void* ws, hipStream_t stream) {
-    const int64_t words = 2 * total_tiles;
-    const uint32_t cgrid = uint32_t(std::min<int64_t>(std::max<int64_t>((words + 255) / 256, 1), 4096));
     timing_begin(WS_KERNEL_RANGES, stream);
-    hipLaunchKernelGGL(k_ranges_clear, dim3(cgrid), dim3(256), 0, stream, tile_ranges, words, (uint32_t*)nullptr);
     const int64_t rchunk = int64_t(kRangeThreads) * kRangeItems;
     const uint32_t rgrid = uint32_t(std::min<int64_t>(std::max<int64_t>((capacity + rchunk - 1) / rchunk, 1), 4096));
     hipLaunchKernelGGL(k_ranges, dim3(rgrid), dim3(kRangeThreads), 0, stream, keys, capacity, d_num_pairs, d_status,

@@ -1,6 +1,6 @@
 // Device-wide exclusive prefix sums.
 //
-// Two schedules, chosen by the number of 4096-item blocks:
+// Two schedules, chosen by the number of blocks:
 //  * one pass (up to kOnePassMaxBlocks blocks): every block scans its items in
 //    registers, publishes its sum, reads its predecessors' published sums
 //    (a decoupled look-back: one wave reads 64 predecessors per round trip
@@ -12,8 +12,13 @@
 //    (Sec. 3.3.2) -- reduce, one-workgroup scan of the block sums, down-sweep
 //    -- each level one dispatch, no workgroup ever waits for another.
 //
-// Loader:  __device__ T operator()(int64_t i) const   (i < n)
-// Writer:  __device__ void operator()(int64_t i, T prefix, T value) const
+// Loader:  using Item = ...;                    what the writer needs of item i
+//          __device__ Item operator()(int64_t i) const      (0 <= i < n)
+//          __device__ static T value(const Item&)           the item's summand
+// Writer:  __device__ void operator()(int64_t i, T prefix, const Item&) const
+// Every thread loads all of its items before it uses any (indices past the
+// end are clamped to the last item and their values replaced by zero), so a
+// block waits for one round of memory latency, not one per item.
 // The number of items n may live in device memory (count pointer), so the
 // launches can be sized for a capacity and captured in a graph.
 #pragma once
@@ -22,9 +27,12 @@
 
 namespace ws {
 
+// Blocks of 256 threads with ITEMS items each (a template parameter of every
+// kernel and launcher: few large blocks shorten the look-back of an input
+// whose items are all present; more, smaller blocks suit a sparse input whose
+// items take dependent loads).
 constexpr int kScanThreads = 256;
-constexpr int kScanItemsPerThread = 16;
-constexpr int kScanBlock = kScanThreads * kScanItemsPerThread;  // 4096 items per block
+constexpr int kScanItems = 16;  // default: 4096 items per block
 constexpr int kPartialThreads = 1024;
 
 __device__ __forceinline__ int64_t scan_count(int64_t cap, const int64_t* d_n) {
@@ -33,19 +41,29 @@ __device__ __forceinline__ int64_t scan_count(int64_t cap, const int64_t* d_n) {
     return v < 0 ? 0 : (v < cap ? v : cap);
 }
 
-template <class T, class Loader>
+template <class T, int ITEMS, class Loader>
 __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(Loader ld, int64_t cap, const int64_t* d_n,
                                                               const int32_t* d_status, T* partials) {
     __shared__ T s_w[kScanThreads / kWave];
     if (d_status && *d_status != 0) return;
     const int64_t n = scan_count(cap, d_n);
-    const int64_t base = int64_t(blockIdx.x) * kScanBlock;
-    T sum = 0;
+    const int64_t base = int64_t(blockIdx.x) * (kScanThreads * ITEMS);
+    if (base >= n) {
+        if (threadIdx.x == 0) partials[blockIdx.x] = T(0);
+        return;
+    }
     // strided over the block so that a wave reads consecutive items
+    typename Loader::Item it[ITEMS];
 #pragma unroll
-    for (int j = 0; j < kScanItemsPerThread; ++j) {
+    for (int j = 0; j < ITEMS; ++j) {
         const int64_t i = base + int64_t(j) * kScanThreads + threadIdx.x;
-        if (i < n) sum += ld(i);
+        it[j] = ld(i < n ? i : n - 1);
+    }
+    T sum = 0;
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) {
+        const int64_t i = base + int64_t(j) * kScanThreads + threadIdx.x;
+        sum += i < n ? Loader::value(it[j]) : T(0);
     }
     sum = wave_sum(sum);
     if (lane_id() == 0) s_w[threadIdx.x / kWave] = sum;
@@ -59,15 +77,15 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(Loader ld, int64_t
 }
 
 // One workgroup: exclusive scan of partials[0, nb) in place; total to *total_out.
-template <class T>
+template <class T, int ITEMS>
 __global__ __launch_bounds__(kPartialThreads) void k_scan_partials(T* partials, int64_t nb_cap, const int64_t* d_n,
                                                                    const int32_t* d_status, T* total_out) {
     __shared__ T s_scan[kPartialThreads / kWave + 1];
     __shared__ T s_carry;
     if (d_status && *d_status != 0) return;
     // number of blocks actually holding items
-    const int64_t n = d_n ? scan_count(nb_cap * kScanBlock, d_n) : nb_cap * kScanBlock;
-    const int64_t nb = d_n ? (n + kScanBlock - 1) / kScanBlock : nb_cap;
+    const int64_t n = d_n ? scan_count(nb_cap * (kScanThreads * ITEMS), d_n) : nb_cap * (kScanThreads * ITEMS);
+    const int64_t nb = d_n ? (n + (kScanThreads * ITEMS) - 1) / (kScanThreads * ITEMS) : nb_cap;
     if (threadIdx.x == 0) s_carry = 0;
     __syncthreads();
     for (int64_t b0 = 0; b0 < nb; b0 += kPartialThreads) {
@@ -84,31 +102,34 @@ __global__ __launch_bounds__(kPartialThreads) void k_scan_partials(T* partials, 
     if (threadIdx.x == 0 && total_out) *total_out = s_carry;
 }
 
-// Wave-striped: wave w owns items base + w*1024 + j*64 + lane (j < 16), so
-// every load and store of the wave covers 64 consecutive items.
-template <class T, class Loader, class Writer>
+// Wave-striped: wave w owns items base + w*64*ITEMS + j*64 + lane (j < ITEMS),
+// so every load and store of the wave covers 64 consecutive items.
+template <class T, int ITEMS, class Loader, class Writer>
 __global__ __launch_bounds__(kScanThreads) void k_scan_down(Loader ld, Writer wr, int64_t cap, const int64_t* d_n,
                                                             const int32_t* d_status, const T* partials) {
-    constexpr int kPerWave = kScanItemsPerThread * kWave;
+    constexpr int kPerWave = ITEMS * kWave;
     __shared__ T s_wave[kScanThreads / kWave];
     if (d_status && *d_status != 0) return;
     const int64_t n = scan_count(cap, d_n);
-    const int64_t base = int64_t(blockIdx.x) * kScanBlock;
+    const int64_t base = int64_t(blockIdx.x) * (kScanThreads * ITEMS);
     if (base >= n) return;
     const int wave = threadIdx.x / kWave;
     const uint32_t lane = lane_id();
     const int64_t wbase = base + int64_t(wave) * kPerWave + lane;
-    T v[kScanItemsPerThread];
+    typename Loader::Item it[ITEMS];
 #pragma unroll
-    for (int j = 0; j < kScanItemsPerThread; ++j) {
+    for (int j = 0; j < ITEMS; ++j) {
         const int64_t i = wbase + j * kWave;
-        v[j] = i < n ? ld(i) : T(0);
+        it[j] = ld(i < n ? i : n - 1);
     }
+    T v[ITEMS];
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) v[j] = wbase + j * kWave < n ? Loader::value(it[j]) : T(0);
     // exclusive prefix of each item inside the wave's run of 1024
-    T ex[kScanItemsPerThread];
+    T ex[ITEMS];
     T carry = 0;
 #pragma unroll
-    for (int j = 0; j < kScanItemsPerThread; ++j) {
+    for (int j = 0; j < ITEMS; ++j) {
         const T inc = wave_inclusive_scan(v[j]);
         ex[j] = carry + inc - v[j];
         carry += __shfl(inc, kWave - 1, kWave);
@@ -118,13 +139,16 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_down(Loader ld, Writer wr
     T off = partials[blockIdx.x];
     for (int w = 0; w < wave; ++w) off += s_wave[w];
 #pragma unroll
-    for (int j = 0; j < kScanItemsPerThread; ++j) {
+    for (int j = 0; j < ITEMS; ++j) {
         const int64_t i = wbase + j * kWave;
-        if (i < n) wr(i, off + ex[j], v[j]);
+        if (i < n) wr(i, off + ex[j], it[j]);
     }
 }
 
-inline int64_t scan_blocks(int64_t cap) { return std::max<int64_t>((cap + kScanBlock - 1) / kScanBlock, 1); }
+inline int64_t scan_blocks(int64_t cap, int items) {
+    const int64_t block = int64_t(kScanThreads) * items;
+    return std::max<int64_t>((cap + block - 1) / block, 1);
+}
 
 // ---------------------------------------------------------- one pass
 
@@ -139,17 +163,17 @@ __global__ __launch_bounds__(Threads) void k_scan_clear(uint64_t* status, int64_
     if (threadIdx.x == 0) *ticket = 0;
 }
 
-template <class T, class Loader, class Writer>
+template <class T, int ITEMS, class Loader, class Writer>
 __global__ __launch_bounds__(kScanThreads) void k_scan_onepass(Loader ld, Writer wr, int64_t cap, const int64_t* d_n,
                                                                const int32_t* d_status, uint64_t* status,
                                                                uint32_t* ticket, T* total_out) {
-    constexpr int kPerWave = kScanItemsPerThread * kWave;
+    constexpr int kPerWave = ITEMS * kWave;
     __shared__ T s_wave[kScanThreads / kWave];
     __shared__ T s_excl;
     __shared__ uint32_t s_block;
     if (d_status && *d_status != 0) return;
     const int64_t n = scan_count(cap, d_n);
-    const int64_t nb = (n + kScanBlock - 1) / kScanBlock;
+    const int64_t nb = (n + (kScanThreads * ITEMS) - 1) / (kScanThreads * ITEMS);
     if (nb == 0) {
         if (blockIdx.x == 0 && threadIdx.x == 0 && total_out) *total_out = T(0);
         return;
@@ -161,17 +185,20 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_onepass(Loader ld, Writer
     const int64_t b = s_block;
     const int wave = threadIdx.x / kWave;
     const uint32_t lane = lane_id();
-    const int64_t wbase = b * kScanBlock + int64_t(wave) * kPerWave + lane;
-    T v[kScanItemsPerThread];
+    const int64_t wbase = b * (kScanThreads * ITEMS) + int64_t(wave) * kPerWave + lane;
+    typename Loader::Item it[ITEMS];
 #pragma unroll
-    for (int j = 0; j < kScanItemsPerThread; ++j) {
+    for (int j = 0; j < ITEMS; ++j) {
         const int64_t i = wbase + j * kWave;
-        v[j] = i < n ? ld(i) : T(0);
+        it[j] = ld(i < n ? i : n - 1);
     }
-    T ex[kScanItemsPerThread];
+    T v[ITEMS];
+#pragma unroll
+    for (int j = 0; j < ITEMS; ++j) v[j] = wbase + j * kWave < n ? Loader::value(it[j]) : T(0);
+    T ex[ITEMS];
     T carry = 0;
 #pragma unroll
-    for (int j = 0; j < kScanItemsPerThread; ++j) {
+    for (int j = 0; j < ITEMS; ++j) {
         const T inc = wave_inclusive_scan(v[j]);
         ex[j] = carry + inc - v[j];
         carry += __shfl(inc, kWave - 1, kWave);
@@ -224,40 +251,49 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_onepass(Loader ld, Writer
     __syncthreads();
     const T off = s_excl + woff;
 #pragma unroll
-    for (int j = 0; j < kScanItemsPerThread; ++j) {
+    for (int j = 0; j < ITEMS; ++j) {
         const int64_t i = wbase + j * kWave;
-        if (i < n) wr(i, off + ex[j], v[j]);
+        if (i < n) wr(i, off + ex[j], it[j]);
     }
 }
 
 // Workspace of one scan over up to `cap` items (either schedule), bytes.
-inline size_t scan_workspace(int64_t cap) {
-    const int64_t nb = scan_blocks(cap);
+inline size_t scan_workspace(int64_t cap, int items = kScanItems) {
+    const int64_t nb = scan_blocks(cap, items);
     return align_up(size_t(nb) * 8) + align_up(8);
 }
 
+// Words at the start of the workspace that must be zero when a one-pass scan
+// (the schedule taken when a status word is given) starts; 0 for the
+// three-level schedule, which needs none.
+inline int64_t scan_sync_words(int64_t cap, int items = kScanItems) {
+    const int64_t nb = scan_blocks(cap, items);
+    return nb <= kOnePassMaxBlocks ? int64_t(align_up(size_t(nb) * 8) + 4) / 4 : 0;
+}
+
 // Scans up to `cap` items (the count read from d_n when given).  `ws` holds
-// scan_workspace(cap) bytes; `d_status` (may be null) is also the word a
-// bounded wait that expires reports into.
-template <class T, class Loader, class Writer>
+// scan_workspace(cap, ITEMS) bytes; `d_status` (may be null) is also the word
+// a bounded wait that expires reports into.  With `precleared` an earlier
+// kernel of the stream zeroed the scan_sync_words(cap, ITEMS) words at `ws`.
+template <class T, int ITEMS = kScanItems, class Loader, class Writer>
 void launch_scan(const Loader& ld, const Writer& wr, int64_t cap, const int64_t* d_n, const int32_t* d_status,
-                 void* ws, T* total_out, hipStream_t stream) {
-    const int64_t nb = scan_blocks(cap);
+                 void* ws, T* total_out, hipStream_t stream, bool precleared = false) {
+    const int64_t nb = scan_blocks(cap, ITEMS);
     char* base = static_cast<char*>(ws);
     if (nb <= kOnePassMaxBlocks && d_status) {
         uint64_t* status = reinterpret_cast<uint64_t*>(base);
         uint32_t* ticket = reinterpret_cast<uint32_t*>(base + align_up(size_t(nb) * 8));
-        hipLaunchKernelGGL(k_scan_clear<256>, dim3(1), dim3(256), 0, stream, status, nb, ticket);
-        hipLaunchKernelGGL((k_scan_onepass<T, Loader, Writer>), dim3(uint32_t(nb)), dim3(kScanThreads), 0, stream, ld,
+        if (!precleared) hipLaunchKernelGGL(k_scan_clear<256>, dim3(1), dim3(256), 0, stream, status, nb, ticket);
+        hipLaunchKernelGGL((k_scan_onepass<T, ITEMS, Loader, Writer>), dim3(uint32_t(nb)), dim3(kScanThreads), 0, stream, ld,
                            wr, cap, d_n, d_status, status, ticket, total_out);
         return;
     }
     T* partials = reinterpret_cast<T*>(base);
-    hipLaunchKernelGGL((k_scan_reduce<T, Loader>), dim3(uint32_t(nb)), dim3(kScanThreads), 0, stream, ld, cap, d_n,
+    hipLaunchKernelGGL((k_scan_reduce<T, ITEMS, Loader>), dim3(uint32_t(nb)), dim3(kScanThreads), 0, stream, ld, cap, d_n,
                        d_status, partials);
-    hipLaunchKernelGGL((k_scan_partials<T>), dim3(1), dim3(kPartialThreads), 0, stream, partials, nb, d_n, d_status,
+    hipLaunchKernelGGL((k_scan_partials<T, ITEMS>), dim3(1), dim3(kPartialThreads), 0, stream, partials, nb, d_n, d_status,
                        total_out);
-    hipLaunchKernelGGL((k_scan_down<T, Loader, Writer>), dim3(uint32_t(nb)), dim3(kScanThreads), 0, stream, ld, wr,
+    hipLaunchKernelGGL((k_scan_down<T, ITEMS, Loader, Writer>), dim3(uint32_t(nb)), dim3(kScanThreads), 0, stream, ld, wr,
                        cap, d_n, d_status, partials);
 }
 

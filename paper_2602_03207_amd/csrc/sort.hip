@@ -43,6 +43,7 @@ constexpr int64_t kSmallSortMax = 1 << 20;   // capacities up to this use small 
 constexpr int kHistThreads = 256;
 constexpr int kMaxBins = 2048;  // passes * radix over every radix width
 constexpr int kLook = 16;       // predecessor tiles read at once by the look-back
+constexpr int kTableItems = 4;  // items per thread of the digit table's prefix sum
 constexpr int64_t kLookbackGrid = 1024;  // workgroups of a look-back pass at most
 constexpr uint32_t kStAgg = 1u << 30;
 constexpr uint32_t kStInc = 2u << 30;
@@ -87,11 +88,12 @@ size_t plan(void* ws, int64_t capacity, int begin_bit, int end_bit, int radix_bi
     if (L.wait_free) {
         const int64_t entries = int64_t(L.radix) * L.max_tiles;
         L.table = reinterpret_cast<uint32_t*>(take(size_t(entries) * 4));
-        L.table_scan = take(scan_workspace(entries));
+        L.table_scan = take(scan_workspace(entries, kTableItems));
     } else {
-        L.hist = reinterpret_cast<uint32_t*>(take(size_t(L.passes) * L.radix * 4));
+        // histograms and tickets side by side: one region to clear
+        L.hist = reinterpret_cast<uint32_t*>(take(size_t(L.passes) * (L.radix + 1) * 4));
+        L.tickets = L.hist ? L.hist + L.passes * L.radix : nullptr;
         L.status = reinterpret_cast<uint32_t*>(take(size_t(L.passes) * L.max_tiles * L.radix * 4));
-        L.tickets = reinterpret_cast<uint32_t*>(take(size_t(L.passes) * 4));
     }
     if (out) *out = L;
     return off;
@@ -277,6 +279,8 @@ struct UpArgs {
     int shift;
     uint32_t* table;
     int64_t max_tiles;
+    uint32_t* clear;  // look-back words of the table's prefix sum, zeroed here
+    int64_t clear_words;
 };
 
 // Digit counts of one tile into table[d][tile] (zeros for tiles past the end).
@@ -285,6 +289,9 @@ __global__ __launch_bounds__(kSortThreads) void k_upsweep(UpArgs a) {
     constexpr int RADIX = 1 << B;
     constexpr int kTile = kSortThreads * ITEMS;
     __shared__ uint32_t s_h[kSortWaves][RADIX];
+    for (int64_t i = int64_t(blockIdx.x) * kSortThreads + threadIdx.x; i < a.clear_words;
+         i += int64_t(gridDim.x) * kSortThreads)
+        a.clear[i] = 0u;
     if (a.d_status && *a.d_status != 0) return;
     const int64_t n = device_count(a.cap, a.d_n);
     const int64_t ntiles = (n + kTile - 1) / kTile;
@@ -370,8 +377,10 @@ __global__ __launch_bounds__(kSortThreads) void k_downsweep(DownArgs a) {
 }
 
 struct TableLoad {
+    using Item = uint32_t;
     const uint32_t* t;
     __device__ uint32_t operator()(int64_t i) const { return t[i]; }
+    __device__ static uint32_t value(uint32_t c) { return c; }
 };
 struct TableStore {
     uint32_t* t;
@@ -573,9 +582,10 @@ void run_pass(const PassLaunch& c) {
     const uint32_t grid = uint32_t(c.L->max_tiles);
     if (c.L->wait_free) {
         hipLaunchKernelGGL((k_upsweep<B, ITEMS>), dim3(grid), dim3(kSortThreads), 0, c.stream, c.ua);
+        // the upsweep zeroed the scan's look-back words (c.ua.clear)
         const int64_t entries = int64_t(1 << B) * c.L->max_tiles;
-        launch_scan<uint32_t>(TableLoad{c.ua.table}, TableStore{c.ua.table}, entries, nullptr, c.d_status,
-                              c.L->table_scan, static_cast<uint32_t*>(nullptr), c.stream);
+        launch_scan<uint32_t, kTableItems>(TableLoad{c.ua.table}, TableStore{c.ua.table}, entries, nullptr, c.d_status,
+                              c.L->table_scan, static_cast<uint32_t*>(nullptr), c.stream, true);
         hipLaunchKernelGGL((k_downsweep<B, ITEMS>), dim3(grid), dim3(kSortThreads), 0, c.stream, c.da);
     } else {
         // workgroups loop over tickets, so the grid need not cover every tile
@@ -604,15 +614,23 @@ size_t sort_workspace(int64_t capacity, int32_t begin_bit, int32_t end_bit, int3
     return plan(nullptr, capacity, begin_bit, end_bit, radix_bits, sparse, nullptr);
 }
 
+void sort_sync_words(void* ws, int64_t capacity, int32_t begin_bit, int32_t end_bit, int32_t radix_bits, bool sparse,
+                     ClearList* c) {
+    SortLayout L;
+    plan(ws, capacity, begin_bit, end_bit, radix_bits, sparse, &L);
+    if (!L.wait_free) c->add(L.hist, int64_t(L.passes) * (L.radix + 1));  // histograms, then tickets
+}
+
 hipError_t launch_sort(const uint64_t* kin, const uint32_t* vin, uint64_t* kout, uint32_t* vout, int64_t n,
                        const int64_t* d_n, const int32_t* d_status, int32_t begin_bit, int32_t end_bit,
-                       int32_t radix_bits, void* ws, hipStream_t stream, bool timed, bool sparse) {
+                       int32_t radix_bits, void* ws, hipStream_t stream, bool timed, bool sparse, bool precleared) {
     SortLayout L;
     plan(ws, n, begin_bit, end_bit, radix_bits, sparse, &L);
     const int hist_id = timed ? WS_KERNEL_SORT_HIST : -1, pass_id = timed ? WS_KERNEL_SORT_PASS : -1;
     if (!L.wait_free) {
-        hipLaunchKernelGGL(k_sort_init, dim3(1), dim3(256), 0, stream, L.hist, L.passes * L.radix, L.tickets,
-                           L.passes);
+        if (!precleared)
+            hipLaunchKernelGGL(k_sort_init, dim3(1), dim3(256), 0, stream, L.hist, L.passes * L.radix, L.tickets,
+                               L.passes);
         HistArgs h;
         h.keys = kin;
         h.cap = n;
@@ -644,7 +662,11 @@ hipError_t launch_sort(const uint64_t* kin, const uint32_t* vin, uint64_t* kout,
         c.L = &L;
         c.d_status = d_status;
         c.stream = stream;
-        c.ua = UpArgs{pk, n, d_n, d_status, shift, L.table, L.max_tiles};
+        c.ua = UpArgs{pk, n, d_n, d_status, shift, L.table, L.max_tiles, nullptr, 0};
+        if (L.wait_free) {
+            c.ua.clear = static_cast<uint32_t*>(L.table_scan);
+            c.ua.clear_words = scan_sync_words(int64_t(1 << bits) * L.max_tiles, kTableItems);
+        }
         c.da = DownArgs{pk, pv, ok, ov, n, d_n, d_status, shift, L.table, L.max_tiles};
         c.pa.kin = pk;
         c.pa.vin = pv;

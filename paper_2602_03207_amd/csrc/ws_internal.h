@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <cstdlib>
+
 #include "../../include/websplat.h"
 
 namespace ws {
@@ -94,6 +96,31 @@ __device__ __forceinline__ void store_agent(uint32_t* p, uint32_t v) {
 // many polls gives up and reports WS_ERR_SPIN_LIMIT instead of hanging.
 constexpr uint32_t kSpinLimit = 1u << 22;
 
+// Synchronisation words (look-back flags, tickets, global histograms) must be
+// zero when the kernel that uses them starts.  Instead of a clearing launch of
+// its own (a few microseconds each, most of it the dependency between
+// back-to-back launches), an earlier kernel of the same stream that does not
+// use the words zeroes them with its spare threads.
+struct ClearList {
+    static constexpr int kMax = 4;
+    uint32_t* ptr[kMax];
+    int64_t words[kMax];
+    int count = 0;
+    void add(void* p, int64_t w) {
+        if (!p || w <= 0) return;
+        if (count == kMax) std::abort();  // a fixed number of regions per launch: a programming error
+        ptr[count] = static_cast<uint32_t*>(p);
+        words[count++] = w;
+    }
+};
+
+// Called by every thread of the clearing kernel: `gid` is its index in the
+// grid, `threads` the grid's thread count.
+__device__ __forceinline__ void clear_words(const ClearList& c, int64_t gid, int64_t threads) {
+    for (int r = 0; r < c.count; ++r)
+        for (int64_t i = gid; i < c.words[r]; i += threads) c.ptr[r][i] = 0u;
+}
+
 // ------------------------------------------------------- shared data
 
 struct GaussPtrs {
@@ -161,10 +188,17 @@ size_t preprocess_workspace(int64_t n, int32_t n_views, int64_t capacity, uint32
 // `sparse`: the device count is expected to be far below the capacity; the
 // sort then always takes the small-tile look-back schedule, whose cost follows
 // the live count (workgroups past it leave at once) rather than the capacity.
+// `precleared`: an earlier kernel of the stream zeroed the words that
+// sort_sync_words lists, so the sort launches no clearing kernel.
 hipError_t launch_sort(const uint64_t* kin, const uint32_t* vin, uint64_t* kout, uint32_t* vout, int64_t n,
                        const int64_t* d_n, const int32_t* d_status, int32_t begin_bit, int32_t end_bit,
-                       int32_t radix_bits, void* ws, hipStream_t stream, bool timed = true, bool sparse = false);
+                       int32_t radix_bits, void* ws, hipStream_t stream, bool timed = true, bool sparse = false,
+                       bool precleared = false);
 size_t sort_workspace(int64_t capacity, int32_t begin_bit, int32_t end_bit, int32_t radix_bits, bool sparse = false);
+// Adds to `c` the words of a sort with these arguments that must be zero when
+// it starts (none for the wait-free schedule, whose passes clear their own).
+void sort_sync_words(void* ws, int64_t capacity, int32_t begin_bit, int32_t end_bit, int32_t radix_bits, bool sparse,
+                     ClearList* c);
 
 // render.hip
 hipError_t launch_render(const ws_splat* splats, int64_t n, const ws_camera* d_cams, int32_t n_views,
