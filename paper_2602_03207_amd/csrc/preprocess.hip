@@ -157,6 +157,7 @@ struct CountStore {
 struct EmitArgs {
     const ws_splat* splats;
     const ws_camera* cams;
+    int32_t n_views;
     const uint32_t* list;
     const uint32_t* offsets;
     const uint32_t* first_entry;
@@ -181,6 +182,7 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(EmitArgs a) {
     __shared__ uint32_t s_tilesx[kEmitSlots];
     __shared__ uint32_t s_scan[kEmitThreads / kWave + 1];
     __shared__ int64_t s_hi;
+    __shared__ uint32_t s_vtoff[kEmitThreads], s_vtx[kEmitThreads];
     if (*a.d_status != 0) return;
     const int64_t m = *a.d_num_pairs;
     if (m > a.capacity) {  // the caller's buffers are too small: report, write nothing
@@ -190,7 +192,21 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(EmitArgs a) {
     const int64_t p0 = int64_t(blockIdx.x) * kEmitPairs;
     if (p0 >= m) return;
     const int64_t p1 = min(p0 + kEmitPairs, m);
-    const int64_t nvis = *a.d_nvis;
+    const int64_t nvis = *a.d_nvis;  // >= 1: there are pairs
+    // first tile id and tiles per row of every view, in LDS (up to one view per
+    // thread; more views fall back to summing the cameras per entry)
+    const bool view_table = a.n_views <= kEmitThreads;
+    if (view_table) {
+        uint32_t tiles = 0, tx = 0;
+        if (int32_t(threadIdx.x) < a.n_views) {
+            tx = uint32_t(ceil_div(a.cams[threadIdx.x].width, a.tile_w));
+            tiles = tx * uint32_t(ceil_div(a.cams[threadIdx.x].height, a.tile_h));
+        }
+        uint32_t total;
+        const uint32_t toff = block_exclusive_scan<kEmitThreads>(tiles, s_scan, &total);
+        s_vtoff[threadIdx.x] = toff;
+        s_vtx[threadIdx.x] = tx;
+    }
     // Rounds: entries e, e + 1, ..., e + kEmitSlots - 1 (entry e owns pair lo)
     // cover the pairs [lo, hi), hi = the first pair of entry e + kEmitSlots
     // (or p1).  Entry starts strictly increase: every listed entry has pairs.
@@ -198,31 +214,40 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(EmitArgs a) {
     int64_t lo = p0;
     while (lo < p1) {
         for (int q = threadIdx.x; q < kEmitPairs; q += kEmitThreads) s_owner[q] = 0;
-        __syncthreads();
         const int slot = threadIdx.x;
         const int64_t ent = e + slot;
-        const bool in = ent < nvis && int64_t(a.offsets[ent]) < p1;
+        // the entry's start and list index, and the round's end, loaded together
+        const int64_t ec = ent < nvis ? ent : nvis - 1;
+        const uint32_t start = a.offsets[ec];
+        const uint32_t idx = a.list[ec];
+        const int64_t next = e + kEmitSlots;
+        const uint32_t next_start = a.offsets[next < nvis ? next : nvis - 1];
+        __syncthreads();
+        const bool in = ent < nvis && int64_t(start) < p1;
         if (in) {
-            const uint32_t start = a.offsets[ent];
-            const uint32_t idx = a.list[ent];
             const int64_t view = int64_t(idx) / a.n;
             const float4 r2 = reinterpret_cast<const float4*>(a.splats + idx)[2];
             const uint32_t r01 = __float_as_uint(r2.z), r23 = __float_as_uint(r2.w);
-            int64_t toff, ioff;
-            view_offsets(a.cams, int32_t(view), a.tile_w, a.tile_h, &toff, &ioff);
+            uint32_t tbase, tilesx;
+            if (view_table) {
+                tbase = s_vtoff[view];
+                tilesx = s_vtx[view];
+            } else {
+                int64_t toff, ioff;
+                view_offsets(a.cams, int32_t(view), a.tile_w, a.tile_h, &toff, &ioff);
+                tbase = uint32_t(toff);
+                tilesx = uint32_t(ceil_div(a.cams[view].width, a.tile_w));
+            }
             s_start[slot] = start;
             s_gid[slot] = uint32_t(int64_t(idx) - view * a.n);
             s_depth[slot] = __float_as_uint(r2.y);
             s_trx[slot] = ((r01 & 0xffffu) / uint32_t(a.tile_w)) | (((r01 >> 16) / uint32_t(a.tile_w)) << 16);
             s_try[slot] = ((r23 & 0xffffu) / uint32_t(a.tile_h)) | (((r23 >> 16) / uint32_t(a.tile_h)) << 16);
-            s_tbase[slot] = uint32_t(toff);
-            s_tilesx[slot] = uint32_t(ceil_div(a.cams[view].width, a.tile_w));
+            s_tbase[slot] = tbase;
+            s_tilesx[slot] = tilesx;
             if (slot > 0) s_owner[int64_t(start) - p0] = uint32_t(slot);
         }
-        if (threadIdx.x == 0) {
-            const int64_t next = e + kEmitSlots;
-            s_hi = next < nvis ? min(p1, int64_t(a.offsets[next])) : p1;
-        }
+        if (threadIdx.x == 0) s_hi = next < nvis ? min(p1, int64_t(next_start)) : p1;
         __syncthreads();
         const int64_t hi = s_hi;
         // owner of pair q = the largest slot that starts at or before q (slot 0
@@ -333,6 +358,7 @@ hipError_t launch_preprocess(const GaussPtrs& g, const ws_camera* d_cams, int32_
     EmitArgs ea;
     ea.splats = splats;
     ea.cams = d_cams;
+    ea.n_views = n_views;
     ea.list = list;
     ea.offsets = pw.offsets;
     ea.first_entry = pw.first_entry;
