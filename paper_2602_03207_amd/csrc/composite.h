@@ -194,64 +194,100 @@ __device__ __forceinline__ void quadrant_pixel(int x0, int y0, int* px, int* py)
     *py = y0 + (w / (TW / 8)) * 8 + (l >> 3);
 }
 
-// Can the splat reach alpha >= alpha_min at any pixel centre of the block
-// [bx0, bx1] x [by0, by1] (inclusive pixel indices)?  With Q(d) = -(qa dx^2 +
-// qb dx dy + qc dy^2) >= 0 the pixel test passes only where Q <= ls -
-// log2(alpha_min) =: R.  Q is convex, so its minimum over the box of offsets
-// d = mean - pixel centre is 0 when the mean lies in the box and otherwise lies
-// on one of the four edges, where it is a one-dimensional quadratic minimised
-// in closed form (clamped to the edge).  The answer is "no" only when that
-// minimum exceeds R by a margin far above the fp32 rounding of this bound and
-// of the per-pixel evaluation (relative to the sizes of the terms involved),
-// so a block it rules out holds no pixel whose fp32 alpha reaches alpha_min:
-// dropping the splat there changes no pixel and no skip decision.  Non-finite
-// values answer "yes".
-struct EllipseCull {
-    float a, b, c, kx, ky, R, scale;  // Q = a dx^2 + b dx dy + c dy^2
-    __device__ __forceinline__ EllipseCull(const StagedSplat& s, float log2_amin) {
+// The pixel columns, per band of tile rows, where a splat can reach
+// alpha >= alpha_min.  In offsets p = pixel centre - mean the per-pixel test
+// passes only where Q(p) = a px^2 + b px py + c py^2 <= ls - log2(alpha_min)
+// (a = -qa, b = -qb, c = -qc: the same quadratic form as the per-pixel
+// exponent).  The threshold is first raised by a bound on the fp32 rounding of
+// the per-pixel evaluation (relative to the sizes of its terms, which the
+// conditioning kappa = 8ac / (4ac - b^2) bounds), so the ellipse below holds
+// every pixel whose fp32 alpha can reach alpha_min.  On a row py of that
+// ellipse, px lies between the roots (-b py -+ sqrt(4aR - (4ac - b^2) py^2)) /
+// 2a; over a band of rows the smallest left root is -hx if the ellipse's
+// leftmost point lies in the band and otherwise that of the row nearer to it
+// (the left root is convex in py), and likewise on the right.  The interval is
+// widened by a bound on the fp32 rounding of this computation before it is
+// turned into whole pixel columns, so dropping a splat from a quadrant outside
+// those columns changes no pixel and no skip decision.  Splats whose form is
+// too ill-conditioned for that bound, or not finite, keep their rectangle.
+struct EllipseRows {
+    float a, b, c, R, det4, hx, hy, inv2a, py_left, mx, my;
+    bool ok, none;
+    __device__ __forceinline__ EllipseRows(const StagedSplat& s, float log2_amin) {
         a = -s.qa;
         b = -s.qb;
         c = -s.qc;
-        kx = b / (2.f * c);  // edge dx = const: dy* = -kx dx
-        ky = b / (2.f * a);  // edge dy = const: dx* = -ky dy
-        R = s.ls - log2_amin;
-        scale = fabsf(s.ls) + fabsf(log2_amin);
+        // hardware reciprocal and square root (about 1 ulp): the margins below
+        // are orders of magnitude wider than their error
+        det4 = fmaf(4.f * a, c, -b * b);
+        const float inv = __builtin_amdgcn_rcpf(det4), ra = __builtin_amdgcn_rcpf(a), rc = __builtin_amdgcn_rcpf(c);
+        const float kappa = 8.f * a * c * inv;
+        const float R0 = s.ls - log2_amin;
+        R = R0 + 1e-5f * (kappa * (fabsf(R0) + 1.f) + fabsf(s.ls) + fabsf(log2_amin) + 1.f);
+        ok = a > 0.f && c > 0.f && det4 > 0.f && kappa < 1e4f && __builtin_isfinite(R) && __builtin_isfinite(kappa) &&
+             __builtin_isfinite(s.u) && __builtin_isfinite(s.v);
+        none = ok && R < 0.f;  // alpha_min is out of reach everywhere
+        const float Rp = fmaxf(R, 0.f);
+        hx = __builtin_amdgcn_sqrtf(4.f * c * Rp * inv);
+        hy = __builtin_amdgcn_sqrtf(4.f * a * Rp * inv);
+        inv2a = 0.5f * ra;
+        py_left = b * hx * (0.5f * rc);  // row of the leftmost point; the rightmost is at -py_left
+        const float k1 = 1.f + kappa;
+        mx = 4.f * __builtin_amdgcn_sqrtf(1e-5f * Rp * k1 * ra) + 1e-5f * (hx * k1 + fabsf(b) * hy * inv2a) + 1e-3f;
+        my = 4.f * __builtin_amdgcn_sqrtf(1e-5f * Rp * k1 * rc) + 1e-5f * hy * k1 + 1e-3f;
     }
-    __device__ __forceinline__ float q(float dx, float dy) const { return fmaf(a * dx, dx, dy * fmaf(b, dx, c * dy)); }
-    __device__ __forceinline__ bool meets(const StagedSplat& s, int bx0, int bx1, int by0, int by1) const {
-        const float lx0 = s.u - (float(bx1) + 0.5f), lx1 = s.u - (float(bx0) + 0.5f);
-        const float ly0 = s.v - (float(by1) + 0.5f), ly1 = s.v - (float(by0) + 0.5f);
-        if (lx0 <= 0.f && lx1 >= 0.f && ly0 <= 0.f && ly1 >= 0.f) return true;
-        const float q0 = q(lx0, __builtin_amdgcn_fmed3f(-kx * lx0, ly0, ly1));
-        const float q1 = q(lx1, __builtin_amdgcn_fmed3f(-kx * lx1, ly0, ly1));
-        const float q2 = q(__builtin_amdgcn_fmed3f(-ky * ly0, lx0, lx1), ly0);
-        const float q3 = q(__builtin_amdgcn_fmed3f(-ky * ly1, lx0, lx1), ly1);
-        const float qmin = fminf(fminf(q0, q1), fminf(q2, q3));
-        const float mx = fmaxf(fabsf(lx0), fabsf(lx1)), my = fmaxf(fabsf(ly0), fabsf(ly1));
-        const float size = fmaf(a * mx, mx, my * fmaf(fabsf(b), mx, c * my)) + scale;
-        const bool finite = __builtin_isfinite(qmin) && __builtin_isfinite(size) && a > 0.f && c > 0.f;
-        return !(finite && qmin > R + 1e-4f * size + 1e-4f);
+    // Intersects [*cx0, *cx1] with the columns the splat can reach on pixel
+    // rows [by0, by1] (non-empty).
+    __device__ __forceinline__ void columns(const StagedSplat& s, int by0, int by1, int* cx0, int* cx1) const {
+        if (!ok) return;
+        const float y0 = (float(by0) + 0.5f) - s.v, y1 = (float(by1) + 0.5f) - s.v;
+        if (none || y0 > hy + my || y1 < -hy - my) {
+            *cx1 = *cx0 - 1;
+            return;
+        }
+        const float yc0 = fminf(fmaxf(y0, -hy), hy), yc1 = fmaxf(fminf(y1, hy), -hy);
+        const float s0 = __builtin_amdgcn_sqrtf(fmaxf(fmaf(-det4 * yc0, yc0, 4.f * a * R), 0.f));
+        const float s1 = __builtin_amdgcn_sqrtf(fmaxf(fmaf(-det4 * yc1, yc1, 4.f * a * R), 0.f));
+        const float left = (py_left >= y0 - my && py_left <= y1 + my)
+                               ? -hx
+                               : fminf((-b * yc0 - s0) * inv2a, (-b * yc1 - s1) * inv2a);
+        const float right = (-py_left >= y0 - my && -py_left <= y1 + my)
+                                ? hx
+                                : fmaxf((-b * yc0 + s0) * inv2a, (-b * yc1 + s1) * inv2a);
+        // pixel x is reachable only if x + 0.5 - u lies in [left - mx, right + mx]
+        const float e = 1e-6f * fabsf(s.u) + 1e-3f;
+        const float f0 = fmaxf(s.u + (left - mx) - 0.5f - e, -1.f);
+        const float f1 = fminf(s.u + (right + mx) - 0.5f + e, 65536.f);
+        *cx0 = max(*cx0, int(ceilf(f0)));
+        *cx1 = min(*cx1, int(floorf(f1)));
     }
 };
 
 // Ballots of "this staged splat meets quadrant q" into masks[q * NW + staging
-// wave]: its rectangle meets the quadrant's pixel block and, on the part they
-// share, the splat can reach alpha_min (EllipseCull).
+// wave]: on the rows its rectangle shares with the quadrant, the columns where
+// it can reach alpha_min (EllipseRows, intersected with its rectangle) meet
+// the quadrant's columns.
 template <int TW, int TH>
 __device__ __forceinline__ void stage_quadrant_masks(const StagedSplat& s, bool valid, int x0, int y0,
                                                      float log2_amin, uint64_t* masks) {
-    constexpr int QX = TW / 8, NQ = (TW / 8) * (TH / 8), NW = TW * TH / kWave;
+    constexpr int QX = TW / 8, QY = TH / 8, NW = TW * TH / kWave;
     const int rx0 = int(s.rxy & 0xffffu), ry0 = int(s.rxy >> 16);
     const int rx1 = rx0 + int(s.rwh & 0xffffu), ry1 = ry0 + int(s.rwh >> 16);
     const int w = threadIdx.x / kWave;
-    const EllipseCull ec(s, log2_amin);
+    const EllipseRows er(s, log2_amin);
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-        const int qx0 = x0 + (q % QX) * 8, qy0 = y0 + (q / QX) * 8;
-        bool meets = valid && rx0 <= qx0 + 7 && rx1 >= qx0 && ry0 <= qy0 + 7 && ry1 >= qy0;
-        if (meets) meets = ec.meets(s, max(rx0, qx0), min(rx1, qx0 + 7), max(ry0, qy0), min(ry1, qy0 + 7));
-        const uint64_t b = wave_ballot(meets);
-        if (lane_id() == 0) masks[q * NW + w] = b;
+    for (int qy = 0; qy < QY; ++qy) {
+        const int by0 = max(ry0, y0 + 8 * qy), by1 = min(ry1, y0 + 8 * qy + 7);
+        const bool rows = valid && by0 <= by1;
+        int cx0 = rx0, cx1 = rx1;
+        if (rows) er.columns(s, by0, by1, &cx0, &cx1);
+#pragma unroll
+        for (int qx = 0; qx < QX; ++qx) {
+            const int qx0 = x0 + 8 * qx;
+            const bool meets = rows && cx0 <= qx0 + 7 && cx1 >= qx0 && cx0 <= cx1;
+            const uint64_t bal = wave_ballot(meets);
+            if (lane_id() == 0) masks[(qy * QX + qx) * NW + w] = bal;
+        }
     }
 }
 
