@@ -167,6 +167,7 @@ struct EmitArgs {
     int64_t n;
     int64_t capacity;
     int32_t tile_w, tile_h;
+    uint32_t tw_shift, th_shift;  // log2 of the tile size
     uint64_t* keys;
     uint32_t* values;
 };
@@ -180,6 +181,7 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(EmitArgs a) {
     __shared__ uint32_t s_try[kEmitSlots];
     __shared__ uint32_t s_tbase[kEmitSlots];
     __shared__ uint32_t s_tilesx[kEmitSlots];
+    __shared__ uint32_t s_magic[kEmitSlots];  // floor((2^32 - 1) / tile-rectangle width)
     __shared__ uint32_t s_scan[kEmitThreads / kWave + 1];
     __shared__ int64_t s_hi;
     __shared__ uint32_t s_vtoff[kEmitThreads], s_vtx[kEmitThreads];
@@ -225,7 +227,7 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(EmitArgs a) {
         __syncthreads();
         const bool in = ent < nvis && int64_t(start) < p1;
         if (in) {
-            const int64_t view = int64_t(idx) / a.n;
+            const int64_t view = int64_t(idx / uint32_t(a.n));  // V n < 2^32
             const float4 r2 = reinterpret_cast<const float4*>(a.splats + idx)[2];
             const uint32_t r01 = __float_as_uint(r2.z), r23 = __float_as_uint(r2.w);
             uint32_t tbase, tilesx;
@@ -241,10 +243,13 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(EmitArgs a) {
             s_start[slot] = start;
             s_gid[slot] = uint32_t(int64_t(idx) - view * a.n);
             s_depth[slot] = __float_as_uint(r2.y);
-            s_trx[slot] = ((r01 & 0xffffu) / uint32_t(a.tile_w)) | (((r01 >> 16) / uint32_t(a.tile_w)) << 16);
-            s_try[slot] = ((r23 & 0xffffu) / uint32_t(a.tile_h)) | (((r23 >> 16) / uint32_t(a.tile_h)) << 16);
+            // tile sizes are powers of two (8, 16, 32)
+            const uint32_t tx0 = (r01 & 0xffffu) >> a.tw_shift, tx1 = (r01 >> 16) >> a.tw_shift;
+            s_trx[slot] = tx0 | (tx1 << 16);
+            s_try[slot] = ((r23 & 0xffffu) >> a.th_shift) | (((r23 >> 16) >> a.th_shift) << 16);
             s_tbase[slot] = tbase;
             s_tilesx[slot] = tilesx;
+            s_magic[slot] = 0xffffffffu / (tx1 - tx0 + 1);
             if (slot > 0) s_owner[int64_t(start) - p0] = uint32_t(slot);
         }
         if (threadIdx.x == 0) s_hi = next < nvis ? min(p1, int64_t(next_start)) : p1;
@@ -294,7 +299,17 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(EmitArgs a) {
                 const uint32_t xr = s_trx[s], yr = s_try[s];
                 const uint32_t tx0 = xr & 0xffffu, tx1 = xr >> 16, ty0 = yr & 0xffffu;
                 const uint32_t w = tx1 - tx0 + 1;
-                const uint32_t row = k / w, col = k - row * w;
+                // k / w by a multiply-high with floor((2^32 - 1) / w), which
+                // undershoots by at most 2 for any 32-bit k; then corrected
+                uint32_t row = __umulhi(k, s_magic[s]), col = k - row * w;
+                if (col >= w) {
+                    ++row;
+                    col -= w;
+                }
+                if (col >= w) {
+                    ++row;
+                    col -= w;
+                }
                 const uint64_t tile = uint64_t(s_tbase[s]) + uint64_t(ty0 + row) * s_tilesx[s] + (tx0 + col);
                 a.keys[p] = (tile << 32) | s_depth[s];
                 a.values[p] = s_gid[s];
@@ -369,6 +384,8 @@ hipError_t launch_preprocess(const GaussPtrs& g, const ws_camera* d_cams, int32_
     ea.capacity = capacity;
     ea.tile_w = o.tile_w;
     ea.tile_h = o.tile_h;
+    ea.tw_shift = uint32_t(__builtin_ctz(uint32_t(o.tile_w)));
+    ea.th_shift = uint32_t(__builtin_ctz(uint32_t(o.tile_h)));
     ea.keys = keys;
     ea.values = values;
     hipLaunchKernelGGL(k_emit, dim3(uint32_t(pw.emit_blocks)), dim3(kEmitThreads), 0, stream, ea);

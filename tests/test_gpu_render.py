@@ -114,6 +114,69 @@ def test_render_component_parity_c1():
     assert worst < 2e-5
 
 
+@pytest.mark.parametrize("tile", [(16, 16), (8, 8), (32, 16)])
+def test_quadrant_culling_keeps_every_contribution(tile):
+    """Thin, rotated, faint and large splats (the cases where a splat's rectangle holds quadrants its
+    alpha >= alpha_min ellipse never reaches) rendered from given records and pairs: every pixel matches
+    the oracle compositing the same records, so the quadrant culling drops no contributing splat."""
+    import torch
+    from paper_2602_03207_amd import binding as B
+    tw, th = tile
+    W, H, n = 512, 384, 3000
+    rng = np.random.default_rng(23)
+    u, v = rng.uniform(-30, W + 30, n), rng.uniform(-30, H + 30, n)
+    s1 = np.exp(rng.uniform(np.log(0.5), np.log(90), n))
+    s2 = s1 / np.exp(rng.uniform(0, np.log(300), n))
+    th_ = rng.uniform(0, np.pi, n)
+    c, s_ = np.cos(th_), np.sin(th_)
+    S00 = c * c * s1 * s1 + s_ * s_ * s2 * s2 + 0.3
+    S11 = s_ * s_ * s1 * s1 + c * c * s2 * s2 + 0.3
+    S01 = c * s_ * (s1 * s1 - s2 * s2)
+    det = S00 * S11 - S01 * S01
+    conic = np.stack([S11 / det, -S01 / det, S00 / det]).astype(np.float32)
+    opacity = np.exp(rng.uniform(np.log(1.02 / 255), np.log(0.99), n)).astype(np.float32)
+    rgb = rng.uniform(0.2, 1.0, (3, n)).astype(np.float32)
+    depth = rng.permutation(np.linspace(1.0, 50.0, n)).astype(np.float32)
+    mean2d = np.stack([u, v]).astype(np.float32)
+    d2 = 2 * np.log(255 * opacity.astype(np.float64))
+    hx, hy = np.sqrt(d2 * S00), np.sqrt(d2 * S11)
+    rect = np.stack([np.ceil(u - hx - 0.5), np.floor(u + hx - 0.5), np.ceil(v - hy - 0.5), np.floor(v + hy - 0.5)])
+    rect = np.stack([np.clip(rect[0], 0, W - 1), np.clip(rect[1], -1, W - 1), np.clip(rect[2], 0, H - 1),
+                     np.clip(rect[3], -1, H - 1)]).astype(np.int32)
+    vis = (rect[1] >= rect[0]) & (rect[3] >= rect[2]) & (u - hx < W) & (u + hx > 0) & (v - hy < H) & (v + hy > 0)
+    tx = (W + tw - 1) // tw
+    keys, vals = [], []
+    for i in np.nonzero(vis)[0]:
+        for ty in range(rect[2, i] // th, rect[3, i] // th + 1):
+            for t in range(rect[0, i] // tw, rect[1, i] // tw + 1):
+                keys.append((ty * tx + t) << 32 | int(depth[i:i + 1].view(np.uint32)[0]))
+                vals.append(i)
+    keys, vals = np.array(keys, np.uint64), np.array(vals, np.uint32)
+    skeys, svals = oracle.stable_sort(keys, vals)
+    n_tiles = tx * ((H + th - 1) // th)
+    ranges = oracle.tile_ranges(skeys, n_tiles)
+    cam = scenegen.Camera(W, H, 400.0, 400.0, W / 2, H / 2, np.eye(3), np.zeros(3), np.zeros(3))
+    ro = oracle_options(tile_w=tw, tile_h=th)
+    rect_or = np.where(vis, rect, np.array([[1], [0], [1], [0]], np.int32))
+    comp = oracle.composite(mean2d, conic, opacity, rgb, rect_or, cam, ro, svals, ranges)
+    rec = pack_splats(mean2d, conic, opacity, rgb, depth, np.where(vis, rect, 0))
+    opts = gpu_options(tile_w=tw, tile_h=th)
+    cams = B.camera_array([cam])
+    d_cams = torch.as_tensor(B.camera_bytes(cams)).cuda()
+    m = skeys.size
+    d_n = torch.tensor([m], dtype=torch.int64, device="cuda")
+    d_status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    ranges_d = torch.empty(2 * n_tiles, dtype=torch.int32, device="cuda")
+    images = torch.empty(3 * W * H, dtype=torch.float32, device="cuda")
+    ws = torch.empty(max(B.ws_render_workspace_size(cams, 1, opts), 256), dtype=torch.uint8, device="cuda")
+    B.ws_render(torch.as_tensor(rec).cuda(), n, cams, d_cams, 1, opts, torch.as_tensor(skeys.view(np.int64)).cuda(),
+                torch.as_tensor(svals.view(np.int32)).cuda(), m, d_n, d_status, ranges_d, images, ws, ws.numel())
+    torch.cuda.synchronize()
+    assert int(d_status.item()) == 0
+    img = images.cpu().numpy().reshape(3, H, W)
+    assert_image_parity(img, comp)
+
+
 @pytest.mark.parametrize("tile", [(16, 16), (8, 8), (16, 8), (32, 16)])
 def test_render_end_to_end_c1(tile):
     scene, cam = scenegen.c1()
