@@ -59,8 +59,27 @@ struct BwdArgs {
 };
 
 struct RawConic {
-    float A, B, C, sigma;
+    float A, B, C, inv_sigma;
 };
+
+// Sum over the 64 lanes of a wave, complete in the last row of 16 lanes
+// (lane 63 among them): DPP permutes within quads and rows, then the row
+// broadcasts of lane 15 and lane 31 into the rows above.  Every step is a
+// VALU add with a permuted operand; no LDS traffic.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_add(float v) {
+    const int moved = __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, ROW_MASK, 0xf, false);
+    return v + __builtin_bit_cast(float, moved);
+}
+__device__ __forceinline__ float wave_sum_last_row(float v) {
+    v = dpp_add<0xb1, 0xf>(v);   // quad_perm [1, 0, 3, 2]: pairs
+    v = dpp_add<0x4e, 0xf>(v);   // quad_perm [2, 3, 0, 1]: quads
+    v = dpp_add<0x124, 0xf>(v);  // row_ror 4: half rows
+    v = dpp_add<0x128, 0xf>(v);  // row_ror 8: every lane holds its row's sum
+    v = dpp_add<0x142, 0xa>(v);  // row_bcast 15 into rows 1 and 3: rows 0+1, rows 2+3
+    v = dpp_add<0x143, 0xc>(v);  // row_bcast 31 into rows 2 and 3: row 3 holds all four
+    return v;
+}
 
 template <int TW, int TH>
 __global__ __launch_bounds__(TW * TH) void k_render_bwd(BwdArgs a) {
@@ -137,7 +156,7 @@ __global__ __launch_bounds__(TW * TH) void k_render_bwd(BwdArgs a) {
                 if (valid) s = stage_splat(vsplats, id);
                 s_batch[threadIdx.x] = s;
                 const float* rec = reinterpret_cast<const float*>(vsplats + (valid ? id : 0));
-                s_conic[threadIdx.x] = RawConic{rec[2], rec[3], rec[4], rec[5]};
+                s_conic[threadIdx.x] = RawConic{rec[2], rec[3], rec[4], 1.f / rec[5]};
             }
 #pragma unroll
             for (int k = 0; k < kNG; ++k) s_acc[k][threadIdx.x] = 0.f;
@@ -161,13 +180,15 @@ __global__ __launch_bounds__(TW * TH) void k_render_bwd(BwdArgs a) {
                 const float alpha = __builtin_amdgcn_fmed3f(araw, 0.f, bk.alpha_max);
                 if (!(alpha < bk.alpha_min)) {
                     contrib = true;
-                    const float one_m = 1.f - alpha;
-                    const float Tk = T / one_m;
+                    // 1 - alpha >= 1 - alpha_max > 0; the hardware reciprocal
+                    // (about 1 ulp) keeps the back-to-front recovery of T well
+                    // inside the gradient tolerance
+                    const float inv = __builtin_amdgcn_rcpf(1.f - alpha);
+                    const float Tk = T * inv;
                     const float w = alpha * Tk;
                     gv[6] = dLdC[0] * w;
                     gv[7] = dLdC[1] * w;
                     gv[8] = dLdC[2] * w;
-                    const float inv = 1.f / one_m;
                     const float dLda = dLdC[0] * (s.r * Tk - R[0] * inv) + dLdC[1] * (s.g * Tk - R[1] * inv) +
                                        dLdC[2] * (s.b * Tk - R[2] * inv);
                     R[0] = fmaf(s.r, w, R[0]);
@@ -177,7 +198,7 @@ __global__ __launch_bounds__(TW * TH) void k_render_bwd(BwdArgs a) {
                     if (!(araw > bk.alpha_max)) {
                         const RawConic& q = s_conic[t];
                         const float gp = dLda * araw;  // dL/dpower
-                        gv[5] = dLda * (araw / q.sigma);  // dL/dsigma = dL/dalpha exp(power)
+                        gv[5] = dLda * (araw * q.inv_sigma);  // dL/dsigma = dL/dalpha exp(power)
                         gv[0] = -gp * (q.A * dx + q.B * dy);
                         gv[1] = -gp * (q.C * dy + q.B * dx);
                         gv[2] = -0.5f * gp * dx * dx;
@@ -189,8 +210,8 @@ __global__ __launch_bounds__(TW * TH) void k_render_bwd(BwdArgs a) {
             if (__ballot(contrib) != 0) {
 #pragma unroll
                 for (int k = 0; k < kNG; ++k) {
-                    const float sum = wave_sum(gv[k]);
-                    if (lane_id() == 0 && sum != 0.f) atomicAdd(&s_acc[k][t], sum);
+                    const float sum = wave_sum_last_row(gv[k]);
+                    if (lane_id() == kWave - 1 && sum != 0.f) atomicAdd(&s_acc[k][t], sum);
                 }
             }
         }
