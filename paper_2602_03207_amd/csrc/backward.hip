@@ -62,23 +62,49 @@ struct RawConic {
     float A, B, C, inv_sigma;
 };
 
-// Sum over the 64 lanes of a wave, complete in the last row of 16 lanes
-// (lane 63 among them): DPP permutes within quads and rows, then the row
-// broadcasts of lane 15 and lane 31 into the rows above.  Every step is a
-// VALU add with a permuted operand; no LDS traffic.
-template <int CTRL, int ROW_MASK>
+// Sums over the 64 lanes of a wave of the nine per-splat gradient values,
+// transposed so that the work halves at every cross-row step: the 32-lane
+// swap pairs up values (v0, v1), (v2, v3), ... and one add leaves each value's
+// half-sums in one half of the wave; the 16-lane swap pairs up those and one
+// add leaves each value's quarter-sums in one row; DPP permutes inside rows
+// then sum each row.  Results, in every lane of the row: q0 holds v0, v2, v1,
+// v3 in rows 0, 1, 2, 3; q1 holds v4, v6, v5, v7; q2 holds v8 in row 0.  Every
+// step is a VALU operation on all 64 lanes (the callers run with all lanes
+// active); no LDS traffic.
+__device__ __forceinline__ void swap32(float& a, float& b) {
+    // both operands are read and written (the swap builtin of this compiler
+    // returns the first register twice); two wait states on either side
+    asm volatile("s_nop 1\n\tv_permlane32_swap_b32 %0, %1\n\ts_nop 1" : "+v"(a), "+v"(b));
+}
+__device__ __forceinline__ void swap16(float& a, float& b) {
+    asm volatile("s_nop 1\n\tv_permlane16_swap_b32 %0, %1\n\ts_nop 1" : "+v"(a), "+v"(b));
+}
+template <int CTRL>
 __device__ __forceinline__ float dpp_add(float v) {
-    const int moved = __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, ROW_MASK, 0xf, false);
+    const int moved = __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xf, 0xf, false);
     return v + __builtin_bit_cast(float, moved);
 }
-__device__ __forceinline__ float wave_sum_last_row(float v) {
-    v = dpp_add<0xb1, 0xf>(v);   // quad_perm [1, 0, 3, 2]: pairs
-    v = dpp_add<0x4e, 0xf>(v);   // quad_perm [2, 3, 0, 1]: quads
-    v = dpp_add<0x124, 0xf>(v);  // row_ror 4: half rows
-    v = dpp_add<0x128, 0xf>(v);  // row_ror 8: every lane holds its row's sum
-    v = dpp_add<0x142, 0xa>(v);  // row_bcast 15 into rows 1 and 3: rows 0+1, rows 2+3
-    v = dpp_add<0x143, 0xc>(v);  // row_bcast 31 into rows 2 and 3: row 3 holds all four
+__device__ __forceinline__ float row_sum(float v) {
+    v = dpp_add<0xb1>(v);   // quad_perm [1, 0, 3, 2]: pairs
+    v = dpp_add<0x4e>(v);   // quad_perm [2, 3, 0, 1]: quads
+    v = dpp_add<0x124>(v);  // row_ror 4
+    v = dpp_add<0x128>(v);  // row_ror 8: every lane holds its row's sum
     return v;
+}
+__device__ __forceinline__ void wave_sum9(float (&v)[kNG], float* q0, float* q1, float* q2) {
+    float z0 = 0.f, z1 = 0.f;
+    swap32(v[0], v[1]);
+    swap32(v[2], v[3]);
+    swap32(v[4], v[5]);
+    swap32(v[6], v[7]);
+    swap32(v[8], z0);
+    float p01 = v[0] + v[1], p23 = v[2] + v[3], p45 = v[4] + v[5], p67 = v[6] + v[7], p8 = v[8] + z0;
+    swap16(p01, p23);
+    swap16(p45, p67);
+    swap16(p8, z1);
+    *q0 = row_sum(p01 + p23);
+    *q1 = row_sum(p45 + p67);
+    *q2 = row_sum(p8 + z1);
 }
 
 template <int TW, int TH>
@@ -208,10 +234,16 @@ __global__ __launch_bounds__(TW * TH) void k_render_bwd(BwdArgs a) {
                 }
             }
             if (__ballot(contrib) != 0) {
-#pragma unroll
-                for (int k = 0; k < kNG; ++k) {
-                    const float sum = wave_sum_last_row(gv[k]);
-                    if (lane_id() == kWave - 1 && sum != 0.f) atomicAdd(&s_acc[k][t], sum);
+                float q0, q1, q2;
+                wave_sum9(gv, &q0, &q1, &q2);
+                // the first lane of each row adds its row's values (distinct addresses)
+                const uint32_t lane = lane_id();
+                if ((lane & 15) == 0) {
+                    const int row = int(lane >> 4);
+                    const int k0 = row == 1 ? 2 : (row == 2 ? 1 : row);  // rows hold v0, v2, v1, v3
+                    if (q0 != 0.f) atomicAdd(&s_acc[k0][t], q0);
+                    if (q1 != 0.f) atomicAdd(&s_acc[4 + k0][t], q1);
+                    if (row == 0 && q2 != 0.f) atomicAdd(&s_acc[8][t], q2);
                 }
             }
         }
