@@ -302,32 +302,36 @@ __device__ __forceinline__ uint64_t uniform_u64(uint64_t v) {
 
 // The set bits of a wave's NW quadrant masks (held in scalar registers), in
 // increasing order (Forward) or decreasing order; next() returns -1 at the end.
+// The mask being walked is always mk[0] (Forward) or mk[NW - 1]: when it runs
+// out the others shift along, so every index is a constant and the masks stay
+// in registers (a walk that picked mk[sw] by a variable index was kept in
+// scratch memory).
 template <int NW, bool Forward>
 struct MaskWalk {
     uint64_t mk[NW];
-    uint64_t m;
     int sw;
 
     __device__ __forceinline__ void init(const uint64_t* quadrant_masks) {
 #pragma unroll
         for (int w = 0; w < NW; ++w) mk[w] = uniform_u64(quadrant_masks[w]);
         sw = Forward ? 0 : NW - 1;
-        m = mk[sw];
-    }
-    __device__ __forceinline__ uint64_t pick(int w) const {
-        uint64_t r = mk[0];
-#pragma unroll
-        for (int i = 1; i < NW; ++i) r = (w == i) ? mk[i] : r;
-        return r;
     }
     __device__ __forceinline__ int next() {
-        while (m == 0) {
+        constexpr int kCur = Forward ? 0 : NW - 1;
+        while (mk[kCur] == 0) {
             sw += Forward ? 1 : -1;
             if (sw < 0 || sw >= NW) return -1;
-            m = pick(sw);
+            if (Forward) {
+#pragma unroll
+                for (int i = 0; i + 1 < NW; ++i) mk[i] = mk[i + 1];
+            } else {
+#pragma unroll
+                for (int i = NW - 1; i > 0; --i) mk[i] = mk[i - 1];
+            }
         }
+        const uint64_t m = mk[kCur];
         const int j = Forward ? __builtin_ctzll(m) : 63 - __builtin_clzll(m);
-        m &= ~(uint64_t(1) << j);
+        mk[kCur] = m & ~(uint64_t(1) << j);
         return sw * kWave + j;
     }
 };
