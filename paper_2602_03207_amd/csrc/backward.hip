@@ -15,10 +15,13 @@
 //     reduced across the wave (shuffles) and across the workgroup (LDS
 //     atomics), then added to device memory with one atomic per value.
 // k_bwd_clear           zeroes the per-(view, splat) gradient buffer.
-// k_preprocess_bwd      one thread per Gaussian, summing over the views: the
+// k_preprocess_bwd_geo  one thread per Gaussian, summing over the views: the
 //     chain through the conic inverse, the EWA covariance, the Jacobian
-//     (branch taken at the clamp), the rotation and scale, the mean
-//     projection, the SH colour (clamped channels give zero) and the sigmoid.
+//     (branch taken at the clamp), the rotation and scale, the mean projection
+//     and the sigmoid.
+// k_preprocess_bwd_sh   one thread per Gaussian, summing over the views: the SH
+//     colour (clamped channels give zero) and the view direction, added to the
+//     mean gradient.
 #include "composite.h"
 #include "project.h"
 #include "ws_internal.h"
@@ -287,53 +290,27 @@ __device__ __forceinline__ void rotmat_vjp(const float* q, const float* G, float
                    y * G[7]);
 }
 
+// Geometry part of the pre-processing adjoint: per Gaussian, over the views in
+// which its centre, conic or opacity received a gradient.
 template <int DEG>
-__global__ __launch_bounds__(128) void k_preprocess_bwd(PreBwdArgs a) {
+__global__ __launch_bounds__(128) void k_preprocess_bwd_geo(PreBwdArgs a) {
     const int64_t i = int64_t(blockIdx.x) * 128 + threadIdx.x;
     const int64_t n = a.g.n;
     if (i >= n) return;
-    constexpr int K = (DEG + 1) * (DEG + 1);
     float gm[3] = {0.f, 0.f, 0.f}, gls[3] = {0.f, 0.f, 0.f}, gq[4] = {0.f, 0.f, 0.f, 0.f}, glogit = 0.f;
-    float gsh[3 * K];
-#pragma unroll
-    for (int k = 0; k < 3 * K; ++k) gsh[k] = 0.f;
     for (int32_t v = 0; v < a.n_views; ++v) {
         const int64_t vi = int64_t(v) * n + i;
-        float gs[kNG];
+        float gs[6];
         bool any = false;
 #pragma unroll
-        for (int k = 0; k < kNG; ++k) {
+        for (int k = 0; k < 6; ++k) {
             gs[k] = a.w.sg[int64_t(k) * a.w.vn + vi];
             any = any || gs[k] != 0.f;
         }
         if (!any) continue;
         const ws_camera& cam = a.cams[v];
         ProjState st;
-        if (!compute_projection<DEG>(a.g, i, cam, a.o, st)) continue;
-        // ---- colour
-        float Y[16];
-        sh_eval_basis(st.dir[0], st.dir[1], st.dir[2], DEG, Y);
-        float wsh[16];
-#pragma unroll
-        for (int k = 0; k < 16; ++k) wsh[k] = 0.f;
-#pragma unroll
-        for (int ch = 0; ch < 3; ++ch) {
-            const float gc = (st.clamp & (1u << ch)) ? 0.f : gs[6 + ch];
-#pragma unroll
-            for (int k = 0; k < K; ++k) {
-                gsh[k * 3 + ch] = fmaf(gc, Y[k], gsh[k * 3 + ch]);
-                wsh[k] = fmaf(gc, a.g.sh[(int64_t(k) * 3 + ch) * n + i], wsh[k]);
-            }
-        }
-        float gdx, gdy, gdz;
-        sh_basis_vjp(st.dir[0], st.dir[1], st.dir[2], DEG, wsh, &gdx, &gdy, &gdz);
-        {
-            const float dd = gdx * st.dir[0] + gdy * st.dir[1] + gdz * st.dir[2];
-            const float idn = 1.f / st.dir_norm;
-            gm[0] += (gdx - st.dir[0] * dd) * idn;
-            gm[1] += (gdy - st.dir[1] * dd) * idn;
-            gm[2] += (gdz - st.dir[2] * dd) * idn;
-        }
+        if (!compute_projection<DEG, false>(a.g, i, cam, a.o, st)) continue;
         // ---- opacity
         glogit += gs[5] * st.sigma * (1.f - st.sigma);
         // ---- conic (A, B, C) = (c, -b, a) / det  ->  Sigma' entries (a, b, c)
@@ -418,6 +395,70 @@ __global__ __launch_bounds__(128) void k_preprocess_bwd(PreBwdArgs a) {
 #pragma unroll
     for (int c = 0; c < 4; ++c) a.out.quats[c * n + i] = gq[c];
     a.out.logits[i] = glogit;
+}
+
+
+// Colour part of the pre-processing adjoint: per Gaussian, over the views in
+// which its colour received a gradient, the SH coefficient gradients (clamped
+// channels give zero) and the gradient of the view direction, which it adds to
+// the mean gradient written by k_preprocess_bwd_geo.  A nonzero colour
+// gradient means the splat was rendered in that view, so its culling tests
+// need not be repeated.  Split from the geometry part so that neither keeps
+// the other's registers live across the view loop.
+template <int DEG>
+__global__ __launch_bounds__(128) void k_preprocess_bwd_sh(PreBwdArgs a) {
+    const int64_t i = int64_t(blockIdx.x) * 128 + threadIdx.x;
+    const int64_t n = a.g.n;
+    if (i >= n) return;
+    constexpr int K = (DEG + 1) * (DEG + 1);
+    float gm[3] = {0.f, 0.f, 0.f};
+    float gsh[3 * K];
+#pragma unroll
+    for (int k = 0; k < 3 * K; ++k) gsh[k] = 0.f;
+    const float mx = a.g.means[i], my = a.g.means[n + i], mz = a.g.means[2 * n + i];
+    for (int32_t v = 0; v < a.n_views; ++v) {
+        const int64_t vi = int64_t(v) * n + i;
+        float gcol[3];
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) gcol[ch] = a.w.sg[int64_t(6 + ch) * a.w.vn + vi];
+        if (gcol[0] == 0.f && gcol[1] == 0.f && gcol[2] == 0.f) continue;
+        const ws_camera& cam = a.cams[v];
+        // the forward's view direction and colour (same arithmetic)
+        float dx = mx - cam.C[0], dy = my - cam.C[1], dz = mz - cam.C[2];
+        const float dir_norm = sqrtf(dx * dx + dy * dy + dz * dz);
+        const float idn = 1.f / dir_norm;
+        dx *= idn;
+        dy *= idn;
+        dz *= idn;
+        float Y[16];
+        sh_eval_basis(dx, dy, dz, DEG, Y);
+        float col[3] = {0.5f, 0.5f, 0.5f};
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) col[ch] = fmaf(a.g.sh[(int64_t(k) * 3 + ch) * n + i], Y[k], col[ch]);
+        }
+        float wsh[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) wsh[k] = 0.f;
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+            const float gc = col[ch] < 0.f ? 0.f : gcol[ch];
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                gsh[k * 3 + ch] = fmaf(gc, Y[k], gsh[k * 3 + ch]);
+                wsh[k] = fmaf(gc, a.g.sh[(int64_t(k) * 3 + ch) * n + i], wsh[k]);
+            }
+        }
+        float gdx, gdy, gdz;
+        sh_basis_vjp(dx, dy, dz, DEG, wsh, &gdx, &gdy, &gdz);
+        const float dd = gdx * dx + gdy * dy + gdz * dz;
+        gm[0] += (gdx - dx * dd) * idn;
+        gm[1] += (gdy - dy * dd) * idn;
+        gm[2] += (gdz - dz * dd) * idn;
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) a.out.means[c * n + i] += gm[c];
 #pragma unroll
     for (int k = 0; k < 3 * K; ++k) a.out.sh[int64_t(k) * n + i] = gsh[k];
 }
@@ -470,11 +511,24 @@ hipError_t launch_render_backward(const GaussPtrs& g, const ws_camera* d_cams, i
     pa.out = grads;
     const dim3 grid(uint32_t((g.n + 127) / 128));
     timing_begin(WS_KERNEL_PREPROCESS_BWD, stream);
+    // geometry first (writes the mean gradient), then colour (adds to it)
     switch (o.sh_degree) {
-        case 0: hipLaunchKernelGGL(k_preprocess_bwd<0>, grid, dim3(128), 0, stream, pa); break;
-        case 1: hipLaunchKernelGGL(k_preprocess_bwd<1>, grid, dim3(128), 0, stream, pa); break;
-        case 2: hipLaunchKernelGGL(k_preprocess_bwd<2>, grid, dim3(128), 0, stream, pa); break;
-        default: hipLaunchKernelGGL(k_preprocess_bwd<3>, grid, dim3(128), 0, stream, pa); break;
+        case 0:
+            hipLaunchKernelGGL(k_preprocess_bwd_geo<0>, grid, dim3(128), 0, stream, pa);
+            hipLaunchKernelGGL(k_preprocess_bwd_sh<0>, grid, dim3(128), 0, stream, pa);
+            break;
+        case 1:
+            hipLaunchKernelGGL(k_preprocess_bwd_geo<1>, grid, dim3(128), 0, stream, pa);
+            hipLaunchKernelGGL(k_preprocess_bwd_sh<1>, grid, dim3(128), 0, stream, pa);
+            break;
+        case 2:
+            hipLaunchKernelGGL(k_preprocess_bwd_geo<2>, grid, dim3(128), 0, stream, pa);
+            hipLaunchKernelGGL(k_preprocess_bwd_sh<2>, grid, dim3(128), 0, stream, pa);
+            break;
+        default:
+            hipLaunchKernelGGL(k_preprocess_bwd_geo<3>, grid, dim3(128), 0, stream, pa);
+            hipLaunchKernelGGL(k_preprocess_bwd_sh<3>, grid, dim3(128), 0, stream, pa);
+            break;
     }
     timing_end(WS_KERNEL_PREPROCESS_BWD, stream);
     return hipGetLastError();

@@ -138,8 +138,10 @@ struct ProjState {
 __device__ __forceinline__ bool finitef(float x) { return __builtin_isfinite(x); }
 
 // Geometry and colour of Gaussian i for camera `cam`, SH degree DEG (equal to
-// o.sh_degree).  Returns st.visible.
-template <int DEG>
+// o.sh_degree).  Returns st.visible.  With COLOUR false the view-dependent
+// colour (and its finiteness test) is skipped: for callers that need the
+// geometry of a splat already known to be visible.
+template <int DEG, bool COLOUR = true>
 __device__ __forceinline__ bool compute_projection(const GaussPtrs& g, int64_t i, const ws_camera& cam,
                                                    const KOpts& o, ProjState& st) {
     const int64_t n = g.n;
@@ -248,6 +250,7 @@ __device__ __forceinline__ bool compute_projection(const GaussPtrs& g, int64_t i
     const uint32_t ty0 = st.rect[2] >> sh, ty1 = st.rect[3] >> sh;
     st.tiles = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
     st.visible = true;
+    if (!COLOUR) return true;
 
     // View-dependent colour
     float dx = mx - cam.C[0], dy = my - cam.C[1], dz = mz - cam.C[2];
