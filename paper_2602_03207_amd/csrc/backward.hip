@@ -168,7 +168,8 @@ __global__ __launch_bounds__(TW * TH) void k_render_bwd(BwdArgs a) {
         dLdC[2] = a.dL[p + 2 * plane];
     }
     float T = ps.T;
-    float R[3] = {a.o.bg[0] * T, a.o.bg[1] * T, a.o.bg[2] * T};
+    // dL/dC . R_k, R_k the suffix colour behind splat k (background included)
+    float SR = (dLdC[0] * a.o.bg[0] + dLdC[1] * a.o.bg[1] + dLdC[2] * a.o.bg[2]) * T;
     const int32_t last = ps.last;
     const float pcx = float(px) + 0.5f, pcy = float(py) + 0.5f;
     const uint32_t pix = inside ? pack_xy(px, py) : kNoPixel;
@@ -198,45 +199,40 @@ __global__ __launch_bounds__(TW * TH) void k_render_bwd(BwdArgs a) {
         for (int t = walk.next(); t >= 0; t = walk.next()) {
             const int32_t j = bstart + t;
             const StagedSplat& s = s_batch[t];
+            // The forward's alpha (same evaluation, same skip decision), then
+            // every lane evaluates the adjoint without branches: a lane that
+            // does not take the splat gets zero weights, so its sums and state
+            // stay unchanged (nested per-lane branches cost more in moves and
+            // mask bookkeeping than the arithmetic they skip).
+            const float dx = s.u - pcx, dy = s.v - pcy;
+            const float araw = raw_alpha(s, dx, dy);
+            const float alpha = __builtin_amdgcn_fmed3f(araw, 0.f, bk.alpha_max);
+            const bool contrib = j <= last && in_rect(s, pix) && !(alpha < bk.alpha_min);
+            if (__ballot(contrib) == 0) continue;
+            const RawConic& q = s_conic[t];
+            // 1 - alpha >= 1 - alpha_max > 0; the hardware reciprocal (about
+            // 1 ulp) keeps the back-to-front recovery of T well inside the
+            // gradient tolerance
+            const float inv = __builtin_amdgcn_rcpf(1.f - alpha);
+            const float Tk = T * inv;
+            const float w = contrib ? alpha * Tk : 0.f;
+            const float Dc = dLdC[0] * s.r + dLdC[1] * s.g + dLdC[2] * s.b;  // dL/dC . c_k
+            // dL/dalpha = dL/dC . (c_k T_k - R_k / (1 - alpha)); zero through the clamp
+            const float dLda = Tk * Dc - inv * SR;
+            const float gp = (contrib && !(araw > bk.alpha_max)) ? dLda * araw : 0.f;  // dL/dpower
             float gv[kNG];
-#pragma unroll
-            for (int k = 0; k < kNG; ++k) gv[k] = 0.f;
-            bool contrib = false;
-            if (j <= last && in_rect(s, pix)) {
-                const float dx = s.u - pcx, dy = s.v - pcy;
-                // the forward's alpha (same evaluation, same skip decision)
-                const float araw = raw_alpha(s, dx, dy);
-                const float alpha = __builtin_amdgcn_fmed3f(araw, 0.f, bk.alpha_max);
-                if (!(alpha < bk.alpha_min)) {
-                    contrib = true;
-                    // 1 - alpha >= 1 - alpha_max > 0; the hardware reciprocal
-                    // (about 1 ulp) keeps the back-to-front recovery of T well
-                    // inside the gradient tolerance
-                    const float inv = __builtin_amdgcn_rcpf(1.f - alpha);
-                    const float Tk = T * inv;
-                    const float w = alpha * Tk;
-                    gv[6] = dLdC[0] * w;
-                    gv[7] = dLdC[1] * w;
-                    gv[8] = dLdC[2] * w;
-                    const float dLda = dLdC[0] * (s.r * Tk - R[0] * inv) + dLdC[1] * (s.g * Tk - R[1] * inv) +
-                                       dLdC[2] * (s.b * Tk - R[2] * inv);
-                    R[0] = fmaf(s.r, w, R[0]);
-                    R[1] = fmaf(s.g, w, R[1]);
-                    R[2] = fmaf(s.b, w, R[2]);
-                    T = Tk;
-                    if (!(araw > bk.alpha_max)) {
-                        const RawConic& q = s_conic[t];
-                        const float gp = dLda * araw;  // dL/dpower
-                        gv[5] = dLda * (araw * q.inv_sigma);  // dL/dsigma = dL/dalpha exp(power)
-                        gv[0] = -gp * (q.A * dx + q.B * dy);
-                        gv[1] = -gp * (q.C * dy + q.B * dx);
-                        gv[2] = -0.5f * gp * dx * dx;
-                        gv[3] = -gp * dx * dy;
-                        gv[4] = -0.5f * gp * dy * dy;
-                    }
-                }
-            }
-            if (__ballot(contrib) != 0) {
+            gv[0] = -gp * (q.A * dx + q.B * dy);
+            gv[1] = -gp * (q.C * dy + q.B * dx);
+            gv[2] = -0.5f * gp * dx * dx;
+            gv[3] = -gp * dx * dy;
+            gv[4] = -0.5f * gp * dy * dy;
+            gv[5] = gp * q.inv_sigma;  // dL/dsigma = dL/dalpha exp(power)
+            gv[6] = dLdC[0] * w;
+            gv[7] = dLdC[1] * w;
+            gv[8] = dLdC[2] * w;
+            SR = fmaf(Dc, w, SR);
+            T = contrib ? Tk : T;
+            {
                 float q0, q1, q2;
                 wave_sum9(gv, &q0, &q1, &q2);
                 // the first lane of each row adds its row's values (distinct addresses)
