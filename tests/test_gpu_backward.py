@@ -68,6 +68,20 @@ def test_backward_multiview_matches_oracle(tile):
     _compare(got, want)
 
 
+@pytest.mark.parametrize("deg", [0, 2])
+def test_backward_sh_degrees_match_oracle(deg):
+    """The geometry and colour adjoint kernels at the SH degrees the other tests leave out, two views
+    (the colour kernel sums the view directions' gradients into the means)."""
+    scene = scenegen.random_scene(2000, 12 + deg, log_scale_mu=-3.0, logit_sd=2.0, sh_degree=deg, dc_sd=0.5,
+                                  rest_sd=0.2)
+    cams = [scenegen.look_at([0.4, 0.3, -3.0], [0, 0, 0], 96, 80), scenegen.look_at([-1.8, 0.2, -2.2], [0, 0, 0], 90, 72)]
+    rng = np.random.default_rng(20 + deg)
+    dLs = [rng.standard_normal((3, c.height, c.width)).astype(np.float32) for c in cams]
+    got, _ = _gpu_grads(scene, cams, dLs)
+    want = _oracle_grads(scene, cams, dLs, oracle_options(sh_degree=deg))
+    _compare(got, want)
+
+
 @pytest.mark.slow
 def test_backward_1080p_l1_view_matches_oracle():
     """One 1920x1080 view of the 1M-Gaussian scene with the L1 loss against a perturbed-scene target."""
