@@ -14,8 +14,10 @@ dominant kernel, batched (one graph replay for 8 views) vs plain (one view per
 launch) forward+backward views/s on 8 1080p views with an L1 loss, batched vs
 plain forward views/s on 64 views of uneven resolution (tile size and radix
 width from the autotuner, persistent ordered render), the
-preprocess+sort HBM fraction of the 6M-Gaussian 4K frame, and the fp64 CPU
-oracle timed on a bounded sample of the same frame.
+preprocess+sort HBM fraction of the 6M-Gaussian 4K frame, the paper's own sort
+workload (a stable 32-bit sort of the visible splats' depths), the ablations
+-RADIUS and -CULL of Sec. 4.4 on the same frame, and the fp64 CPU oracle timed
+on a bounded sample of the same frame.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -176,15 +178,86 @@ def bench_frames(args):
     sort_ms = time_sort(rg)
     with open(STATS_FILE) as f:
         stats = json.load(f)
-    if stats["pairs"] != m:
-        log(f"note: GPU pair count {m} differs from the oracle's {stats['pairs']} (rectangle bounds at a margin)")
+    if stats["pairs"] != rg.num_pairs:  # the oracle's count is for 16x16 tiles
+        log(f"note: GPU pair count {rg.num_pairs} (16x16 tiles) differs from the oracle's {stats['pairs']} "
+            "(rectangle bounds at a margin)")
     work = c2_work(stats, m)
-    return dict(r=r, m=m, wall=wall, frame_ms=frame_ms, graph_wall=graph_wall, graph_ms=graph_ms,
+    return dict(r=r, g=g, cam=cam, opts=opts, m=m, wall=wall, frame_ms=frame_ms, graph_wall=graph_wall,
+                graph_ms=graph_ms,
                 graph_same=graph_same, tune=tune, w16=w16, ms16=ms16, same16=same16, m16=rg.num_pairs,
                 kernels=kt, sort_ms=sort_ms, frame_sort_ms=frame_sort_ms,
                 passes=math.ceil(rg.end_bit / 8),
                 frame_passes=math.ceil((r.end_bit - r.begin_bit) / (tune.radix_bits or 8)), work=work,
                 stats=stats, end_bit=r.end_bit, end_bit16=rg.end_bit, tile=(tune.tile_w, tune.tile_h))
+
+
+def bench_ablations(res, frames=10):
+    """The ablations of Sec. 4.4 on the tuned 1080p frame: -RADIUS (a 3-sigma extent for every splat
+    instead of the opacity-aware one) and -CULL (no viewport cull, near cull only), each against the
+    default: pairs, per-frame sort and render time, and the pixels that change."""
+    import torch
+    from paper_2602_03207_amd import binding as B
+    from paper_2602_03207_amd.pipeline import Renderer
+    g, cam, opts = res["g"], res["cam"], res["opts"]
+    stream = torch.cuda.current_stream()
+    out, base = {}, None
+    for name, extra in (("default", 0), ("radius_3sigma", B.WS_FLAG_FIXED_3SIGMA),
+                        ("no_viewport_cull", B.WS_FLAG_NO_VIEWPORT_CULL)):
+        o = B.ws_options.from_buffer_copy(opts)
+        o.flags = opts.flags | extra
+        r = Renderer([cam], o)
+        for _ in range(3):
+            r.forward(g, stream)
+        torch.cuda.synchronize()
+        st = [torch.cuda.Event(enable_timing=True) for _ in range(frames)]
+        en = [torch.cuda.Event(enable_timing=True) for _ in range(frames)]
+        for i in range(frames):
+            st[i].record(stream)
+            r.forward(g, stream)
+            en[i].record(stream)
+        torch.cuda.synchronize()
+        kt = kernel_times(lambda: r.forward(g, stream), ["preprocess", "scan_emit", "sort_pass", "render"])
+        img = r.images.clone()
+        e = {"pairs": r.num_pairs, "frame_ms": round(statistics.median(a.elapsed_time(b) for a, b in zip(st, en)), 4),
+             "preprocess_emit_ms": round(kt["preprocess"]["ms_per_frame"] + kt["scan_emit"]["ms_per_frame"], 4),
+             "sort_ms": round(kt["sort_pass"]["ms_per_frame"], 4), "render_ms": round(kt["render"]["ms_per_frame"], 4)}
+        if base is None:
+            base = img
+        else:
+            d = (img - base).abs().view(3, -1).amax(0)
+            e["pixels_changed"] = int((d > 0).sum().item())
+            e["max_abs_diff"] = round(float(d.max().item()), 6)
+        out[name] = e
+        del r
+    return out
+
+
+def bench_depth_sort(res, iters=20):
+    """The paper's own sort workload (Sec. 3.3.2): a stable sort of the visible splats' fp32 depth
+    keys of the 1080p frame (32 bits, 4 x 8-bit passes) through ws_sort, keys already in HBM."""
+    import torch
+    from paper_2602_03207_amd import binding as B
+    r = res["r"]
+    stream = torch.cuda.current_stream()
+    vis = r.tiles_touched != 0
+    keys = r.splats[:, 9].contiguous().view(torch.int32)[vis].to(torch.int64) & 0xffffffff
+    n = int(keys.numel())
+    vals = torch.arange(n, dtype=torch.int32, device=keys.device)
+    ko, vo = torch.empty_like(keys), torch.empty_like(vals)
+    need = B.ws_sort_workspace_size(max(n, 1), 0, 32, 8)
+    ws = torch.empty(need, dtype=torch.uint8, device=keys.device)
+    st = torch.zeros(1, dtype=torch.int32, device=keys.device)
+    B.ws_sort(keys, vals, ko, vo, n, None, st, 0, 32, 8, ws, need, stream)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(iters):
+        B.ws_sort(keys, vals, ko, vo, n, None, st, 0, 32, 8, ws, need, stream)
+    b.record(stream)
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / iters
+    ordered = bool((ko[1:] >= ko[:-1]).all().item()) and bool(torch.equal(keys[vo.long()], ko))
+    return {"keys": n, "bits": 32, "passes": 4, "ms": round(ms, 4), "keys_per_s": round(n / (ms * 1e-3), 1),
+            "sorted": ordered and int(st.item()) == 0}
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "c2_frame_hbm_traffic.md")
@@ -414,6 +487,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-large", action="store_true")
     ap.add_argument("--no-multiview", action="store_true")
+    ap.add_argument("--no-ablations", action="store_true")
     ap.add_argument("--mv-views", type=int, default=64)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also copy a 256 MiB buffer 4 times (a plain copy kernel of known size, used to scale "
@@ -487,6 +561,11 @@ def main():
         "dominant_kernel": dom,
         "roofline": roof,
     }
+    log("leg: depth sort of the visible splats (32-bit keys)")
+    line["depth_sort"] = bench_depth_sort(res)
+    if not args.no_ablations:
+        log("leg: ablations -RADIUS and -CULL (Sec. 4.4)")
+        line["ablations"] = bench_ablations(res)
     if not args.no_batched:
         log("leg: batched vs plain fwd+bwd (8 views, 1920x1080)")
         line["batched_fwd_bwd"] = bench_batched(args)
