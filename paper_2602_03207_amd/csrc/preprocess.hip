@@ -172,6 +172,22 @@ struct EmitArgs {
     uint32_t* values;
 };
 
+// DPP move of v by the given control word; lanes without a source read 0.
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ uint32_t dpp_shift_in_zero(uint32_t v) {
+    return uint32_t(__builtin_amdgcn_update_dpp(0, int(v), CTRL, ROW_MASK, 0xf, false));
+}
+// Inclusive prefix maximum over the 64 lanes of a wave (values >= 0).
+__device__ __forceinline__ uint32_t wave_inclusive_max(uint32_t v) {
+    v = max(v, dpp_shift_in_zero<0x111>(v));        // row_shr 1
+    v = max(v, dpp_shift_in_zero<0x112>(v));        // row_shr 2
+    v = max(v, dpp_shift_in_zero<0x114>(v));        // row_shr 4
+    v = max(v, dpp_shift_in_zero<0x118>(v));        // row_shr 8: prefix maxima within each row
+    v = max(v, dpp_shift_in_zero<0x142, 0xa>(v));   // row_bcast 15 into rows 1 and 3
+    v = max(v, dpp_shift_in_zero<0x143, 0xc>(v));   // row_bcast 31 into rows 2 and 3
+    return v;
+}
+
 __global__ __launch_bounds__(kEmitThreads) void k_emit(EmitArgs a) {
     __shared__ uint32_t s_owner[kEmitPairs];
     __shared__ uint32_t s_start[kEmitSlots];
@@ -195,9 +211,13 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(EmitArgs a) {
     if (p0 >= m) return;
     const int64_t p1 = min(p0 + kEmitPairs, m);
     const int64_t nvis = *a.d_nvis;  // >= 1: there are pairs
-    // first tile id and tiles per row of every view, in LDS (up to one view per
-    // thread; more views fall back to summing the cameras per entry)
-    const bool view_table = a.n_views <= kEmitThreads;
+    int64_t e = a.first_entry[blockIdx.x];
+    // first tile id and tiles per row of every view: one view needs no table;
+    // up to one view per thread they come from a table in LDS; more views fall
+    // back to summing the cameras per entry
+    const bool one_view = a.n_views == 1;
+    const uint32_t tx_one = uint32_t(ceil_div(a.cams[0].width, a.tile_w));
+    const bool view_table = !one_view && a.n_views <= kEmitThreads;
     if (view_table) {
         uint32_t tiles = 0, tx = 0;
         if (int32_t(threadIdx.x) < a.n_views) {
@@ -212,7 +232,6 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(EmitArgs a) {
     // Rounds: entries e, e + 1, ..., e + kEmitSlots - 1 (entry e owns pair lo)
     // cover the pairs [lo, hi), hi = the first pair of entry e + kEmitSlots
     // (or p1).  Entry starts strictly increase: every listed entry has pairs.
-    int64_t e = a.first_entry[blockIdx.x];
     int64_t lo = p0;
     while (lo < p1) {
         for (int q = threadIdx.x; q < kEmitPairs; q += kEmitThreads) s_owner[q] = 0;
@@ -231,7 +250,10 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(EmitArgs a) {
             const float4 r2 = reinterpret_cast<const float4*>(a.splats + idx)[2];
             const uint32_t r01 = __float_as_uint(r2.z), r23 = __float_as_uint(r2.w);
             uint32_t tbase, tilesx;
-            if (view_table) {
+            if (one_view) {
+                tbase = 0;
+                tilesx = tx_one;
+            } else if (view_table) {
                 tbase = s_vtoff[view];
                 tilesx = s_vtx[view];
             } else {
@@ -264,22 +286,17 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(EmitArgs a) {
             run = max(run, s_owner[threadIdx.x * kEmitItems + j]);
             own[j] = run;
         }
-        // exclusive max-scan of the threads' last owners
+        // exclusive max-scan of the threads' last owners: inside the wave by DPP
+        // (prefix maxima within rows of 16 by shifts, then the row broadcasts),
+        // across the waves through LDS
         {
-            uint32_t v = run;
+            const uint32_t v = wave_inclusive_max(run);
             const uint32_t lane = lane_id();
-#pragma unroll
-            for (int d = 1; d < kWave; d <<= 1) {
-                const uint32_t o = __shfl_up(v, d, kWave);
-                if (lane >= uint32_t(d)) v = max(v, o);
-            }
             const int wave = threadIdx.x / kWave;
             if (lane == kWave - 1) s_scan[wave] = v;
             __syncthreads();
-            uint32_t before = 0;
+            uint32_t before = dpp_shift_in_zero<0x138>(v);  // wave_shr 1: the previous lane's prefix, 0 in lane 0
             for (int w = 0; w < wave; ++w) before = max(before, s_scan[w]);
-            const uint32_t prev = __shfl_up(v, 1, kWave);
-            if (lane > 0) before = max(before, prev);
 #pragma unroll
             for (int j = 0; j < kEmitItems; ++j) own[j] = max(own[j], before);
         }
