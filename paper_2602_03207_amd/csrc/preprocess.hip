@@ -172,19 +172,15 @@ struct EmitArgs {
     uint32_t* values;
 };
 
-// DPP move of v by the given control word; lanes without a source read 0.
-template <int CTRL, int ROW_MASK = 0xf>
-__device__ __forceinline__ uint32_t dpp_shift_in_zero(uint32_t v) {
-    return uint32_t(__builtin_amdgcn_update_dpp(0, int(v), CTRL, ROW_MASK, 0xf, false));
-}
-// Inclusive prefix maximum over the 64 lanes of a wave (values >= 0).
+// Inclusive prefix maximum over the 64 lanes of a wave (values >= 0), by the
+// DPP steps of wave_inclusive_scan.
 __device__ __forceinline__ uint32_t wave_inclusive_max(uint32_t v) {
-    v = max(v, dpp_shift_in_zero<0x111>(v));        // row_shr 1
-    v = max(v, dpp_shift_in_zero<0x112>(v));        // row_shr 2
-    v = max(v, dpp_shift_in_zero<0x114>(v));        // row_shr 4
-    v = max(v, dpp_shift_in_zero<0x118>(v));        // row_shr 8: prefix maxima within each row
-    v = max(v, dpp_shift_in_zero<0x142, 0xa>(v));   // row_bcast 15 into rows 1 and 3
-    v = max(v, dpp_shift_in_zero<0x143, 0xc>(v));   // row_bcast 31 into rows 2 and 3
+    v = max(v, dpp_move<0x111>(v));        // row_shr 1
+    v = max(v, dpp_move<0x112>(v));        // row_shr 2
+    v = max(v, dpp_move<0x114>(v));        // row_shr 4
+    v = max(v, dpp_move<0x118>(v));        // row_shr 8: prefix maxima within each row
+    v = max(v, dpp_move<0x142, 0xa>(v));   // row_bcast 15 into rows 1 and 3
+    v = max(v, dpp_move<0x143, 0xc>(v));   // row_bcast 31 into rows 2 and 3
     return v;
 }
 
@@ -295,7 +291,7 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(EmitArgs a) {
             const int wave = threadIdx.x / kWave;
             if (lane == kWave - 1) s_scan[wave] = v;
             __syncthreads();
-            uint32_t before = dpp_shift_in_zero<0x138>(v);  // wave_shr 1: the previous lane's prefix, 0 in lane 0
+            uint32_t before = dpp_move<0x138>(v);  // wave_shr 1: the previous lane's prefix, 0 in lane 0
             for (int w = 0; w < wave; ++w) before = max(before, s_scan[w]);
 #pragma unroll
             for (int j = 0; j < kEmitItems; ++j) own[j] = max(own[j], before);

@@ -132,7 +132,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_down(Loader ld, Writer wr
     for (int j = 0; j < ITEMS; ++j) {
         const T inc = wave_inclusive_scan(v[j]);
         ex[j] = carry + inc - v[j];
-        carry += __shfl(inc, kWave - 1, kWave);
+        carry += last_lane(inc);
     }
     if (lane == 0) s_wave[wave] = carry;
     __syncthreads();
@@ -201,7 +201,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_onepass(Loader ld, Writer
     for (int j = 0; j < ITEMS; ++j) {
         const T inc = wave_inclusive_scan(v[j]);
         ex[j] = carry + inc - v[j];
-        carry += __shfl(inc, kWave - 1, kWave);
+        carry += last_lane(inc);
     }
     if (lane == 0) s_wave[wave] = carry;
     __syncthreads();

@@ -22,16 +22,38 @@ __device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
 
 __device__ __forceinline__ uint32_t lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)); }
 
-// Inclusive prefix sum across the 64 lanes of a wave.
+// DPP move of a 32-bit value by the control word CTRL (row_shr, row_bcast,
+// wave_shr, ...), rows outside ROW_MASK and lanes without a source read 0.
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ uint32_t dpp_move(uint32_t v) {
+    return uint32_t(__builtin_amdgcn_update_dpp(0, int(v), CTRL, ROW_MASK, 0xf, false));
+}
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ uint64_t dpp_move(uint64_t v) {
+    return uint64_t(dpp_move<CTRL, ROW_MASK>(uint32_t(v))) | (uint64_t(dpp_move<CTRL, ROW_MASK>(uint32_t(v >> 32))) << 32);
+}
+
+// Inclusive prefix sum across the 64 lanes of a wave (unsigned 32- or 64-bit):
+// shifts by 1, 2, 4 and 8 within each row of 16 lanes, then the broadcast of
+// lane 15 into rows 1 and 3 and of lane 31 into rows 2 and 3 -- DPP operands
+// of ordinary adds, no LDS round trips.
 template <class T>
 __device__ __forceinline__ T wave_inclusive_scan(T v) {
-    const uint32_t lane = lane_id();
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        T o = __shfl_up(v, d, kWave);
-        if (lane >= uint32_t(d)) v += o;
-    }
+    v += dpp_move<0x111>(v);  // row_shr 1
+    v += dpp_move<0x112>(v);  // row_shr 2
+    v += dpp_move<0x114>(v);  // row_shr 4
+    v += dpp_move<0x118>(v);  // row_shr 8
+    v += dpp_move<0x142, 0xa>(v);  // row_bcast 15
+    v += dpp_move<0x143, 0xc>(v);  // row_bcast 31
     return v;
+}
+
+// The value of lane 63 (uniform).
+__device__ __forceinline__ uint32_t last_lane(uint32_t v) {
+    return uint32_t(__builtin_amdgcn_readlane(int(v), kWave - 1));
+}
+__device__ __forceinline__ uint64_t last_lane(uint64_t v) {
+    return uint64_t(last_lane(uint32_t(v))) | (uint64_t(last_lane(uint32_t(v >> 32))) << 32);
 }
 
 template <class T>
