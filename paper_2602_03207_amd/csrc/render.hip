@@ -104,9 +104,9 @@ __global__ __launch_bounds__(kRangeThreads) void k_ranges(const uint64_t* __rest
             uint64_t gaps = __ballot(ghi > glo);
             while (gaps) {
                 const int l = __builtin_ctzll(gaps);
-                const uint32_t lo = uint32_t(__shfl(int(glo), l, kWave));
-                const uint32_t hi = uint32_t(__shfl(int(ghi), l, kWave));
-                const uint32_t pos = uint32_t(__shfl(int(uint32_t(i + 1)), l, kWave));
+                const uint32_t lo = uint32_t(__builtin_amdgcn_readlane(int(glo), l));
+                const uint32_t hi = uint32_t(__builtin_amdgcn_readlane(int(ghi), l));
+                const uint32_t pos = uint32_t(__builtin_amdgcn_readlane(int(uint32_t(i + 1)), l));
                 fill_empty(ranges, lo, hi, pos, lane, kWave);
                 gaps &= gaps - 1;
             }

@@ -33,7 +33,30 @@ __device__ __forceinline__ uint64_t dpp_move(uint64_t v) {
     return uint64_t(dpp_move<CTRL, ROW_MASK>(uint32_t(v))) | (uint64_t(dpp_move<CTRL, ROW_MASK>(uint32_t(v >> 32))) << 32);
 }
 
-// Inclusive prefix sum across the 64 lanes of a wave (unsigned 32- or 64-bit):
+// The value of lane 63 (uniform).
+__device__ __forceinline__ uint32_t last_lane(uint32_t v) {
+    return uint32_t(__builtin_amdgcn_readlane(int(v), kWave - 1));
+}
+__device__ __forceinline__ uint64_t last_lane(uint64_t v) {
+    return uint64_t(last_lane(uint32_t(v))) | (uint64_t(last_lane(uint32_t(v >> 32))) << 32);
+}
+
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ float dpp_move(float v) {
+    return __builtin_bit_cast(float, dpp_move<CTRL, ROW_MASK>(__builtin_bit_cast(uint32_t, v)));
+}
+__device__ __forceinline__ float last_lane(float v) {
+    return __builtin_bit_cast(float, last_lane(__builtin_bit_cast(uint32_t, v)));
+}
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ double dpp_move(double v) {
+    return __builtin_bit_cast(double, dpp_move<CTRL, ROW_MASK>(__builtin_bit_cast(uint64_t, v)));
+}
+__device__ __forceinline__ double last_lane(double v) {
+    return __builtin_bit_cast(double, last_lane(__builtin_bit_cast(uint64_t, v)));
+}
+
+// Inclusive prefix sum across the 64 lanes of a wave (32- or 64-bit):
 // shifts by 1, 2, 4 and 8 within each row of 16 lanes, then the broadcast of
 // lane 15 into rows 1 and 3 and of lane 31 into rows 2 and 3 -- DPP operands
 // of ordinary adds, no LDS round trips.
@@ -48,19 +71,12 @@ __device__ __forceinline__ T wave_inclusive_scan(T v) {
     return v;
 }
 
-// The value of lane 63 (uniform).
-__device__ __forceinline__ uint32_t last_lane(uint32_t v) {
-    return uint32_t(__builtin_amdgcn_readlane(int(v), kWave - 1));
-}
-__device__ __forceinline__ uint64_t last_lane(uint64_t v) {
-    return uint64_t(last_lane(uint32_t(v))) | (uint64_t(last_lane(uint32_t(v >> 32))) << 32);
-}
 
+// Sum over the 64 lanes of a wave, as a uniform value (the last lane of the
+// DPP prefix sum).
 template <class T>
 __device__ __forceinline__ T wave_sum(T v) {
-#pragma unroll
-    for (int d = kWave / 2; d >= 1; d >>= 1) v += __shfl_xor(v, d, kWave);
-    return v;
+    return last_lane(wave_inclusive_scan(v));
 }
 
 // Workgroups of a 1-D grid are dealt to the 8 XCDs round-robin by blockIdx.
