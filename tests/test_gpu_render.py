@@ -221,6 +221,56 @@ def test_render_end_to_end_c2(depth_first):
     print(f"C2: worst {worst:.2e}, flagged {frac:.2e}, M gpu {r.num_pairs} oracle {ref['keys'].size}")
 
 
+@pytest.mark.slow
+def test_render_c2_in_the_benchmark_configuration():
+    """The headline frame exactly as bench.py times it (32x16 tiles, 6-bit digits, depth-first emission,
+    one graph replay of the device-sized forward) against the oracle's image of the same view."""
+    import torch
+    from paper_2602_03207_amd import binding as B
+    from paper_2602_03207_amd.batched import BatchedForward
+    from paper_2602_03207_amd.pipeline import GaussianTensors
+    scene, cam = scenegen.c2()
+    opts = gpu_options(sh_degree=3, tile_w=32, tile_h=16, radix_bits=6, flags=B.WS_FLAG_DEPTH_FIRST)
+    bf = BatchedForward([cam], opts, GaussianTensors.from_scene(scene))
+    bf.capture()
+    for _ in range(3):
+        bf.replay()
+    bf.check()
+    torch.cuda.synchronize()
+    img = bf.r.image(0).cpu().numpy()
+    bf.close()
+    ref = oracle.render(scene, cam, oracle_options(sh_degree=3, tile_w=32, tile_h=16))
+    worst, frac = assert_image_parity(img, ref)
+    print(f"C2 (bench configuration): worst {worst:.2e}, flagged {frac:.2e}")
+
+
+@pytest.mark.slow
+def test_render_c3_sampled_pixels():
+    """The 6M-Gaussian 4K frame (the large-scene workload): pair count against the oracle's and 4000
+    sampled pixels against the oracle compositing just those pixels."""
+    import torch
+    from paper_2602_03207_amd import binding as B
+    from paper_2602_03207_amd.pipeline import GaussianTensors, Renderer
+    scene, cam = scenegen.c3()
+    r = Renderer([cam], gpu_options(sh_degree=3, flags=B.WS_FLAG_DEPTH_FIRST))
+    r.forward(GaussianTensors.from_scene(scene))
+    torch.cuda.synchronize()
+    assert r.status() == 0
+    img = r.image(0).cpu().numpy()
+    ro = oracle_options(sh_degree=3)
+    m_ref = oracle.pair_count(scene, cam, ro)
+    assert abs(r.num_pairs - m_ref) <= 1e-4 * m_ref, (r.num_pairs, m_ref)  # rectangle bounds at a margin
+    rng = np.random.default_rng(31)
+    mask = np.zeros((cam.height, cam.width), np.uint8)
+    mask.reshape(-1)[rng.choice(cam.height * cam.width, 4000, replace=False)] = 1
+    ref = oracle.render(scene, cam, ro, mask=mask)
+    sel = mask.astype(bool)
+    sub = {k: (v[:, sel] if v.ndim == 3 else v[sel]) for k, v in ref.items()
+           if k in ("rgb", "alpha_margin", "t_margin")}
+    worst, frac = assert_image_parity(img[:, sel], sub)
+    print(f"C3 sampled: worst {worst:.2e}, flagged {frac:.2e}, M gpu {r.num_pairs} oracle {m_ref}")
+
+
 def test_invariance_tile_size_radix_width_and_emission_order():
     from paper_2602_03207_amd import binding as B
     scene, cam = scenegen.c1()
