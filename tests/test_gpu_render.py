@@ -271,6 +271,38 @@ def test_render_c3_sampled_pixels():
     print(f"C3 sampled: worst {worst:.2e}, flagged {frac:.2e}, M gpu {r.num_pairs} oracle {m_ref}")
 
 
+@pytest.mark.slow
+def test_render_c4_all_views_one_launch_sampled_pixels():
+    """The 64-view workload of uneven resolution rendered as one batched call (persistent ordered render,
+    32x16 tiles, 6-bit digits, depth-first emission, as the multi-view benchmark runs it): three views of
+    different sizes, 2000 sampled pixels each, against the oracle compositing just those pixels."""
+    import torch
+    from paper_2602_03207_amd import binding as B
+    from paper_2602_03207_amd.pipeline import GaussianTensors, Renderer
+    scene, cams = scenegen.c4()
+    flags = B.WS_FLAG_DEPTH_FIRST | B.WS_FLAG_ORDERED_RENDER
+    r = Renderer(cams, gpu_options(sh_degree=3, tile_w=32, tile_h=16, radix_bits=6, flags=flags))
+    r.forward(GaussianTensors.from_scene(scene))
+    torch.cuda.synchronize()
+    assert r.status() == 0
+    sizes = {}
+    for v, c in enumerate(cams):
+        sizes.setdefault((c.width, c.height), v)
+    rng = np.random.default_rng(41)
+    ro = oracle_options(sh_degree=3, tile_w=32, tile_h=16)
+    for v in sorted(sizes.values()):
+        cam = cams[v]
+        img = r.image(v).cpu().numpy()
+        mask = np.zeros((cam.height, cam.width), np.uint8)
+        mask.reshape(-1)[rng.choice(cam.height * cam.width, 2000, replace=False)] = 1
+        ref = oracle.render(scene, cam, ro, mask=mask)
+        sel = mask.astype(bool)
+        sub = {k: (val[:, sel] if val.ndim == 3 else val[sel]) for k, val in ref.items()
+               if k in ("rgb", "alpha_margin", "t_margin")}
+        worst, frac = assert_image_parity(img[:, sel], sub)
+        print(f"C4 view {v} ({cam.width}x{cam.height}): worst {worst:.2e}, flagged {frac:.2e}")
+
+
 def test_invariance_tile_size_radix_width_and_emission_order():
     from paper_2602_03207_amd import binding as B
     scene, cam = scenegen.c1()
