@@ -99,6 +99,12 @@ typedef struct ws_options {
     float alpha_max;          /* alpha = min(alpha_max, sigma exp(power)) (0.99) */
     float t_min;              /* stop before the transmittance falls below t_min (1e-4) */
     float bg[3];              /* background colour, weighted by the final transmittance */
+    int32_t bin_x, bin_y;     /* key cells ("bins") of bin_x x bin_y tiles, each 1, 2, 4 or 8 (0 reads as 1).
+                                 With 1 x 1 the pair keys name tiles.  With larger bins ws_preprocess keys
+                                 name bins (ids laid out like tile ids, over bins of bin_x * tile_w by
+                                 bin_y * tile_h pixels), tiles_touched counts bins, ws_sort orders the bin
+                                 bits, and ws_expand_bins turns each bin's list into the lists of its tiles
+                                 for ws_render and ws_render_backward.  Images do not change. */
 } ws_options;
 
 typedef struct ws_gaussians {
@@ -148,6 +154,13 @@ size_t ws_render_backward_workspace_size(int64_t n, int32_t n_views);
 /* Total tile count of the views (the length of the tile_ranges array / 2). */
 int64_t ws_total_tiles(const ws_camera* cams, int32_t n_views, const ws_options* opt);
 
+/* Total key-cell count of the views: bins of bin_x x bin_y tiles (equal to
+ * ws_total_tiles with 1 x 1 bins).  The pair keys' high words lie below it. */
+int64_t ws_total_bins(const ws_camera* cams, int32_t n_views, const ws_options* opt);
+
+/* Bytes of workspace for ws_expand_bins over these host cameras. */
+size_t ws_expand_bins_workspace_size(const ws_camera* cams, int32_t n_views, const ws_options* opt);
+
 /* Total image floats of the views: sum of 3 * width * height. */
 int64_t ws_total_image_floats(const ws_camera* cams, int32_t n_views);
 
@@ -158,10 +171,11 @@ int64_t ws_total_image_floats(const ws_camera* cams, int32_t n_views);
  *   cams        host array of n_views cameras (read during the call, for sizes)
  *   d_cams      device copy of the same n_views cameras (read by the kernels)
  *   splats      out [n_views][n] ws_splat
- *   tiles_touched out [n_views][n] uint32: tiles covered by the splat, 0 if culled
- *   keys, values out [capacity]: pair j = ((global tile id) << 32 | fp32 bits of
- *               depth, Gaussian id), emitted for views in order, Gaussians in id
- *               order and tiles row-major inside each splat's rectangle
+ *   tiles_touched out [n_views][n] uint32: tiles (bins, with bins larger than
+ *               one tile) covered by the splat, 0 if culled
+ *   keys, values out [capacity]: pair j = ((global tile or bin id) << 32 | fp32
+ *               bits of depth, Gaussian id), emitted for views in order, Gaussians
+ *               in id order and tiles row-major inside each splat's rectangle
  *   d_num_pairs out device int64: the number of pairs M (also when M > capacity)
  *   d_status    in/out device int32; set to WS_ERR_CAPACITY when M > capacity
  *               (pairs beyond capacity are not written).  The caller zeroes it
@@ -187,9 +201,34 @@ ws_status ws_sort(const uint64_t* keys_in, const uint32_t* values_in, uint64_t* 
                   int64_t n, const int64_t* d_n, const int32_t* d_status, int32_t begin_bit, int32_t end_bit,
                   int32_t radix_bits, void* ws, size_t ws_bytes, void* stream);
 
+/* Per-tile lists from bin-sorted pairs, for options with bins larger than
+ * one tile (Sec. 3.2: a tile's list holds the splats whose footprint meets the
+ * tile, in depth order).  A bin's pairs are contiguous after the sort and in
+ * key order; every tile of the bin keeps, in that order, the pairs whose pixel
+ * rectangle meets the tile.  The result is the same ids in the same order as
+ * the tile's run of pairs when the keys name tiles.
+ *   splats        [n_views][n] from ws_preprocess (their pixel rectangles decide)
+ *   keys, values  pairs from ws_sort over the bin bits; count = min(*d_num_pairs, capacity)
+ *   tile_values   out [tile_capacity] uint32: every tile's list of Gaussian ids.
+ *                 Each bin reserves its pair count once per tile of the bin,
+ *                 so tile_capacity >= bin_x * bin_y * capacity is required
+ *                 (and tile_capacity < 2^32); slots past a tile's end are
+ *                 left unwritten.
+ *   tile_ranges   out [total_tiles][2] uint32: [start, end) of each tile's list
+ * tile_values / tile_ranges then go to ws_render (keys = NULL) and to
+ * ws_render_backward as its values / tile_ranges. */
+ws_status ws_expand_bins(const ws_splat* splats, int64_t n, const ws_camera* cams, const ws_camera* d_cams,
+                         int32_t n_views, const ws_options* opt, const uint64_t* keys, const uint32_t* values,
+                         int64_t capacity, const int64_t* d_num_pairs, const int32_t* d_status,
+                         uint32_t* tile_values, int64_t tile_capacity, uint32_t* tile_ranges, void* ws,
+                         size_t ws_bytes, void* stream);
+
 /* Tile ranges and front-to-back compositing (Eq. 2, Eq. 4).
  *   splats        [n_views][n] from ws_preprocess
- *   keys, values  tile-sorted pairs from ws_sort; count = min(*d_num_pairs, capacity)
+ *   keys, values  tile-sorted pairs from ws_sort; count = min(*d_num_pairs, capacity).
+ *                 keys = NULL: tile_ranges is an input instead (from
+ *                 ws_expand_bins, with values = its tile_values and capacity
+ *                 = its tile_capacity); required with bins larger than one tile
  *   tile_ranges   out [total_tiles][2] uint32: [start, end) of each tile's pairs
  *   images        out: views packed back to back, each [3][H][W] fp32
  * Per pixel, splats are taken in key order: a splat is skipped if the pixel is
@@ -206,7 +245,8 @@ ws_status ws_render(const ws_splat* splats, int64_t n, const ws_camera* cams, co
  * to back to find every pixel's final transmittance and last contributor,
  * then walks back to front; no per-pixel state is stored by the forward.
  * Discrete decisions (culls, skips, early stop, clamps) take the derivative
- * of the branch taken. */
+ * of the branch taken.  values / tile_ranges are the lists ws_render read
+ * (with bins larger than one tile: ws_expand_bins' tile_values / tile_ranges). */
 ws_status ws_render_backward(const ws_gaussians* g, const ws_camera* cams, const ws_camera* d_cams,
                              int32_t n_views, const ws_options* opt, const ws_splat* splats,
                              const uint32_t* values, const uint32_t* tile_ranges, const float* dL_dimages,

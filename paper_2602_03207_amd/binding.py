@@ -34,7 +34,7 @@ EXPORTED = [
     "ws_render_backward_workspace_size", "ws_total_tiles", "ws_total_image_floats", "ws_preprocess", "ws_sort",
     "ws_render", "ws_render_backward", "ws_l1_loss", "ws_l1_loss_workspace_size", "ws_graph_begin", "ws_graph_end",
     "ws_graph_launch", "ws_graph_destroy", "ws_last_error", "ws_status_string", "ws_version", "ws_timing_start",
-    "ws_timing_stop",
+    "ws_timing_stop", "ws_total_bins", "ws_expand_bins_workspace_size", "ws_expand_bins",
 ]
 
 KERNELS = {"preprocess": 0, "scan_emit": 1, "sort_hist": 2, "sort_pass": 3, "ranges": 4, "render": 5,
@@ -56,7 +56,8 @@ class ws_camera(C.Structure):
 class ws_options(C.Structure):
     _fields_ = [("tile_w", C.c_int32), ("tile_h", C.c_int32), ("sh_degree", C.c_int32), ("radix_bits", C.c_int32),
                 ("flags", C.c_uint32), ("near_z", C.c_float), ("lowpass", C.c_float), ("clamp_fov", C.c_float),
-                ("alpha_min", C.c_float), ("alpha_max", C.c_float), ("t_min", C.c_float), ("bg", C.c_float * 3)]
+                ("alpha_min", C.c_float), ("alpha_max", C.c_float), ("t_min", C.c_float), ("bg", C.c_float * 3),
+                ("bin_x", C.c_int32), ("bin_y", C.c_int32)]
 
 
 class ws_gaussians(C.Structure):
@@ -97,6 +98,12 @@ def load():
     lib.ws_l1_loss_workspace_size.restype = sz
     lib.ws_total_tiles.argtypes = [P(ws_camera), i32, P(ws_options)]
     lib.ws_total_tiles.restype = i64
+    lib.ws_total_bins.argtypes = [P(ws_camera), i32, P(ws_options)]
+    lib.ws_total_bins.restype = i64
+    lib.ws_expand_bins_workspace_size.argtypes = [P(ws_camera), i32, P(ws_options)]
+    lib.ws_expand_bins_workspace_size.restype = sz
+    lib.ws_expand_bins.argtypes = [vp, i64, P(ws_camera), vp, i32, P(ws_options), vp, vp, i64, vp, vp, vp, i64, vp,
+                                   vp, sz, vp]
     lib.ws_total_image_floats.argtypes = [P(ws_camera), i32]
     lib.ws_total_image_floats.restype = i64
     lib.ws_preprocess.argtypes = [P(ws_gaussians), P(ws_camera), vp, i32, P(ws_options), vp, vp, vp, vp, i64, vp,
@@ -117,7 +124,8 @@ def load():
     lib.ws_version.restype = i32
     lib.ws_timing_start.argtypes = [i32]
     lib.ws_timing_stop.argtypes = [P(C.c_double), P(C.c_int64)]
-    for name in ("ws_timing_start", "ws_timing_stop", "ws_preprocess", "ws_sort", "ws_render", "ws_render_backward", "ws_l1_loss", "ws_graph_begin",
+    for name in ("ws_timing_start", "ws_timing_stop", "ws_preprocess", "ws_sort", "ws_expand_bins", "ws_render",
+                 "ws_render_backward", "ws_l1_loss", "ws_graph_begin",
                  "ws_graph_end", "ws_graph_launch", "ws_graph_destroy"):
         getattr(lib, name).restype = i32
     _lib = lib
@@ -176,9 +184,10 @@ def camera_bytes(cam_arr) -> np.ndarray:
 
 
 def make_options(tile_w=16, tile_h=16, sh_degree=0, radix_bits=0, flags=0, near_z=0.2, lowpass=0.3, clamp_fov=1.3,
-                 alpha_min=1.0 / 255.0, alpha_max=0.99, t_min=1e-4, bg=(0.0, 0.0, 0.0)) -> ws_options:
+                 alpha_min=1.0 / 255.0, alpha_max=0.99, t_min=1e-4, bg=(0.0, 0.0, 0.0), bin_x=1, bin_y=1) -> ws_options:
     o = ws_options()
     o.tile_w, o.tile_h, o.sh_degree, o.radix_bits, o.flags = tile_w, tile_h, sh_degree, radix_bits, flags
+    o.bin_x, o.bin_y = bin_x, bin_y
     o.near_z, o.lowpass, o.clamp_fov = near_z, lowpass, clamp_fov
     o.alpha_min, o.alpha_max, o.t_min = alpha_min, alpha_max, t_min
     o.bg[:] = [float(b) for b in bg]
@@ -226,6 +235,14 @@ def ws_total_tiles(cams, n_views, opt):
     return load().ws_total_tiles(cams, n_views, C.byref(opt))
 
 
+def ws_total_bins(cams, n_views, opt):
+    return load().ws_total_bins(cams, n_views, C.byref(opt))
+
+
+def ws_expand_bins_workspace_size(cams, n_views, opt):
+    return load().ws_expand_bins_workspace_size(cams, n_views, C.byref(opt))
+
+
 def ws_total_image_floats(cams, n_views):
     return load().ws_total_image_floats(cams, n_views)
 
@@ -243,6 +260,13 @@ def ws_sort(keys_in, values_in, keys_out, values_out, n, d_n, d_status, begin_bi
             ws_bytes, stream=None):
     _check(load().ws_sort(_ptr(keys_in), _ptr(values_in), _ptr(keys_out), _ptr(values_out), n, _ptr(d_n),
                           _ptr(d_status), begin_bit, end_bit, radix_bits, _ptr(ws), ws_bytes, _stream(stream)))
+
+
+def ws_expand_bins(splats, n, cams, d_cams, n_views, opt, keys, values, capacity, d_num_pairs, d_status, tile_values,
+                   tile_capacity, tile_ranges, ws, ws_bytes, stream=None):
+    _check(load().ws_expand_bins(_ptr(splats), n, cams, _ptr(d_cams), n_views, C.byref(opt), _ptr(keys),
+                                 _ptr(values), capacity, _ptr(d_num_pairs), _ptr(d_status), _ptr(tile_values),
+                                 tile_capacity, _ptr(tile_ranges), _ptr(ws), ws_bytes, _stream(stream)))
 
 
 def ws_render(splats, n, cams, d_cams, n_views, opt, keys, values, capacity, d_num_pairs, d_status, tile_ranges,

@@ -45,6 +45,9 @@ ws_status check_options(const ws_options* o) {
         return fail(WS_ERR_UNSUPPORTED, "sh_degree %d not supported (0..3)", o->sh_degree);
     if (o->radix_bits < 0 || o->radix_bits > 8)
         return fail(WS_ERR_INVALID_ARGUMENT, "radix_bits %d out of range (0..8)", o->radix_bits);
+    for (const int32_t b : {o->bin_x, o->bin_y})
+        if (b != 0 && b != 1 && b != 2 && b != 4 && b != 8)
+            return fail(WS_ERR_INVALID_ARGUMENT, "bin_x / bin_y must be 1, 2, 4 or 8 (0 reads as 1), got %d", b);
     if (o->flags & ~(WS_FLAG_FIXED_3SIGMA | WS_FLAG_NO_VIEWPORT_CULL | WS_FLAG_ORDERED_RENDER | WS_FLAG_DEPTH_FIRST))
         return fail(WS_ERR_INVALID_ARGUMENT, "unknown flag bits 0x%x", o->flags);
     if (!finite_pos(o->near_z)) return fail(WS_ERR_INVALID_ARGUMENT, "near_z must be finite and > 0");
@@ -104,6 +107,14 @@ int64_t total_tiles_of(const ws_camera* cams, int32_t n_views, int32_t tw, int32
     for (int32_t v = 0; v < n_views; ++v) t += int64_t(ws::ceil_div(cams[v].width, tw)) * ws::ceil_div(cams[v].height, th);
     return t;
 }
+
+// Key cells of the views: tiles, or bins of bin_x x bin_y tiles.
+int64_t total_bins_of(const ws_camera* cams, int32_t n_views, const ws_options* o) {
+    const ws::KOpts k = ws::to_kopts(*o);
+    return total_tiles_of(cams, n_views, k.cell_w(), k.cell_h());
+}
+
+bool binned(const ws_options* o) { return o->bin_x > 1 || o->bin_y > 1; }
 
 ws::GaussPtrs gauss_ptrs(const ws_gaussians* g) {
     ws::GaussPtrs p;
@@ -187,7 +198,7 @@ ws_status ws_timing_stop(double* total_ms, int64_t* launches) {
     return WS_OK;
 }
 
-int32_t ws_version(void) { return 10000; }
+int32_t ws_version(void) { return 10100; }
 
 const char* ws_last_error(void) { return g_last_error.c_str(); }
 
@@ -218,6 +229,17 @@ size_t ws_sort_workspace_size(int64_t capacity, int32_t begin_bit, int32_t end_b
 int64_t ws_total_tiles(const ws_camera* cams, int32_t n_views, const ws_options* opt) {
     if (!cams || !opt || n_views < 1 || opt->tile_w < 1 || opt->tile_h < 1) return -1;
     return total_tiles_of(cams, n_views, opt->tile_w, opt->tile_h);
+}
+
+int64_t ws_total_bins(const ws_camera* cams, int32_t n_views, const ws_options* opt) {
+    if (!cams || !opt || n_views < 1 || opt->tile_w < 1 || opt->tile_h < 1 || opt->bin_x < 0 || opt->bin_y < 0)
+        return -1;
+    return total_bins_of(cams, n_views, opt);
+}
+
+size_t ws_expand_bins_workspace_size(const ws_camera* cams, int32_t n_views, const ws_options* opt) {
+    if (ws_total_bins(cams, n_views, opt) < 0) return 0;
+    return ws::expand_workspace(total_bins_of(cams, n_views, opt));
 }
 
 int64_t ws_total_image_floats(const ws_camera* cams, int32_t n_views) {
@@ -257,8 +279,8 @@ ws_status ws_preprocess(const ws_gaussians* g, const ws_camera* cams, const ws_c
     if (capacity < 0) return fail(WS_ERR_INVALID_ARGUMENT, "capacity < 0");
     if (capacity > 0 && (!keys || !values)) return fail(WS_ERR_INVALID_ARGUMENT, "keys / values is NULL");
     if (!d_num_pairs || !d_status) return fail(WS_ERR_INVALID_ARGUMENT, "d_num_pairs / d_status is NULL");
-    if (total_tiles_of(cams, n_views, opt->tile_w, opt->tile_h) > (int64_t(1) << 32))
-        return fail(WS_ERR_UNSUPPORTED, "more than 2^32 tiles");
+    if (total_bins_of(cams, n_views, opt) > (int64_t(1) << 32))
+        return fail(WS_ERR_UNSUPPORTED, "more than 2^32 tiles (bins)");
     if ((s = check_ws(ws, ws_bytes, ws::preprocess_workspace(g->n, n_views, capacity, opt->flags))) != WS_OK) return s;
     if (reinterpret_cast<uintptr_t>(splats) % 16 != 0)
         return fail(WS_ERR_INVALID_ARGUMENT, "splats must be 16-byte aligned");
@@ -296,10 +318,14 @@ ws_status ws_render(const ws_splat* splats, int64_t n, const ws_camera* cams, co
     if ((s = check_cameras(cams, d_cams, n_views)) != WS_OK) return s;
     if ((s = check_options(opt)) != WS_OK) return s;
     if (capacity < 0 || capacity > (int64_t(1) << 32) - 1) return fail(WS_ERR_INVALID_ARGUMENT, "capacity out of range");
-    if (capacity > 0 && (!keys || !values)) return fail(WS_ERR_INVALID_ARGUMENT, "keys / values is NULL");
+    if (capacity > 0 && !values) return fail(WS_ERR_INVALID_ARGUMENT, "values is NULL");
+    if (binned(opt) && keys)
+        return fail(WS_ERR_INVALID_ARGUMENT, "with bins larger than one tile, pass keys = NULL and the lists and "
+                                             "ranges of ws_expand_bins");
     if (n > 0 && !splats) return fail(WS_ERR_INVALID_ARGUMENT, "splats is NULL");
-    if (!d_num_pairs || !d_status || !tile_ranges || !images)
-        return fail(WS_ERR_INVALID_ARGUMENT, "d_num_pairs / d_status / tile_ranges / images is NULL");
+    if (!d_status || !tile_ranges || !images)
+        return fail(WS_ERR_INVALID_ARGUMENT, "d_status / tile_ranges / images is NULL");
+    if (keys && !d_num_pairs) return fail(WS_ERR_INVALID_ARGUMENT, "d_num_pairs is NULL");
     const int64_t tiles = total_tiles_of(cams, n_views, opt->tile_w, opt->tile_h);
     if (tiles > (int64_t(1) << 31)) return fail(WS_ERR_UNSUPPORTED, "more than 2^31 tiles");
     const ws::KOpts ko = ws::to_kopts(*opt);
@@ -307,6 +333,37 @@ ws_status ws_render(const ws_splat* splats, int64_t n, const ws_camera* cams, co
     const hipError_t e = ws::launch_render(splats, n, d_cams, n_views, tiles, ko, keys, values, capacity, d_num_pairs,
                                            d_status, tile_ranges, images, ws, static_cast<hipStream_t>(stream));
     return hip_status(e, "ws_render launch");
+}
+
+ws_status ws_expand_bins(const ws_splat* splats, int64_t n, const ws_camera* cams, const ws_camera* d_cams,
+                         int32_t n_views, const ws_options* opt, const uint64_t* keys, const uint32_t* values,
+                         int64_t capacity, const int64_t* d_num_pairs, const int32_t* d_status,
+                         uint32_t* tile_values, int64_t tile_capacity, uint32_t* tile_ranges, void* ws,
+                         size_t ws_bytes, void* stream) {
+    ws_status s;
+    if (n < 0 || n > kMaxGaussians) return fail(WS_ERR_INVALID_ARGUMENT, "n out of range");
+    if ((s = check_cameras(cams, d_cams, n_views)) != WS_OK) return s;
+    if ((s = check_options(opt)) != WS_OK) return s;
+    if (!binned(opt)) return fail(WS_ERR_INVALID_ARGUMENT, "ws_expand_bins needs bins larger than one tile");
+    if (int64_t(n) * n_views > kMaxGaussians) return fail(WS_ERR_INVALID_ARGUMENT, "n * n_views must be < 2^31");
+    const int64_t per_bin = int64_t(opt->bin_x) * opt->bin_y;
+    if (capacity < 0 || capacity > kMaxSortN) return fail(WS_ERR_INVALID_ARGUMENT, "capacity out of range");
+    if (tile_capacity < per_bin * capacity || tile_capacity > (int64_t(1) << 32) - 1)
+        return fail(WS_ERR_INVALID_ARGUMENT,
+                    "tile_capacity must hold bin_x * bin_y * capacity = %lld entries and be below 2^32",
+                    (long long)(per_bin * capacity));
+    if (capacity > 0 && (!keys || !values || !tile_values))
+        return fail(WS_ERR_INVALID_ARGUMENT, "keys / values / tile_values is NULL");
+    if (n > 0 && !splats) return fail(WS_ERR_INVALID_ARGUMENT, "splats is NULL");
+    if (!d_num_pairs || !d_status || !tile_ranges)
+        return fail(WS_ERR_INVALID_ARGUMENT, "d_num_pairs / d_status / tile_ranges is NULL");
+    const int64_t bins = total_bins_of(cams, n_views, opt);
+    if (bins * per_bin > (int64_t(1) << 31) - 8) return fail(WS_ERR_UNSUPPORTED, "too many tiles");
+    if ((s = check_ws(ws, ws_bytes, ws::expand_workspace(bins))) != WS_OK) return s;
+    const hipError_t e = ws::launch_expand(splats, n, d_cams, n_views, bins, ws::to_kopts(*opt), keys, values,
+                                           capacity, d_num_pairs, d_status, tile_values, tile_ranges, ws,
+                                           static_cast<hipStream_t>(stream));
+    return hip_status(e, "ws_expand_bins launch");
 }
 
 ws_status ws_render_backward(const ws_gaussians* g, const ws_camera* cams, const ws_camera* d_cams,

@@ -166,8 +166,8 @@ struct EmitArgs {
     int32_t* d_status;
     int64_t n;
     int64_t capacity;
-    int32_t tile_w, tile_h;
-    uint32_t tw_shift, th_shift;  // log2 of the tile size
+    int32_t tile_w, tile_h;        // pixel size of a key cell (tile or bin)
+    uint32_t tw_shift, th_shift;  // log2 of the cell size
     uint64_t* keys;
     uint32_t* values;
 };
@@ -261,7 +261,7 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(EmitArgs a) {
             s_start[slot] = start;
             s_gid[slot] = uint32_t(int64_t(idx) - view * a.n);
             s_depth[slot] = __float_as_uint(r2.y);
-            // tile sizes are powers of two (8, 16, 32)
+            // cell sizes are powers of two
             const uint32_t tx0 = (r01 & 0xffffu) >> a.tw_shift, tx1 = (r01 >> 16) >> a.tw_shift;
             s_trx[slot] = tx0 | (tx1 << 16);
             s_try[slot] = ((r23 & 0xffffu) >> a.th_shift) | (((r23 >> 16) >> a.th_shift) << 16);
@@ -395,10 +395,11 @@ hipError_t launch_preprocess(const GaussPtrs& g, const ws_camera* d_cams, int32_
     ea.d_status = d_status;
     ea.n = std::max<int64_t>(g.n, 1);
     ea.capacity = capacity;
-    ea.tile_w = o.tile_w;
-    ea.tile_h = o.tile_h;
-    ea.tw_shift = uint32_t(__builtin_ctz(uint32_t(o.tile_w)));
-    ea.th_shift = uint32_t(__builtin_ctz(uint32_t(o.tile_h)));
+    // keys name cells: tiles, or bins of tiles
+    ea.tile_w = o.cell_w();
+    ea.tile_h = o.cell_h();
+    ea.tw_shift = uint32_t(__builtin_ctz(uint32_t(o.cell_w())));
+    ea.th_shift = uint32_t(__builtin_ctz(uint32_t(o.cell_h())));
     ea.keys = keys;
     ea.values = values;
     hipLaunchKernelGGL(k_emit, dim3(uint32_t(pw.emit_blocks)), dim3(kEmitThreads), 0, stream, ea);

@@ -244,8 +244,8 @@ __device__ __forceinline__ bool compute_projection(const GaussPtrs& g, int64_t i
     }
     if (!(x0 <= x1) || !(y0 <= y1)) return false;
     st.rect[0] = uint16_t(x0); st.rect[1] = uint16_t(x1); st.rect[2] = uint16_t(y0); st.rect[3] = uint16_t(y1);
-    // tile sizes are powers of two (8, 16, 32)
-    const uint32_t sw = uint32_t(__builtin_ctz(uint32_t(o.tile_w))), sh = uint32_t(__builtin_ctz(uint32_t(o.tile_h)));
+    // key cells (tiles or bins of tiles) are powers of two in size
+    const uint32_t sw = uint32_t(__builtin_ctz(uint32_t(o.cell_w()))), sh = uint32_t(__builtin_ctz(uint32_t(o.cell_h())));
     const uint32_t tx0 = st.rect[0] >> sw, tx1 = st.rect[1] >> sw;
     const uint32_t ty0 = st.rect[2] >> sh, ty1 = st.rect[3] >> sh;
     st.tiles = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);

@@ -24,6 +24,11 @@
 //                             longest tiles start first and no workgroup
 //                             waits for another.  The order in which tiles are
 //                             processed does not change any pixel.
+// k_expand                    (bins larger than one tile) one workgroup per
+//                             tile: streams its bin's run of pairs, keeps, in
+//                             order, the ids whose pixel rectangle meets the
+//                             tile, and writes them to a slot of the bin's
+//                             pair count reserved for that tile.
 // The per-(pixel, splat) arithmetic lives in composite.h and is shared with
 // the backward pass, so both take exactly the same skip / stop decisions.
 #include "composite.h"
@@ -111,6 +116,124 @@ __global__ __launch_bounds__(kRangeThreads) void k_ranges(const uint64_t* __rest
                 gaps &= gaps - 1;
             }
         }
+    }
+}
+
+// ---- per-tile lists from bin lists
+//
+// A bin of 2^bxs x 2^bys tiles owns the run [bs, be) of the bin-sorted pairs;
+// its tile k (row-major inside the bin) writes its list at
+// (bs << (bxs + bys)) + k * (be - bs), a slot as long as the bin's run, so the
+// slots of all tiles of all bins are disjoint and no count or prefix sum over
+// tiles is needed first.  A tile keeps the pairs whose pixel rectangle meets
+// it: the same test by which the emission would have listed the splat in that
+// tile (the tile range is the pixel range shifted by log2 of the tile size),
+// so the list equals the tile's run of pairs under tile keys.  Items are taken
+// in list order (item j of thread t is entry c + j * 256 + t) and placed by
+// wave ballots and a per-round count in LDS, so the order is preserved.
+constexpr int kExpandThreads = 256;
+constexpr int kExpandItems = 4;
+constexpr int kExpandWaves = kExpandThreads / kWave;
+
+struct ExpandArgs {
+    const ws_splat* splats;
+    int64_t n;
+    const ws_camera* cams;
+    int32_t n_views;
+    int32_t tile_w, tile_h;
+    uint32_t tws, ths;  // log2 of the tile size
+    uint32_t bxs, bys;  // log2 of the bin size in tiles
+    int64_t blocks;     // bins << (bxs + bys)
+    const uint32_t* values;
+    const uint32_t* bin_ranges;
+    const int32_t* d_status;
+    uint32_t* tile_values;
+    uint32_t* tile_ranges;
+};
+
+__global__ __launch_bounds__(kExpandThreads) void k_expand(ExpandArgs a) {
+    __shared__ uint32_t s_cnt[2][kExpandItems][kExpandWaves];
+    if (*a.d_status != 0) return;
+    // Workgroups are dealt to the 8 XCDs in turn; numbering them XCD-major
+    // puts the tiles of one bin (consecutive logical blocks) on one XCD, so
+    // that its L2 serves the bin's list to all of them.  The grid is a
+    // multiple of 8, so every logical block below 8 * per is produced.
+    const uint32_t per = gridDim.x / 8;
+    const int64_t L = int64_t(blockIdx.x % 8) * per + blockIdx.x / 8;
+    if (L >= a.blocks) return;
+    const uint32_t kl = a.bxs + a.bys;
+    const int64_t bin = L >> kl;
+    const uint32_t k = uint32_t(L) & ((1u << kl) - 1u);
+    int64_t boff = 0, toff = 0;
+    int32_t v = 0, txn = 1, tyn = 1, bxn = 1;
+    for (;; ++v) {
+        txn = ceil_div(a.cams[v].width, a.tile_w);
+        tyn = ceil_div(a.cams[v].height, a.tile_h);
+        bxn = (txn + (1 << a.bxs) - 1) >> a.bxs;
+        const int64_t nb = int64_t(bxn) * ((tyn + (1 << a.bys) - 1) >> a.bys);
+        if (bin < boff + nb || v == a.n_views - 1) break;
+        boff += nb;
+        toff += int64_t(txn) * tyn;
+    }
+    const int64_t lb = bin - boff;
+    const int32_t by = int32_t(lb / bxn), bx = int32_t(lb - int64_t(by) * bxn);
+    const int32_t tx = (bx << a.bxs) + int32_t(k & ((1u << a.bxs) - 1u));
+    const int32_t ty = (by << a.bys) + int32_t(k >> a.bxs);
+    if (tx >= txn || ty >= tyn) return;  // bins on the right / bottom edge hold fewer tiles
+    const int64_t tile = toff + int64_t(ty) * txn + tx;
+    const uint32_t bs = a.bin_ranges[2 * bin], be = a.bin_ranges[2 * bin + 1];
+    const uint32_t base = (bs << kl) + k * (be - bs);
+    const ws_splat* vs = a.splats + int64_t(v) * a.n;
+    const uint32_t lane = lane_id();
+    const int wave = threadIdx.x / kWave;
+    uint32_t count = 0;
+    int buf = 0;
+    for (uint32_t c = bs; c < be; c += kExpandThreads * kExpandItems) {
+        uint32_t id[kExpandItems];
+        bool keep[kExpandItems];
+#pragma unroll
+        for (int j = 0; j < kExpandItems; ++j) {
+            const uint32_t idx = c + uint32_t(j * kExpandThreads) + threadIdx.x;
+            id[j] = idx < be ? a.values[idx] : 0xffffffffu;
+        }
+#pragma unroll
+        for (int j = 0; j < kExpandItems; ++j) {
+            keep[j] = false;
+            if (id[j] < uint64_t(a.n)) {
+                // words 10 and 11 of the record: x0 | x1 << 16, y0 | y1 << 16
+                const uint2 r = reinterpret_cast<const uint2*>(vs + id[j])[5];
+                const int32_t tx0 = int32_t((r.x & 0xffffu) >> a.tws), tx1 = int32_t((r.x >> 16) >> a.tws);
+                const int32_t ty0 = int32_t((r.y & 0xffffu) >> a.ths), ty1 = int32_t((r.y >> 16) >> a.ths);
+                keep[j] = tx0 <= tx && tx <= tx1 && ty0 <= ty && ty <= ty1;
+            }
+        }
+        uint32_t below[kExpandItems];
+#pragma unroll
+        for (int j = 0; j < kExpandItems; ++j) {
+            const uint64_t m = __builtin_amdgcn_ballot_w64(keep[j]);
+            below[j] = lanes_below(m);
+            if (lane == 0) s_cnt[buf][j][wave] = uint32_t(__builtin_popcountll(m));
+        }
+        __syncthreads();
+        uint32_t pos = count;
+#pragma unroll
+        for (int j = 0; j < kExpandItems; ++j) {
+            uint32_t wpre = 0, tot = 0;
+#pragma unroll
+            for (int w = 0; w < kExpandWaves; ++w) {
+                const uint32_t cw = s_cnt[buf][j][w];
+                wpre += w < wave ? cw : 0u;
+                tot += cw;
+            }
+            if (keep[j]) a.tile_values[base + pos + wpre + below[j]] = id[j];
+            pos += tot;
+        }
+        count = pos;
+        buf ^= 1;  // the next round writes the other half: one barrier per round suffices
+    }
+    if (threadIdx.x == 0) {
+        a.tile_ranges[2 * tile] = base;
+        a.tile_ranges[2 * tile + 1] = base + count;
     }
 }
 
@@ -310,6 +433,41 @@ void launch_render_t(const RenderArgs& ra, const OrderWs* ow, hipStream_t stream
 
 }  // namespace
 
+size_t expand_workspace(int64_t total_bins) { return align_up(size_t(std::max<int64_t>(total_bins, 1)) * 8); }
+
+hipError_t launch_expand(const ws_splat* splats, int64_t n, const ws_camera* d_cams, int32_t n_views,
+                         int64_t total_bins, const KOpts& o, const uint64_t* keys, const uint32_t* values,
+                         int64_t capacity, const int64_t* d_num_pairs, const int32_t* d_status,
+                         uint32_t* tile_values, uint32_t* tile_ranges, void* ws, hipStream_t stream) {
+    uint32_t* bin_ranges = static_cast<uint32_t*>(ws);
+    timing_begin(WS_KERNEL_RANGES, stream);
+    const int64_t rchunk = int64_t(kRangeThreads) * kRangeItems;
+    const uint32_t rgrid = uint32_t(std::min<int64_t>(std::max<int64_t>((capacity + rchunk - 1) / rchunk, 1), 4096));
+    hipLaunchKernelGGL(k_ranges, dim3(rgrid), dim3(kRangeThreads), 0, stream, keys, capacity, d_num_pairs, d_status,
+                       bin_ranges, total_bins);
+    ExpandArgs ea;
+    ea.splats = splats;
+    ea.n = std::max<int64_t>(n, 1);
+    ea.cams = d_cams;
+    ea.n_views = n_views;
+    ea.tile_w = o.tile_w;
+    ea.tile_h = o.tile_h;
+    ea.tws = uint32_t(__builtin_ctz(uint32_t(o.tile_w)));
+    ea.ths = uint32_t(__builtin_ctz(uint32_t(o.tile_h)));
+    ea.bxs = uint32_t(__builtin_ctz(uint32_t(o.bin_x)));
+    ea.bys = uint32_t(__builtin_ctz(uint32_t(o.bin_y)));
+    ea.blocks = total_bins << (ea.bxs + ea.bys);
+    ea.values = values;
+    ea.bin_ranges = bin_ranges;
+    ea.d_status = d_status;
+    ea.tile_values = tile_values;
+    ea.tile_ranges = tile_ranges;
+    const uint32_t grid = uint32_t((ea.blocks + 7) / 8 * 8);
+    if (grid > 0) hipLaunchKernelGGL(k_expand, dim3(grid), dim3(kExpandThreads), 0, stream, ea);
+    timing_end(WS_KERNEL_RANGES, stream);
+    return hipGetLastError();
+}
+
 size_t render_workspace(int64_t total_tiles, const KOpts& o) {
     if (o.flags & WS_FLAG_ORDERED_RENDER) return order_ws(nullptr, total_tiles, nullptr);
     return align_up(64);
@@ -319,12 +477,15 @@ hipError_t launch_render(const ws_splat* splats, int64_t n, const ws_camera* d_c
                          int64_t total_tiles, const KOpts& o, const uint64_t* keys, const uint32_t* values,
                          int64_t capacity, const int64_t* d_num_pairs, const int32_t* d_status,
                          uint32_t* tile_ranges, float* images, void* ws, hipStream_t stream) {
-    timing_begin(WS_KERNEL_RANGES, stream);
-    const int64_t rchunk = int64_t(kRangeThreads) * kRangeItems;
-    const uint32_t rgrid = uint32_t(std::min<int64_t>(std::max<int64_t>((capacity + rchunk - 1) / rchunk, 1), 4096));
-    hipLaunchKernelGGL(k_ranges, dim3(rgrid), dim3(kRangeThreads), 0, stream, keys, capacity, d_num_pairs, d_status,
-                       tile_ranges, total_tiles);
-    timing_end(WS_KERNEL_RANGES, stream);
+    if (keys) {  // otherwise the ranges are given (ws_expand_bins)
+        timing_begin(WS_KERNEL_RANGES, stream);
+        const int64_t rchunk = int64_t(kRangeThreads) * kRangeItems;
+        const uint32_t rgrid =
+            uint32_t(std::min<int64_t>(std::max<int64_t>((capacity + rchunk - 1) / rchunk, 1), 4096));
+        hipLaunchKernelGGL(k_ranges, dim3(rgrid), dim3(kRangeThreads), 0, stream, keys, capacity, d_num_pairs,
+                           d_status, tile_ranges, total_tiles);
+        timing_end(WS_KERNEL_RANGES, stream);
+    }
     if (total_tiles == 0) return hipGetLastError();
     RenderArgs ra;
     ra.splats = splats;

@@ -184,11 +184,17 @@ struct KOpts {
     uint32_t flags;
     float near_z, lowpass, clamp_fov, alpha_min, alpha_max, t_min;
     float bg[3];
+    int32_t bin_x, bin_y;  // tiles per key cell (1, 2, 4 or 8)
+    // pixel size of the cells that pair keys name: a tile, or a bin of tiles
+    __host__ __device__ int32_t cell_w() const { return tile_w * bin_x; }
+    __host__ __device__ int32_t cell_h() const { return tile_h * bin_y; }
 };
 
 inline KOpts to_kopts(const ws_options& o) {
     KOpts k;
     k.tile_w = o.tile_w; k.tile_h = o.tile_h; k.sh_degree = o.sh_degree; k.flags = o.flags;
+    k.bin_x = o.bin_x > 1 ? o.bin_x : 1;
+    k.bin_y = o.bin_y > 1 ? o.bin_y : 1;
     k.near_z = o.near_z; k.lowpass = o.lowpass; k.clamp_fov = o.clamp_fov;
     k.alpha_min = o.alpha_min; k.alpha_max = o.alpha_max; k.t_min = o.t_min;
     k.bg[0] = o.bg[0]; k.bg[1] = o.bg[1]; k.bg[2] = o.bg[2];
@@ -244,6 +250,11 @@ hipError_t launch_render(const ws_splat* splats, int64_t n, const ws_camera* d_c
                          int64_t capacity, const int64_t* d_num_pairs, const int32_t* d_status,
                          uint32_t* tile_ranges, float* images, void* ws, hipStream_t stream);
 size_t render_workspace(int64_t total_tiles, const KOpts& o);
+size_t expand_workspace(int64_t total_bins);
+hipError_t launch_expand(const ws_splat* splats, int64_t n, const ws_camera* d_cams, int32_t n_views,
+                         int64_t total_bins, const KOpts& o, const uint64_t* keys, const uint32_t* values,
+                         int64_t capacity, const int64_t* d_num_pairs, const int32_t* d_status,
+                         uint32_t* tile_values, uint32_t* tile_ranges, void* ws, hipStream_t stream);
 
 // backward.hip
 hipError_t launch_render_backward(const GaussPtrs& g, const ws_camera* d_cams, int32_t n_views,

@@ -8,6 +8,11 @@ order; it never computes anything itself.  Two sequences are provided:
 * device-sized (`forward_capacity`): the sort and the render read M from
   device memory and are launched for the preallocated capacity, so the
   whole frame (and a backward) can be captured in a HIP graph.
+
+With bins larger than one tile (options bin_x, bin_y) the pairs name bins:
+the sort orders the bin bits, and `ws_expand_bins` builds every tile's list
+(in `tile_vals`, one slot per tile of the bin's pair count) and the tile
+ranges that the render and the backward read.
 """
 from __future__ import annotations
 
@@ -84,6 +89,8 @@ class Renderer:
         self.ws_sort = Workspace(self.device)
         self.ws_render = Workspace(self.device)
         self.ws_bwd = Workspace(self.device)
+        self.ws_expand = Workspace(self.device)
+        self.tile_vals = None
         self.n = -1
         self.d_num_pairs = torch.zeros(1, dtype=torch.int64, device=self.device)
         self.d_status = torch.zeros(1, dtype=torch.int32, device=self.device)
@@ -96,8 +103,9 @@ class Renderer:
         self.cam_arr = B.camera_array(self.cams)
         self.d_cams = torch.as_tensor(B.camera_bytes(self.cam_arr)).to(self.device)
         self.total_tiles = B.ws_total_tiles(self.cam_arr, self.n_views, self.opts)
+        self.total_bins = B.ws_total_bins(self.cam_arr, self.n_views, self.opts)
         self.image_floats = B.ws_total_image_floats(self.cam_arr, self.n_views)
-        self.end_bit = 32 + tile_bits(self.total_tiles)
+        self.end_bit = 32 + tile_bits(self.total_bins)
         self.tile_ranges = torch.empty(2 * self.total_tiles, dtype=torch.int32, device=self.device)
         self.images = torch.empty(self.image_floats, dtype=torch.float32, device=self.device)
         self.image_offsets = np.concatenate([[0], np.cumsum([3 * c.width * c.height for c in self.cams])])
@@ -119,6 +127,21 @@ class Renderer:
         self.vals_a = torch.empty(cap, dtype=torch.int32, device=self.device)
         self.keys_b = torch.empty(cap, dtype=torch.int64, device=self.device)
         self.vals_b = torch.empty(cap, dtype=torch.int32, device=self.device)
+        if self.binned:
+            self.tile_vals = torch.empty(self.per_bin * cap, dtype=torch.int32, device=self.device)
+
+    @property
+    def per_bin(self) -> int:
+        return max(int(self.opts.bin_x), 1) * max(int(self.opts.bin_y), 1)
+
+    @property
+    def binned(self) -> bool:
+        return self.per_bin > 1
+
+    @property
+    def lists(self) -> torch.Tensor:
+        """The per-tile lists that the render and the backward read."""
+        return self.tile_vals if self.binned else self.vals_b
 
     def image(self, v):
         c = self.cams[v]
@@ -149,9 +172,23 @@ class Renderer:
         """Pairs emitted in depth order only need their tile bits sorted (stable)."""
         return 32 if (self.opts.flags & B.WS_FLAG_DEPTH_FIRST) else 0
 
+    def expand(self, cap, stream=None):
+        """Tile lists and ranges from the bin-sorted pairs (bins larger than one tile)."""
+        need = B.ws_expand_bins_workspace_size(self.cam_arr, self.n_views, self.opts)
+        ws = self.ws_expand.get(need)
+        B.ws_expand_bins(self.splats, self.n, self.cam_arr, self.d_cams, self.n_views, self.opts, self.keys_b,
+                         self.vals_b, cap, self.d_num_pairs, self.d_status, self.tile_vals, self.per_bin * cap,
+                         self.tile_ranges, ws, ws.numel(), stream)
+
     def render(self, cap, stream=None):
         need = B.ws_render_workspace_size(self.cam_arr, self.n_views, self.opts)
         ws = self.ws_render.get(need)
+        if self.binned:
+            self.expand(cap, stream)
+            B.ws_render(self.splats, self.n, self.cam_arr, self.d_cams, self.n_views, self.opts, None, self.tile_vals,
+                        self.per_bin * cap, self.d_num_pairs, self.d_status, self.tile_ranges, self.images, ws,
+                        ws.numel(), stream)
+            return
         B.ws_render(self.splats, self.n, self.cam_arr, self.d_cams, self.n_views, self.opts, self.keys_b, self.vals_b,
                     cap, self.d_num_pairs, self.d_status, self.tile_ranges, self.images, ws, ws.numel(), stream)
 
@@ -191,7 +228,7 @@ class Renderer:
         need = B.ws_render_backward_workspace_size(g.n, self.n_views)
         ws = self.ws_bwd.get(need)
         gs = B.make_grads(grads["means"], grads["log_scales"], grads["quats"], grads["opacity_logits"], grads["sh"])
-        B.ws_render_backward(g.struct(), self.cam_arr, self.d_cams, self.n_views, self.opts, self.splats, self.vals_b,
+        B.ws_render_backward(g.struct(), self.cam_arr, self.d_cams, self.n_views, self.opts, self.splats, self.lists,
                              self.tile_ranges, dL_dimages, self.d_status, gs, ws, ws.numel(), stream)
         return grads
 

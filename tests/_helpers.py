@@ -13,10 +13,10 @@ def oracle_options(tile_w=16, tile_h=16, sh_degree=0, flags=0, bg=(0.0, 0.0, 0.0
                           t_min=F32(1e-4), bg=tuple(F32(b) for b in bg))
 
 
-def gpu_options(tile_w=16, tile_h=16, sh_degree=0, flags=0, radix_bits=0, bg=(0.0, 0.0, 0.0)):
+def gpu_options(tile_w=16, tile_h=16, sh_degree=0, flags=0, radix_bits=0, bg=(0.0, 0.0, 0.0), bin_x=1, bin_y=1):
     from paper_2602_03207_amd import binding as B
     return B.make_options(tile_w=tile_w, tile_h=tile_h, sh_degree=sh_degree, flags=flags, radix_bits=radix_bits,
-                          bg=bg)
+                          bg=bg, bin_x=bin_x, bin_y=bin_y)
 
 
 def unpack_splats(splats_f32: np.ndarray):

@@ -50,7 +50,8 @@ def test_library_exports_every_declared_function(lib):
 def test_struct_layouts_match_the_header():
     assert C.sizeof(B.ws_camera) == 88 == B.CAMERA_BYTES
     assert B.ws_camera.R.offset == 24 and B.ws_camera.C.offset == 72
-    assert C.sizeof(B.ws_options) == 56
+    assert C.sizeof(B.ws_options) == 64
+    assert B.ws_options.bin_x.offset == 56 and B.ws_options.bin_y.offset == 60
     assert C.sizeof(B.ws_gaussians) == 48
     assert B.SPLAT_BYTES == 48
 
@@ -163,6 +164,58 @@ def test_preprocess_and_render_reject_bad_options_on_the_host(lib):
     st = lib.ws_render(vp(0x2000), 0, cams, None, 1, C.byref(o), vp(0x4000), vp(0x5000), 16, vp(0x6000),
                        vp(0x7000), vp(0x9000), vp(0xa000), vp(0xb000), 1 << 20, None)
     assert st == B.WS_ERR_INVALID_ARGUMENT
+
+
+def test_bin_counts_and_workspace(lib):
+    cams = (B.ws_camera * 3)(_cam(1920, 1080), _cam(512, 512), _cam(77, 61))
+    # 1x1 bins are tiles
+    for tw, th in ((16, 16), (32, 16), (8, 8)):
+        o = _opts(tile_w=tw, tile_h=th)
+        assert lib.ws_total_bins(cams, 3, C.byref(o)) == lib.ws_total_tiles(cams, 3, C.byref(o))
+        o.bin_x = o.bin_y = 0  # 0 reads as 1
+        assert lib.ws_total_bins(cams, 3, C.byref(o)) == lib.ws_total_tiles(cams, 3, C.byref(o))
+    # bins of 4x4 tiles of 32x16 pixels: 128x64-pixel cells, partial cells at the right / bottom edges
+    o = _opts(tile_w=32, tile_h=16, bin_x=4, bin_y=4)
+    want = sum(-(-w // 128) * -(-h // 64) for w, h in ((1920, 1080), (512, 512), (77, 61)))
+    assert lib.ws_total_bins(cams, 3, C.byref(o)) == want == 15 * 17 + 4 * 8 + 1
+    assert lib.ws_total_tiles(cams, 3, C.byref(o)) == 60 * 68 + 16 * 32 + 3 * 4
+    o = _opts(tile_w=16, tile_h=8, bin_x=2, bin_y=8)
+    assert lib.ws_total_bins(cams, 1, C.byref(o)) == 60 * 17
+    assert lib.ws_expand_bins_workspace_size(cams, 3, C.byref(o)) >= 8 * lib.ws_total_bins(cams, 3, C.byref(o))
+
+
+def test_bins_are_checked_on_the_host(lib):
+    g = B.ws_gaussians()
+    g.n = 0
+    cams = (B.ws_camera * 1)(_cam(64, 48))
+    vp = C.c_void_p
+    for bx, by in ((3, 1), (1, 16), (-1, 1)):
+        o = _opts(bin_x=bx, bin_y=by)
+        st = lib.ws_preprocess(C.byref(g), cams, vp(0x1000), 1, C.byref(o), vp(0x2000), vp(0x3000), vp(0x4000),
+                               vp(0x5000), 16, vp(0x6000), vp(0x7000), vp(0x8000), 1 << 20, None)
+        assert st == B.WS_ERR_INVALID_ARGUMENT and "bin" in _err(lib), (bx, by)
+    ws = vp(0x100000)
+    # expansion needs bins larger than one tile
+    o = _opts()
+    st = lib.ws_expand_bins(vp(0x2000), 10, cams, vp(0x1000), 1, C.byref(o), vp(0x4000), vp(0x5000), 16,
+                            vp(0x6000), vp(0x7000), vp(0x8000), 64, vp(0x9000), ws, 1 << 20, None)
+    assert st == B.WS_ERR_INVALID_ARGUMENT and "bins" in _err(lib)
+    # the tile lists need bin_x * bin_y slots per pair
+    o = _opts(bin_x=2, bin_y=2)
+    st = lib.ws_expand_bins(vp(0x2000), 10, cams, vp(0x1000), 1, C.byref(o), vp(0x4000), vp(0x5000), 16,
+                            vp(0x6000), vp(0x7000), vp(0x8000), 63, vp(0x9000), ws, 1 << 20, None)
+    assert st == B.WS_ERR_INVALID_ARGUMENT and "tile_capacity" in _err(lib)
+    st = lib.ws_expand_bins(vp(0x2000), 10, cams, vp(0x1000), 1, C.byref(o), vp(0x4000), vp(0x5000), 1 << 30,
+                            vp(0x6000), vp(0x7000), vp(0x8000), 1 << 32, vp(0x9000), ws, 1 << 20, None)
+    assert st == B.WS_ERR_INVALID_ARGUMENT
+    # workspace too small
+    st = lib.ws_expand_bins(vp(0x2000), 10, cams, vp(0x1000), 1, C.byref(o), vp(0x4000), vp(0x5000), 16,
+                            vp(0x6000), vp(0x7000), vp(0x8000), 64, vp(0x9000), ws, 0, None)
+    assert st == B.WS_ERR_WORKSPACE_TOO_SMALL
+    # with bins the render takes the expanded lists, never the bin keys
+    st = lib.ws_render(vp(0x2000), 10, cams, vp(0x1000), 1, C.byref(o), vp(0x4000), vp(0x5000), 16, vp(0x6000),
+                       vp(0x7000), vp(0x9000), vp(0xa000), vp(0xb000), 1 << 20, None)
+    assert st == B.WS_ERR_INVALID_ARGUMENT and "ws_expand_bins" in _err(lib)
 
 
 def test_product_path_fails_loudly_without_the_library(monkeypatch, tmp_path):
