@@ -58,26 +58,29 @@ def kernel_times(run_frame, kernels, frames=5):
     return out
 
 
-def c2_work(stats, m_pairs):
+def c2_work(stats, m_pairs, keys32=True):
     """Algorithmic bytes (or flops) per launch of each kernel for the 1M-Gaussian 1080p frame.
 
     Pairs are emitted in depth order (the visible splats are compacted and
-    stably sorted by depth first), so the frame's sort covers the tile bits only.
+    stably sorted by depth first), so the frame's sort covers the tile bits only;
+    with 32-bit keys a pair is a 4-byte tile id and a 4-byte Gaussian id.
     """
     n = stats["n"]
     vis, opac, near = stats["status_counts"][0], stats["status_counts"][1], stats["status_counts"][2]
     n_o = n - opac - near          # read scales and rotations
     k_sh = 16
     e, c = stats["evaluations"], stats["contributions"]
-    # compaction: read 4n flags, write 12 per visible entry (+ its 4-byte depth read);
-    # depth sort of the visible entries (u64 key, u32 value): 8 for the histogram + 4 passes x 24;
-    # counts: list 4 + tile count 4 + offset 4; emission: offset 4 + list 4 + record 16 per entry, 12 per pair
-    scan_emit = 4 * n + (16 + 8 + 96 + 12 + 24) * vis + 12 * m_pairs
+    # compaction: read 4n flags, write the list entry (4) and its depth key (4 or 8) per visible entry
+    # (+ its 4-byte depth read); depth sort of the visible entries (key, u32 value): one key read for the
+    # histograms + 4 passes reading and writing key and value; counts: list 4 + tile count 4 + offset 4;
+    # emission: offset 4 + list 4 + record 16 per entry, key + value per pair
+    kb = 4 if keys32 else 8
+    scan_emit = 4 * n + (4 + kb + 4 + kb + 4 * 2 * (kb + 4) + 12 + 24) * vis + (kb + 4) * m_pairs
     return {
         "preprocess": ("hbm", 16 * n + 28 * n_o + 12 * k_sh * vis + 4 * n + 48 * vis),
         "scan_emit": ("hbm", scan_emit),
-        "sort_hist": ("hbm", 8 * m_pairs),
-        "sort_pass": ("hbm", 24 * m_pairs),
+        "sort_hist": ("hbm", kb * m_pairs),
+        "sort_pass": ("hbm", 2 * (kb + 4) * m_pairs),
         # flops (an FMA counts 2) of the compositing rule: every evaluated (pixel, splat) entry takes 17
         # (offset 2, quadratic form 8, exp 1, opacity and clamp 2, skip test 1, transmittance 2, stop
         # test 1); every composited one 7 more (weight 1, three colour FMAs 6)
@@ -97,7 +100,7 @@ def bench_frames(args):
     from paper_2602_03207_amd.batched import BatchedForward
 
     scene, cam = scenegen.c2()
-    base = B.make_options(sh_degree=3, flags=B.WS_FLAG_DEPTH_FIRST)
+    base = B.make_options(sh_degree=3, flags=B.WS_FLAG_DEPTH_FIRST | B.WS_FLAG_KEYS32)
     g = GaussianTensors.from_scene(scene)
     stream = torch.cuda.current_stream()
     # tile size and radix width from the autotuner (neither changes a pixel; the tuner checks it)
@@ -149,11 +152,15 @@ def bench_frames(args):
     graph_wall, graph_ms, gimg = graph_frames(opts)
     graph_same = bool(torch.equal(gimg.view(torch.int32), r.images.view(torch.int32)))
     log(f"frames (graph): {args.steps} in {graph_wall:.3f} s, images equal to the plain path: {graph_same}")
-    # reference: the same graph frame with 16x16 tiles and 8-bit digits
-    ref_opts = B.make_options(sh_degree=3, flags=B.WS_FLAG_DEPTH_FIRST)
+    # references: the same graph frame with 16x16 tiles and 8-bit digits, and with 64-bit (tile | depth) keys
+    ref_opts = B.make_options(sh_degree=3, flags=base.flags)
     w16, ms16, img16 = graph_frames(ref_opts)
     same16 = bool(torch.equal(img16.view(torch.int32), r.images.view(torch.int32)))
-    del gimg, img16
+    o64 = B.ws_options.from_buffer_copy(opts)
+    o64.flags = opts.flags & ~B.WS_FLAG_KEYS32
+    w64, ms64, img64 = graph_frames(o64)
+    same64 = bool(torch.equal(img64.view(torch.int32), r.images.view(torch.int32)))
+    del gimg, img16, img64
     # per-kernel times
     names = ["preprocess", "scan_emit", "sort_hist", "sort_pass", "ranges", "render"]
     kt = kernel_times(lambda: r.forward(g, stream), names)
@@ -181,10 +188,11 @@ def bench_frames(args):
     if stats["pairs"] != rg.num_pairs:  # the oracle's count is for 16x16 tiles
         log(f"note: GPU pair count {rg.num_pairs} (16x16 tiles) differs from the oracle's {stats['pairs']} "
             "(rectangle bounds at a margin)")
-    work = c2_work(stats, m)
+    work = c2_work(stats, m, keys32=bool(opts.flags & B.WS_FLAG_KEYS32))
     return dict(r=r, g=g, cam=cam, opts=opts, m=m, wall=wall, frame_ms=frame_ms, graph_wall=graph_wall,
                 graph_ms=graph_ms,
                 graph_same=graph_same, tune=tune, w16=w16, ms16=ms16, same16=same16, m16=rg.num_pairs,
+                w64=w64, ms64=ms64, same64=same64,
                 kernels=kt, sort_ms=sort_ms, frame_sort_ms=frame_sort_ms,
                 passes=math.ceil(rg.end_bit / 8),
                 frame_passes=math.ceil((r.end_bit - r.begin_bit) / (tune.radix_bits or 8)), work=work,
@@ -234,27 +242,28 @@ def bench_ablations(res, frames=10):
 
 def bench_depth_sort(res, iters=20):
     """The paper's own sort workload (Sec. 3.3.2): a stable sort of the visible splats' fp32 depth
-    keys of the 1080p frame (32 bits, 4 x 8-bit passes) through ws_sort, keys already in HBM."""
+    keys of the 1080p frame (32 bits, 4 x 8-bit passes) through ws_sort32, keys already in HBM."""
     import torch
     from paper_2602_03207_amd import binding as B
     r = res["r"]
     stream = torch.cuda.current_stream()
     vis = r.tiles_touched != 0
-    keys = r.splats[:, 9].contiguous().view(torch.int32)[vis].to(torch.int64) & 0xffffffff
+    keys = r.splats[:, 9].contiguous().view(torch.int32)[vis].contiguous()
     n = int(keys.numel())
     vals = torch.arange(n, dtype=torch.int32, device=keys.device)
     ko, vo = torch.empty_like(keys), torch.empty_like(vals)
-    need = B.ws_sort_workspace_size(max(n, 1), 0, 32, 8)
+    need = B.ws_sort32_workspace_size(max(n, 1), 0, 32, 8)
     ws = torch.empty(need, dtype=torch.uint8, device=keys.device)
     st = torch.zeros(1, dtype=torch.int32, device=keys.device)
-    B.ws_sort(keys, vals, ko, vo, n, None, st, 0, 32, 8, ws, need, stream)
+    B.ws_sort32(keys, vals, ko, vo, n, None, st, 0, 32, 8, ws, need, stream)
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     a.record(stream)
     for _ in range(iters):
-        B.ws_sort(keys, vals, ko, vo, n, None, st, 0, 32, 8, ws, need, stream)
+        B.ws_sort32(keys, vals, ko, vo, n, None, st, 0, 32, 8, ws, need, stream)
     b.record(stream)
     torch.cuda.synchronize()
     ms = a.elapsed_time(b) / iters
+    # positive fp32 depths: the signed view orders like the unsigned bits
     ordered = bool((ko[1:] >= ko[:-1]).all().item()) and bool(torch.equal(keys[vo.long()], ko))
     return {"keys": n, "bits": 32, "passes": 4, "ms": round(ms, 4), "keys_per_s": round(n / (ms * 1e-3), 1),
             "sorted": ordered and int(st.item()) == 0}
@@ -312,7 +321,7 @@ def bench_batched(args):
     from paper_2602_03207_amd.pipeline import GaussianTensors, Renderer
 
     scene, cams, target_scene = scenegen.c5(n_views=args.views)
-    opts = B.make_options(sh_degree=3, flags=B.WS_FLAG_DEPTH_FIRST)
+    opts = B.make_options(sh_degree=3, flags=B.WS_FLAG_DEPTH_FIRST | B.WS_FLAG_KEYS32)
     g = GaussianTensors.from_scene(scene)
     tr = Renderer(cams, opts)
     tr.forward(GaussianTensors.from_scene(target_scene))
@@ -365,7 +374,7 @@ def bench_multiview(args):
     scene, cams = scenegen.c4(n_views=args.mv_views)
     g = GaussianTensors.from_scene(scene)
     del scene
-    base = B.make_options(sh_degree=3, flags=B.WS_FLAG_DEPTH_FIRST | B.WS_FLAG_ORDERED_RENDER)
+    base = B.make_options(sh_degree=3, flags=B.WS_FLAG_DEPTH_FIRST | B.WS_FLAG_KEYS32 | B.WS_FLAG_ORDERED_RENDER)
     tune = autotune(g, cams, base, radix_bits=(6, 7, 8), reps=3, log=log)
     opts = tune.apply(base)
     bf = BatchedForward(cams, opts, g)
@@ -410,7 +419,7 @@ def bench_large(args):
     from paper_2602_03207_amd.pipeline import GaussianTensors, Renderer
 
     scene, cam = scenegen.c3()
-    opts = B.make_options(sh_degree=3, flags=B.WS_FLAG_DEPTH_FIRST)
+    opts = B.make_options(sh_degree=3, flags=B.WS_FLAG_DEPTH_FIRST | B.WS_FLAG_KEYS32)
     g = GaussianTensors.from_scene(scene)
     del scene
     r = Renderer([cam], opts)
@@ -428,9 +437,10 @@ def bench_large(args):
     # culling counts that only the device knows cheaply: opacity test from the logits
     sig = torch.sigmoid(g.opacity_logits.double()).cpu()
     n_o_upper = int((sig >= 1.0 / 255.0).sum())  # opacity survivors (near-culled ones read no scales either)
+    # 32-bit keys: depth keys of the visible entries and tile keys of the pairs are 4 bytes
     pre_bytes = 16 * n + 28 * n_o_upper + 192 * n_v + 4 * n + 48 * n_v
-    emit_bytes = 4 * n + (16 + 8 + 96 + 12 + 24) * n_v + 12 * m
-    sort_bytes = 8 * m + 24 * m * passes
+    emit_bytes = 4 * n + (4 + 4 + 4 + 4 + 4 * 16 + 12 + 24) * n_v + 8 * m
+    sort_bytes = 4 * m + 16 * m * passes
     t_pre = kt["preprocess"]["ms_per_frame"] + kt["scan_emit"]["ms_per_frame"]
     t_sort = kt["sort_hist"]["ms_per_frame"] + kt["sort_pass"]["ms_per_frame"]
     total_bytes = pre_bytes + emit_bytes + sort_bytes
@@ -536,7 +546,7 @@ def main():
                    "sh_degree": 3, "tile": f"{tune.tile_w}x{tune.tile_h}", "radix_bits": tune.radix_bits,
                    "tuned_by": "autotuner (tile size x radix width, images checked bit-identical)",
                    "pairs": res["m"],
-                   "emission": "depth-first (tile bits sorted per frame)",
+                   "emission": "depth-first, 32-bit tile keys (tile bits sorted per frame)",
                    "frame": "one graph replay (preprocess, device-sized sort and render)"},
         "frame_ms_median": round(med, 4),
         "frame_ms_p99": round(p99, 4),
@@ -545,6 +555,9 @@ def main():
         "frames_per_s_16x16": round(args.steps / res["w16"], 2),
         "frame_ms_median_16x16": round(statistics.median(res["ms16"]), 4),
         "images_equal_16x16": res["same16"],
+        "frames_per_s_keys64": round(args.steps / res["w64"], 2),
+        "frame_ms_median_keys64": round(statistics.median(res["ms64"]), 4),
+        "images_equal_keys64": res["same64"],
         "plain_frames_per_s": round(args.steps / res["wall"], 2),
         "plain_frame_ms_median": round(plain_med, 4),
         "sorted_keys_per_s": round(keys_per_s, 1),

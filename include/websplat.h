@@ -8,8 +8,8 @@
  *                       Sec. 2.1 Eq. 1-2), view-dependent SH colour (Eq. 3),
  *                       opacity and bounding-box culling (Sec. 3.2, Sec. 3.4
  *                       Eq. 7-8), then compaction into (tile | depth) keys.
- *   ws_sort             stable LSD radix sort of the 64-bit keys with their
- *                       32-bit values; each pass places an element at
+ *   ws_sort, ws_sort32  stable LSD radix sort of 64-bit (or 32-bit) keys with
+ *                       their 32-bit values; each pass places an element at
  *                       base_d + prefix_wg + rank_local (Sec. 3.3.2, Eq. 5-6).
  *   ws_render           per-tile front-to-back alpha compositing (Eq. 2, Eq. 4).
  *   ws_render_backward  reverse mode of ws_render and ws_preprocess.
@@ -86,6 +86,11 @@ typedef struct ws_camera {
 #define WS_FLAG_DEPTH_FIRST      8u  /* preprocess: emit pairs in (depth, view * n + id) order instead of
                                         (view * n + id) order; a stable sort of the tile bits alone
                                         [32, end_bit) then yields the full (tile, depth) order */
+#define WS_FLAG_KEYS32          16u  /* with WS_FLAG_DEPTH_FIRST only: keys are uint32_t tile (or bin) ids,
+                                        the high words of the 64-bit keys, without the depth word (the
+                                        emission order already is the depth order); ws_sort32 on bits
+                                        [0, end_bit - 32) then gives the same lists; ws_render and
+                                        ws_expand_bins read such keys */
 
 typedef struct ws_options {
     int32_t tile_w, tile_h;   /* 16x16 (default), 8x8, 16x8 or 32x16 pixels */
@@ -145,6 +150,9 @@ size_t ws_preprocess_workspace_size(int64_t n, int32_t n_views, int64_t capacity
  * [begin_bit, end_bit) with digits of radix_bits (0 = default). */
 size_t ws_sort_workspace_size(int64_t capacity, int32_t begin_bit, int32_t end_bit, int32_t radix_bits);
 
+/* The same for ws_sort32 (end_bit <= 32). */
+size_t ws_sort32_workspace_size(int64_t capacity, int32_t begin_bit, int32_t end_bit, int32_t radix_bits);
+
 /* Bytes of workspace for ws_render over these host cameras. */
 size_t ws_render_workspace_size(const ws_camera* cams, int32_t n_views, const ws_options* opt);
 
@@ -175,7 +183,9 @@ int64_t ws_total_image_floats(const ws_camera* cams, int32_t n_views);
  *               one tile) covered by the splat, 0 if culled
  *   keys, values out [capacity]: pair j = ((global tile or bin id) << 32 | fp32
  *               bits of depth, Gaussian id), emitted for views in order, Gaussians
- *               in id order and tiles row-major inside each splat's rectangle
+ *               in id order and tiles row-major inside each splat's rectangle.
+ *               keys is uint64_t[capacity], or uint32_t[capacity] holding the
+ *               tile (bin) id alone with WS_FLAG_KEYS32
  *   d_num_pairs out device int64: the number of pairs M (also when M > capacity)
  *   d_status    in/out device int32; set to WS_ERR_CAPACITY when M > capacity
  *               (pairs beyond capacity are not written).  The caller zeroes it
@@ -183,7 +193,7 @@ int64_t ws_total_image_floats(const ws_camera* cams, int32_t n_views);
  * Culls (no pair): sigma < alpha_min, p.z <= near_z, non-finite parameters or
  * zero quaternion, and a pixel rectangle that contains no pixel centre. */
 ws_status ws_preprocess(const ws_gaussians* g, const ws_camera* cams, const ws_camera* d_cams, int32_t n_views,
-                        const ws_options* opt, ws_splat* splats, uint32_t* tiles_touched, uint64_t* keys,
+                        const ws_options* opt, ws_splat* splats, uint32_t* tiles_touched, void* keys,
                         uint32_t* values, int64_t capacity, int64_t* d_num_pairs, int32_t* d_status, void* ws,
                         size_t ws_bytes, void* stream);
 
@@ -201,6 +211,12 @@ ws_status ws_sort(const uint64_t* keys_in, const uint32_t* values_in, uint64_t* 
                   int64_t n, const int64_t* d_n, const int32_t* d_status, int32_t begin_bit, int32_t end_bit,
                   int32_t radix_bits, void* ws, size_t ws_bytes, void* stream);
 
+/* ws_sort on 32-bit keys (Sec. 3.3.2), e.g. the tile ids of WS_FLAG_KEYS32 or
+ * fp32 depth bits: same contract, 0 <= begin_bit < end_bit <= 32. */
+ws_status ws_sort32(const uint32_t* keys_in, const uint32_t* values_in, uint32_t* keys_out, uint32_t* values_out,
+                    int64_t n, const int64_t* d_n, const int32_t* d_status, int32_t begin_bit, int32_t end_bit,
+                    int32_t radix_bits, void* ws, size_t ws_bytes, void* stream);
+
 /* Per-tile lists from bin-sorted pairs, for options with bins larger than
  * one tile (Sec. 3.2: a tile's list holds the splats whose footprint meets the
  * tile, in depth order).  A bin's pairs are contiguous after the sort and in
@@ -208,7 +224,8 @@ ws_status ws_sort(const uint64_t* keys_in, const uint32_t* values_in, uint64_t* 
  * rectangle meets the tile.  The result is the same ids in the same order as
  * the tile's run of pairs when the keys name tiles.
  *   splats        [n_views][n] from ws_preprocess (their pixel rectangles decide)
- *   keys, values  pairs from ws_sort over the bin bits; count = min(*d_num_pairs, capacity)
+ *   keys, values  pairs from ws_sort over the bin bits (ws_sort32 with
+ *                 WS_FLAG_KEYS32); count = min(*d_num_pairs, capacity)
  *   tile_values   out [tile_capacity] uint32: every tile's list of Gaussian ids.
  *                 Each bin reserves its pair count once per tile of the bin,
  *                 so tile_capacity >= bin_x * bin_y * capacity is required
@@ -218,14 +235,15 @@ ws_status ws_sort(const uint64_t* keys_in, const uint32_t* values_in, uint64_t* 
  * tile_values / tile_ranges then go to ws_render (keys = NULL) and to
  * ws_render_backward as its values / tile_ranges. */
 ws_status ws_expand_bins(const ws_splat* splats, int64_t n, const ws_camera* cams, const ws_camera* d_cams,
-                         int32_t n_views, const ws_options* opt, const uint64_t* keys, const uint32_t* values,
+                         int32_t n_views, const ws_options* opt, const void* keys, const uint32_t* values,
                          int64_t capacity, const int64_t* d_num_pairs, const int32_t* d_status,
                          uint32_t* tile_values, int64_t tile_capacity, uint32_t* tile_ranges, void* ws,
                          size_t ws_bytes, void* stream);
 
 /* Tile ranges and front-to-back compositing (Eq. 2, Eq. 4).
  *   splats        [n_views][n] from ws_preprocess
- *   keys, values  tile-sorted pairs from ws_sort; count = min(*d_num_pairs, capacity).
+ *   keys, values  tile-sorted pairs from ws_sort (uint64_t keys) or ws_sort32
+ *                 (uint32_t keys, WS_FLAG_KEYS32); count = min(*d_num_pairs, capacity).
  *                 keys = NULL: tile_ranges is an input instead (from
  *                 ws_expand_bins, with values = its tile_values and capacity
  *                 = its tile_capacity); required with bins larger than one tile
@@ -235,7 +253,7 @@ ws_status ws_expand_bins(const ws_splat* splats, int64_t n, const ws_camera* cam
  * outside its rectangle or alpha < alpha_min; the pixel stops before a splat
  * that would bring the transmittance below t_min; output = C + T * bg. */
 ws_status ws_render(const ws_splat* splats, int64_t n, const ws_camera* cams, const ws_camera* d_cams,
-                    int32_t n_views, const ws_options* opt, const uint64_t* keys, const uint32_t* values,
+                    int32_t n_views, const ws_options* opt, const void* keys, const uint32_t* values,
                     int64_t capacity, const int64_t* d_num_pairs, const int32_t* d_status, uint32_t* tile_ranges,
                     float* images, void* ws, size_t ws_bytes, void* stream);
 

@@ -28,13 +28,15 @@ WS_FLAG_FIXED_3SIGMA = 1
 WS_FLAG_NO_VIEWPORT_CULL = 2
 WS_FLAG_ORDERED_RENDER = 4
 WS_FLAG_DEPTH_FIRST = 8
+WS_FLAG_KEYS32 = 16
 
 EXPORTED = [
     "ws_preprocess_workspace_size", "ws_sort_workspace_size", "ws_render_workspace_size",
     "ws_render_backward_workspace_size", "ws_total_tiles", "ws_total_image_floats", "ws_preprocess", "ws_sort",
     "ws_render", "ws_render_backward", "ws_l1_loss", "ws_l1_loss_workspace_size", "ws_graph_begin", "ws_graph_end",
     "ws_graph_launch", "ws_graph_destroy", "ws_last_error", "ws_status_string", "ws_version", "ws_timing_start",
-    "ws_timing_stop", "ws_total_bins", "ws_expand_bins_workspace_size", "ws_expand_bins",
+    "ws_timing_stop", "ws_total_bins", "ws_expand_bins_workspace_size", "ws_expand_bins", "ws_sort32",
+    "ws_sort32_workspace_size",
 ]
 
 KERNELS = {"preprocess": 0, "scan_emit": 1, "sort_hist": 2, "sort_pass": 3, "ranges": 4, "render": 5,
@@ -90,6 +92,8 @@ def load():
     lib.ws_preprocess_workspace_size.restype = sz
     lib.ws_sort_workspace_size.argtypes = [i64, i32, i32, i32]
     lib.ws_sort_workspace_size.restype = sz
+    lib.ws_sort32_workspace_size.argtypes = [i64, i32, i32, i32]
+    lib.ws_sort32_workspace_size.restype = sz
     lib.ws_render_workspace_size.argtypes = [P(ws_camera), i32, P(ws_options)]
     lib.ws_render_workspace_size.restype = sz
     lib.ws_render_backward_workspace_size.argtypes = [i64, i32]
@@ -109,6 +113,7 @@ def load():
     lib.ws_preprocess.argtypes = [P(ws_gaussians), P(ws_camera), vp, i32, P(ws_options), vp, vp, vp, vp, i64, vp,
                                   vp, vp, sz, vp]
     lib.ws_sort.argtypes = [vp, vp, vp, vp, i64, vp, vp, i32, i32, i32, vp, sz, vp]
+    lib.ws_sort32.argtypes = [vp, vp, vp, vp, i64, vp, vp, i32, i32, i32, vp, sz, vp]
     lib.ws_render.argtypes = [vp, i64, P(ws_camera), vp, i32, P(ws_options), vp, vp, i64, vp, vp, vp, vp, vp, sz,
                               vp]
     lib.ws_render_backward.argtypes = [P(ws_gaussians), P(ws_camera), vp, i32, P(ws_options), vp, vp, vp, vp, vp,
@@ -124,7 +129,8 @@ def load():
     lib.ws_version.restype = i32
     lib.ws_timing_start.argtypes = [i32]
     lib.ws_timing_stop.argtypes = [P(C.c_double), P(C.c_int64)]
-    for name in ("ws_timing_start", "ws_timing_stop", "ws_preprocess", "ws_sort", "ws_expand_bins", "ws_render",
+    for name in ("ws_timing_start", "ws_timing_stop", "ws_preprocess", "ws_sort", "ws_sort32", "ws_expand_bins",
+                 "ws_render",
                  "ws_render_backward", "ws_l1_loss", "ws_graph_begin",
                  "ws_graph_end", "ws_graph_launch", "ws_graph_destroy"):
         getattr(lib, name).restype = i32
@@ -219,6 +225,10 @@ def ws_sort_workspace_size(capacity, begin_bit, end_bit, radix_bits=0):
     return load().ws_sort_workspace_size(capacity, begin_bit, end_bit, radix_bits)
 
 
+def ws_sort32_workspace_size(capacity, begin_bit, end_bit, radix_bits=0):
+    return load().ws_sort32_workspace_size(capacity, begin_bit, end_bit, radix_bits)
+
+
 def ws_render_workspace_size(cams, n_views, opt):
     return load().ws_render_workspace_size(cams, n_views, C.byref(opt))
 
@@ -260,6 +270,12 @@ def ws_sort(keys_in, values_in, keys_out, values_out, n, d_n, d_status, begin_bi
             ws_bytes, stream=None):
     _check(load().ws_sort(_ptr(keys_in), _ptr(values_in), _ptr(keys_out), _ptr(values_out), n, _ptr(d_n),
                           _ptr(d_status), begin_bit, end_bit, radix_bits, _ptr(ws), ws_bytes, _stream(stream)))
+
+
+def ws_sort32(keys_in, values_in, keys_out, values_out, n, d_n, d_status, begin_bit, end_bit, radix_bits, ws,
+              ws_bytes, stream=None):
+    _check(load().ws_sort32(_ptr(keys_in), _ptr(values_in), _ptr(keys_out), _ptr(values_out), n, _ptr(d_n),
+                            _ptr(d_status), begin_bit, end_bit, radix_bits, _ptr(ws), ws_bytes, _stream(stream)))
 
 
 def ws_expand_bins(splats, n, cams, d_cams, n_views, opt, keys, values, capacity, d_num_pairs, d_status, tile_values,

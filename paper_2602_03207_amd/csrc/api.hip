@@ -48,8 +48,11 @@ ws_status check_options(const ws_options* o) {
     for (const int32_t b : {o->bin_x, o->bin_y})
         if (b != 0 && b != 1 && b != 2 && b != 4 && b != 8)
             return fail(WS_ERR_INVALID_ARGUMENT, "bin_x / bin_y must be 1, 2, 4 or 8 (0 reads as 1), got %d", b);
-    if (o->flags & ~(WS_FLAG_FIXED_3SIGMA | WS_FLAG_NO_VIEWPORT_CULL | WS_FLAG_ORDERED_RENDER | WS_FLAG_DEPTH_FIRST))
+    if (o->flags & ~(WS_FLAG_FIXED_3SIGMA | WS_FLAG_NO_VIEWPORT_CULL | WS_FLAG_ORDERED_RENDER | WS_FLAG_DEPTH_FIRST |
+                     WS_FLAG_KEYS32))
         return fail(WS_ERR_INVALID_ARGUMENT, "unknown flag bits 0x%x", o->flags);
+    if ((o->flags & WS_FLAG_KEYS32) && !(o->flags & WS_FLAG_DEPTH_FIRST))
+        return fail(WS_ERR_INVALID_ARGUMENT, "WS_FLAG_KEYS32 needs WS_FLAG_DEPTH_FIRST (the keys carry no depth)");
     if (!finite_pos(o->near_z)) return fail(WS_ERR_INVALID_ARGUMENT, "near_z must be finite and > 0");
     if (!(std::isfinite(o->lowpass) && o->lowpass >= 0.f))
         return fail(WS_ERR_INVALID_ARGUMENT, "lowpass must be finite and >= 0");
@@ -223,7 +226,13 @@ size_t ws_preprocess_workspace_size(int64_t n, int32_t n_views, int64_t capacity
 size_t ws_sort_workspace_size(int64_t capacity, int32_t begin_bit, int32_t end_bit, int32_t radix_bits) {
     if (capacity < 0 || begin_bit < 0 || end_bit > 64 || begin_bit >= end_bit || radix_bits < 0 || radix_bits > 8)
         return 0;
-    return ws::sort_workspace(capacity, begin_bit, end_bit, radix_bits);
+    return ws::sort_workspace(capacity, begin_bit, end_bit, radix_bits, false, 8);
+}
+
+size_t ws_sort32_workspace_size(int64_t capacity, int32_t begin_bit, int32_t end_bit, int32_t radix_bits) {
+    if (capacity < 0 || begin_bit < 0 || end_bit > 32 || begin_bit >= end_bit || radix_bits < 0 || radix_bits > 8)
+        return 0;
+    return ws::sort_workspace(capacity, begin_bit, end_bit, radix_bits, false, 4);
 }
 
 int64_t ws_total_tiles(const ws_camera* cams, int32_t n_views, const ws_options* opt) {
@@ -265,7 +274,7 @@ size_t ws_l1_loss_workspace_size(int64_t n) {
 }
 
 ws_status ws_preprocess(const ws_gaussians* g, const ws_camera* cams, const ws_camera* d_cams, int32_t n_views,
-                        const ws_options* opt, ws_splat* splats, uint32_t* tiles_touched, uint64_t* keys,
+                        const ws_options* opt, ws_splat* splats, uint32_t* tiles_touched, void* keys,
                         uint32_t* values, int64_t capacity, int64_t* d_num_pairs, int32_t* d_status, void* ws,
                         size_t ws_bytes, void* stream) {
     ws_status s;
@@ -290,27 +299,55 @@ ws_status ws_preprocess(const ws_gaussians* g, const ws_camera* cams, const ws_c
     return hip_status(e, "ws_preprocess launch");
 }
 
+extern "C++" {
+namespace {
+
+template <typename K>
+ws_status sort_checked(const char* name, const K* keys_in, const uint32_t* values_in, K* keys_out,
+                       uint32_t* values_out, int64_t n, const int64_t* d_n, const int32_t* d_status, int32_t begin_bit,
+                       int32_t end_bit, int32_t radix_bits, void* ws, size_t ws_bytes, void* stream) {
+    constexpr int kBits = int(sizeof(K)) * 8;
+    if (n < 0 || n > kMaxSortN)
+        return fail(WS_ERR_INVALID_ARGUMENT, "%s: n = %lld out of range (0..2^30-1)", name, (long long)n);
+    if (begin_bit < 0 || end_bit > kBits || begin_bit >= end_bit)
+        return fail(WS_ERR_INVALID_ARGUMENT, "%s: need 0 <= begin_bit < end_bit <= %d (got %d, %d)", name, kBits,
+                    begin_bit, end_bit);
+    if (radix_bits < 0 || radix_bits > 8)
+        return fail(WS_ERR_INVALID_ARGUMENT, "%s: radix_bits %d out of range", name, radix_bits);
+    if (n == 0) return WS_OK;
+    if (!keys_in || !values_in || !keys_out || !values_out)
+        return fail(WS_ERR_INVALID_ARGUMENT, "%s: a key/value pointer is NULL", name);
+    if (overlaps(keys_in, size_t(n) * sizeof(K), keys_out, size_t(n) * sizeof(K)) ||
+        overlaps(values_in, size_t(n) * 4, values_out, size_t(n) * 4))
+        return fail(WS_ERR_INVALID_ARGUMENT, "%s: output buffers must not overlap the inputs", name);
+    ws_status s;
+    if ((s = check_ws(ws, ws_bytes, ws::sort_workspace(n, begin_bit, end_bit, radix_bits, false, int(sizeof(K))))) !=
+        WS_OK)
+        return s;
+    const hipError_t e = ws::launch_sort(keys_in, values_in, keys_out, values_out, n, d_n, d_status, begin_bit,
+                                         end_bit, radix_bits, ws, static_cast<hipStream_t>(stream));
+    return hip_status(e, name);
+}
+
+}  // namespace
+}  // extern "C++"
+
 ws_status ws_sort(const uint64_t* keys_in, const uint32_t* values_in, uint64_t* keys_out, uint32_t* values_out,
                   int64_t n, const int64_t* d_n, const int32_t* d_status, int32_t begin_bit, int32_t end_bit,
                   int32_t radix_bits, void* ws, size_t ws_bytes, void* stream) {
-    if (n < 0 || n > kMaxSortN) return fail(WS_ERR_INVALID_ARGUMENT, "n = %lld out of range (0..2^30-1)", (long long)n);
-    if (begin_bit < 0 || end_bit > 64 || begin_bit >= end_bit)
-        return fail(WS_ERR_INVALID_ARGUMENT, "need 0 <= begin_bit < end_bit <= 64 (got %d, %d)", begin_bit, end_bit);
-    if (radix_bits < 0 || radix_bits > 8) return fail(WS_ERR_INVALID_ARGUMENT, "radix_bits %d out of range", radix_bits);
-    if (n == 0) return WS_OK;
-    if (!keys_in || !values_in || !keys_out || !values_out) return fail(WS_ERR_INVALID_ARGUMENT, "a key/value pointer is NULL");
-    if (overlaps(keys_in, size_t(n) * 8, keys_out, size_t(n) * 8) ||
-        overlaps(values_in, size_t(n) * 4, values_out, size_t(n) * 4))
-        return fail(WS_ERR_INVALID_ARGUMENT, "output buffers must not overlap the inputs");
-    ws_status s;
-    if ((s = check_ws(ws, ws_bytes, ws::sort_workspace(n, begin_bit, end_bit, radix_bits))) != WS_OK) return s;
-    const hipError_t e = ws::launch_sort(keys_in, values_in, keys_out, values_out, n, d_n, d_status, begin_bit,
-                                         end_bit, radix_bits, ws, static_cast<hipStream_t>(stream));
-    return hip_status(e, "ws_sort launch");
+    return sort_checked("ws_sort", keys_in, values_in, keys_out, values_out, n, d_n, d_status, begin_bit, end_bit,
+                        radix_bits, ws, ws_bytes, stream);
+}
+
+ws_status ws_sort32(const uint32_t* keys_in, const uint32_t* values_in, uint32_t* keys_out, uint32_t* values_out,
+                    int64_t n, const int64_t* d_n, const int32_t* d_status, int32_t begin_bit, int32_t end_bit,
+                    int32_t radix_bits, void* ws, size_t ws_bytes, void* stream) {
+    return sort_checked("ws_sort32", keys_in, values_in, keys_out, values_out, n, d_n, d_status, begin_bit, end_bit,
+                        radix_bits, ws, ws_bytes, stream);
 }
 
 ws_status ws_render(const ws_splat* splats, int64_t n, const ws_camera* cams, const ws_camera* d_cams,
-                    int32_t n_views, const ws_options* opt, const uint64_t* keys, const uint32_t* values,
+                    int32_t n_views, const ws_options* opt, const void* keys, const uint32_t* values,
                     int64_t capacity, const int64_t* d_num_pairs, const int32_t* d_status, uint32_t* tile_ranges,
                     float* images, void* ws, size_t ws_bytes, void* stream) {
     ws_status s;
@@ -336,7 +373,7 @@ ws_status ws_render(const ws_splat* splats, int64_t n, const ws_camera* cams, co
 }
 
 ws_status ws_expand_bins(const ws_splat* splats, int64_t n, const ws_camera* cams, const ws_camera* d_cams,
-                         int32_t n_views, const ws_options* opt, const uint64_t* keys, const uint32_t* values,
+                         int32_t n_views, const ws_options* opt, const void* keys, const uint32_t* values,
                          int64_t capacity, const int64_t* d_num_pairs, const int32_t* d_status,
                          uint32_t* tile_values, int64_t tile_capacity, uint32_t* tile_ranges, void* ws,
                          size_t ws_bytes, void* stream) {

@@ -14,8 +14,10 @@
 // k_emit        one workgroup per 2048 pairs, in rounds of up to 256 entries:
 //               loads the entries that cover the round's pairs, finds each
 //               pair's owner by marking the entry starts in LDS and taking a
-//               running maximum, and writes key = (tile << 32) | depth bits,
-//               value = Gaussian id with coalesced stores.  Work per
+//               running maximum, and writes key = (tile << 32) | depth bits
+//               (the tile alone as a 32-bit key with WS_FLAG_KEYS32, where the
+//               depth order is the emission order), value = Gaussian id with
+//               coalesced stores.  Work per
 //               workgroup is fixed, whatever the size of the splats.
 // Both prefix sums are those of scan.h (one pass with look-back up to 1024
 // workgroups, else the wait-free three-level scan).  k_preprocess zeroes the
@@ -44,8 +46,8 @@ struct PreprocessWs {
     uint32_t* list_a;       // [V n] visible entries in index order
     uint32_t* list_b;       // [V n] the same, sorted by depth (depth-first mode)
     uint32_t* depth;        // [V n] fp32 depth bits of every visible entry (depth-first mode)
-    uint64_t* dkey_a;       // [V n] fp32 depth bits of list_a (depth-first mode)
-    uint64_t* dkey_b;
+    uint32_t* dkey_a;       // [V n] fp32 depth bits of list_a (depth-first mode)
+    uint32_t* dkey_b;
     uint32_t* offsets;      // [V n] first pair of each list entry
     uint32_t* first_entry;  // [emit blocks] list entry owning each block's first pair
     void* scan_a;           // workspaces of the two prefix sums
@@ -76,9 +78,9 @@ size_t layout(void* ws, int64_t n, int32_t n_views, int64_t capacity, bool depth
     if (depth_first) {
         p.list_b = reinterpret_cast<uint32_t*>(take(size_t(ents) * 4));
         p.depth = reinterpret_cast<uint32_t*>(take(size_t(ents) * 4));
-        p.dkey_a = reinterpret_cast<uint64_t*>(take(size_t(ents) * 8));
-        p.dkey_b = reinterpret_cast<uint64_t*>(take(size_t(ents) * 8));
-        p.sort_ws = take(sort_workspace(ents, 0, 31, 8, true));
+        p.dkey_a = reinterpret_cast<uint32_t*>(take(size_t(ents) * 4));
+        p.dkey_b = reinterpret_cast<uint32_t*>(take(size_t(ents) * 4));
+        p.sort_ws = take(sort_workspace(ents, 0, 31, 8, true, 4));
     }
     if (out) *out = p;
     return off;
@@ -124,7 +126,7 @@ struct FlagLoad {
 };
 struct CompactStore {
     uint32_t* list;
-    uint64_t* dkeys;  // null unless depth-first
+    uint32_t* dkeys;  // null unless depth-first
     __device__ void operator()(int64_t i, uint64_t pos, const FlagItem& it) const {
         if (it.tiles == 0u) return;
         list[pos] = uint32_t(i);
@@ -168,7 +170,7 @@ struct EmitArgs {
     int64_t capacity;
     int32_t tile_w, tile_h;        // pixel size of a key cell (tile or bin)
     uint32_t tw_shift, th_shift;  // log2 of the cell size
-    uint64_t* keys;
+    void* keys;                   // uint64_t, or uint32_t cell ids (K32)
     uint32_t* values;
 };
 
@@ -184,6 +186,7 @@ __device__ __forceinline__ uint32_t wave_inclusive_max(uint32_t v) {
     return v;
 }
 
+template <bool K32>
 __global__ __launch_bounds__(kEmitThreads) void k_emit(EmitArgs a) {
     __shared__ uint32_t s_owner[kEmitPairs];
     __shared__ uint32_t s_start[kEmitSlots];
@@ -324,7 +327,8 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(EmitArgs a) {
                     col -= w;
                 }
                 const uint64_t tile = uint64_t(s_tbase[s]) + uint64_t(ty0 + row) * s_tilesx[s] + (tx0 + col);
-                a.keys[p] = (tile << 32) | s_depth[s];
+                if (K32) static_cast<uint32_t*>(a.keys)[p] = uint32_t(tile);
+                else static_cast<uint64_t*>(a.keys)[p] = (tile << 32) | s_depth[s];
                 a.values[p] = s_gid[s];
             }
         }
@@ -341,7 +345,7 @@ size_t preprocess_workspace(int64_t n, int32_t n_views, int64_t capacity, uint32
 }
 
 hipError_t launch_preprocess(const GaussPtrs& g, const ws_camera* d_cams, int32_t n_views, const KOpts& o,
-                             ws_splat* splats, uint32_t* tiles_touched, uint64_t* keys, uint32_t* values,
+                             ws_splat* splats, uint32_t* tiles_touched, void* keys, uint32_t* values,
                              int64_t capacity, int64_t* d_num_pairs, int32_t* d_status, void* ws,
                              hipStream_t stream) {
     const bool depth_first = (o.flags & WS_FLAG_DEPTH_FIRST) != 0;
@@ -351,7 +355,7 @@ hipError_t launch_preprocess(const GaussPtrs& g, const ws_camera* d_cams, int32_
     const int64_t ents = std::max<int64_t>(pw.total, 1);
     ClearList clr;
     clr.add(pw.scan_a, scan_sync_words(pw.total, kCompactItems));
-    if (depth_first) sort_sync_words(pw.sort_ws, ents, 0, 31, 8, true, &clr);
+    if (depth_first) sort_sync_words(pw.sort_ws, ents, 0, 31, 8, true, 4, &clr);
     clr.add(pw.scan_b, scan_sync_words(ents, kCountItems));
     timing_begin(WS_KERNEL_PREPROCESS, stream);
     switch (o.sh_degree) {
@@ -402,7 +406,10 @@ hipError_t launch_preprocess(const GaussPtrs& g, const ws_camera* d_cams, int32_
     ea.th_shift = uint32_t(__builtin_ctz(uint32_t(o.cell_h())));
     ea.keys = keys;
     ea.values = values;
-    hipLaunchKernelGGL(k_emit, dim3(uint32_t(pw.emit_blocks)), dim3(kEmitThreads), 0, stream, ea);
+    if (o.flags & WS_FLAG_KEYS32)
+        hipLaunchKernelGGL(k_emit<true>, dim3(uint32_t(pw.emit_blocks)), dim3(kEmitThreads), 0, stream, ea);
+    else
+        hipLaunchKernelGGL(k_emit<false>, dim3(uint32_t(pw.emit_blocks)), dim3(kEmitThreads), 0, stream, ea);
     timing_end(WS_KERNEL_SCAN_EMIT, stream);
     return hipGetLastError();
 }

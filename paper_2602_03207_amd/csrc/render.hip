@@ -1,8 +1,8 @@
 // Tile ranges and front-to-back compositing (Eq. 2, Eq. 4).
 //
 // k_ranges                    [start, end) of every tile's run of pairs in the
-//                             tile-sorted key list, written where key >> 32
-//                             changes; the tiles without pairs between two
+//                             tile-sorted key list, written where the tile
+//                             (key >> 32, or the 32-bit key itself) changes; the tiles without pairs between two
 //                             runs get an empty range at that boundary, so
 //                             every tile is written once and no clearing
 //                             launch is needed.
@@ -55,7 +55,12 @@ __device__ __forceinline__ void fill_empty(uint32_t* ranges, uint32_t lo, uint32
     for (uint32_t t = lo + first; t < hi; t += step) r[t] = make_uint2(pos, pos);
 }
 
-__global__ __launch_bounds__(kRangeThreads) void k_ranges(const uint64_t* __restrict__ keys, int64_t cap,
+// The tile (or bin) a key names: the high word of a 64-bit key, a 32-bit key itself.
+__device__ __forceinline__ uint32_t cell_of(uint64_t k) { return uint32_t(k >> 32); }
+__device__ __forceinline__ uint32_t cell_of(uint32_t k) { return k; }
+
+template <typename K>
+__global__ __launch_bounds__(kRangeThreads) void k_ranges(const K* __restrict__ keys, int64_t cap,
                                                           const int64_t* d_n, const int32_t* d_status,
                                                           uint32_t* __restrict__ ranges, int64_t total_tiles) {
     if (*d_status != 0) return;
@@ -67,8 +72,8 @@ __global__ __launch_bounds__(kRangeThreads) void k_ranges(const uint64_t* __rest
         return;
     }
     if (blockIdx.x == 0) {  // tiles before the first run
-        const uint64_t t0 = keys[0] >> 32;
-        fill_empty(ranges, 0, uint32_t(t0 < T ? t0 : T), 0, threadIdx.x, kRangeThreads);
+        const uint32_t t0 = cell_of(keys[0]);
+        fill_empty(ranges, 0, t0 < T ? t0 : T, 0, threadIdx.x, kRangeThreads);
     }
     const uint32_t lane = lane_id();
     constexpr int64_t kChunk = int64_t(kRangeThreads) * kRangeItems;
@@ -80,9 +85,9 @@ __global__ __launch_bounds__(kRangeThreads) void k_ranges(const uint64_t* __rest
 #pragma unroll
         for (int j = 0; j < kRangeItems; ++j) {
             const int64_t i = base + j * kRangeThreads + threadIdx.x;
-            t[j] = i < m ? uint32_t(keys[i] >> 32) : 0xffffffffu;
+            t[j] = i < m ? cell_of(keys[i]) : 0xffffffffu;
             const int64_t ie = i + off;
-            edge[j] = (off != 0 && ie >= 0 && ie < m) ? uint32_t(keys[ie] >> 32) : 0xffffffffu;
+            edge[j] = (off != 0 && ie >= 0 && ie < m) ? cell_of(keys[ie]) : 0xffffffffu;
         }
 #pragma unroll
         for (int j = 0; j < kRangeItems; ++j) {
@@ -420,6 +425,16 @@ uint32_t persistent_grid() {
     return uint32_t(cached[dev]);
 }
 
+void launch_ranges(const KOpts& o, const void* keys, int64_t capacity, const int64_t* d_num_pairs,
+                   const int32_t* d_status, uint32_t* ranges, int64_t cells, uint32_t grid, hipStream_t stream) {
+    if (o.flags & WS_FLAG_KEYS32)
+        hipLaunchKernelGGL(k_ranges<uint32_t>, dim3(grid), dim3(kRangeThreads), 0, stream,
+                           static_cast<const uint32_t*>(keys), capacity, d_num_pairs, d_status, ranges, cells);
+    else
+        hipLaunchKernelGGL(k_ranges<uint64_t>, dim3(grid), dim3(kRangeThreads), 0, stream,
+                           static_cast<const uint64_t*>(keys), capacity, d_num_pairs, d_status, ranges, cells);
+}
+
 template <int TW, int TH>
 void launch_render_t(const RenderArgs& ra, const OrderWs* ow, hipStream_t stream) {
     if (!ow) {
@@ -436,15 +451,14 @@ void launch_render_t(const RenderArgs& ra, const OrderWs* ow, hipStream_t stream
 size_t expand_workspace(int64_t total_bins) { return align_up(size_t(std::max<int64_t>(total_bins, 1)) * 8); }
 
 hipError_t launch_expand(const ws_splat* splats, int64_t n, const ws_camera* d_cams, int32_t n_views,
-                         int64_t total_bins, const KOpts& o, const uint64_t* keys, const uint32_t* values,
+                         int64_t total_bins, const KOpts& o, const void* keys, const uint32_t* values,
                          int64_t capacity, const int64_t* d_num_pairs, const int32_t* d_status,
                          uint32_t* tile_values, uint32_t* tile_ranges, void* ws, hipStream_t stream) {
     uint32_t* bin_ranges = static_cast<uint32_t*>(ws);
     timing_begin(WS_KERNEL_RANGES, stream);
     const int64_t rchunk = int64_t(kRangeThreads) * kRangeItems;
     const uint32_t rgrid = uint32_t(std::min<int64_t>(std::max<int64_t>((capacity + rchunk - 1) / rchunk, 1), 4096));
-    hipLaunchKernelGGL(k_ranges, dim3(rgrid), dim3(kRangeThreads), 0, stream, keys, capacity, d_num_pairs, d_status,
-                       bin_ranges, total_bins);
+    launch_ranges(o, keys, capacity, d_num_pairs, d_status, bin_ranges, total_bins, rgrid, stream);
     ExpandArgs ea;
     ea.splats = splats;
     ea.n = std::max<int64_t>(n, 1);
@@ -474,7 +488,7 @@ size_t render_workspace(int64_t total_tiles, const KOpts& o) {
 }
 
 hipError_t launch_render(const ws_splat* splats, int64_t n, const ws_camera* d_cams, int32_t n_views,
-                         int64_t total_tiles, const KOpts& o, const uint64_t* keys, const uint32_t* values,
+                         int64_t total_tiles, const KOpts& o, const void* keys, const uint32_t* values,
                          int64_t capacity, const int64_t* d_num_pairs, const int32_t* d_status,
                          uint32_t* tile_ranges, float* images, void* ws, hipStream_t stream) {
     if (keys) {  // otherwise the ranges are given (ws_expand_bins)
@@ -482,8 +496,7 @@ hipError_t launch_render(const ws_splat* splats, int64_t n, const ws_camera* d_c
         const int64_t rchunk = int64_t(kRangeThreads) * kRangeItems;
         const uint32_t rgrid =
             uint32_t(std::min<int64_t>(std::max<int64_t>((capacity + rchunk - 1) / rchunk, 1), 4096));
-        hipLaunchKernelGGL(k_ranges, dim3(rgrid), dim3(kRangeThreads), 0, stream, keys, capacity, d_num_pairs,
-                           d_status, tile_ranges, total_tiles);
+        launch_ranges(o, keys, capacity, d_num_pairs, d_status, tile_ranges, total_tiles, rgrid, stream);
         timing_end(WS_KERNEL_RANGES, stream);
     }
     if (total_tiles == 0) return hipGetLastError();

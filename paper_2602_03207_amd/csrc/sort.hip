@@ -1,4 +1,5 @@
-// Stable LSD radix sort of (u64 key, u32 value) pairs (Sec. 3.3.2).
+// Stable LSD radix sort of (key, u32 value) pairs, keys of 64 or 32 bits
+// (Sec. 3.3.2).
 //
 // Each pass places an element at base_d + prefix_wg + rank_local (Eq. 5-6):
 //   base_d      count of the digits below d in the whole array,
@@ -50,7 +51,7 @@ constexpr uint32_t kStInc = 2u << 30;
 constexpr uint32_t kStMask = (1u << 30) - 1;
 
 struct SortLayout {
-    uint64_t* alt_keys;
+    void* alt_keys;      // [capacity] keys of the key width
     uint32_t* alt_vals;
     uint32_t* hist;      // look-back: [passes][radix]
     uint32_t* status;    // look-back: [passes][max_tiles][radix]
@@ -64,7 +65,8 @@ struct SortLayout {
 
 int default_radix(int r) { return r <= 0 ? 8 : r; }
 
-size_t plan(void* ws, int64_t capacity, int begin_bit, int end_bit, int radix_bits, bool sparse, SortLayout* out) {
+size_t plan(void* ws, int64_t capacity, int begin_bit, int end_bit, int radix_bits, bool sparse, int key_bytes,
+            SortLayout* out) {
     SortLayout L{};
     L.r = default_radix(radix_bits);
     L.radix = 1 << L.r;
@@ -82,7 +84,7 @@ size_t plan(void* ws, int64_t capacity, int begin_bit, int end_bit, int radix_bi
         return ptr;
     };
     if (L.passes > 1) {
-        L.alt_keys = reinterpret_cast<uint64_t*>(take(size_t(capacity) * 8));
+        L.alt_keys = take(size_t(capacity) * size_t(key_bytes));
         L.alt_vals = reinterpret_cast<uint32_t*>(take(size_t(capacity) * 4));
     }
     if (L.wait_free) {
@@ -111,11 +113,11 @@ __device__ __forceinline__ int64_t device_count(int64_t cap, const int64_t* d_n)
 // wave w is element tile*TILE + w*ITEMS*64 + j*64 + l, so each wave's items
 // are in input order.
 
-template <int B, int ITEMS>
+template <int B, int ITEMS, typename K>
 struct TileSmem {
     static constexpr int kTile = kSortThreads * ITEMS;
     static constexpr int kRadix = 1 << B;
-    uint64_t buf[kTile];  // reorder buffer: keys, then values (as u32)
+    K buf[kTile];  // reorder buffer: keys, then values (as u32)
     uint32_t whist[kSortWaves][kRadix];
     uint32_t tile_off[kRadix];
     uint32_t global[kRadix];
@@ -123,8 +125,8 @@ struct TileSmem {
     uint32_t tile;
 };
 
-template <int B>
-__device__ __forceinline__ uint32_t digit_of(uint64_t k, int shift) {
+template <int B, typename K>
+__device__ __forceinline__ uint32_t digit_of(K k, int shift) {
     return uint32_t(k >> shift) & ((1u << B) - 1u);
 }
 
@@ -132,9 +134,9 @@ __device__ __forceinline__ uint32_t digit_of(uint64_t k, int shift) {
 // digits of its wave.  On return whist[w][d] holds the exclusive prefix over
 // waves of digit d's count and *cnt_out (threads t < 2^B) the tile's count of
 // digit t.  whist must be zero on entry.
-template <int B, int ITEMS>
-__device__ __forceinline__ void load_and_rank(TileSmem<B, ITEMS>& sm, const uint64_t* kin, int64_t n, int64_t tile,
-                                              int shift, uint64_t* key, uint32_t* rank, uint32_t* cnt_out) {
+template <int B, int ITEMS, typename K>
+__device__ __forceinline__ void load_and_rank(TileSmem<B, ITEMS, K>& sm, const K* kin, int64_t n, int64_t tile,
+                                              int shift, K* key, uint32_t* rank, uint32_t* cnt_out) {
     constexpr int kTile = kSortThreads * ITEMS;
     const int wave = threadIdx.x / kWave;
     const uint32_t lane = lane_id();
@@ -142,7 +144,7 @@ __device__ __forceinline__ void load_and_rank(TileSmem<B, ITEMS>& sm, const uint
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
         const int64_t idx = wbase + j * kWave + lane;
-        key[j] = idx < n ? kin[idx] : 0ull;
+        key[j] = idx < n ? kin[idx] : K(0);
     }
     // Phase 1: lanes of the wave holding the same digit (matched bit by bit),
     // this lane's rank among them and the group's leader (lowest lane).
@@ -202,9 +204,9 @@ __device__ __forceinline__ void load_and_rank(TileSmem<B, ITEMS>& sm, const uint
 // and values second through the same buffer.  The values are read only after
 // the keys are staged, which keeps them out of registers during the ranking.
 // Requires tile_off (and for flush_tile global) visible to the workgroup.
-template <int B, int ITEMS>
-__device__ __forceinline__ void stage_keys(TileSmem<B, ITEMS>& sm, int64_t n, int64_t tile, int shift,
-                                           const uint64_t* key, uint32_t* rank) {
+template <int B, int ITEMS, typename K>
+__device__ __forceinline__ void stage_keys(TileSmem<B, ITEMS, K>& sm, int64_t n, int64_t tile, int shift,
+                                           const K* key, uint32_t* rank) {
     constexpr int kTile = kSortThreads * ITEMS;
     const int wave = threadIdx.x / kWave;
     const uint32_t lane = lane_id();
@@ -230,10 +232,9 @@ __device__ __forceinline__ void load_vals(const uint32_t* vin, int64_t n, int64_
 }
 
 // Caller synchronises the workgroup between stage_keys and this call.
-template <int B, int ITEMS>
-__device__ __forceinline__ void flush_tile(TileSmem<B, ITEMS>& sm, int64_t n, int64_t tile, int shift,
-                                           const uint32_t* pos, const uint32_t* val, uint64_t* kout,
-                                           uint32_t* vout) {
+template <int B, int ITEMS, typename K>
+__device__ __forceinline__ void flush_tile(TileSmem<B, ITEMS, K>& sm, int64_t n, int64_t tile, int shift,
+                                           const uint32_t* pos, const uint32_t* val, K* kout, uint32_t* vout) {
     constexpr int kTile = kSortThreads * ITEMS;
     const int wave = threadIdx.x / kWave;
     const uint32_t lane = lane_id();
@@ -245,7 +246,7 @@ __device__ __forceinline__ void flush_tile(TileSmem<B, ITEMS>& sm, int64_t n, in
         const int i = threadIdx.x + k * kSortThreads;
         out[k] = 0xffffffffu;
         if (i < tile_n) {
-            const uint64_t kk = sm.buf[i];
+            const K kk = sm.buf[i];
             const uint32_t d = digit_of<B>(kk, shift);
             out[k] = sm.global[d] + uint32_t(i) - sm.tile_off[d];
             if (int64_t(out[k]) < n) kout[out[k]] = kk;  // always true for consistent counts; guards the write
@@ -264,15 +265,16 @@ __device__ __forceinline__ void flush_tile(TileSmem<B, ITEMS>& sm, int64_t n, in
     }
 }
 
-template <int B, int ITEMS>
-__device__ __forceinline__ void clear_whist(TileSmem<B, ITEMS>& sm) {
+template <int B, int ITEMS, typename K>
+__device__ __forceinline__ void clear_whist(TileSmem<B, ITEMS, K>& sm) {
     for (int i = threadIdx.x; i < kSortWaves * (1 << B); i += kSortThreads) (&sm.whist[0][0])[i] = 0;
 }
 
 // ------------------------------------------------ wait-free schedule
 
+template <typename K>
 struct UpArgs {
-    const uint64_t* kin;
+    const K* kin;
     int64_t cap;
     const int64_t* d_n;
     const int32_t* d_status;
@@ -284,8 +286,8 @@ struct UpArgs {
 };
 
 // Digit counts of one tile into table[d][tile] (zeros for tiles past the end).
-template <int B, int ITEMS>
-__global__ __launch_bounds__(kSortThreads) void k_upsweep(UpArgs a) {
+template <int B, int ITEMS, typename K>
+__global__ __launch_bounds__(kSortThreads) void k_upsweep(UpArgs<K> a) {
     constexpr int RADIX = 1 << B;
     constexpr int kTile = kSortThreads * ITEMS;
     __shared__ uint32_t s_h[kSortWaves][RADIX];
@@ -303,11 +305,11 @@ __global__ __launch_bounds__(kSortThreads) void k_upsweep(UpArgs a) {
     __syncthreads();
     const int64_t wbase = tile * kTile + int64_t(wave) * (ITEMS * kWave) + lane_id();
     // all of the tile's loads in flight before the first use
-    uint64_t k[ITEMS];
+    K k[ITEMS];
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
         const int64_t idx = wbase + j * kWave;
-        k[j] = idx < n ? a.kin[idx] : 0ull;
+        k[j] = idx < n ? a.kin[idx] : K(0);
     }
 #pragma unroll
     for (int j = 0; j < ITEMS; ++j) {
@@ -333,10 +335,11 @@ __global__ __launch_bounds__(kSortThreads) void k_upsweep(UpArgs a) {
     }
 }
 
+template <typename K>
 struct DownArgs {
-    const uint64_t* kin;
+    const K* kin;
     const uint32_t* vin;
-    uint64_t* kout;
+    K* kout;
     uint32_t* vout;
     int64_t cap;
     const int64_t* d_n;
@@ -346,10 +349,10 @@ struct DownArgs {
     int64_t max_tiles;
 };
 
-template <int B, int ITEMS>
-__global__ __launch_bounds__(kSortThreads) void k_downsweep(DownArgs a) {
+template <int B, int ITEMS, typename K>
+__global__ __launch_bounds__(kSortThreads) void k_downsweep(DownArgs<K> a) {
     constexpr int kTile = kSortThreads * ITEMS;
-    __shared__ TileSmem<B, ITEMS> sm;
+    __shared__ TileSmem<B, ITEMS, K> sm;
     if (a.d_status && *a.d_status != 0) return;
     const int64_t n = device_count(a.cap, a.d_n);
     const int64_t ntiles = (n + kTile - 1) / kTile;
@@ -357,10 +360,10 @@ __global__ __launch_bounds__(kSortThreads) void k_downsweep(DownArgs a) {
     const int64_t tile = xcd_contiguous(blockIdx.x, uint32_t(ntiles));
     clear_whist(sm);
     __syncthreads();
-    uint64_t key[ITEMS];
+    K key[ITEMS];
     uint32_t rank[ITEMS];
     uint32_t cnt;
-    load_and_rank<B, ITEMS>(sm, a.kin, n, tile, a.shift, key, rank, &cnt);
+    load_and_rank<B, ITEMS, K>(sm, a.kin, n, tile, a.shift, key, rank, &cnt);
     // the values are in flight during the scan and the staging of the keys
     uint32_t val[ITEMS];
     load_vals<ITEMS>(a.vin, n, tile, val);
@@ -371,9 +374,9 @@ __global__ __launch_bounds__(kSortThreads) void k_downsweep(DownArgs a) {
         sm.global[threadIdx.x] = a.table[int64_t(threadIdx.x) * a.max_tiles + tile];
     }
     __syncthreads();
-    stage_keys<B, ITEMS>(sm, n, tile, a.shift, key, rank);
+    stage_keys<B, ITEMS, K>(sm, n, tile, a.shift, key, rank);
     __syncthreads();
-    flush_tile<B, ITEMS>(sm, n, tile, a.shift, rank, val, a.kout, a.vout);
+    flush_tile<B, ITEMS, K>(sm, n, tile, a.shift, rank, val, a.kout, a.vout);
 }
 
 struct TableLoad {
@@ -394,8 +397,9 @@ __global__ void k_sort_init(uint32_t* hist, int bins, uint32_t* tickets, int pas
     for (int i = threadIdx.x; i < passes; i += blockDim.x) tickets[i] = 0;
 }
 
+template <typename K>
 struct HistArgs {
-    const uint64_t* keys;
+    const K* keys;
     int64_t cap;
     const int64_t* d_n;
     const int32_t* d_status;
@@ -408,7 +412,8 @@ struct HistArgs {
 
 // Digit histograms of every pass from one read of the keys, and clearing of
 // the look-back words of the tiles the passes will use.
-__global__ __launch_bounds__(kHistThreads) void k_sort_hist(HistArgs a) {
+template <typename K>
+__global__ __launch_bounds__(kHistThreads) void k_sort_hist(HistArgs<K> a) {
     __shared__ uint32_t s_h[kHistThreads / kWave][kMaxBins];
     if (a.d_status && *a.d_status != 0) return;
     const int64_t n = device_count(a.cap, a.d_n);
@@ -429,7 +434,7 @@ __global__ __launch_bounds__(kHistThreads) void k_sort_hist(HistArgs a) {
     __syncthreads();
     const uint32_t mask_full = uint32_t(radix - 1);
     for (int64_t i = int64_t(blockIdx.x) * kHistThreads + threadIdx.x; i < n; i += gsize) {
-        const uint64_t k = a.keys[i];
+        const K k = a.keys[i];
         const uint64_t active = __ballot(true);
         const bool first = lanes_below(active) == 0;
         for (int p = 0; p < a.passes; ++p) {
@@ -454,10 +459,11 @@ __global__ __launch_bounds__(kHistThreads) void k_sort_hist(HistArgs a) {
     }
 }
 
+template <typename K>
 struct PassArgs {
-    const uint64_t* kin;
+    const K* kin;
     const uint32_t* vin;
-    uint64_t* kout;
+    K* kout;
     uint32_t* vout;
     int64_t cap;
     const int64_t* d_n;
@@ -469,14 +475,14 @@ struct PassArgs {
     uint32_t* ticket;
 };
 
-template <int B, int ITEMS>
-__device__ __forceinline__ void sort_tile_lookback(TileSmem<B, ITEMS>& sm, const PassArgs& a, int64_t n,
+template <int B, int ITEMS, typename K>
+__device__ __forceinline__ void sort_tile_lookback(TileSmem<B, ITEMS, K>& sm, const PassArgs<K>& a, int64_t n,
                                                    int64_t tile) {
     constexpr int RADIX = 1 << B;
-    uint64_t key[ITEMS];
+    K key[ITEMS];
     uint32_t rank[ITEMS];
     uint32_t cnt;
-    load_and_rank<B, ITEMS>(sm, a.kin, n, tile, a.shift, key, rank, &cnt);
+    load_and_rank<B, ITEMS, K>(sm, a.kin, n, tile, a.shift, key, rank, &cnt);
     const int t = threadIdx.x;
     if (t < RADIX) store_agent(&a.status[tile * RADIX + t], (tile == 0 ? kStInc : kStAgg) | cnt);
     uint32_t total;
@@ -486,7 +492,7 @@ __device__ __forceinline__ void sort_tile_lookback(TileSmem<B, ITEMS>& sm, const
     if (t < RADIX) sm.tile_off[t] = toff;
     __syncthreads();
     // the keys wait in LDS (and the values are in flight) during the look-back
-    stage_keys<B, ITEMS>(sm, n, tile, a.shift, key, rank);
+    stage_keys<B, ITEMS, K>(sm, n, tile, a.shift, key, rank);
     uint32_t val[ITEMS];
     load_vals<ITEMS>(a.vin, n, tile, val);
     if (t < RADIX) {
@@ -540,13 +546,13 @@ __device__ __forceinline__ void sort_tile_lookback(TileSmem<B, ITEMS>& sm, const
         sm.global[t] = dbase + excl;
     }
     __syncthreads();
-    flush_tile<B, ITEMS>(sm, n, tile, a.shift, rank, val, a.kout, a.vout);
+    flush_tile<B, ITEMS, K>(sm, n, tile, a.shift, rank, val, a.kout, a.vout);
 }
 
-template <int B, int ITEMS>
-__global__ __launch_bounds__(kSortThreads) void k_sort_pass(PassArgs a) {
+template <int B, int ITEMS, typename K>
+__global__ __launch_bounds__(kSortThreads) void k_sort_pass(PassArgs<K> a) {
     constexpr int kTile = kSortThreads * ITEMS;
-    __shared__ TileSmem<B, ITEMS> sm;
+    __shared__ TileSmem<B, ITEMS, K> sm;
     if (a.d_status && *a.d_status != 0) return;
     const int64_t n = device_count(a.cap, a.d_n);
     const int64_t ntiles = (n + kTile - 1) / kTile;
@@ -561,77 +567,83 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_pass(PassArgs a) {
         __syncthreads();
         const int64_t tile = sm.tile;
         if (tile >= ntiles) return;
-        sort_tile_lookback<B, ITEMS>(sm, a, n, tile);
+        sort_tile_lookback<B, ITEMS, K>(sm, a, n, tile);
         __syncthreads();  // the tile's LDS is reused by the next ticket
     }
 }
 
 // ------------------------------------------------ dispatch
 
+template <typename K>
 struct PassLaunch {
     const SortLayout* L;
-    UpArgs ua;
-    DownArgs da;
-    PassArgs pa;
+    UpArgs<K> ua;
+    DownArgs<K> da;
+    PassArgs<K> pa;
     const int32_t* d_status;
     hipStream_t stream;
 };
 
-template <int B, int ITEMS>
-void run_pass(const PassLaunch& c) {
+template <int B, int ITEMS, typename K>
+void run_pass(const PassLaunch<K>& c) {
     const uint32_t grid = uint32_t(c.L->max_tiles);
     if (c.L->wait_free) {
-        hipLaunchKernelGGL((k_upsweep<B, ITEMS>), dim3(grid), dim3(kSortThreads), 0, c.stream, c.ua);
+        hipLaunchKernelGGL((k_upsweep<B, ITEMS, K>), dim3(grid), dim3(kSortThreads), 0, c.stream, c.ua);
         // the upsweep zeroed the scan's look-back words (c.ua.clear)
         const int64_t entries = int64_t(1 << B) * c.L->max_tiles;
         launch_scan<uint32_t, kTableItems>(TableLoad{c.ua.table}, TableStore{c.ua.table}, entries, nullptr, c.d_status,
                               c.L->table_scan, static_cast<uint32_t*>(nullptr), c.stream, true);
-        hipLaunchKernelGGL((k_downsweep<B, ITEMS>), dim3(grid), dim3(kSortThreads), 0, c.stream, c.da);
+        hipLaunchKernelGGL((k_downsweep<B, ITEMS, K>), dim3(grid), dim3(kSortThreads), 0, c.stream, c.da);
     } else {
         // workgroups loop over tickets, so the grid need not cover every tile
         const uint32_t lgrid = uint32_t(std::min<int64_t>(c.L->max_tiles, kLookbackGrid));
-        hipLaunchKernelGGL((k_sort_pass<B, ITEMS>), dim3(lgrid), dim3(kSortThreads), 0, c.stream, c.pa);
+        hipLaunchKernelGGL((k_sort_pass<B, ITEMS, K>), dim3(lgrid), dim3(kSortThreads), 0, c.stream, c.pa);
     }
 }
 
-template <int ITEMS>
-void run_pass_bits(const PassLaunch& c, int bits) {
+template <int ITEMS, typename K>
+void run_pass_bits(const PassLaunch<K>& c, int bits) {
     switch (bits) {
-        case 1: run_pass<1, ITEMS>(c); break;
-        case 2: run_pass<2, ITEMS>(c); break;
-        case 3: run_pass<3, ITEMS>(c); break;
-        case 4: run_pass<4, ITEMS>(c); break;
-        case 5: run_pass<5, ITEMS>(c); break;
-        case 6: run_pass<6, ITEMS>(c); break;
-        case 7: run_pass<7, ITEMS>(c); break;
-        default: run_pass<8, ITEMS>(c); break;
+        case 1: run_pass<1, ITEMS, K>(c); break;
+        case 2: run_pass<2, ITEMS, K>(c); break;
+        case 3: run_pass<3, ITEMS, K>(c); break;
+        case 4: run_pass<4, ITEMS, K>(c); break;
+        case 5: run_pass<5, ITEMS, K>(c); break;
+        case 6: run_pass<6, ITEMS, K>(c); break;
+        case 7: run_pass<7, ITEMS, K>(c); break;
+        default: run_pass<8, ITEMS, K>(c); break;
     }
 }
 
 }  // namespace
 
-size_t sort_workspace(int64_t capacity, int32_t begin_bit, int32_t end_bit, int32_t radix_bits, bool sparse) {
-    return plan(nullptr, capacity, begin_bit, end_bit, radix_bits, sparse, nullptr);
+size_t sort_workspace(int64_t capacity, int32_t begin_bit, int32_t end_bit, int32_t radix_bits, bool sparse,
+                      int key_bytes) {
+    return plan(nullptr, capacity, begin_bit, end_bit, radix_bits, sparse, key_bytes, nullptr);
 }
 
 void sort_sync_words(void* ws, int64_t capacity, int32_t begin_bit, int32_t end_bit, int32_t radix_bits, bool sparse,
-                     ClearList* c) {
+                     int key_bytes, ClearList* c) {
     SortLayout L;
-    plan(ws, capacity, begin_bit, end_bit, radix_bits, sparse, &L);
+    plan(ws, capacity, begin_bit, end_bit, radix_bits, sparse, key_bytes, &L);
     if (!L.wait_free) c->add(L.hist, int64_t(L.passes) * (L.radix + 1));  // histograms, then tickets
 }
 
-hipError_t launch_sort(const uint64_t* kin, const uint32_t* vin, uint64_t* kout, uint32_t* vout, int64_t n,
-                       const int64_t* d_n, const int32_t* d_status, int32_t begin_bit, int32_t end_bit,
-                       int32_t radix_bits, void* ws, hipStream_t stream, bool timed, bool sparse, bool precleared) {
+namespace {
+
+template <typename K>
+hipError_t launch_sort_t(const K* kin, const uint32_t* vin, K* kout, uint32_t* vout, int64_t n, const int64_t* d_n,
+                         const int32_t* d_status, int32_t begin_bit, int32_t end_bit, int32_t radix_bits, void* ws,
+                         hipStream_t stream, bool timed, bool sparse, bool precleared) {
     SortLayout L;
-    plan(ws, n, begin_bit, end_bit, radix_bits, sparse, &L);
+    plan(ws, n, begin_bit, end_bit, radix_bits, sparse, int(sizeof(K)), &L);
+    K* alt_keys = static_cast<K*>(L.alt_keys);
     const int hist_id = timed ? WS_KERNEL_SORT_HIST : -1, pass_id = timed ? WS_KERNEL_SORT_PASS : -1;
     if (!L.wait_free) {
         if (!precleared)
             hipLaunchKernelGGL(k_sort_init, dim3(1), dim3(256), 0, stream, L.hist, L.passes * L.radix, L.tickets,
                                L.passes);
-        HistArgs h;
+        HistArgs<K> h;
         h.keys = kin;
         h.cap = n;
         h.d_n = d_n;
@@ -647,27 +659,27 @@ hipError_t launch_sort(const uint64_t* kin, const uint32_t* vin, uint64_t* kout,
         // few workgroups: each adds its bins to the global histogram once
         const int64_t hist_blocks = std::min<int64_t>(std::max<int64_t>((n + 4095) / 4096, 1), 256);
         timing_begin(hist_id, stream);
-        hipLaunchKernelGGL(k_sort_hist, dim3(uint32_t(hist_blocks)), dim3(kHistThreads), 0, stream, h);
+        hipLaunchKernelGGL(k_sort_hist<K>, dim3(uint32_t(hist_blocks)), dim3(kHistThreads), 0, stream, h);
         timing_end(hist_id, stream);
     }
     for (int p = 0; p < L.passes; ++p) {
-        const uint64_t* pk = p == 0 ? kin : ((L.passes - p) % 2 == 0 ? kout : L.alt_keys);
+        const K* pk = p == 0 ? kin : ((L.passes - p) % 2 == 0 ? kout : alt_keys);
         const uint32_t* pv = p == 0 ? vin : ((L.passes - p) % 2 == 0 ? vout : L.alt_vals);
         const bool to_out = (L.passes - 1 - p) % 2 == 0;
-        uint64_t* ok = to_out ? kout : L.alt_keys;
+        K* ok = to_out ? kout : alt_keys;
         uint32_t* ov = to_out ? vout : L.alt_vals;
         const int shift = begin_bit + p * L.r;
         const int bits = std::min(L.r, end_bit - shift);
-        PassLaunch c;
+        PassLaunch<K> c;
         c.L = &L;
         c.d_status = d_status;
         c.stream = stream;
-        c.ua = UpArgs{pk, n, d_n, d_status, shift, L.table, L.max_tiles, nullptr, 0};
+        c.ua = UpArgs<K>{pk, n, d_n, d_status, shift, L.table, L.max_tiles, nullptr, 0};
         if (L.wait_free) {
             c.ua.clear = static_cast<uint32_t*>(L.table_scan);
             c.ua.clear_words = scan_sync_words(int64_t(1 << bits) * L.max_tiles, kTableItems);
         }
-        c.da = DownArgs{pk, pv, ok, ov, n, d_n, d_status, shift, L.table, L.max_tiles};
+        c.da = DownArgs<K>{pk, pv, ok, ov, n, d_n, d_status, shift, L.table, L.max_tiles};
         c.pa.kin = pk;
         c.pa.vin = pv;
         c.pa.kout = ok;
@@ -681,11 +693,27 @@ hipError_t launch_sort(const uint64_t* kin, const uint32_t* vin, uint64_t* kout,
         c.pa.status = L.wait_free ? nullptr : L.status + int64_t(p) * L.max_tiles * L.radix;
         c.pa.ticket = L.wait_free ? nullptr : L.tickets + p;
         timing_begin(pass_id, stream);
-        if (L.items == kItemsSmall) run_pass_bits<kItemsSmall>(c, bits);
-        else run_pass_bits<kItemsLarge>(c, bits);
+        if (L.items == kItemsSmall) run_pass_bits<kItemsSmall, K>(c, bits);
+        else run_pass_bits<kItemsLarge, K>(c, bits);
         timing_end(pass_id, stream);
     }
     return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_sort(const uint64_t* kin, const uint32_t* vin, uint64_t* kout, uint32_t* vout, int64_t n,
+                       const int64_t* d_n, const int32_t* d_status, int32_t begin_bit, int32_t end_bit,
+                       int32_t radix_bits, void* ws, hipStream_t stream, bool timed, bool sparse, bool precleared) {
+    return launch_sort_t<uint64_t>(kin, vin, kout, vout, n, d_n, d_status, begin_bit, end_bit, radix_bits, ws, stream,
+                                   timed, sparse, precleared);
+}
+
+hipError_t launch_sort(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout, int64_t n,
+                       const int64_t* d_n, const int32_t* d_status, int32_t begin_bit, int32_t end_bit,
+                       int32_t radix_bits, void* ws, hipStream_t stream, bool timed, bool sparse, bool precleared) {
+    return launch_sort_t<uint32_t>(kin, vin, kout, vout, n, d_n, d_status, begin_bit, end_bit, radix_bits, ws, stream,
+                                   timed, sparse, precleared);
 }
 
 }  // namespace ws

@@ -220,8 +220,9 @@ __device__ __forceinline__ void view_offsets(const ws_camera* cams, int32_t v, i
 // ---------------------------------------------------- launchers (host)
 
 // preprocess.hip
+// keys: uint64_t (cell << 32 | depth bits), or uint32_t cell ids with WS_FLAG_KEYS32
 hipError_t launch_preprocess(const GaussPtrs& g, const ws_camera* d_cams, int32_t n_views, const KOpts& o,
-                             ws_splat* splats, uint32_t* tiles_touched, uint64_t* keys, uint32_t* values,
+                             ws_splat* splats, uint32_t* tiles_touched, void* keys, uint32_t* values,
                              int64_t capacity, int64_t* d_num_pairs, int32_t* d_status, void* ws,
                              hipStream_t stream);
 size_t preprocess_workspace(int64_t n, int32_t n_views, int64_t capacity, uint32_t flags);
@@ -234,25 +235,31 @@ size_t preprocess_workspace(int64_t n, int32_t n_views, int64_t capacity, uint32
 // the live count (workgroups past it leave at once) rather than the capacity.
 // `precleared`: an earlier kernel of the stream zeroed the words that
 // sort_sync_words lists, so the sort launches no clearing kernel.
+// The two overloads sort 64-bit and 32-bit keys; key_bytes below is 8 or 4.
 hipError_t launch_sort(const uint64_t* kin, const uint32_t* vin, uint64_t* kout, uint32_t* vout, int64_t n,
                        const int64_t* d_n, const int32_t* d_status, int32_t begin_bit, int32_t end_bit,
                        int32_t radix_bits, void* ws, hipStream_t stream, bool timed = true, bool sparse = false,
                        bool precleared = false);
-size_t sort_workspace(int64_t capacity, int32_t begin_bit, int32_t end_bit, int32_t radix_bits, bool sparse = false);
+hipError_t launch_sort(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout, int64_t n,
+                       const int64_t* d_n, const int32_t* d_status, int32_t begin_bit, int32_t end_bit,
+                       int32_t radix_bits, void* ws, hipStream_t stream, bool timed = true, bool sparse = false,
+                       bool precleared = false);
+size_t sort_workspace(int64_t capacity, int32_t begin_bit, int32_t end_bit, int32_t radix_bits, bool sparse = false,
+                      int key_bytes = 8);
 // Adds to `c` the words of a sort with these arguments that must be zero when
 // it starts (none for the wait-free schedule, whose passes clear their own).
 void sort_sync_words(void* ws, int64_t capacity, int32_t begin_bit, int32_t end_bit, int32_t radix_bits, bool sparse,
-                     ClearList* c);
+                     int key_bytes, ClearList* c);
 
 // render.hip
 hipError_t launch_render(const ws_splat* splats, int64_t n, const ws_camera* d_cams, int32_t n_views,
-                         int64_t total_tiles, const KOpts& o, const uint64_t* keys, const uint32_t* values,
+                         int64_t total_tiles, const KOpts& o, const void* keys, const uint32_t* values,
                          int64_t capacity, const int64_t* d_num_pairs, const int32_t* d_status,
                          uint32_t* tile_ranges, float* images, void* ws, hipStream_t stream);
 size_t render_workspace(int64_t total_tiles, const KOpts& o);
 size_t expand_workspace(int64_t total_bins);
 hipError_t launch_expand(const ws_splat* splats, int64_t n, const ws_camera* d_cams, int32_t n_views,
-                         int64_t total_bins, const KOpts& o, const uint64_t* keys, const uint32_t* values,
+                         int64_t total_bins, const KOpts& o, const void* keys, const uint32_t* values,
                          int64_t capacity, const int64_t* d_num_pairs, const int32_t* d_status,
                          uint32_t* tile_values, uint32_t* tile_ranges, void* ws, hipStream_t stream);
 

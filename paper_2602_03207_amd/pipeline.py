@@ -9,6 +9,9 @@ order; it never computes anything itself.  Two sequences are provided:
   device memory and are launched for the preallocated capacity, so the
   whole frame (and a backward) can be captured in a HIP graph.
 
+With WS_FLAG_KEYS32 (depth-first emission only) the keys are 32-bit tile
+ids and the sort is `ws_sort32` over the tile bits.
+
 With bins larger than one tile (options bin_x, bin_y) the pairs name bins:
 the sort orders the bin bits, and `ws_expand_bins` builds every tile's list
 (in `tile_vals`, one slot per tile of the bin's pair count) and the tile
@@ -123,12 +126,18 @@ class Renderer:
             return
         cap = int(cap)
         self.capacity = cap
-        self.keys_a = torch.empty(cap, dtype=torch.int64, device=self.device)
+        kt = torch.int32 if self.keys32 else torch.int64
+        self.keys_a = torch.empty(cap, dtype=kt, device=self.device)
         self.vals_a = torch.empty(cap, dtype=torch.int32, device=self.device)
-        self.keys_b = torch.empty(cap, dtype=torch.int64, device=self.device)
+        self.keys_b = torch.empty(cap, dtype=kt, device=self.device)
         self.vals_b = torch.empty(cap, dtype=torch.int32, device=self.device)
         if self.binned:
             self.tile_vals = torch.empty(self.per_bin * cap, dtype=torch.int32, device=self.device)
+
+    @property
+    def keys32(self) -> bool:
+        """Keys are 32-bit tile (bin) ids (WS_FLAG_KEYS32)."""
+        return bool(self.opts.flags & B.WS_FLAG_KEYS32)
 
     @property
     def per_bin(self) -> int:
@@ -161,11 +170,17 @@ class Renderer:
         rb = self.opts.radix_bits if radix_bits is None else radix_bits
         cap = self.capacity if device_count else n_pairs
         begin = self.begin_bit
+        d_n = self.d_num_pairs if device_count else None
+        if self.keys32:  # the tile bits are the whole key
+            need = B.ws_sort32_workspace_size(max(cap, 1), 0, self.end_bit - 32, rb)
+            ws = self.ws_sort.get(need)
+            B.ws_sort32(self.keys_a, self.vals_a, self.keys_b, self.vals_b, cap, d_n, self.d_status, 0,
+                        self.end_bit - 32, rb, ws, ws.numel(), stream)
+            return
         need = B.ws_sort_workspace_size(max(cap, 1), begin, self.end_bit, rb)
         ws = self.ws_sort.get(need)
-        B.ws_sort(self.keys_a, self.vals_a, self.keys_b, self.vals_b, cap,
-                  self.d_num_pairs if device_count else None, self.d_status, begin, self.end_bit, rb, ws, ws.numel(),
-                  stream)
+        B.ws_sort(self.keys_a, self.vals_a, self.keys_b, self.vals_b, cap, d_n, self.d_status, begin, self.end_bit,
+                  rb, ws, ws.numel(), stream)
 
     @property
     def begin_bit(self) -> int:

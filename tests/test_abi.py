@@ -134,6 +134,26 @@ def test_sort_rejects_bad_arguments_on_the_host(lib):
     assert lib.ws_sort(a, b, c, d, 1000, None, None, 0, 32, 8, vp(0x500004), need, None) == B.WS_ERR_INVALID_ARGUMENT
 
 
+def test_sort32_rejects_bad_arguments_on_the_host(lib):
+    vp = C.c_void_p
+    a, b, c, d = vp(0x100000), vp(0x200000), vp(0x300000), vp(0x400000)
+    ws = vp(0x500000)
+    # bits beyond the 32-bit key
+    st = lib.ws_sort32(a, b, c, d, 10, None, None, 0, 33, 8, ws, 1 << 20, None)
+    assert st == B.WS_ERR_INVALID_ARGUMENT and "ws_sort32" in _err(lib) and "32" in _err(lib)
+    assert lib.ws_sort32_workspace_size(1000, 0, 33, 8) == 0
+    assert lib.ws_sort32(a, b, c, d, 10, None, None, 7, 7, 8, ws, 1 << 20, None) == B.WS_ERR_INVALID_ARGUMENT
+    assert lib.ws_sort32(a, b, c, d, 10, None, None, 0, 32, 0, ws, 0, None) == B.WS_ERR_WORKSPACE_TOO_SMALL
+    # keys of 4 bytes: outputs 4 * 10 bytes past the inputs do not overlap them, 4 * 10 - 1 do
+    assert lib.ws_sort32(a, b, vp(0x100000 + 39), d, 10, None, None, 0, 32, 8, ws, 1 << 20, None) == \
+        B.WS_ERR_INVALID_ARGUMENT
+    need = lib.ws_sort32_workspace_size(10, 0, 32, 8)
+    assert lib.ws_sort32(a, b, c, d, 0, None, None, 0, 32, 8, None, 0, None) == B.WS_OK
+    assert lib.ws_sort32(a, b, c, d, 10, None, None, 0, 32, 8, ws, need - 1, None) == B.WS_ERR_WORKSPACE_TOO_SMALL
+    # the 32-bit sort needs less workspace than the 64-bit one for the same pairs (half-width key buffer)
+    assert lib.ws_sort32_workspace_size(1 << 20, 0, 32, 8) < lib.ws_sort_workspace_size(1 << 20, 0, 32, 8)
+
+
 def test_preprocess_and_render_reject_bad_options_on_the_host(lib):
     g = B.ws_gaussians()
     g.n = 0
@@ -148,6 +168,7 @@ def test_preprocess_and_render_reject_bad_options_on_the_host(lib):
         dict(alpha_min=0.0),
         dict(alpha_max=1.0),
         dict(t_min=0.0),
+        dict(flags=B.WS_FLAG_KEYS32),  # 32-bit keys carry no depth: depth-first emission is required
     ]
     for kw in bad:
         o = _opts(**kw)
