@@ -37,6 +37,7 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 # 157.3 TFLOP/s figure needs packed fp32 instructions, which this library is built without
 FP32_VALU_PEAK_TFLOPS = 78.6
 STATS_FILE = os.path.join(ROOT, "tests", "golden", "c2_oracle_stats.json")
+TUNE_BINS = ((1, 1), (2, 2), (4, 2))  # bins of tiles the autotuner tries besides tile keys
 
 
 def log(msg):
@@ -103,10 +104,10 @@ def bench_frames(args):
     base = B.make_options(sh_degree=3, flags=B.WS_FLAG_DEPTH_FIRST | B.WS_FLAG_KEYS32)
     g = GaussianTensors.from_scene(scene)
     stream = torch.cuda.current_stream()
-    # tile size and radix width from the autotuner (neither changes a pixel; the tuner checks it)
-    tune = autotune(g, [cam], base, reps=3, log=log)
+    # tile size, radix width and bins from the autotuner (none changes a pixel; the tuner checks it)
+    tune = autotune(g, [cam], base, reps=3, log=log, bins=TUNE_BINS)
     opts = tune.apply(base)
-    log(f"tuned: tile {tune.tile_w}x{tune.tile_h}, radix {tune.radix_bits}")
+    log(f"tuned: tile {tune.tile_w}x{tune.tile_h}, radix {tune.radix_bits}, bins {tune.bin_x}x{tune.bin_y}")
 
     def graph_frames(o):
         bf = BatchedForward([cam], o, g)
@@ -375,7 +376,7 @@ def bench_multiview(args):
     g = GaussianTensors.from_scene(scene)
     del scene
     base = B.make_options(sh_degree=3, flags=B.WS_FLAG_DEPTH_FIRST | B.WS_FLAG_KEYS32 | B.WS_FLAG_ORDERED_RENDER)
-    tune = autotune(g, cams, base, radix_bits=(6, 7, 8), reps=3, log=log)
+    tune = autotune(g, cams, base, radix_bits=(6, 7, 8), reps=3, log=log, bins=TUNE_BINS)
     opts = tune.apply(base)
     bf = BatchedForward(cams, opts, g)
     bf.capture()
@@ -404,7 +405,7 @@ def bench_multiview(args):
     return {"views": len(cams), "resolutions": {f"{w}x{h}": sum(1 for c in cams if (c.width, c.height) == (w, h))
                                                 for w, h in res},
             "pairs": pairs, "tuned": {"tile": f"{tune.tile_w}x{tune.tile_h}", "radix_bits": tune.radix_bits,
-                                      "candidates": len(tune.table)},
+                                      "bins": f"{tune.bin_x}x{tune.bin_y}", "candidates": len(tune.table)},
             "batched_views_per_s": round(len(cams) / t_batched, 2), "plain_views_per_s": round(len(cams) / t_plain, 2),
             "batched_ms": round(t_batched * 1e3, 3), "plain_ms": round(t_plain * 1e3, 3),
             "speedup": round(t_plain / t_batched, 3), "images_bit_equal": same}
@@ -458,11 +459,38 @@ def bench_large(args):
     torch.cuda.synchronize()
     copy_gbs = 2 * src.numel() * 4 * 5 / (c0.elapsed_time(c1) * 1e-3) / 1e9
     del src, dst
+    # whole frames (device-sized sequence) for a few layouts of the same frame; images must be identical
+    del r
+    frames, ref = {}, None
+    for (tw, th), (bx, by) in (((16, 16), (1, 1)), ((32, 16), (1, 1)), ((16, 16), (4, 2)), ((32, 16), (2, 2))):
+        o = B.ws_options.from_buffer_copy(opts)
+        o.tile_w, o.tile_h, o.bin_x, o.bin_y = tw, th, bx, by
+        rf = Renderer([cam], o)
+        mf = rf.forward(g, stream)
+        rf._ensure_capacity(int(mf * 1.1) + 4096)
+        for _ in range(3):
+            rf.forward_capacity(g, stream)
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(10)]
+        for a, b in ev:
+            a.record(stream)
+            rf.forward_capacity(g, stream)
+            b.record(stream)
+        torch.cuda.synchronize()
+        if rf.status() != 0:
+            raise B.WsError(rf.status(), B.ws_status_string(rf.status()))
+        if ref is None:
+            ref = rf.images.clone()
+        same = bool(torch.equal(ref.view(torch.int32), rf.images.view(torch.int32)))
+        frames[f"{tw}x{th} bins {bx}x{by}"] = {"pairs": mf, "frame_ms": round(statistics.median(
+            a.elapsed_time(b) for a, b in ev), 4), "images_equal": same}
+        del rf
+    del ref
     return {"n": n, "pairs": m, "visible": n_v, "passes": passes, "preprocess_sort_bytes": total_bytes,
             "preprocess_sort_ms": round(total_ms, 4), "achieved_GBs": round(gbs, 1),
             "hbm_frac": round(gbs / HBM_PEAK_GBS, 4), "copy_1GiB_GBs": round(copy_gbs, 1),
             "frac_of_copy": round(gbs / copy_gbs, 4),
             "kernels_ms_per_frame": {k: round(v["ms_per_frame"], 4) for k, v in kt.items()},
+            "frames": frames,
             "note": "opacity survivors counted as the scale/rotation readers (an upper bound on that term)"}
 
 
@@ -544,7 +572,8 @@ def main():
         "config": {"workload": "1M Gaussians on 20 spheres/planes, bimodal opacity, SH degree 3, one 1920x1080 "
                                "view", "gaussians": 1_000_000, "width": 1920, "height": 1080,
                    "sh_degree": 3, "tile": f"{tune.tile_w}x{tune.tile_h}", "radix_bits": tune.radix_bits,
-                   "tuned_by": "autotuner (tile size x radix width, images checked bit-identical)",
+                   "bins": f"{tune.bin_x}x{tune.bin_y}",
+                   "tuned_by": "autotuner (tile size x radix width x bins, images checked bit-identical)",
                    "pairs": res["m"],
                    "emission": "depth-first, 32-bit tile keys (tile bits sorted per frame)",
                    "frame": "one graph replay (preprocess, device-sized sort and render)"},

@@ -109,7 +109,13 @@ typedef struct ws_options {
                                  name bins (ids laid out like tile ids, over bins of bin_x * tile_w by
                                  bin_y * tile_h pixels), tiles_touched counts bins, ws_sort orders the bin
                                  bits, and ws_expand_bins turns each bin's list into the lists of its tiles
-                                 for ws_render and ws_render_backward.  Images do not change. */
+                                 for ws_render and ws_render_backward.  Images do not change.
+                                 Coverage mask: let b = ceil(log2(ws_total_bins)), at least 1.  If
+                                 b + bin_x * bin_y <= 32, the key's cell word (the high word of a 64-bit
+                                 key, a 32-bit key itself) holds the bin id in bits [0, b) and, above it,
+                                 bit b + row * bin_x + col set for each tile (col, row) of the bin that the
+                                 splat's rectangle meets; the sort must then order bits [0, b) of the cell
+                                 word only (ws_sort on [32, 32 + b), ws_sort32 on [0, b)). */
 } ws_options;
 
 typedef struct ws_gaussians {

@@ -119,6 +119,19 @@ int64_t total_bins_of(const ws_camera* cams, int32_t n_views, const ws_options* 
 
 bool binned(const ws_options* o) { return o->bin_x > 1 || o->bin_y > 1; }
 
+// Kernel options with the position of the bins' coverage mask in the key's
+// cell word: above the ceil(log2(total bins)) bits of the bin id (at least 1),
+// when those bits and one bit per tile of a bin fit in 32.
+ws::KOpts kopts_for(const ws_options* o, const ws_camera* cams, int32_t n_views) {
+    ws::KOpts k = ws::to_kopts(*o);
+    if (!binned(o)) return k;
+    const int64_t bins = total_bins_of(cams, n_views, o);
+    int32_t bits = 1;
+    while ((int64_t(1) << bits) < bins) ++bits;
+    if (bits + k.bin_x * k.bin_y <= 32) k.mask_shift = bits;
+    return k;
+}
+
 ws::GaussPtrs gauss_ptrs(const ws_gaussians* g) {
     ws::GaussPtrs p;
     p.means = g->means;
@@ -293,7 +306,7 @@ ws_status ws_preprocess(const ws_gaussians* g, const ws_camera* cams, const ws_c
     if ((s = check_ws(ws, ws_bytes, ws::preprocess_workspace(g->n, n_views, capacity, opt->flags))) != WS_OK) return s;
     if (reinterpret_cast<uintptr_t>(splats) % 16 != 0)
         return fail(WS_ERR_INVALID_ARGUMENT, "splats must be 16-byte aligned");
-    const hipError_t e = ws::launch_preprocess(gauss_ptrs(g), d_cams, n_views, ws::to_kopts(*opt), splats,
+    const hipError_t e = ws::launch_preprocess(gauss_ptrs(g), d_cams, n_views, kopts_for(opt, cams, n_views), splats,
                                                tiles_touched, keys, values, capacity, d_num_pairs, d_status, ws,
                                                static_cast<hipStream_t>(stream));
     return hip_status(e, "ws_preprocess launch");
@@ -365,7 +378,7 @@ ws_status ws_render(const ws_splat* splats, int64_t n, const ws_camera* cams, co
     if (keys && !d_num_pairs) return fail(WS_ERR_INVALID_ARGUMENT, "d_num_pairs is NULL");
     const int64_t tiles = total_tiles_of(cams, n_views, opt->tile_w, opt->tile_h);
     if (tiles > (int64_t(1) << 31)) return fail(WS_ERR_UNSUPPORTED, "more than 2^31 tiles");
-    const ws::KOpts ko = ws::to_kopts(*opt);
+    const ws::KOpts ko = kopts_for(opt, cams, n_views);
     if ((s = check_ws(ws, ws_bytes, ws::render_workspace(tiles, ko))) != WS_OK) return s;
     const hipError_t e = ws::launch_render(splats, n, d_cams, n_views, tiles, ko, keys, values, capacity, d_num_pairs,
                                            d_status, tile_ranges, images, ws, static_cast<hipStream_t>(stream));
@@ -397,7 +410,7 @@ ws_status ws_expand_bins(const ws_splat* splats, int64_t n, const ws_camera* cam
     const int64_t bins = total_bins_of(cams, n_views, opt);
     if (bins * per_bin > (int64_t(1) << 31) - 8) return fail(WS_ERR_UNSUPPORTED, "too many tiles");
     if ((s = check_ws(ws, ws_bytes, ws::expand_workspace(bins))) != WS_OK) return s;
-    const hipError_t e = ws::launch_expand(splats, n, d_cams, n_views, bins, ws::to_kopts(*opt), keys, values,
+    const hipError_t e = ws::launch_expand(splats, n, d_cams, n_views, bins, kopts_for(opt, cams, n_views), keys, values,
                                            capacity, d_num_pairs, d_status, tile_values, tile_ranges, ws,
                                            static_cast<hipStream_t>(stream));
     return hip_status(e, "ws_expand_bins launch");

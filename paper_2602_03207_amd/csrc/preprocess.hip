@@ -17,7 +17,9 @@
 //               running maximum, and writes key = (tile << 32) | depth bits
 //               (the tile alone as a 32-bit key with WS_FLAG_KEYS32, where the
 //               depth order is the emission order), value = Gaussian id with
-//               coalesced stores.  Work per
+//               coalesced stores.  With bins of tiles as key cells the bits
+//               above the bin id carry, where they fit, the mask of the bin's
+//               tiles that the splat's rectangle meets (bit row * bin_x + col).  Work per
 //               workgroup is fixed, whatever the size of the splats.
 // Both prefix sums are those of scan.h (one pass with look-back up to 1024
 // workgroups, else the wait-free three-level scan).  k_preprocess zeroes the
@@ -170,9 +172,31 @@ struct EmitArgs {
     int64_t capacity;
     int32_t tile_w, tile_h;        // pixel size of a key cell (tile or bin)
     uint32_t tw_shift, th_shift;  // log2 of the cell size
+    uint32_t tws, ths;            // log2 of the tile size (bins only)
+    uint32_t bxs, bys;            // log2 of the bin size in tiles (bins only)
+    int32_t mask_shift;           // bit of the cell word where the coverage mask starts, -1: no mask
     void* keys;                   // uint64_t, or uint32_t cell ids (K32)
     uint32_t* values;
 };
+
+// The tiles of bin (cx, cy) that a splat's pixel rectangle (x0 | x1 << 16,
+// y0 | y1 << 16) meets, as bits row * bin_x + col of the bin's tiles.  The bin
+// is one the rectangle meets, so the column and row spans are not empty; the
+// rectangle is clipped to the image, so no bit names a tile past its edge.
+__device__ __forceinline__ uint32_t bin_coverage(uint32_t prx, uint32_t pry, uint32_t cx, uint32_t cy,
+                                                 const EmitArgs& a) {
+    const uint32_t t0x = (prx & 0xffffu) >> a.tws, t1x = (prx >> 16) >> a.tws;
+    const uint32_t t0y = (pry & 0xffffu) >> a.ths, t1y = (pry >> 16) >> a.ths;
+    const uint32_t bx0 = cx << a.bxs, by0 = cy << a.bys;  // the bin's first tile
+    const uint32_t bx1 = bx0 + (1u << a.bxs) - 1u, by1 = by0 + (1u << a.bys) - 1u;
+    if (t1x < bx0 || t0x > bx1 || t1y < by0 || t0y > by1) return 0u;  // (not reached)
+    const uint32_t c0 = max(t0x, bx0) - bx0, c1 = min(t1x, bx1) - bx0;  // <= 7
+    const uint32_t r0 = max(t0y, by0) - by0, r1 = min(t1y, by1) - by0;  // <= 7
+    const uint32_t row = (0xffffffffu >> (31u - c1)) & (0xffffffffu << c0);  // bits c0..c1
+    uint32_t m = 0;
+    for (uint32_t r = r0; r <= r1; ++r) m |= row << (r << a.bxs);
+    return m;
+}
 
 // Inclusive prefix maximum over the 64 lanes of a wave (values >= 0), by the
 // DPP steps of wave_inclusive_scan.
@@ -186,7 +210,7 @@ __device__ __forceinline__ uint32_t wave_inclusive_max(uint32_t v) {
     return v;
 }
 
-template <bool K32>
+template <bool K32, bool MASK>
 __global__ __launch_bounds__(kEmitThreads) void k_emit(EmitArgs a) {
     __shared__ uint32_t s_owner[kEmitPairs];
     __shared__ uint32_t s_start[kEmitSlots];
@@ -197,6 +221,7 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(EmitArgs a) {
     __shared__ uint32_t s_tbase[kEmitSlots];
     __shared__ uint32_t s_tilesx[kEmitSlots];
     __shared__ uint32_t s_magic[kEmitSlots];  // floor((2^32 - 1) / tile-rectangle width)
+    __shared__ uint32_t s_prx[MASK ? kEmitSlots : 1], s_pry[MASK ? kEmitSlots : 1];  // pixel rectangle
     __shared__ uint32_t s_scan[kEmitThreads / kWave + 1];
     __shared__ int64_t s_hi;
     __shared__ uint32_t s_vtoff[kEmitThreads], s_vtx[kEmitThreads];
@@ -271,6 +296,10 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(EmitArgs a) {
             s_tbase[slot] = tbase;
             s_tilesx[slot] = tilesx;
             s_magic[slot] = 0xffffffffu / (tx1 - tx0 + 1);
+            if (MASK) {
+                s_prx[slot] = r01;
+                s_pry[slot] = r23;
+            }
             if (slot > 0) s_owner[int64_t(start) - p0] = uint32_t(slot);
         }
         if (threadIdx.x == 0) s_hi = next < nvis ? min(p1, int64_t(next_start)) : p1;
@@ -327,8 +356,10 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(EmitArgs a) {
                     col -= w;
                 }
                 const uint64_t tile = uint64_t(s_tbase[s]) + uint64_t(ty0 + row) * s_tilesx[s] + (tx0 + col);
-                if (K32) static_cast<uint32_t*>(a.keys)[p] = uint32_t(tile);
-                else static_cast<uint64_t*>(a.keys)[p] = (tile << 32) | s_depth[s];
+                uint32_t word = uint32_t(tile);  // the cell id (< 2^32; below 2^mask_shift with a mask)
+                if (MASK) word |= bin_coverage(s_prx[s], s_pry[s], tx0 + col, ty0 + row, a) << a.mask_shift;
+                if (K32) static_cast<uint32_t*>(a.keys)[p] = word;
+                else static_cast<uint64_t*>(a.keys)[p] = (uint64_t(word) << 32) | s_depth[s];
                 a.values[p] = s_gid[s];
             }
         }
@@ -404,12 +435,19 @@ hipError_t launch_preprocess(const GaussPtrs& g, const ws_camera* d_cams, int32_
     ea.tile_h = o.cell_h();
     ea.tw_shift = uint32_t(__builtin_ctz(uint32_t(o.cell_w())));
     ea.th_shift = uint32_t(__builtin_ctz(uint32_t(o.cell_h())));
+    ea.tws = uint32_t(__builtin_ctz(uint32_t(o.tile_w)));
+    ea.ths = uint32_t(__builtin_ctz(uint32_t(o.tile_h)));
+    ea.bxs = uint32_t(__builtin_ctz(uint32_t(o.bin_x)));
+    ea.bys = uint32_t(__builtin_ctz(uint32_t(o.bin_y)));
+    ea.mask_shift = o.mask_shift;
     ea.keys = keys;
     ea.values = values;
-    if (o.flags & WS_FLAG_KEYS32)
-        hipLaunchKernelGGL(k_emit<true>, dim3(uint32_t(pw.emit_blocks)), dim3(kEmitThreads), 0, stream, ea);
-    else
-        hipLaunchKernelGGL(k_emit<false>, dim3(uint32_t(pw.emit_blocks)), dim3(kEmitThreads), 0, stream, ea);
+    const dim3 eg(uint32_t(pw.emit_blocks)), eb(kEmitThreads);
+    const bool k32 = (o.flags & WS_FLAG_KEYS32) != 0, mask = o.mask_shift >= 0;
+    if (k32 && mask) hipLaunchKernelGGL((k_emit<true, true>), eg, eb, 0, stream, ea);
+    else if (k32) hipLaunchKernelGGL((k_emit<true, false>), eg, eb, 0, stream, ea);
+    else if (mask) hipLaunchKernelGGL((k_emit<false, true>), eg, eb, 0, stream, ea);
+    else hipLaunchKernelGGL((k_emit<false, false>), eg, eb, 0, stream, ea);
     timing_end(WS_KERNEL_SCAN_EMIT, stream);
     return hipGetLastError();
 }

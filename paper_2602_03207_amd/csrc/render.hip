@@ -27,8 +27,10 @@
 // k_expand                    (bins larger than one tile) one workgroup per
 //                             tile: streams its bin's run of pairs, keeps, in
 //                             order, the ids whose pixel rectangle meets the
-//                             tile, and writes them to a slot of the bin's
-//                             pair count reserved for that tile.
+//                             tile (the bin-coverage bit of the key where the
+//                             key carries the mask, else the splat's
+//                             rectangle), and writes them to a slot of the
+//                             bin's pair count reserved for that tile.
 // The per-(pixel, splat) arithmetic lives in composite.h and is shared with
 // the backward pass, so both take exactly the same skip / stop decisions.
 #include "composite.h"
@@ -62,17 +64,22 @@ __device__ __forceinline__ uint32_t cell_of(uint32_t k) { return k; }
 template <typename K>
 __global__ __launch_bounds__(kRangeThreads) void k_ranges(const K* __restrict__ keys, int64_t cap,
                                                           const int64_t* d_n, const int32_t* d_status,
-                                                          uint32_t* __restrict__ ranges, int64_t total_tiles) {
+                                                          uint32_t* __restrict__ ranges, int64_t total_tiles,
+                                                          uint32_t cell_mask) {
     if (*d_status != 0) return;
     int64_t m = *d_n;
     m = m < cap ? m : cap;
     const uint32_t T = uint32_t(total_tiles);
+    // only the cell word of each key is read: the key itself, or the high
+    // word of a 64-bit key, as 32-bit loads (the same code for both widths)
+    constexpr int64_t S = int64_t(sizeof(K) / 4);
+    const uint32_t* __restrict__ cw = reinterpret_cast<const uint32_t*>(keys) + (S - 1);
     if (m == 0) {
         fill_empty(ranges, 0, T, 0, blockIdx.x * kRangeThreads + threadIdx.x, gridDim.x * kRangeThreads);
         return;
     }
     if (blockIdx.x == 0) {  // tiles before the first run
-        const uint32_t t0 = cell_of(keys[0]);
+        const uint32_t t0 = cw[0] & cell_mask;
         fill_empty(ranges, 0, t0 < T ? t0 : T, 0, threadIdx.x, kRangeThreads);
     }
     const uint32_t lane = lane_id();
@@ -85,9 +92,18 @@ __global__ __launch_bounds__(kRangeThreads) void k_ranges(const K* __restrict__ 
 #pragma unroll
         for (int j = 0; j < kRangeItems; ++j) {
             const int64_t i = base + j * kRangeThreads + threadIdx.x;
-            t[j] = i < m ? cell_of(keys[i]) : 0xffffffffu;
+            t[j] = i < m ? cw[i * S] : 0xffffffffu;
             const int64_t ie = i + off;
-            edge[j] = (off != 0 && ie >= 0 && ie < m) ? cell_of(keys[ie]) : 0xffffffffu;
+            edge[j] = (off != 0 && ie >= 0 && ie < m) ? cw[ie * S] : 0xffffffffu;
+        }
+        // the coverage bits are stripped only once every load has been issued
+        // (masking inside the loads' conditions made the compiler wait after each)
+#pragma unroll
+        for (int j = 0; j < kRangeItems; ++j) {
+            const int64_t i = base + j * kRangeThreads + threadIdx.x;
+            if (i < m) t[j] &= cell_mask;
+            const int64_t ie = i + off;
+            if (off != 0 && ie >= 0 && ie < m) edge[j] &= cell_mask;
         }
 #pragma unroll
         for (int j = 0; j < kRangeItems; ++j) {
@@ -149,6 +165,8 @@ struct ExpandArgs {
     uint32_t tws, ths;  // log2 of the tile size
     uint32_t bxs, bys;  // log2 of the bin size in tiles
     int64_t blocks;     // bins << (bxs + bys)
+    const void* keys;   // the bin-sorted keys (read where they carry the coverage mask)
+    int32_t mask_shift;
     const uint32_t* values;
     const uint32_t* bin_ranges;
     const int32_t* d_status;
@@ -156,6 +174,7 @@ struct ExpandArgs {
     uint32_t* tile_ranges;
 };
 
+template <typename K, bool MASK>
 __global__ __launch_bounds__(kExpandThreads) void k_expand(ExpandArgs a) {
     __shared__ uint32_t s_cnt[2][kExpandItems][kExpandWaves];
     if (*a.d_status != 0) return;
@@ -194,17 +213,20 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand(ExpandArgs a) {
     uint32_t count = 0;
     int buf = 0;
     for (uint32_t c = bs; c < be; c += kExpandThreads * kExpandItems) {
-        uint32_t id[kExpandItems];
+        uint32_t id[kExpandItems], cov[kExpandItems];
         bool keep[kExpandItems];
 #pragma unroll
         for (int j = 0; j < kExpandItems; ++j) {
             const uint32_t idx = c + uint32_t(j * kExpandThreads) + threadIdx.x;
             id[j] = idx < be ? a.values[idx] : 0xffffffffu;
+            if (MASK) cov[j] = idx < be ? cell_of(static_cast<const K*>(a.keys)[idx]) >> a.mask_shift : 0u;
         }
 #pragma unroll
         for (int j = 0; j < kExpandItems; ++j) {
             keep[j] = false;
-            if (id[j] < uint64_t(a.n)) {
+            if (MASK) {
+                keep[j] = id[j] < uint64_t(a.n) && ((cov[j] >> k) & 1u) != 0u;
+            } else if (id[j] < uint64_t(a.n)) {
                 // words 10 and 11 of the record: x0 | x1 << 16, y0 | y1 << 16
                 const uint2 r = reinterpret_cast<const uint2*>(vs + id[j])[5];
                 const int32_t tx0 = int32_t((r.x & 0xffffu) >> a.tws), tx1 = int32_t((r.x >> 16) >> a.tws);
@@ -429,10 +451,12 @@ void launch_ranges(const KOpts& o, const void* keys, int64_t capacity, const int
                    const int32_t* d_status, uint32_t* ranges, int64_t cells, uint32_t grid, hipStream_t stream) {
     if (o.flags & WS_FLAG_KEYS32)
         hipLaunchKernelGGL(k_ranges<uint32_t>, dim3(grid), dim3(kRangeThreads), 0, stream,
-                           static_cast<const uint32_t*>(keys), capacity, d_num_pairs, d_status, ranges, cells);
+                           static_cast<const uint32_t*>(keys), capacity, d_num_pairs, d_status, ranges, cells,
+                           o.cell_mask());
     else
         hipLaunchKernelGGL(k_ranges<uint64_t>, dim3(grid), dim3(kRangeThreads), 0, stream,
-                           static_cast<const uint64_t*>(keys), capacity, d_num_pairs, d_status, ranges, cells);
+                           static_cast<const uint64_t*>(keys), capacity, d_num_pairs, d_status, ranges, cells,
+                           o.cell_mask());
 }
 
 template <int TW, int TH>
@@ -471,13 +495,20 @@ hipError_t launch_expand(const ws_splat* splats, int64_t n, const ws_camera* d_c
     ea.bxs = uint32_t(__builtin_ctz(uint32_t(o.bin_x)));
     ea.bys = uint32_t(__builtin_ctz(uint32_t(o.bin_y)));
     ea.blocks = total_bins << (ea.bxs + ea.bys);
+    ea.keys = keys;
+    ea.mask_shift = o.mask_shift;
     ea.values = values;
     ea.bin_ranges = bin_ranges;
     ea.d_status = d_status;
     ea.tile_values = tile_values;
     ea.tile_ranges = tile_ranges;
     const uint32_t grid = uint32_t((ea.blocks + 7) / 8 * 8);
-    if (grid > 0) hipLaunchKernelGGL(k_expand, dim3(grid), dim3(kExpandThreads), 0, stream, ea);
+    if (grid > 0) {
+        const bool k32 = (o.flags & WS_FLAG_KEYS32) != 0, mask = o.mask_shift >= 0;
+        if (mask && k32) hipLaunchKernelGGL((k_expand<uint32_t, true>), dim3(grid), dim3(kExpandThreads), 0, stream, ea);
+        else if (mask) hipLaunchKernelGGL((k_expand<uint64_t, true>), dim3(grid), dim3(kExpandThreads), 0, stream, ea);
+        else hipLaunchKernelGGL((k_expand<uint32_t, false>), dim3(grid), dim3(kExpandThreads), 0, stream, ea);
+    }
     timing_end(WS_KERNEL_RANGES, stream);
     return hipGetLastError();
 }

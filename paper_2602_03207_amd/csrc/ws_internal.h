@@ -185,9 +185,17 @@ struct KOpts {
     float near_z, lowpass, clamp_fov, alpha_min, alpha_max, t_min;
     float bg[3];
     int32_t bin_x, bin_y;  // tiles per key cell (1, 2, 4 or 8)
+    // Bins only: the bit of the key's cell word (the high word of a 64-bit
+    // key, a 32-bit key itself) where the mask of the bin's tiles that the
+    // splat covers starts (= the bits of the cell id); -1 without a mask.
+    int32_t mask_shift;
     // pixel size of the cells that pair keys name: a tile, or a bin of tiles
     __host__ __device__ int32_t cell_w() const { return tile_w * bin_x; }
     __host__ __device__ int32_t cell_h() const { return tile_h * bin_y; }
+    // the cell id bits of a key's cell word
+    __host__ __device__ uint32_t cell_mask() const {
+        return mask_shift < 0 ? 0xffffffffu : (1u << mask_shift) - 1u;
+    }
 };
 
 inline KOpts to_kopts(const ws_options& o) {
@@ -195,6 +203,7 @@ inline KOpts to_kopts(const ws_options& o) {
     k.tile_w = o.tile_w; k.tile_h = o.tile_h; k.sh_degree = o.sh_degree; k.flags = o.flags;
     k.bin_x = o.bin_x > 1 ? o.bin_x : 1;
     k.bin_y = o.bin_y > 1 ? o.bin_y : 1;
+    k.mask_shift = -1;  // set by the caller that knows the cameras (bins only)
     k.near_z = o.near_z; k.lowpass = o.lowpass; k.clamp_fov = o.clamp_fov;
     k.alpha_min = o.alpha_min; k.alpha_max = o.alpha_max; k.t_min = o.t_min;
     k.bg[0] = o.bg[0]; k.bg[1] = o.bg[1]; k.bg[2] = o.bg[2];

@@ -50,14 +50,21 @@ def test_autotune_picks_a_candidate_and_caches_it(tmp_path):
     cams = _views()[:3]
     base = gpu_options(flags=B.WS_FLAG_ORDERED_RENDER)
     cache = str(tmp_path / "tune.json")
-    tiles, radix = ((16, 16), (8, 8)), (6, 8)
-    res = autotune(g, cams, base, tiles=tiles, radix_bits=radix, reps=2, cache_path=cache)
+    tiles, radix, bins = ((16, 16), (8, 8)), (6, 8), ((1, 1), (2, 2))
+    # every candidate's images must equal the first's (the tuner raises otherwise), bins included
+    res = autotune(g, cams, base, tiles=tiles, radix_bits=radix, reps=2, cache_path=cache, bins=bins)
     assert (res.tile_w, res.tile_h) in tiles and res.radix_bits in radix and not res.cached
-    assert len(res.table) == 4 and res.ms == min(row[3] for row in res.table)
+    assert (res.bin_x, res.bin_y) in bins
+    assert len(res.table) == 8 and res.ms == min(row[5] for row in res.table)
     stored = json.load(open(cache))
     assert res.signature in stored
-    again = autotune(g, cams, base, tiles=tiles, radix_bits=radix, reps=2, cache_path=cache)
-    assert again.cached and (again.tile_w, again.tile_h, again.radix_bits) == (res.tile_w, res.tile_h, res.radix_bits)
+    again = autotune(g, cams, base, tiles=tiles, radix_bits=radix, reps=2, cache_path=cache, bins=bins)
+    assert again.cached and (again.tile_w, again.tile_h, again.radix_bits, again.bin_x, again.bin_y) == \
+        (res.tile_w, res.tile_h, res.radix_bits, res.bin_x, res.bin_y)
     o = res.apply(base)
-    assert (o.tile_w, o.tile_h, o.radix_bits) == (res.tile_w, res.tile_h, res.radix_bits)
+    assert (o.tile_w, o.tile_h, o.radix_bits, o.bin_x, o.bin_y) == \
+        (res.tile_w, res.tile_h, res.radix_bits, res.bin_x, res.bin_y)
     assert o.flags == base.flags
+    # a search without bins is cached under another signature
+    plain = autotune(g, cams, base, tiles=tiles, radix_bits=radix, reps=2, cache_path=cache)
+    assert not plain.cached and (plain.bin_x, plain.bin_y) == (1, 1) and len(plain.table) == 4

@@ -3,9 +3,12 @@ ws_expand_bins rebuilds every tile's list from its bin's list (Sec. 3.2: a tile 
 footprint meets it, in depth order).
 
 The pins: the bin pairs equal the oracle's pairs for cells of the bin's pixel size (the oracle's emission
-rule at another cell size), every expanded tile list equals, id for id, that tile's run of pairs in the
-path whose keys name tiles (the oracle's tile-sorted pairs for a single view), and images are identical to
-the bit."""
+rule at another cell size); where the key carries the mask of the bin's tiles that a splat covers, that
+mask equals the tiles the oracle lists the splat in; every expanded tile list equals, id for id, that
+tile's run of pairs in the path whose keys name tiles (the oracle's tile-sorted pairs for a single view),
+and images are identical to the bit."""
+import math
+
 import numpy as np
 import pytest
 
@@ -40,12 +43,44 @@ def _multiview():
     return scene, cams
 
 
-@pytest.mark.parametrize("depth_first", [False, True])
+def _mask_shift(total_bins, per_bin):
+    """Where the bins' coverage mask starts in a key's cell word: above the bin id's bits, if both fit in
+    32 bits (-1: the keys carry no mask)."""
+    bits = max(1, math.ceil(math.log2(max(total_bins, 2))))
+    return bits if bits + per_bin <= 32 else -1
+
+
+def _split_words(words, shift):
+    words = words.astype(np.uint64)
+    if shift < 0:
+        return words, None
+    return words & np.uint64((1 << shift) - 1), words >> np.uint64(shift)
+
+
+def _expected_masks(scene, cam, tile, bins):
+    """(Gaussian id, bin) -> mask of the bin's tiles (bit row * bin_x + col) in the oracle's tile-level pairs."""
+    ro = oracle_options(tile_w=tile[0], tile_h=tile[1])
+    kt, vt = oracle.emit(scene, cam, ro)
+    ntx, _ = oracle.tiles_xy(cam, ro)
+    t = (kt >> np.uint64(32)).astype(np.int64)
+    tx, ty = t % ntx, t // ntx
+    bx, by = tx // bins[0], ty // bins[1]
+    nbx = -(-ntx // bins[0])
+    bid = by * nbx + bx
+    bit = (ty - by * bins[1]) * bins[0] + (tx - bx * bins[0])
+    out = {}
+    for gid, b, bt in zip(vt.tolist(), bid.tolist(), bit.tolist()):
+        out[(gid, b)] = out.get((gid, b), 0) | (1 << bt)
+    return out
+
+
+@pytest.mark.parametrize("mode", ["gaussian_order", "depth_first", "keys32"])
 @pytest.mark.parametrize("tile,bins", [((16, 16), (2, 2)), ((32, 16), (4, 4)), ((8, 8), (8, 4)), ((16, 8), (1, 8))])
-def test_bin_pairs_match_the_oracle_at_the_bin_size(tile, bins, depth_first):
+def test_bin_pairs_match_the_oracle_at_the_bin_size(tile, bins, mode):
     from paper_2602_03207_amd import binding as B
     scene, cam = scenegen.c1()
-    flags = B.WS_FLAG_DEPTH_FIRST if depth_first else 0
+    flags = {"gaussian_order": 0, "depth_first": B.WS_FLAG_DEPTH_FIRST,
+             "keys32": B.WS_FLAG_DEPTH_FIRST | B.WS_FLAG_KEYS32}[mode]
     r = _renderer(scene, [cam], tile_w=tile[0], tile_h=tile[1], bin_x=bins[0], bin_y=bins[1], flags=flags)
     cell = oracle_options(tile_w=tile[0] * bins[0], tile_h=tile[1] * bins[1])
     keys, vals = oracle.emit(scene, cam, cell)
@@ -53,11 +88,32 @@ def test_bin_pairs_match_the_oracle_at_the_bin_size(tile, bins, depth_first):
     assert m == keys.size
     tt = r.tiles_touched.cpu().numpy().astype(np.int64)
     assert tt.sum() == m
+    shift = _mask_shift(r.total_bins, bins[0] * bins[1])
+    assert (shift >= 0) == (bins[0] * bins[1] <= 16)  # every bin size here but 8 x 4 carries the mask
+
+    def cells_and_masks(t):
+        a = t[:m].cpu().numpy()
+        if mode == "keys32":
+            return _split_words(a.view(np.uint32), shift), None
+        k = a.view(np.uint64)
+        return _split_words((k >> np.uint64(32)).astype(np.uint32), shift), k & np.uint64(0xFFFFFFFF)
+
     sk, sv = oracle.stable_sort(keys, vals)
-    assert np.array_equal(r.keys_b[:m].cpu().numpy().view(np.uint64), sk)
-    assert np.array_equal(r.vals_b[:m].cpu().numpy().view(np.uint32), sv)
-    if not depth_first:
-        assert np.array_equal(r.keys_a[:m].cpu().numpy().view(np.uint64), keys)
+    (cells, masks), depth = cells_and_masks(r.keys_b)
+    gv = r.vals_b[:m].cpu().numpy().view(np.uint32)
+    assert np.array_equal(gv, sv)
+    assert np.array_equal(cells, sk >> np.uint64(32))
+    if depth is not None:
+        assert np.array_equal(depth, sk & np.uint64(0xFFFFFFFF))
+    if masks is not None:
+        # every pair's mask holds exactly the bin's tiles that the oracle lists the splat in
+        want = _expected_masks(scene, cam, tile, bins)
+        assert len(want) == m
+        got = {(int(v), int(c)): int(mk) for v, c, mk in zip(gv, cells, masks)}
+        assert got == want
+    if mode == "gaussian_order":
+        (cells_a, _), depth_a = cells_and_masks(r.keys_a)
+        assert np.array_equal((cells_a << np.uint64(32)) | depth_a, keys)
         assert np.array_equal(r.vals_a[:m].cpu().numpy().view(np.uint32), vals)
 
 
