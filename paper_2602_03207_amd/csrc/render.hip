@@ -24,13 +24,16 @@
 //                             longest tiles start first and no workgroup
 //                             waits for another.  The order in which tiles are
 //                             processed does not change any pixel.
-// k_expand                    (bins larger than one tile) one workgroup per
-//                             tile: streams its bin's run of pairs, keeps, in
-//                             order, the ids whose pixel rectangle meets the
-//                             tile (the bin-coverage bit of the key where the
-//                             key carries the mask, else the splat's
-//                             rectangle), and writes them to a slot of the
-//                             bin's pair count reserved for that tile.
+// k_expand_bin<K>             (bins larger than one tile, keys carrying the
+//                             coverage mask) one workgroup per bin, one wave
+//                             per tile of the bin: the waves stream the bin's
+//                             run of pairs together and each keeps, in order,
+//                             the ids whose coverage bit names its tile,
+//                             writing them to a slot of the bin's pair count
+//                             reserved for that tile.
+// k_expand                    (larger bins, keys without the mask) the same
+//                             lists, one workgroup per tile, deciding from
+//                             each splat's pixel rectangle.
 // The per-(pixel, splat) arithmetic lives in composite.h and is shared with
 // the backward pass, so both take exactly the same skip / stop decisions.
 #include "composite.h"
@@ -174,7 +177,6 @@ struct ExpandArgs {
     uint32_t* tile_ranges;
 };
 
-template <typename K, bool MASK>
 __global__ __launch_bounds__(kExpandThreads) void k_expand(ExpandArgs a) {
     __shared__ uint32_t s_cnt[2][kExpandItems][kExpandWaves];
     if (*a.d_status != 0) return;
@@ -213,20 +215,17 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand(ExpandArgs a) {
     uint32_t count = 0;
     int buf = 0;
     for (uint32_t c = bs; c < be; c += kExpandThreads * kExpandItems) {
-        uint32_t id[kExpandItems], cov[kExpandItems];
+        uint32_t id[kExpandItems];
         bool keep[kExpandItems];
 #pragma unroll
         for (int j = 0; j < kExpandItems; ++j) {
             const uint32_t idx = c + uint32_t(j * kExpandThreads) + threadIdx.x;
             id[j] = idx < be ? a.values[idx] : 0xffffffffu;
-            if (MASK) cov[j] = idx < be ? cell_of(static_cast<const K*>(a.keys)[idx]) >> a.mask_shift : 0u;
         }
 #pragma unroll
         for (int j = 0; j < kExpandItems; ++j) {
             keep[j] = false;
-            if (MASK) {
-                keep[j] = id[j] < uint64_t(a.n) && ((cov[j] >> k) & 1u) != 0u;
-            } else if (id[j] < uint64_t(a.n)) {
+            if (id[j] < uint64_t(a.n)) {
                 // words 10 and 11 of the record: x0 | x1 << 16, y0 | y1 << 16
                 const uint2 r = reinterpret_cast<const uint2*>(vs + id[j])[5];
                 const int32_t tx0 = int32_t((r.x & 0xffffu) >> a.tws), tx1 = int32_t((r.x >> 16) >> a.tws);
@@ -259,6 +258,69 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand(ExpandArgs a) {
         buf ^= 1;  // the next round writes the other half: one barrier per round suffices
     }
     if (threadIdx.x == 0) {
+        a.tile_ranges[2 * tile] = base;
+        a.tile_ranges[2 * tile + 1] = base + count;
+    }
+}
+
+// One workgroup per bin of a view (the bin ids of all views in order), wave w
+// handling tile w of the bin (row-major inside the bin); the tile's slot and
+// list are those of k_expand.  Each wave reads the bin's keys and ids (the
+// waves of a workgroup read the same addresses, so the bin's run comes from
+// HBM about once), keeps the pairs whose coverage bit w is set and compacts
+// them in order with a ballot per item: no LDS and no barrier.  Waves of tiles
+// past the view's right or bottom edge leave at once.
+constexpr int kExpandBinItems = 8;
+
+template <typename K>
+__global__ __launch_bounds__(1024) void k_expand_bin(ExpandArgs a, int64_t bins) {
+    if (*a.d_status != 0) return;
+    const int64_t bin = blockIdx.x;
+    if (bin >= bins) return;
+    const uint32_t k = threadIdx.x / kWave;  // tile of the bin
+    const uint32_t kl = a.bxs + a.bys;
+    int64_t boff = 0, toff = 0;
+    int32_t v = 0, txn = 1, tyn = 1, bxn = 1;
+    for (;; ++v) {
+        txn = ceil_div(a.cams[v].width, a.tile_w);
+        tyn = ceil_div(a.cams[v].height, a.tile_h);
+        bxn = (txn + (1 << a.bxs) - 1) >> a.bxs;
+        const int64_t nb = int64_t(bxn) * ((tyn + (1 << a.bys) - 1) >> a.bys);
+        if (bin < boff + nb || v == a.n_views - 1) break;
+        boff += nb;
+        toff += int64_t(txn) * tyn;
+    }
+    const int64_t lb = bin - boff;
+    const int32_t by = int32_t(lb / bxn), bx = int32_t(lb - int64_t(by) * bxn);
+    const int32_t tx = (bx << a.bxs) + int32_t(k & ((1u << a.bxs) - 1u));
+    const int32_t ty = (by << a.bys) + int32_t(k >> a.bxs);
+    if (tx >= txn || ty >= tyn) return;  // bins on the right / bottom edge hold fewer tiles
+    const int64_t tile = toff + int64_t(ty) * txn + tx;
+    const uint32_t bs = a.bin_ranges[2 * bin], be = a.bin_ranges[2 * bin + 1];
+    const uint32_t base = (bs << kl) + k * (be - bs);
+    const K* keys = static_cast<const K*>(a.keys);
+    const uint32_t lane = lane_id();
+    uint32_t count = 0;
+    for (uint32_t c = bs; c < be; c += kWave * kExpandBinItems) {
+        uint32_t id[kExpandBinItems], cov[kExpandBinItems];
+        // every load of the round in flight before the first use
+#pragma unroll
+        for (int j = 0; j < kExpandBinItems; ++j) {
+            const uint32_t idx = c + uint32_t(j * kWave) + lane;
+            const uint32_t ic = idx < be ? idx : be - 1;
+            id[j] = a.values[ic];
+            cov[j] = cell_of(keys[ic]);
+        }
+#pragma unroll
+        for (int j = 0; j < kExpandBinItems; ++j) {
+            const uint32_t idx = c + uint32_t(j * kWave) + lane;
+            const bool keep = idx < be && id[j] < uint64_t(a.n) && (((cov[j] >> a.mask_shift) >> k) & 1u) != 0u;
+            const uint64_t m = __builtin_amdgcn_ballot_w64(keep);
+            if (keep) a.tile_values[base + count + lanes_below(m)] = id[j];
+            count += uint32_t(__builtin_popcountll(m));
+        }
+    }
+    if (lane == 0) {
         a.tile_ranges[2 * tile] = base;
         a.tile_ranges[2 * tile + 1] = base + count;
     }
@@ -503,11 +565,19 @@ hipError_t launch_expand(const ws_splat* splats, int64_t n, const ws_camera* d_c
     ea.tile_values = tile_values;
     ea.tile_ranges = tile_ranges;
     const uint32_t grid = uint32_t((ea.blocks + 7) / 8 * 8);
-    if (grid > 0) {
-        const bool k32 = (o.flags & WS_FLAG_KEYS32) != 0, mask = o.mask_shift >= 0;
-        if (mask && k32) hipLaunchKernelGGL((k_expand<uint32_t, true>), dim3(grid), dim3(kExpandThreads), 0, stream, ea);
-        else if (mask) hipLaunchKernelGGL((k_expand<uint64_t, true>), dim3(grid), dim3(kExpandThreads), 0, stream, ea);
-        else hipLaunchKernelGGL((k_expand<uint32_t, false>), dim3(grid), dim3(kExpandThreads), 0, stream, ea);
+    const bool k32 = (o.flags & WS_FLAG_KEYS32) != 0;
+    if (o.mask_shift >= 0) {  // one workgroup per bin, one wave per tile of the bin (at most 16 tiles)
+        const uint32_t threads = uint32_t(kWave << (ea.bxs + ea.bys));
+        if (total_bins > 0) {
+            if (k32)
+                hipLaunchKernelGGL(k_expand_bin<uint32_t>, dim3(uint32_t(total_bins)), dim3(threads), 0, stream, ea,
+                                   total_bins);
+            else
+                hipLaunchKernelGGL(k_expand_bin<uint64_t>, dim3(uint32_t(total_bins)), dim3(threads), 0, stream, ea,
+                                   total_bins);
+        }
+    } else if (grid > 0) {
+        hipLaunchKernelGGL(k_expand, dim3(grid), dim3(kExpandThreads), 0, stream, ea);
     }
     timing_end(WS_KERNEL_RANGES, stream);
     return hipGetLastError();
