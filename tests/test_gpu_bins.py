@@ -165,7 +165,9 @@ def test_binned_ordered_render_and_graph_replay_equal_plain():
     from paper_2602_03207_amd.pipeline import GaussianTensors
     scene, cams = _multiview()
     base = _renderer(scene, cams, tile_w=16, tile_h=16)
-    for flags in (B.WS_FLAG_DEPTH_FIRST, B.WS_FLAG_DEPTH_FIRST | B.WS_FLAG_ORDERED_RENDER):
+    k32 = B.WS_FLAG_DEPTH_FIRST | B.WS_FLAG_KEYS32
+    for flags in (B.WS_FLAG_DEPTH_FIRST, B.WS_FLAG_DEPTH_FIRST | B.WS_FLAG_ORDERED_RENDER, k32,
+                  k32 | B.WS_FLAG_ORDERED_RENDER):
         opts = gpu_options(sh_degree=scene.sh_degree, tile_w=16, tile_h=16, bin_x=4, bin_y=2, flags=flags)
         bf = BatchedForward(cams, opts, GaussianTensors.from_scene(scene))
         for _ in range(3):

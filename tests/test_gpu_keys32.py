@@ -165,3 +165,21 @@ def test_keys32_with_bins(tile, bins):
     for (a0, a1), (b0, b1) in zip(rp, rb):
         assert np.array_equal(vp[a0:a1], vb[b0:b1])
     assert np.array_equal(plain.images.cpu().numpy().view(np.uint32), binned.images.cpu().numpy().view(np.uint32))
+
+
+@pytest.mark.parametrize("n", [5000, 1_500_000])  # look-back and wait-free schedules
+def test_sort32_respects_status_word(n):
+    import torch
+    from paper_2602_03207_amd import binding as B
+    kin = torch.arange(n, 0, -1, dtype=torch.int32, device="cuda")
+    vin = torch.arange(n, dtype=torch.int32, device="cuda")
+    kout = torch.full((n,), -1, dtype=torch.int32, device="cuda")
+    vout = torch.full((n,), -1, dtype=torch.int32, device="cuda")
+    d_status = torch.tensor([B.WS_ERR_CAPACITY], dtype=torch.int32, device="cuda")
+    need = B.ws_sort32_workspace_size(n, 0, 32, 0)
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+    print(f"ws_sort32 with a set status word, n={n}", flush=True)
+    B.ws_sort32(kin, vin, kout, vout, n, None, d_status, 0, 32, 0, ws, ws.numel())
+    torch.cuda.synchronize()
+    assert bool((kout == -1).all()) and bool((vout == -1).all())
+    assert int(d_status.item()) == B.WS_ERR_CAPACITY
