@@ -207,8 +207,13 @@ __global__ __launch_bounds__(TW * TH) void k_render_bwd(BwdArgs a) {
             const float dx = s.u - pcx, dy = s.v - pcy;
             const float araw = raw_alpha(s, dx, dy);
             const float alpha = __builtin_amdgcn_fmed3f(araw, 0.f, bk.alpha_max);
-            const bool contrib = j <= last && in_rect(s, pix) && !(alpha < bk.alpha_min);
-            if (__ballot(contrib) == 0) continue;
+            // the lane decisions as lane masks (ballots of the comparisons, as in
+            // the forward), applied with inverse ballots: no per-lane branches
+            const uint64_t cmask = wave_ballot(j <= last) & wave_ballot(in_rect(s, pix)) &
+                                   wave_ballot(!(alpha < bk.alpha_min));
+            if (cmask == 0) continue;
+            const bool contrib = lane_in(cmask);
+            const bool unclamped = lane_in(cmask & wave_ballot(!(araw > bk.alpha_max)));
             const RawConic& q = s_conic[t];
             // 1 - alpha >= 1 - alpha_max > 0; the hardware reciprocal (about
             // 1 ulp) keeps the back-to-front recovery of T well inside the
@@ -219,7 +224,7 @@ __global__ __launch_bounds__(TW * TH) void k_render_bwd(BwdArgs a) {
             const float Dc = dLdC[0] * s.r + dLdC[1] * s.g + dLdC[2] * s.b;  // dL/dC . c_k
             // dL/dalpha = dL/dC . (c_k T_k - R_k / (1 - alpha)); zero through the clamp
             const float dLda = Tk * Dc - inv * SR;
-            const float gp = (contrib && !(araw > bk.alpha_max)) ? dLda * araw : 0.f;  // dL/dpower
+            const float gp = unclamped ? dLda * araw : 0.f;  // dL/dpower
             float gv[kNG];
             gv[0] = -gp * (q.A * dx + q.B * dy);
             gv[1] = -gp * (q.C * dy + q.B * dx);
