@@ -447,6 +447,7 @@ def bench_large(args):
     sort_bytes = 4 * m + 16 * m * passes
     t_pre = kt["preprocess"]["ms_per_frame"] + kt["scan_emit"]["ms_per_frame"]
     t_sort = kt["sort_hist"]["ms_per_frame"] + kt["sort_pass"]["ms_per_frame"]
+    sort_keys_per_s = m / (t_sort * 1e-3)
     total_bytes = pre_bytes + emit_bytes + sort_bytes
     total_ms = t_pre + t_sort
     gbs = total_bytes / (total_ms * 1e-3) / 1e9
@@ -493,8 +494,49 @@ def bench_large(args):
             "hbm_frac": round(gbs / HBM_PEAK_GBS, 4), "copy_1GiB_GBs": round(copy_gbs, 1),
             "frac_of_copy": round(gbs / copy_gbs, 4),
             "kernels_ms_per_frame": {k: round(v["ms_per_frame"], 4) for k, v in kt.items()},
+            "sort_keys_per_s": round(sort_keys_per_s, 1),
+            "sort_workload": f"the frame's sort: {passes} passes over the tile bits of {m} 32-bit keys",
             "frames": frames,
             "note": "opacity survivors counted as the scale/rotation readers (an upper bound on that term)"}
+
+
+def bench_small(args, frames=200):
+    """The 10K-Gaussian 256x256 frame (SH degree 0, 16x16 tiles, 32-bit keys) as one graph replay: frames/s,
+    and the image against the plain path."""
+    import torch
+
+    import scenegen
+    from paper_2602_03207_amd import binding as B
+    from paper_2602_03207_amd.batched import BatchedForward
+    from paper_2602_03207_amd.pipeline import GaussianTensors, Renderer
+
+    scene, cam = scenegen.c1()
+    g = GaussianTensors.from_scene(scene)
+    opts = B.make_options(sh_degree=0, flags=B.WS_FLAG_DEPTH_FIRST | B.WS_FLAG_KEYS32)
+    r = Renderer([cam], opts)
+    m = r.forward(g)
+    bf = BatchedForward([cam], opts, g)
+    bf.capture()
+    for _ in range(10):
+        bf.replay()
+    bf.check()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(frames)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for a, b in ev:
+        a.record(bf.stream)
+        bf.replay()
+        b.record(bf.stream)
+    bf.stream.synchronize()
+    wall = time.perf_counter() - t0
+    bf.check()
+    ms = sorted(a.elapsed_time(b) for a, b in ev)
+    same = bool(torch.equal(bf.r.images.view(torch.int32), r.images.view(torch.int32)))
+    bf.close()
+    return {"workload": "10K Gaussians, SH degree 0, one 256x256 view, 16x16 tiles", "pairs": m,
+            "frames_per_s": round(frames / wall, 1), "frame_ms_median": round(statistics.median(ms), 4),
+            "frame_ms_p99": round(ms[min(len(ms) - 1, int(0.99 * len(ms)))], 4),
+            "images_equal_plain": same}
 
 
 def cpu_baseline(args):
@@ -617,6 +659,8 @@ def main():
     if not args.no_multiview:
         log(f"leg: batched vs plain forward ({args.mv_views} views of uneven resolution)")
         line["multiview_forward"] = bench_multiview(args)
+    log("leg: 10K Gaussians, 256x256")
+    line["small_scene"] = bench_small(args)
     if not args.no_large:
         log("leg: 6M Gaussians, 3840x2160")
         line["large_scene_preprocess_sort"] = bench_large(args)
