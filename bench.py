@@ -12,8 +12,9 @@ Printed (one JSON line): frames/s (`value`), sorted keys/s of the frame's pair
 buffer, per-kernel launch times measured with HIP events, the roofline of the
 dominant kernel, batched (one graph replay for 8 views) vs plain (one view per
 launch) forward+backward views/s on 8 1080p views with an L1 loss, batched vs
-plain forward views/s on 64 views of uneven resolution (tile size and radix
-width from the autotuner, persistent ordered render), the
+plain forward views/s on 64 views of uneven resolution (tile size, radix
+width, bins and render schedule from the autotuner), frames/s of the
+10K-Gaussian 256x256 frame, the
 preprocess+sort HBM fraction of the 6M-Gaussian 4K frame, the paper's own sort
 workload (a stable 32-bit sort of the visible splats' depths), the ablations
 -RADIUS and -CULL of Sec. 4.4 on the same frame, and the fp64 CPU oracle timed
@@ -105,7 +106,7 @@ def bench_frames(args):
     g = GaussianTensors.from_scene(scene)
     stream = torch.cuda.current_stream()
     # tile size, radix width and bins from the autotuner (none changes a pixel; the tuner checks it)
-    tune = autotune(g, [cam], base, reps=3, log=log, bins=TUNE_BINS)
+    tune = autotune(g, [cam], base, reps=3, log=log, bins=TUNE_BINS, ordered=(False, True))
     opts = tune.apply(base)
     log(f"tuned: tile {tune.tile_w}x{tune.tile_h}, radix {tune.radix_bits}, bins {tune.bin_x}x{tune.bin_y}")
 
@@ -365,8 +366,9 @@ def bench_batched(args):
 
 
 def bench_multiview(args):
-    """64 orbit views of uneven resolution: one graph replay (persistent ordered render, autotuned tile
-    size and radix width) vs one view per launch sequence; forward only."""
+    """64 orbit views of uneven resolution: one graph replay (autotuned tile size, radix width, bins and
+    render schedule: one workgroup per tile or persistent ordered workgroups) vs one view per launch
+    sequence; forward only."""
     import torch
 
     import scenegen
@@ -379,7 +381,7 @@ def bench_multiview(args):
     g = GaussianTensors.from_scene(scene)
     del scene
     base = B.make_options(sh_degree=3, flags=B.WS_FLAG_DEPTH_FIRST | B.WS_FLAG_KEYS32 | B.WS_FLAG_ORDERED_RENDER)
-    tune = autotune(g, cams, base, radix_bits=(6, 7, 8), reps=3, log=log, bins=TUNE_BINS)
+    tune = autotune(g, cams, base, radix_bits=(6, 7, 8), reps=3, log=log, bins=TUNE_BINS, ordered=(False, True))
     opts = tune.apply(base)
     bf = BatchedForward(cams, opts, g)
     bf.capture()
@@ -408,7 +410,8 @@ def bench_multiview(args):
     return {"views": len(cams), "resolutions": {f"{w}x{h}": sum(1 for c in cams if (c.width, c.height) == (w, h))
                                                 for w, h in res},
             "pairs": pairs, "tuned": {"tile": f"{tune.tile_w}x{tune.tile_h}", "radix_bits": tune.radix_bits,
-                                      "bins": f"{tune.bin_x}x{tune.bin_y}", "candidates": len(tune.table)},
+                                      "bins": f"{tune.bin_x}x{tune.bin_y}", "ordered_render": tune.ordered,
+                                      "candidates": len(tune.table)},
             "batched_views_per_s": round(len(cams) / t_batched, 2), "plain_views_per_s": round(len(cams) / t_plain, 2),
             "batched_ms": round(t_batched * 1e3, 3), "plain_ms": round(t_plain * 1e3, 3),
             "speedup": round(t_plain / t_batched, 3), "images_bit_equal": same}
@@ -617,8 +620,9 @@ def main():
         "config": {"workload": "1M Gaussians on 20 spheres/planes, bimodal opacity, SH degree 3, one 1920x1080 "
                                "view", "gaussians": 1_000_000, "width": 1920, "height": 1080,
                    "sh_degree": 3, "tile": f"{tune.tile_w}x{tune.tile_h}", "radix_bits": tune.radix_bits,
-                   "bins": f"{tune.bin_x}x{tune.bin_y}",
-                   "tuned_by": "autotuner (tile size x radix width x bins, images checked bit-identical)",
+                   "bins": f"{tune.bin_x}x{tune.bin_y}", "ordered_render": tune.ordered,
+                   "tuned_by": "autotuner (tile size x radix width x bins x render schedule, images checked "
+                               "bit-identical)",
                    "pairs": res["m"],
                    "emission": "depth-first, 32-bit tile keys (tile bits sorted per frame)",
                    "frame": "one graph replay (preprocess, device-sized sort and render)"},

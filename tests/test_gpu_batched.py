@@ -55,7 +55,8 @@ def test_autotune_picks_a_candidate_and_caches_it(tmp_path):
     res = autotune(g, cams, base, tiles=tiles, radix_bits=radix, reps=2, cache_path=cache, bins=bins)
     assert (res.tile_w, res.tile_h) in tiles and res.radix_bits in radix and not res.cached
     assert (res.bin_x, res.bin_y) in bins
-    assert len(res.table) == 8 and res.ms == min(row[5] for row in res.table)
+    assert len(res.table) == 8 and res.ms == min(row[6] for row in res.table)
+    assert res.ordered == bool(base.flags & B.WS_FLAG_ORDERED_RENDER)  # the options' schedule by default
     stored = json.load(open(cache))
     assert res.signature in stored
     again = autotune(g, cams, base, tiles=tiles, radix_bits=radix, reps=2, cache_path=cache, bins=bins)
@@ -68,3 +69,9 @@ def test_autotune_picks_a_candidate_and_caches_it(tmp_path):
     # a search without bins is cached under another signature
     plain = autotune(g, cams, base, tiles=tiles, radix_bits=radix, reps=2, cache_path=cache)
     assert not plain.cached and (plain.bin_x, plain.bin_y) == (1, 1) and len(plain.table) == 4
+    # both render schedules: every candidate's images equal the first's, the choice is applied to the flags
+    both = autotune(g, cams, base, tiles=((16, 16),), radix_bits=(8,), reps=2, ordered=(False, True))
+    assert len(both.table) == 2 and {row[5] for row in both.table} == {False, True}
+    ob = both.apply(base)
+    assert bool(ob.flags & B.WS_FLAG_ORDERED_RENDER) == both.ordered
+    assert (ob.flags & ~B.WS_FLAG_ORDERED_RENDER) == (base.flags & ~B.WS_FLAG_ORDERED_RENDER)
