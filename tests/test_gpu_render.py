@@ -223,25 +223,31 @@ def test_render_end_to_end_c2(depth_first):
 
 @pytest.mark.slow
 def test_render_c2_in_the_benchmark_configuration():
-    """The headline frame exactly as bench.py times it (32x16 tiles, 6-bit digits, depth-first emission,
-    one graph replay of the device-sized forward) against the oracle's image of the same view."""
+    """The headline frame exactly as bench.py times it (depth-first emission, 32-bit tile keys, one graph
+    replay of the device-sized forward) in the layouts its autotuner picks among (16x16 tiles in 2x2 or 4x2
+    bins, 32x16 tiles without bins), each against the oracle's image of the same view."""
     import torch
     from paper_2602_03207_amd import binding as B
     from paper_2602_03207_amd.batched import BatchedForward
     from paper_2602_03207_amd.pipeline import GaussianTensors
     scene, cam = scenegen.c2()
-    opts = gpu_options(sh_degree=3, tile_w=32, tile_h=16, radix_bits=6, flags=B.WS_FLAG_DEPTH_FIRST)
-    bf = BatchedForward([cam], opts, GaussianTensors.from_scene(scene))
-    bf.capture()
-    for _ in range(3):
-        bf.replay()
-    bf.check()
-    torch.cuda.synchronize()
-    img = bf.r.image(0).cpu().numpy()
-    bf.close()
-    ref = oracle.render(scene, cam, oracle_options(sh_degree=3, tile_w=32, tile_h=16))
-    worst, frac = assert_image_parity(img, ref)
-    print(f"C2 (bench configuration): worst {worst:.2e}, flagged {frac:.2e}")
+    g = GaussianTensors.from_scene(scene)
+    ref = oracle.render(scene, cam, oracle_options(sh_degree=3))
+    flags = B.WS_FLAG_DEPTH_FIRST | B.WS_FLAG_KEYS32
+    for tile, bins, rb in (((16, 16), (4, 2), 7), ((16, 16), (2, 2), 6), ((32, 16), (1, 1), 6)):
+        print(f"C2 benchmark layout: tile {tile} bins {bins} radix {rb}", flush=True)
+        opts = gpu_options(sh_degree=3, tile_w=tile[0], tile_h=tile[1], radix_bits=rb, flags=flags, bin_x=bins[0],
+                           bin_y=bins[1])
+        bf = BatchedForward([cam], opts, g)
+        bf.capture()
+        for _ in range(3):
+            bf.replay()
+        bf.check()
+        torch.cuda.synchronize()
+        img = bf.r.image(0).cpu().numpy()
+        bf.close()
+        worst, frac = assert_image_parity(img, ref)
+        print(f"C2 (tile {tile}, bins {bins}): worst {worst:.2e}, flagged {frac:.2e}")
 
 
 @pytest.mark.slow
@@ -252,8 +258,9 @@ def test_render_c3_sampled_pixels():
     from paper_2602_03207_amd import binding as B
     from paper_2602_03207_amd.pipeline import GaussianTensors, Renderer
     scene, cam = scenegen.c3()
+    g = GaussianTensors.from_scene(scene)
     r = Renderer([cam], gpu_options(sh_degree=3, flags=B.WS_FLAG_DEPTH_FIRST))
-    r.forward(GaussianTensors.from_scene(scene))
+    r.forward(g)
     torch.cuda.synchronize()
     assert r.status() == 0
     img = r.image(0).cpu().numpy()
@@ -268,28 +275,43 @@ def test_render_c3_sampled_pixels():
     sub = {k: (v[:, sel] if v.ndim == 3 else v[sel]) for k, v in ref.items()
            if k in ("rgb", "alpha_margin", "t_margin")}
     worst, frac = assert_image_parity(img[:, sel], sub)
-    print(f"C3 sampled: worst {worst:.2e}, flagged {frac:.2e}, M gpu {r.num_pairs} oracle {m_ref}")
+    # the fastest 4K layout (16x16 tiles in 4x2 bins, 32-bit keys, device-sized sequence): the same image
+    m_gpu = r.num_pairs
+    del r
+    rb = Renderer([cam], gpu_options(sh_degree=3, flags=B.WS_FLAG_DEPTH_FIRST | B.WS_FLAG_KEYS32, bin_x=4,
+                                     bin_y=2))
+    m = rb.forward(g)
+    rb._ensure_capacity(int(m * 1.1) + 4096)
+    rb.forward_capacity(g)
+    torch.cuda.synchronize()
+    assert rb.status() == 0
+    assert np.array_equal(rb.image(0).cpu().numpy().view(np.uint32), img.view(np.uint32))
+    print(f"C3 sampled: worst {worst:.2e}, flagged {frac:.2e}, M gpu {m_gpu} oracle {m_ref}")
 
 
 @pytest.mark.slow
 def test_render_c4_all_views_one_launch_sampled_pixels():
-    """The 64-view workload of uneven resolution rendered as one batched call (persistent ordered render,
-    32x16 tiles, 6-bit digits, depth-first emission, as the multi-view benchmark runs it): three views of
-    different sizes, 2000 sampled pixels each, against the oracle compositing just those pixels."""
+    """The 64-view workload of uneven resolution rendered as one batched call in the layouts the multi-view
+    benchmark's autotuner picks among (here 16x16 tiles in 4x2 bins with 32-bit keys and one workgroup per
+    tile, and 32x16 tiles with the persistent ordered render): three views of different sizes, 2000 sampled
+    pixels each, against the oracle compositing just those pixels; both layouts give identical images."""
     import torch
     from paper_2602_03207_amd import binding as B
     from paper_2602_03207_amd.pipeline import GaussianTensors, Renderer
     scene, cams = scenegen.c4()
-    flags = B.WS_FLAG_DEPTH_FIRST | B.WS_FLAG_ORDERED_RENDER
-    r = Renderer(cams, gpu_options(sh_degree=3, tile_w=32, tile_h=16, radix_bits=6, flags=flags))
-    r.forward(GaussianTensors.from_scene(scene))
+    g = GaussianTensors.from_scene(scene)
+    r = Renderer(cams, gpu_options(sh_degree=3, tile_w=16, tile_h=16, radix_bits=8, bin_x=4, bin_y=2,
+                                   flags=B.WS_FLAG_DEPTH_FIRST | B.WS_FLAG_KEYS32))
+    m = r.forward(g)
+    r._ensure_capacity(int(m * 1.1) + 4096)
+    r.forward_capacity(g)
     torch.cuda.synchronize()
     assert r.status() == 0
     sizes = {}
     for v, c in enumerate(cams):
         sizes.setdefault((c.width, c.height), v)
     rng = np.random.default_rng(41)
-    ro = oracle_options(sh_degree=3, tile_w=32, tile_h=16)
+    ro = oracle_options(sh_degree=3)
     for v in sorted(sizes.values()):
         cam = cams[v]
         img = r.image(v).cpu().numpy()
@@ -301,6 +323,14 @@ def test_render_c4_all_views_one_launch_sampled_pixels():
                if k in ("rgb", "alpha_margin", "t_margin")}
         worst, frac = assert_image_parity(img[:, sel], sub)
         print(f"C4 view {v} ({cam.width}x{cam.height}): worst {worst:.2e}, flagged {frac:.2e}")
+    images = r.images.clone()
+    del r
+    ro_r = Renderer(cams, gpu_options(sh_degree=3, tile_w=32, tile_h=16, radix_bits=6,
+                                      flags=B.WS_FLAG_DEPTH_FIRST | B.WS_FLAG_ORDERED_RENDER))
+    ro_r.forward(g)
+    torch.cuda.synchronize()
+    assert ro_r.status() == 0
+    assert torch.equal(ro_r.images.view(torch.int32), images.view(torch.int32))
 
 
 def test_invariance_tile_size_radix_width_and_emission_order():
