@@ -84,7 +84,9 @@ def test_backward_sh_degrees_match_oracle(deg):
 
 @pytest.mark.slow
 def test_backward_1080p_l1_view_matches_oracle():
-    """One 1920x1080 view of the 1M-Gaussian scene with the L1 loss against a perturbed-scene target."""
+    """One 1920x1080 view of the 1M-Gaussian scene with the L1 loss against a perturbed-scene target, with
+    tile keys and in the training benchmark's layout (16x16 tiles in 4x2 bins, 32-bit keys)."""
+    from paper_2602_03207_amd import binding as B
     scene, cams, target_scene = scenegen.c5(n_views=1)
     cam = cams[0]
     ro = oracle_options(sh_degree=3)
@@ -92,8 +94,26 @@ def test_backward_1080p_l1_view_matches_oracle():
     tgt = oracle.forward_backward(target_scene, cam, ro)["image"]
     _, dL = oracle.l1_loss_grad(img, tgt)
     dL = dL.astype(np.float32)
-    got, _ = _gpu_grads(scene, [cam], [dL])
     want = _oracle_grads(scene, [cam], [dL], ro)
+    for kw in ({}, dict(bin_x=4, bin_y=2, flags=B.WS_FLAG_DEPTH_FIRST | B.WS_FLAG_KEYS32)):
+        print(f"1080p backward, options {kw}", flush=True)
+        got, _ = _gpu_grads(scene, [cam], [dL], **kw)
+        _compare(got, want)
+
+
+@pytest.mark.parametrize("bins", [(4, 2), (2, 2)])
+def test_backward_binned_32bit_keys_match_oracle(bins):
+    """The training benchmark's layout (16x16 tiles in bins, 32-bit keys, depth-first emission): the
+    backward reads the expanded per-tile lists; three views of uneven size against the oracle."""
+    from paper_2602_03207_amd import binding as B
+    scene = scenegen.random_scene(2500, 8, log_scale_mu=-3.0, logit_sd=2.0, sh_degree=1, dc_sd=0.5, rest_sd=0.2)
+    cams = [scenegen.look_at([0.3, -0.2, -3.0], [0, 0, 0], 128, 96), scenegen.look_at([2.0, 0.5, -2.0], [0, 0, 0], 77, 61),
+            scenegen.look_at([-1.0, -1.5, -2.0], [0, 0, 0], 100, 100)]
+    rng = np.random.default_rng(5)
+    dLs = [rng.standard_normal((3, c.height, c.width)).astype(np.float32) for c in cams]
+    got, _ = _gpu_grads(scene, cams, dLs, bin_x=bins[0], bin_y=bins[1],
+                        flags=B.WS_FLAG_DEPTH_FIRST | B.WS_FLAG_KEYS32)
+    want = _oracle_grads(scene, cams, dLs, oracle_options(sh_degree=1))
     _compare(got, want)
 
 
@@ -119,8 +139,10 @@ def test_autograd_function_matches_backward_call():
         assert torch.allclose(p.grad, ref[k], rtol=1e-4, atol=1e-5 * rms), k
 
 
-def test_batched_graph_equals_plain_and_replays_consistently():
+@pytest.mark.parametrize("layout", ["tile_keys", "bench"])
+def test_batched_graph_equals_plain_and_replays_consistently(layout):
     import torch
+    from paper_2602_03207_amd import binding as B
     from paper_2602_03207_amd.batched import BatchedStep, PlainStep
     from paper_2602_03207_amd.pipeline import GaussianTensors, Renderer
     scene = scenegen.random_scene(4000, 10, log_scale_mu=-3.2, sh_degree=3, dc_sd=0.5, rest_sd=0.2)
@@ -128,7 +150,8 @@ def test_batched_graph_equals_plain_and_replays_consistently():
     rng = np.random.default_rng(1)
     res = [(128, 128), (160, 90), (96, 120), (200, 64)]
     cams = scenegen.orbit_cameras(rng, len(res), res)
-    opts = gpu_options(sh_degree=3)
+    opts = gpu_options(sh_degree=3) if layout == "tile_keys" else \
+        gpu_options(sh_degree=3, bin_x=4, bin_y=2, flags=B.WS_FLAG_DEPTH_FIRST | B.WS_FLAG_KEYS32)
     g = GaussianTensors.from_scene(scene)
     tr = Renderer(cams, opts)
     tr.forward(GaussianTensors.from_scene(target))
