@@ -2,10 +2,12 @@
 //
 // k_ranges                    [start, end) of every tile's run of pairs in the
 //                             tile-sorted key list, written where the tile
-//                             (key >> 32, or the 32-bit key itself) changes; the tiles without pairs between two
-//                             runs get an empty range at that boundary, so
-//                             every tile is written once and no clearing
-//                             launch is needed.
+//                             changes (the key's cell word: key >> 32, or the
+//                             32-bit key itself, without the bins' coverage
+//                             mask); the tiles without pairs between two runs
+//                             get an empty range at that boundary, so every
+//                             tile is written once and no clearing launch is
+//                             needed.
 // k_render<TW, TH>            one workgroup of TW*TH threads per tile, one
 //                             pixel per thread, one 8x8 quadrant per wave.
 //                             The tile's splats are staged in LDS in batches
