@@ -183,3 +183,61 @@ def test_sort32_respects_status_word(n):
     torch.cuda.synchronize()
     assert bool((kout == -1).all()) and bool((vout == -1).all())
     assert int(d_status.item()) == B.WS_ERR_CAPACITY
+
+
+@pytest.mark.parametrize("bins", [(1, 1), (4, 2)])
+def test_keys32_empty_frame_and_capacity_overflow(bins):
+    """32-bit keys at the edges: a frame without pairs renders the background with every range empty; a
+    capacity below M is reported in the status word on the device-sized path and nothing downstream writes."""
+    import torch
+    from paper_2602_03207_amd import binding as B
+    from paper_2602_03207_amd.pipeline import GaussianTensors, Renderer
+    flags = B.WS_FLAG_DEPTH_FIRST | B.WS_FLAG_KEYS32
+    cams = [scenegen.look_at([0, 0, -3], [0, 0, 0], 100, 80), scenegen.look_at([2, -1, -2], [0, 0, 0], 64, 120)]
+    far = scenegen.random_scene(500, 3, sh_degree=1)
+    far.means[2] = -50.0  # behind both cameras
+    print(f"keys32 empty frame, bins {bins}", flush=True)
+    r = _frame(far, cams, bin_x=bins[0], bin_y=bins[1], flags=flags, bg=(0.25, 0.5, 0.75))
+    assert r.num_pairs == 0
+    rng_ = r.tile_ranges.cpu().numpy().view(np.uint32).reshape(-1, 2)
+    assert (rng_[:, 0] == rng_[:, 1]).all()
+    for v in range(len(cams)):
+        img = r.image(v).cpu().numpy()
+        assert np.array_equal(img, np.broadcast_to(np.array([0.25, 0.5, 0.75], np.float32)[:, None, None], img.shape))
+    scene = scenegen.random_scene(6000, 12, log_scale_mu=-3.0, sh_degree=1, dc_sd=0.4, rest_sd=0.2)
+    print(f"keys32 capacity overflow, bins {bins}", flush=True)
+    rr = Renderer(cams, gpu_options(sh_degree=1, bin_x=bins[0], bin_y=bins[1], flags=flags), capacity=1024)
+    g = GaussianTensors.from_scene(scene)
+    rr.tile_ranges.fill_(7)
+    rr.images.fill_(-1.0)
+    rr.d_status.zero_()
+    rr.preprocess(g)
+    assert int(rr.d_num_pairs.item()) > 1024
+    rr.sort(rr.capacity, device_count=True)
+    rr.render(rr.capacity)
+    torch.cuda.synchronize()
+    assert rr.status() == B.WS_ERR_CAPACITY
+    assert (rr.tile_ranges.cpu().numpy() == 7).all() and bool((rr.images == -1.0).all())
+    # the plain sequence grows its buffers and renders the same image as 64-bit keys
+    m = rr.forward(g)
+    torch.cuda.synchronize()
+    assert rr.status() == 0 and m > 1024
+    ref = _frame(scene, cams, bin_x=bins[0], bin_y=bins[1], flags=B.WS_FLAG_DEPTH_FIRST)
+    assert torch.equal(rr.images.view(torch.int32), ref.images.view(torch.int32))
+
+
+def test_keys32_single_pair():
+    """One visible splat covering one tile: one pair, one non-empty range, the oracle's pixels."""
+    from paper_2602_03207_amd import binding as B
+    scene = scenegen.random_scene(1, 5, sh_degree=0, log_scale_mu=-5.0, log_scale_sd=0.0)
+    scene.means[:, 0] = [0.1, 0.1, 0.0]  # centre at pixel (33.8, 33.8): its rectangle stays inside one tile
+    scene.opacity_logits[0] = 4.0
+    cam = scenegen.look_at([0, 0, -3], [0, 0, 0], 64, 64)
+    r = _frame(scene, [cam], flags=B.WS_FLAG_DEPTH_FIRST | B.WS_FLAG_KEYS32)
+    keys, vals = oracle.emit(scene, cam, oracle_options())
+    assert r.num_pairs == keys.size == 1
+    assert np.array_equal(r.keys_b[:r.num_pairs].cpu().numpy().view(np.uint32),
+                          (np.sort(keys) >> np.uint64(32)).astype(np.uint32))
+    ref = oracle.render(scene, cam, oracle_options())
+    err = np.abs(r.image(0).cpu().numpy().astype(np.float64) - ref["rgb"]).max()
+    assert err < 2e-4, err
