@@ -38,7 +38,7 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 # 157.3 TFLOP/s figure needs packed fp32 instructions, which this library is built without
 FP32_VALU_PEAK_TFLOPS = 78.6
 STATS_FILE = os.path.join(ROOT, "tests", "golden", "c2_oracle_stats.json")
-TUNE_BINS = ((1, 1), (2, 2), (4, 2))  # bins of tiles the autotuner tries besides tile keys
+TUNE_BINS = ((1, 1), (2, 2), (4, 2), (4, 4))  # bins of tiles the autotuner tries besides tile keys
 
 
 def log(msg):
