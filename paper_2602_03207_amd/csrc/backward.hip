@@ -240,14 +240,16 @@ __global__ __launch_bounds__(TW * TH) void k_render_bwd(BwdArgs a) {
             {
                 float q0, q1, q2;
                 wave_sum9(gv, &q0, &q1, &q2);
-                // the first lane of each row adds its row's values (distinct addresses)
+                // the first lane of each row adds its row's values (distinct addresses);
+                // some lane contributes, so the sums are rarely zero and are added
+                // without a test (adding +0 changes no sum)
                 const uint32_t lane = lane_id();
                 if ((lane & 15) == 0) {
                     const int row = int(lane >> 4);
                     const int k0 = row == 1 ? 2 : (row == 2 ? 1 : row);  // rows hold v0, v2, v1, v3
-                    if (q0 != 0.f) atomicAdd(&s_acc[k0][t], q0);
-                    if (q1 != 0.f) atomicAdd(&s_acc[4 + k0][t], q1);
-                    if (row == 0 && q2 != 0.f) atomicAdd(&s_acc[8][t], q2);
+                    atomicAdd(&s_acc[k0][t], q0);
+                    atomicAdd(&s_acc[4 + k0][t], q1);
+                    if (row == 0) atomicAdd(&s_acc[8][t], q2);
                 }
             }
         }
