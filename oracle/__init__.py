@@ -19,7 +19,10 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.cpp")
-_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+# ORACLE_SANITIZE=1 selects a build with AddressSanitizer and UndefinedBehaviorSanitizer (host code only;
+# the process must preload the ASan runtime, e.g. LD_PRELOAD=$(g++ -print-file-name=libasan.so))
+_SANITIZE = os.environ.get("ORACLE_SANITIZE", "") == "1"
+_LIB_PATH = os.path.join(_HERE, "liboracle_san.so" if _SANITIZE else "liboracle.so")
 _lib = None
 
 STATUS = {"visible": 0, "opacity": 1, "near": 2, "degenerate": 3, "viewport": 4}
@@ -27,13 +30,22 @@ FLAG_FIXED_3SIGMA = 1
 FLAG_NO_VIEWPORT_CULL = 2
 
 
-def build(verbose=False):
-    """Compile oracle.cpp into liboracle.so with g++ (no GPU code involved)."""
-    cmd = ["g++", "-O2", "-std=c++17", "-Wall", "-Wextra", "-shared", "-fPIC", "-o", _LIB_PATH, _SRC]
+def build(verbose=False, sanitize=None):
+    """Compile oracle.cpp into liboracle.so with g++ (no GPU code involved).
+
+    sanitize=True (default: the ORACLE_SANITIZE environment variable) builds liboracle_san.so with
+    -fsanitize=address,undefined instead, any undefined behaviour being fatal."""
+    sanitize = _SANITIZE if sanitize is None else sanitize
+    out = os.path.join(_HERE, "liboracle_san.so" if sanitize else "liboracle.so")
+    if sanitize:
+        cmd = ["g++", "-O1", "-g", "-std=c++17", "-Wall", "-Wextra", "-fsanitize=address,undefined",
+               "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer", "-shared", "-fPIC", "-o", out, _SRC]
+    else:
+        cmd = ["g++", "-O2", "-std=c++17", "-Wall", "-Wextra", "-shared", "-fPIC", "-o", out, _SRC]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)
-    return _LIB_PATH
+    return out
 
 
 def _load():
@@ -55,6 +67,10 @@ def _load():
     lib.orc_render_brute.argtypes = [i64, d, d, d, d, d, P(_Camera), P(_Options), P(C.c_uint8), P(_Image)]
     lib.orc_forward_backward.argtypes = [i64, d, d, d, d, d, P(_Camera), P(_Options), d, d, d, d, d, d, d, d]
     lib.orc_forward_backward.restype = C.c_uint64
+    lib.orc_composite_outcomes.argtypes = [i64, d, d, d, d, P(C.c_int32), P(_Camera), P(_Options), P(C.c_uint32),
+                                           P(C.c_int64), i64, P(C.c_uint8), i32, i64, P(C.c_int64), P(C.c_int32),
+                                           d, d]
+    lib.orc_composite_outcomes.restype = i64
     lib.orc_sh_basis.argtypes = [d, i32, d]
     lib.orc_quat_to_rotmat.argtypes = [d, d]
     _lib = lib
@@ -207,8 +223,48 @@ def _image_buffers(H, W):
                 t_margin=np.full((H, W), np.inf), hash=np.zeros((H, W), np.uint64))
 
 
-def composite(mean2d, conic, opacity, rgb, pix_rect, cam, opts: Options, vals, ranges, tile_offset=0, mask=None):
-    """Tiled front-to-back compositing of given projected splats (fp64) and a sorted pair list."""
+def composite_outcomes(mean2d, conic, opacity, rgb, pix_rect, cam, opts: Options, vals, ranges, tile_offset=0,
+                       mask=None, max_out=64):
+    """The pixels whose compositing takes a decision within fp32 reach of its threshold (alpha_min or t_min),
+    with every composite that the combinations of those decisions give (each a correct result of the rule for an
+    fp32 evaluation; reading A25).  Same inputs as composite().
+
+    Returns dict(pix [k] flat pixel indices, n_out [k] (0: more than max_out combinations, not enumerated),
+    rgb [k, max_out, 3] the outcomes, bound [k] the transmittance at the pixel's first such decision times the
+    largest colour of its list: no choice there can move the pixel by more)."""
+    lib = _load()
+    n = int(np.asarray(opacity).shape[0])
+    mean2d, conic, opacity, rgb = _f64(mean2d), _f64(conic), _f64(opacity), _f64(rgb)
+    pr = np.ascontiguousarray(pix_rect, dtype=np.int32)
+    v = np.ascontiguousarray(vals, dtype=np.uint32)
+    rg = np.ascontiguousarray(ranges, dtype=np.int64)
+    mk = None if mask is None else np.ascontiguousarray(mask, dtype=np.uint8)
+    cam_s, opt_s = _cam(cam), _opts(opts)
+
+    def call(cap, pix, n_out, out_rgb, bound):
+        P = C.POINTER
+        return lib.orc_composite_outcomes(
+            n, _dp(mean2d), _dp(conic), _dp(opacity), _dp(rgb), pr.ctypes.data_as(P(C.c_int32)), C.byref(cam_s),
+            C.byref(opt_s), v.ctypes.data_as(P(C.c_uint32)), rg.ctypes.data_as(P(C.c_int64)), tile_offset,
+            None if mk is None else mk.ctypes.data_as(P(C.c_uint8)), max_out, cap,
+            None if pix is None else pix.ctypes.data_as(P(C.c_int64)),
+            None if n_out is None else n_out.ctypes.data_as(P(C.c_int32)),
+            None if out_rgb is None else _dp(out_rgb), None if bound is None else _dp(bound))
+
+    count = int(call(0, None, None, None, None))
+    pix = np.zeros(max(count, 1), np.int64)
+    n_out = np.zeros(max(count, 1), np.int32)
+    out_rgb = np.zeros((max(count, 1), max_out, 3))
+    bound = np.zeros(max(count, 1))
+    call(count, pix, n_out, out_rgb, bound)
+    return dict(pix=pix[:count], n_out=n_out[:count], rgb=out_rgb[:count], bound=bound[:count])
+
+
+def composite(mean2d, conic, opacity, rgb, pix_rect, cam, opts: Options, vals, ranges, tile_offset=0, mask=None,
+              outcomes=False):
+    """Tiled front-to-back compositing of given projected splats (fp64) and a sorted pair list.
+
+    outcomes=True also attaches composite_outcomes() of the same inputs as out["outcomes"]."""
     lib = _load()
     n = int(np.asarray(opacity).shape[0])
     mean2d, conic, opacity, rgb = _f64(mean2d), _f64(conic), _f64(opacity), _f64(rgb)
@@ -224,15 +280,18 @@ def composite(mean2d, conic, opacity, rgb, pix_rect, cam, opts: Options, vals, r
                       C.byref(_cam(cam)), C.byref(_opts(opts)), v.size, v.ctypes.data_as(C.POINTER(C.c_uint32)),
                       rg.ctypes.data_as(C.POINTER(C.c_int64)), tile_offset,
                       None if mk is None else mk.ctypes.data_as(C.POINTER(C.c_uint8)), C.byref(img))
+    if outcomes:
+        out["outcomes"] = composite_outcomes(mean2d, conic, opacity, rgb, pr, cam, opts, v, rg, tile_offset, mask)
     return out
 
 
-def render(scene, cam, opts: Options, mode="tiled", mask=None) -> dict:
+def render(scene, cam, opts: Options, mode="tiled", mask=None, outcomes=False) -> dict:
     """Whole forward path for one view.
 
     mode="tiled": preprocess, emit, stable sort, tile ranges, composite (the
     pipeline's own steps).  mode="brute": every validly projected Gaussian at
     every pixel in (fp32 depth bits, id) order, no culling (the definition).
+    outcomes=True (tiled mode) attaches composite_outcomes() as out["outcomes"].
     """
     _check_opts(scene, opts)
     if mode == "brute":
@@ -251,7 +310,7 @@ def render(scene, cam, opts: Options, mode="tiled", mask=None) -> dict:
     tx, ty = tiles_xy(cam, opts)
     ranges = tile_ranges(skeys, tx * ty)
     out = composite(proj["mean2d"], proj["conic"], proj["opacity"], proj["rgb"], proj["pix_rect"], cam, opts,
-                    svals, ranges, 0, mask)
+                    svals, ranges, 0, mask, outcomes=outcomes)
     out.update(proj=proj, keys=keys, vals=vals, sorted_keys=skeys, sorted_vals=svals, ranges=ranges)
     return out
 
@@ -296,6 +355,19 @@ def quat_to_rotmat(q):
 
 
 def l1_loss_grad(image, target):
-    """L1 loss = mean |I - I*| over all elements; dL/dI = sign(I - I*) / numel with sign(0) = 0."""
-    diff = np.asarray(image, np.float64) - np.asarray(target, np.float64)
-    return np.abs(diff).mean(), np.sign(diff) / diff.size
+    """Photometric L1 of the training workload (reading A19: the mean over every element of every view).
+
+    `image` and `target` are arrays of the same shape, or equally long sequences of per-view arrays (views of
+    any size).  Returns (loss, dL/dI): loss = sum |I - I*| / numel and dL/dI = sign(I - I*) / numel with
+    sign(0) = 0, numel counting the elements of all views; the gradient comes back in the input's form.
+    """
+    views = isinstance(image, (list, tuple))
+    imgs = list(image) if views else [image]
+    tgts = list(target) if views else [target]
+    if len(imgs) != len(tgts):
+        raise ValueError("image and target hold different numbers of views")
+    diffs = [np.asarray(i, np.float64) - np.asarray(t, np.float64) for i, t in zip(imgs, tgts)]
+    numel = sum(d.size for d in diffs)
+    loss = sum(float(np.abs(d).sum()) for d in diffs) / numel
+    grads = [np.sign(d) / numel for d in diffs]
+    return loss, (grads if views else grads[0])

@@ -29,9 +29,15 @@
 // The only fp32 step is the depth key, which the method defines as the bits
 // of the fp32 depth.
 //
-// Parity status: every function here is pinned by the CPU test-suite
-// (closed forms, brute force, invariants, std::stable_sort, finite
-// differences); none is "parity unpinned".
+// Parity status: each function here is pinned by the CPU test-suite against
+// something other than itself: closed forms of single Gaussians (projection,
+// footprint, pixel values, gradients), brute-force compositing, culling and
+// transmittance invariants, std::stable_sort / sorted(), fp64 finite
+// differences, and every spherical-harmonic term against scipy's complex
+// spherical harmonics converted to the real basis.  The L1 loss (in the Python
+// wrapper) is pinned on hand-computed batches.  The decision-outcome
+// enumeration at the end of this file is test infrastructure for comparing an
+// fp32 implementation; its primary outcome is composite_pixel's result.
 
 #include <algorithm>
 #include <cmath>
@@ -513,6 +519,138 @@ void stable_sort_pairs(int64_t n, uint64_t* keys, uint32_t* vals, int begin_bit,
     std::copy(v2.begin(), v2.end(), vals);
 }
 
+// ------------------------------------------- decisions within fp32 reach
+//
+// Test infrastructure for parity with an fp32 implementation.  The GPU
+// evaluates the same rule from fp32-rounded splat records in fp32, so each of
+// its discrete decisions (alpha >= alpha_min, T' < t_min) may differ from the
+// fp64 one wherever the fp64 value lies within the fp32 error of the
+// threshold, and each choice there is a correct result of the rule (several
+// correct results: reading A25).  For one pixel this enumerates, depth first,
+// the composites of every combination of such decisions.
+//
+// Error bound of ln(alpha) as the fp32 path computes it (ln units):
+//   the centre rounded to fp32 (at most 2^-23 |u| per coordinate) times the
+//   gradient of the exponent in the centre, plus 2^-18 (cond + 1)(|power| + 1)
+//   for the conic's rounding and the evaluation (cond = the conic's condition
+//   number), plus 2^-18 (|ln sigma| + 1).
+// Error bound of ln(T): the sum over the composited splats of
+// alpha / (1 - alpha) times their ln(alpha) bound, plus 2^-22 per step.
+struct SplatError {  // the per-splat parts of the bound
+    double eu, ev;      // 2^-23 (|u| + 1), 2^-23 (|v| + 1)
+    double cond1;       // 2^-18 (cond + 1)
+    double ls;          // 2^-18 (|ln sigma| + 1)
+    double ln_sigma_rel;  // ln(sigma / alpha_min)
+};
+
+SplatError splat_error(const PixelSplat& s, const Options& opt) {
+    SplatError e;
+    e.eu = std::ldexp(std::fabs(s.u) + 1.0, -23);
+    e.ev = std::ldexp(std::fabs(s.v) + 1.0, -23);
+    const double tr = s.A + s.C, det = s.A * s.C - s.B * s.B;
+    const double disc = std::sqrt(std::max(tr * tr - 4.0 * det, 0.0));
+    const double lmin = 0.5 * (tr - disc), lmax = 0.5 * (tr + disc);
+    e.cond1 = std::ldexp((lmin > 0.0 ? lmax / lmin : 1e30) + 1.0, -18);
+    e.ls = s.sigma > 0.0 ? std::ldexp(std::fabs(std::log(s.sigma)) + 1.0, -18) : 0.0;
+    e.ln_sigma_rel = s.sigma > 0.0 ? std::log(s.sigma / opt.alpha_min) : -INFINITY;
+    return e;
+}
+
+double alpha_log_error(const PixelSplat& s, const SplatError& e, double dx, double dy, double power) {
+    const double gu = std::fabs(s.A * dx + s.B * dy), gv = std::fabs(s.B * dx + s.C * dy);
+    return gu * e.eu + gv * e.ev + e.cond1 * (std::fabs(power) + 1.0) + e.ls;
+}
+
+struct OutcomeSearch {
+    const std::vector<PixelSplat>* S;
+    const std::vector<SplatError>* E;
+    const int64_t* ids;
+    int64_t count;
+    const Options* opt;
+    int32_t px, py;
+    double pcx, pcy;
+    size_t max_out;
+    std::vector<double> out;  // 3 per outcome
+    bool capped = false;
+    bool uncertain = false;
+    double first_T = 0.0;  // transmittance at the first decision within reach
+
+    void record(const double* C, double T) {
+        double v[3];
+        for (int ch = 0; ch < 3; ++ch) v[ch] = C[ch] + T * opt->bg[ch];
+        for (size_t k = 0; k < out.size(); k += 3)
+            if (out[k] == v[0] && out[k + 1] == v[1] && out[k + 2] == v[2]) return;
+        if (out.size() / 3 >= max_out) { capped = true; return; }
+        out.insert(out.end(), v, v + 3);
+    }
+    void mark(double T) {
+        if (!uncertain) first_T = T;
+        uncertain = true;
+    }
+
+    // continue the pixel from list entry j with transmittance T, colour C and
+    // the error bound lnT_err of ln T
+    void run(int64_t j, double T, const double* Cin, double lnT_err) {
+        if (capped) return;
+        double C[3] = {Cin[0], Cin[1], Cin[2]};
+        for (; j < count; ++j) {
+            const PixelSplat& s = (*S)[size_t(ids[j])];
+            // a pixel more than one pixel outside the rectangle is far from the
+            // alpha_min ellipse, which the rectangle bounds exactly
+            if (px < s.x0 - 1 || px > s.x1 + 1 || py < s.y0 - 1 || py > s.y1 + 1) continue;
+            const bool in_rect = !(px < s.x0 || px > s.x1 || py < s.y0 || py > s.y1);
+            const double dx = s.u - pcx, dy = s.v - pcy;
+            const double power = -0.5 * (s.A * dx * dx + s.C * dy * dy) - s.B * dx * dy;
+            const double alpha_raw = s.sigma * std::exp(power);
+            const double alpha = std::min(opt->alpha_max, alpha_raw);
+            const SplatError& se = (*E)[size_t(ids[j])];
+            const double ea = s.sigma > 0.0 ? alpha_log_error(s, se, dx, dy, power) : 0.0;
+            const double la = se.ln_sigma_rel + power;
+            const bool take_here = in_rect && alpha >= opt->alpha_min;
+            if (std::fabs(la) <= ea && alpha_raw > 0.0) {  // the alpha test within reach: both choices valid
+                mark(T);
+                if (take_here) {
+                    run(j + 1, T, C, lnT_err);  // the other choice: skip j
+                } else if (take(j, T, C, lnT_err, alpha, ea)) {  // the other choice: take j
+                    double Cn[3];
+                    for (int ch = 0; ch < 3; ++ch) Cn[ch] = C[ch] + s.rgb[ch] * alpha * T;
+                    run(j + 1, T * (1.0 - alpha), Cn, lnT_err + alpha / (1.0 - alpha) * ea + std::ldexp(1.0, -22));
+                }
+            }
+            if (!take_here) continue;
+            if (!take(j, T, C, lnT_err, alpha, ea)) return;  // stopped (its outcomes are recorded)
+            for (int ch = 0; ch < 3; ++ch) C[ch] += s.rgb[ch] * alpha * T;
+            lnT_err += alpha / (1.0 - alpha) * ea + std::ldexp(1.0, -22);
+            T *= 1.0 - alpha;
+        }
+        record(C, T);
+    }
+
+    // Splat j is taken (alpha >= alpha_min).  Applies the transmittance test:
+    // returns true if the pixel continues past j with this splat composited
+    // (the caller updates T and C), false when every continuation has been
+    // handled here.
+    bool take(int64_t j, double T, const double* C, double lnT_err, double alpha, double ea) {
+        const PixelSplat& s = (*S)[size_t(ids[j])];
+        const double Tn = T * (1.0 - alpha);
+        const double et = lnT_err + alpha / (1.0 - alpha) * ea + std::ldexp(1.0, -21);
+        const double lt = std::log(Tn / opt->t_min);
+        if (std::fabs(lt) <= et) {  // the stop test within reach: both valid
+            mark(T);
+            record(C, T);  // stop before j
+            double Cn[3];
+            for (int ch = 0; ch < 3; ++ch) Cn[ch] = C[ch] + s.rgb[ch] * alpha * T;
+            run(j + 1, Tn, Cn, lnT_err + alpha / (1.0 - alpha) * ea + std::ldexp(1.0, -22));
+            return false;
+        }
+        if (Tn < opt->t_min) {
+            record(C, T);
+            return false;
+        }
+        return true;
+    }
+};
+
 }  // namespace
 
 // ======================================================================
@@ -765,6 +903,72 @@ uint64_t orc_forward_backward(int64_t n, const double* means, const double* log_
         }
     }
     return h;
+}
+
+// Pixels whose compositing takes a decision within fp32 reach of its
+// threshold, with every composite the combinations of those decisions give
+// (tiled lists as in orc_composite; pixels with mask != 0).  Writes, for up to
+// cap such pixels, pix[k] (flat pixel index), n_out[k] (outcomes, at most
+// max_out; 0 when the enumeration was cut at max_out), out_rgb[k][max_out][3]
+// and bound[k] = the transmittance at the pixel's first such decision times
+// the largest colour of its list (everything composited from there on weighs
+// at most that transmittance).  Returns the number of such pixels, which may
+// exceed cap (then only the first cap are written).
+int64_t orc_composite_outcomes(int64_t n, const double* mean2d, const double* conic, const double* opacity,
+                               const double* rgb, const int32_t* pix_rect, const Camera* cam, const Options* opt,
+                               const uint32_t* vals, const int64_t* ranges, int64_t tile_offset,
+                               const uint8_t* mask, int32_t max_out, int64_t cap, int64_t* pix, int32_t* n_out,
+                               double* out_rgb, double* bound) {
+    std::vector<PixelSplat> S(static_cast<size_t>(n));
+    for (int64_t i = 0; i < n; ++i)
+        S[size_t(i)] = PixelSplat{mean2d[i], mean2d[n + i], conic[i], conic[n + i], conic[2 * n + i], opacity[i],
+                                  {rgb[i], rgb[n + i], rgb[2 * n + i]},
+                                  pix_rect[i], pix_rect[n + i], pix_rect[2 * n + i], pix_rect[3 * n + i]};
+    std::vector<SplatError> E(S.size());
+    for (size_t i = 0; i < S.size(); ++i) E[i] = splat_error(S[i], *opt);
+    const int32_t W = cam->width, H = cam->height;
+    const int32_t tx_n = (W + opt->tile_w - 1) / opt->tile_w, ty_n = (H + opt->tile_h - 1) / opt->tile_h;
+    std::vector<int64_t> ids;
+    int64_t found = 0;
+    for (int32_t ty = 0; ty < ty_n; ++ty)
+        for (int32_t tx = 0; tx < tx_n; ++tx) {
+            const int64_t tile = tile_offset + int64_t(ty) * tx_n + tx;
+            const int64_t s0 = ranges[2 * tile], e0 = ranges[2 * tile + 1];
+            ids.resize(size_t(e0 - s0));
+            double maxc = std::max({std::fabs(opt->bg[0]), std::fabs(opt->bg[1]), std::fabs(opt->bg[2])});
+            for (int64_t j = s0; j < e0; ++j) {
+                ids[size_t(j - s0)] = vals[j];
+                for (int ch = 0; ch < 3; ++ch) maxc = std::max(maxc, std::fabs(S[vals[j]].rgb[ch]));
+            }
+            for (int32_t py = ty * opt->tile_h; py < std::min(H, (ty + 1) * opt->tile_h); ++py)
+                for (int32_t px = tx * opt->tile_w; px < std::min(W, (tx + 1) * opt->tile_w); ++px) {
+                    const int64_t p = int64_t(py) * W + px;
+                    if (mask && !mask[p]) continue;
+                    OutcomeSearch o;
+                    o.S = &S;
+                    o.E = &E;
+                    o.ids = ids.data();
+                    o.count = int64_t(ids.size());
+                    o.opt = opt;
+                    o.px = px;
+                    o.py = py;
+                    o.pcx = px + 0.5;
+                    o.pcy = py + 0.5;
+                    o.max_out = size_t(std::max(max_out, 1));
+                    const double C0[3] = {0.0, 0.0, 0.0};
+                    o.run(0, 1.0, C0, 0.0);
+                    if (!o.uncertain) continue;
+                    if (found < cap) {
+                        pix[found] = p;
+                        const size_t k = o.out.size() / 3;
+                        n_out[found] = o.capped ? 0 : int32_t(k);
+                        for (size_t q = 0; q < o.out.size(); ++q) out_rgb[size_t(found) * size_t(max_out) * 3 + q] = o.out[q];
+                        bound[found] = o.first_T * maxc;
+                    }
+                    ++found;
+                }
+        }
+    return found;
 }
 
 // Building blocks exposed for the pins.

@@ -4,7 +4,7 @@ import pytest
 
 import oracle
 import scenegen
-from _helpers import (assert_image_parity, gpu_options, oracle_options, pack_splats, pixel_flags)
+from _helpers import assert_image_parity, gpu_options, oracle_options, pack_splats
 
 pytestmark = pytest.mark.gpu
 
@@ -91,7 +91,7 @@ def test_render_component_parity_c1():
     rec = pack_splats(f32(p["mean2d"]), f32(p["conic"]), f32(p["opacity"]), f32(p["rgb"]), p["depth32"],
                       np.where(vis, p["pix_rect"], 0))
     comp = oracle.composite(f32(p["mean2d"]), f32(p["conic"]), f32(p["opacity"]), f32(p["rgb"]), p["pix_rect"], cam,
-                            ro, ref["sorted_vals"], ref["ranges"])
+                            ro, ref["sorted_vals"], ref["ranges"], outcomes=True)
     m = ref["sorted_keys"].size
     opts = gpu_options()
     cams = B.camera_array([cam])
@@ -158,7 +158,7 @@ def test_quadrant_culling_keeps_every_contribution(tile):
     cam = scenegen.Camera(W, H, 400.0, 400.0, W / 2, H / 2, np.eye(3), np.zeros(3), np.zeros(3))
     ro = oracle_options(tile_w=tw, tile_h=th)
     rect_or = np.where(vis, rect, np.array([[1], [0], [1], [0]], np.int32))
-    comp = oracle.composite(mean2d, conic, opacity, rgb, rect_or, cam, ro, svals, ranges)
+    comp = oracle.composite(mean2d, conic, opacity, rgb, rect_or, cam, ro, svals, ranges, outcomes=True)
     rec = pack_splats(mean2d, conic, opacity, rgb, depth, np.where(vis, rect, 0))
     opts = gpu_options(tile_w=tw, tile_h=th)
     cams = B.camera_array([cam])
@@ -181,7 +181,7 @@ def test_quadrant_culling_keeps_every_contribution(tile):
 def test_render_end_to_end_c1(tile):
     scene, cam = scenegen.c1()
     r = _full(scene, [cam], tile_w=tile[0], tile_h=tile[1])
-    ref = oracle.render(scene, cam, oracle_options(*tile))
+    ref = oracle.render(scene, cam, oracle_options(*tile), outcomes=True)
     assert r.num_pairs == ref["keys"].size
     assert_image_parity(r.image(0).cpu().numpy(), ref)
 
@@ -191,7 +191,7 @@ def test_render_end_to_end_tiny_near_plane_sh2():
                                   logit_sd=2.5, sh_degree=2, dc_sd=0.5, rest_sd=0.2)
     cam = scenegen.look_at([0.2, 0.1, -0.6], [0, 0, 1], 161, 97)  # ragged tiles in both directions
     r = _full(scene, [cam])
-    ref = oracle.render(scene, cam, oracle_options(sh_degree=2))
+    ref = oracle.render(scene, cam, oracle_options(sh_degree=2), outcomes=True)
     assert_image_parity(r.image(0).cpu().numpy(), ref)
 
 
@@ -216,7 +216,7 @@ def test_render_end_to_end_c2(depth_first):
     from paper_2602_03207_amd import binding as B
     scene, cam = scenegen.c2()
     r = _full(scene, [cam], flags=B.WS_FLAG_DEPTH_FIRST if depth_first else 0)
-    ref = oracle.render(scene, cam, oracle_options(sh_degree=3))
+    ref = oracle.render(scene, cam, oracle_options(sh_degree=3), outcomes=True)
     worst, frac = assert_image_parity(r.image(0).cpu().numpy(), ref)
     print(f"C2: worst {worst:.2e}, flagged {frac:.2e}, M gpu {r.num_pairs} oracle {ref['keys'].size}")
 
@@ -232,7 +232,7 @@ def test_render_c2_in_the_benchmark_configuration():
     from paper_2602_03207_amd.pipeline import GaussianTensors
     scene, cam = scenegen.c2()
     g = GaussianTensors.from_scene(scene)
-    ref = oracle.render(scene, cam, oracle_options(sh_degree=3))
+    ref = oracle.render(scene, cam, oracle_options(sh_degree=3), outcomes=True)
     flags = B.WS_FLAG_DEPTH_FIRST | B.WS_FLAG_KEYS32
     for tile, bins, rb in (((16, 16), (4, 2), 7), ((16, 16), (2, 2), 6), ((32, 16), (1, 1), 6)):
         print(f"C2 benchmark layout: tile {tile} bins {bins} radix {rb}", flush=True)
@@ -270,11 +270,8 @@ def test_render_c3_sampled_pixels():
     rng = np.random.default_rng(31)
     mask = np.zeros((cam.height, cam.width), np.uint8)
     mask.reshape(-1)[rng.choice(cam.height * cam.width, 4000, replace=False)] = 1
-    ref = oracle.render(scene, cam, ro, mask=mask)
-    sel = mask.astype(bool)
-    sub = {k: (v[:, sel] if v.ndim == 3 else v[sel]) for k, v in ref.items()
-           if k in ("rgb", "alpha_margin", "t_margin")}
-    worst, frac = assert_image_parity(img[:, sel], sub)
+    ref = oracle.render(scene, cam, ro, mask=mask, outcomes=True)
+    worst, frac = assert_image_parity(img, ref, sel=mask.astype(bool))
     # the fastest 4K layout (16x16 tiles in 4x2 bins, 32-bit keys, device-sized sequence): the same image
     m_gpu = r.num_pairs
     del r
@@ -317,11 +314,8 @@ def test_render_c4_all_views_one_launch_sampled_pixels():
         img = r.image(v).cpu().numpy()
         mask = np.zeros((cam.height, cam.width), np.uint8)
         mask.reshape(-1)[rng.choice(cam.height * cam.width, 2000, replace=False)] = 1
-        ref = oracle.render(scene, cam, ro, mask=mask)
-        sel = mask.astype(bool)
-        sub = {k: (val[:, sel] if val.ndim == 3 else val[sel]) for k, val in ref.items()
-               if k in ("rgb", "alpha_margin", "t_margin")}
-        worst, frac = assert_image_parity(img[:, sel], sub)
+        ref = oracle.render(scene, cam, ro, mask=mask, outcomes=True)
+        worst, frac = assert_image_parity(img, ref, sel=mask.astype(bool))
         print(f"C4 view {v} ({cam.width}x{cam.height}): worst {worst:.2e}, flagged {frac:.2e}")
     images = r.images.clone()
     del r
@@ -384,7 +378,7 @@ def test_ordered_persistent_render_equals_plain(tile):
     assert ordered.status() == 0
     assert np.array_equal(ordered.images.cpu().numpy().view(np.uint32), plain.images.cpu().numpy().view(np.uint32))
     # and against the oracle on the first view
-    ref = oracle.render(scene, cams[0], oracle_options(*tile))
+    ref = oracle.render(scene, cams[0], oracle_options(*tile), outcomes=True)
     assert_image_parity(ordered.image(0).cpu().numpy(), ref)
 
 
@@ -395,6 +389,6 @@ def test_ablation_flags_match_oracle(flags):
                                   logit_sd=2.5, sh_degree=1, dc_sd=0.5, rest_sd=0.2)
     cam = scenegen.look_at([0.3, 0.2, -1.4], [0, 0, 0.5], 150, 110)
     r = _full(scene, [cam], flags=flags)
-    ref = oracle.render(scene, cam, oracle_options(sh_degree=1, flags=flags))
+    ref = oracle.render(scene, cam, oracle_options(sh_degree=1, flags=flags), outcomes=True)
     assert r.num_pairs == ref["keys"].size
     assert_image_parity(r.image(0).cpu().numpy(), ref)

@@ -604,3 +604,90 @@ def test_p17_non_finite_colour_culls_as_degenerate():
         img = oracle.render(sc, cam, opts, mode=mode)["rgb"]
         ref = oracle.render(alone, cam, opts, mode=mode)["rgb"]
         assert np.all(np.isfinite(img)) and np.array_equal(img, ref), mode
+
+
+def _real_sh_from_complex(l, m, d):
+    """Real SH of reading A10 built from scipy's complex Y_l^|m| (which carries the Condon-Shortley phase):
+    sqrt(2) Re for m > 0, sqrt(2) Im for m < 0, Y_l^0 for m = 0.  Independent of the oracle's polynomials."""
+    from scipy.special import sph_harm_y
+    theta = math.acos(max(-1.0, min(1.0, d[2])))
+    phi = math.atan2(d[1], d[0])
+    c = complex(sph_harm_y(l, abs(m), theta, phi))
+    if m == 0:
+        return c.real
+    return math.sqrt(2.0) * (c.real if m > 0 else c.imag)
+
+
+def test_p9c_sh_every_term_against_scipy():
+    """Every basis function Y_k, k = l^2 + l + m (degrees 0-3), value and sign, equals the real SH built from
+    scipy's complex spherical harmonics under reading A10.  A sign flip, a swap of two functions of one degree,
+    a wrong constant or a wrong index fails here (orthonormality alone is blind to the first two)."""
+    rng = np.random.default_rng(2602)
+    dirs = [np.array(v, float) for v in ([1, 0, 0], [0, 1, 0], [0, 0, 1], [-1, 0, 0], [0, -1, 0], [0, 0, -1])]
+    for _ in range(200):
+        v = rng.standard_normal(3)
+        dirs.append(v / np.linalg.norm(v))
+    worst = 0.0
+    for d in dirs:
+        Y = oracle.sh_basis(d, 3)
+        for l in range(4):
+            for m in range(-l, l + 1):
+                want = _real_sh_from_complex(l, m, d)
+                worst = max(worst, abs(Y[l * l + l + m] - want))
+    assert worst < 1e-13, worst
+    # the basis at a lower degree is the prefix of the degree-3 basis
+    for deg in range(3):
+        assert np.array_equal(oracle.sh_basis(dirs[7], deg), oracle.sh_basis(dirs[7], 3)[: (deg + 1) ** 2])
+
+
+def test_p9d_sh_terms_at_chosen_directions():
+    """Hand-derived values of degree 2-3 terms (sign and index) where only one or two terms are nonzero."""
+    s = 1.0 / math.sqrt(2.0)
+    # d = (1, 1, 0)/sqrt 2: xy = 1/2, z = 0
+    Y = oracle.sh_basis(np.array([s, s, 0.0]), 3)
+    assert abs(Y[4] - 0.5 * math.sqrt(15 / PI) * 0.5) < 1e-15          # m = -2: xy term, positive
+    assert abs(Y[5]) < 1e-15 and abs(Y[7]) < 1e-15 and abs(Y[14]) < 1e-15 and abs(Y[10]) < 1e-15
+    assert abs(Y[8]) < 1e-15                                             # x^2 - y^2 = 0
+    # d = (1, 0, 1)/sqrt 2: xz = 1/2, y = 0
+    Y = oracle.sh_basis(np.array([s, 0.0, s]), 3)
+    assert abs(Y[7] + 0.5 * math.sqrt(15 / PI) * 0.5) < 1e-15          # m = +1 carries the Condon-Shortley minus
+    assert abs(Y[5]) < 1e-15 and abs(Y[4]) < 1e-15 and abs(Y[9]) < 1e-15 and abs(Y[11]) < 1e-15
+    # d = +x: the m = +3 cubic is -k3a x (x^2 - 3y^2) = -k3a; m = +1 cubic is -k3c x (4z^2 - x^2 - y^2) = +k3c
+    Y = oracle.sh_basis(np.array([1.0, 0.0, 0.0]), 3)
+    assert abs(Y[15] + 0.25 * math.sqrt(35 / (2 * PI))) < 1e-15
+    assert abs(Y[13] - 0.25 * math.sqrt(21 / (2 * PI))) < 1e-15
+    assert abs(Y[8] - 0.25 * math.sqrt(15 / PI)) < 1e-15               # m = +2: x^2 - y^2 = 1
+    # d = +y: the m = -3 cubic is -k3a y (3x^2 - y^2) = +k3a
+    Y = oracle.sh_basis(np.array([0.0, 1.0, 0.0]), 3)
+    assert abs(Y[9] - 0.25 * math.sqrt(35 / (2 * PI))) < 1e-15
+    # d = +z: only the m = 0 terms survive, each sqrt((2l+1)/4pi)
+    Y = oracle.sh_basis(np.array([0.0, 0.0, 1.0]), 3)
+    for l in range(4):
+        for m in range(-l, l + 1):
+            want = math.sqrt((2 * l + 1) / (4 * PI)) if m == 0 else 0.0
+            assert abs(Y[l * l + l + m] - want) < 1e-15, (l, m)
+
+
+def test_p18_l1_loss_hand_computed():
+    """L1 of reading A19 on a hand-computed batch: the mean over every element of every view, sign(0) = 0."""
+    img = np.array([1.0, 2.0, 3.0, 4.0])
+    tgt = np.array([1.0, 0.0, 5.0, 4.5])
+    loss, g = oracle.l1_loss_grad(img, tgt)
+    assert loss == (0 + 2 + 2 + 0.5) / 4
+    assert np.array_equal(g, [0.0, 0.25, -0.25, -0.25])
+    # two views of different sizes: one mean over all 6 elements, not a mean of per-view means
+    v0, t0 = np.array([[0.5, 0.5]]), np.array([[0.25, 0.5]])
+    v1, t1 = np.array([1.0, 1.0, 1.0, 2.0]), np.array([0.0, 3.0, 1.0, 2.0])
+    loss, (g0, g1) = oracle.l1_loss_grad([v0, v1], [t0, t1])
+    assert loss == (0.25 + 0 + 1 + 2 + 0 + 0) / 6
+    assert g0.shape == (1, 2) and np.array_equal(g0, [[1 / 6, 0.0]])
+    assert np.array_equal(g1, [1 / 6, -1 / 6, 0.0, 0.0])
+    # the gradient is the subgradient: finite differences away from the kinks
+    rng = np.random.default_rng(9)
+    a, b = rng.normal(size=50), rng.normal(size=50)
+    _, ga = oracle.l1_loss_grad(a, b)
+    for i in range(0, 50, 7):
+        e = np.zeros(50)
+        e[i] = 1e-7
+        fd = (oracle.l1_loss_grad(a + e, b)[0] - oracle.l1_loss_grad(a - e, b)[0]) / 2e-7
+        assert abs(fd - ga[i]) < 1e-9
