@@ -91,6 +91,9 @@ typedef struct ws_camera {
                                         emission order already is the depth order); ws_sort32 on bits
                                         [0, end_bit - 32) then gives the same lists; ws_render and
                                         ws_expand_bins read such keys */
+#define WS_FLAG_ACCUMULATE_GRADS 32u  /* ws_render_backward: add the gradients to `grads` instead of
+                                         overwriting them (a batch rendered by several calls, e.g. one view
+                                         each, then sums its gradients in the library) */
 
 typedef struct ws_options {
     int32_t tile_w, tile_h;   /* 16x16 (default), 8x8, 16x8 or 32x16 pixels */
@@ -270,17 +273,27 @@ ws_status ws_render(const ws_splat* splats, int64_t n, const ws_camera* cams, co
  * then walks back to front; no per-pixel state is stored by the forward.
  * Discrete decisions (culls, skips, early stop, clamps) take the derivative
  * of the branch taken.  values / tile_ranges are the lists ws_render read
- * (with bins larger than one tile: ws_expand_bins' tile_values / tile_ranges). */
+ * (with bins larger than one tile: ws_expand_bins' tile_values / tile_ranges).
+ * With WS_FLAG_ACCUMULATE_GRADS in opt->flags the gradients are added to
+ * `grads` instead.  d_status: the forward's status word; if it is non-zero
+ * (the forward did not complete) no kernel writes anything, `grads` included. */
 ws_status ws_render_backward(const ws_gaussians* g, const ws_camera* cams, const ws_camera* d_cams,
                              int32_t n_views, const ws_options* opt, const ws_splat* splats,
                              const uint32_t* values, const uint32_t* tile_ranges, const float* dL_dimages,
                              const int32_t* d_status, ws_gaussian_grads* grads, void* ws, size_t ws_bytes,
                              void* stream);
 
-/* L1 photometric loss: *d_loss = mean |images - targets| over n floats and
- * dL_dimages = sign(images - targets) / n (sign(0) = 0).  Deterministic. */
-ws_status ws_l1_loss(const float* images, const float* targets, int64_t n, float* dL_dimages, float* d_loss,
-                     void* ws, size_t ws_bytes, void* stream);
+/* L1 photometric loss of the multi-view training step (the mean over every
+ * image element of the batch).  Over the n floats of this call:
+ *   *d_loss    = sum |images - targets| / total
+ *   dL_dimages = sign(images - targets) / total        (sign(0) = 0)
+ * total is the element count of the whole batch the mean is taken over
+ * (total >= n); 0 means n.  A batch split over several calls (say one view
+ * each) passes the batch's count to every call: the *d_loss values then add
+ * up to the batch loss and the gradients are those of the batch loss.
+ * Deterministic (fixed-order reduction in fp64, rounded once to fp32). */
+ws_status ws_l1_loss(const float* images, const float* targets, int64_t n, int64_t total, float* dL_dimages,
+                     float* d_loss, void* ws, size_t ws_bytes, void* stream);
 size_t ws_l1_loss_workspace_size(int64_t n);
 
 /* ----------------------------------------------------------- HIP graphs */

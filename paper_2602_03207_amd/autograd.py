@@ -28,7 +28,7 @@ class RenderGaussians(torch.autograd.Function):
     @staticmethod
     def backward(ctx, grad_images):
         r: Renderer = ctx.renderer
-        grads = r.backward(ctx.g, grad_images.contiguous(), stream=torch.cuda.current_stream())
+        grads = r.backward(ctx.g, grad_images.contiguous(), stream=torch.cuda.current_stream(), check=True)
         return grads["means"], grads["log_scales"], grads["quats"], grads["opacity_logits"], grads["sh"], None
 
 

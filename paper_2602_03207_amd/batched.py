@@ -10,8 +10,9 @@ are sized from a measured frame with headroom; a replay that would need more
 sets the device status word (checked by `check()`), never writes out of bounds.
 
 `PlainStep` is the reference sequence it is compared with: a host loop over
-views, each a single-view forward (with its pair-count read-back), loss and
-backward, gradients accumulated on the device.
+views, each a single-view forward (with its pair-count read-back), loss (each
+view's share of the batch mean) and backward, whose gradients the library adds
+to the batch's.
 
 `BatchedForward` / `PlainForward` are the forward-only counterparts (many
 views rendered by one captured graph vs one view per launch sequence).
@@ -55,7 +56,7 @@ class BatchedStep:
         s = self.stream
         with torch.cuda.stream(s):
             self.r.forward_capacity(self.g, stream=s)
-            B.ws_l1_loss(self.r.images, self.targets, self.r.image_floats, self.dL, self.loss, self.ws_loss,
+            B.ws_l1_loss(self.r.images, self.targets, self.r.image_floats, 0, self.dL, self.loss, self.ws_loss,
                          self.ws_loss.numel(), s)
             self.r.backward(self.g, self.dL, grads=self.grads, stream=s)
 
@@ -102,21 +103,17 @@ class PlainStep:
         self.ws_loss = torch.empty(max(B.ws_l1_loss_workspace_size(max(sizes)), 256), dtype=torch.uint8,
                                    device=device)
         self.grads = _zero_grads(g)
-        self.view_grads = _zero_grads(g)
 
     def step(self, stream=None):
         for k in self.grads:
             self.grads[k].zero_()
         for v, r in enumerate(self.renderers):
             r.forward(self.g, stream=stream)
-            n = r.image_floats
-            B.ws_l1_loss(r.images, self.targets[v], n, self.dL[v], self.loss[v:v + 1], self.ws_loss,
-                         self.ws_loss.numel(), stream)
-            # the batch loss is the mean over all views' pixels: rescale the per-view mean
-            self.dL[v].mul_(n / self.total)
-            r.backward(self.g, self.dL[v], grads=self.view_grads, stream=stream)
-            for k in self.grads:
-                self.grads[k].add_(self.view_grads[k])
+            # each view's share of the batch loss (the mean over every view's elements)
+            B.ws_l1_loss(r.images, self.targets[v], r.image_floats, self.total, self.dL[v], self.loss[v:v + 1],
+                         self.ws_loss, self.ws_loss.numel(), stream)
+            # the library adds each view's gradients to the batch's (WS_FLAG_ACCUMULATE_GRADS)
+            r.backward(self.g, self.dL[v], grads=self.grads, stream=stream, accumulate=True)
         return self.grads
 
     def images(self):

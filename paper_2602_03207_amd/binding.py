@@ -29,6 +29,7 @@ WS_FLAG_NO_VIEWPORT_CULL = 2
 WS_FLAG_ORDERED_RENDER = 4
 WS_FLAG_DEPTH_FIRST = 8
 WS_FLAG_KEYS32 = 16
+WS_FLAG_ACCUMULATE_GRADS = 32
 
 EXPORTED = [
     "ws_preprocess_workspace_size", "ws_sort_workspace_size", "ws_render_workspace_size",
@@ -118,7 +119,7 @@ def load():
                               vp]
     lib.ws_render_backward.argtypes = [P(ws_gaussians), P(ws_camera), vp, i32, P(ws_options), vp, vp, vp, vp, vp,
                                        P(ws_gaussian_grads), vp, sz, vp]
-    lib.ws_l1_loss.argtypes = [vp, vp, i64, vp, vp, vp, sz, vp]
+    lib.ws_l1_loss.argtypes = [vp, vp, i64, i64, vp, vp, vp, sz, vp]
     lib.ws_graph_begin.argtypes = [vp]
     lib.ws_graph_end.argtypes = [vp, P(vp)]
     lib.ws_graph_launch.argtypes = [vp, vp]
@@ -299,9 +300,9 @@ def ws_render_backward(g, cams, d_cams, n_views, opt, splats, values, tile_range
                                      C.byref(grads), _ptr(ws), ws_bytes, _stream(stream)))
 
 
-def ws_l1_loss(images, targets, n, dL_dimages, d_loss, ws, ws_bytes, stream=None):
-    _check(load().ws_l1_loss(_ptr(images), _ptr(targets), n, _ptr(dL_dimages), _ptr(d_loss), _ptr(ws), ws_bytes,
-                             _stream(stream)))
+def ws_l1_loss(images, targets, n, total, dL_dimages, d_loss, ws, ws_bytes, stream=None):
+    _check(load().ws_l1_loss(_ptr(images), _ptr(targets), n, total, _ptr(dL_dimages), _ptr(d_loss), _ptr(ws),
+                             ws_bytes, _stream(stream)))
 
 
 def ws_graph_begin(stream):

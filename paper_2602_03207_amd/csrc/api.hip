@@ -49,7 +49,7 @@ ws_status check_options(const ws_options* o) {
         if (b != 0 && b != 1 && b != 2 && b != 4 && b != 8)
             return fail(WS_ERR_INVALID_ARGUMENT, "bin_x / bin_y must be 1, 2, 4 or 8 (0 reads as 1), got %d", b);
     if (o->flags & ~(WS_FLAG_FIXED_3SIGMA | WS_FLAG_NO_VIEWPORT_CULL | WS_FLAG_ORDERED_RENDER | WS_FLAG_DEPTH_FIRST |
-                     WS_FLAG_KEYS32))
+                     WS_FLAG_KEYS32 | WS_FLAG_ACCUMULATE_GRADS))
         return fail(WS_ERR_INVALID_ARGUMENT, "unknown flag bits 0x%x", o->flags);
     if ((o->flags & WS_FLAG_KEYS32) && !(o->flags & WS_FLAG_DEPTH_FIRST))
         return fail(WS_ERR_INVALID_ARGUMENT, "WS_FLAG_KEYS32 needs WS_FLAG_DEPTH_FIRST (the keys carry no depth)");
@@ -445,13 +445,17 @@ ws_status ws_render_backward(const ws_gaussians* g, const ws_camera* cams, const
     return hip_status(e, "ws_render_backward launch");
 }
 
-ws_status ws_l1_loss(const float* images, const float* targets, int64_t n, float* dL_dimages, float* d_loss,
-                     void* ws, size_t ws_bytes, void* stream) {
+ws_status ws_l1_loss(const float* images, const float* targets, int64_t n, int64_t total, float* dL_dimages,
+                     float* d_loss, void* ws, size_t ws_bytes, void* stream) {
     if (n < 1) return fail(WS_ERR_INVALID_ARGUMENT, "n must be >= 1");
+    if (total == 0) total = n;
+    if (total < n)
+        return fail(WS_ERR_INVALID_ARGUMENT, "total (%lld) must be 0 or >= n (%lld)", (long long)total, (long long)n);
     if (!images || !targets || !dL_dimages || !d_loss) return fail(WS_ERR_INVALID_ARGUMENT, "a pointer is NULL");
     ws_status s;
     if ((s = check_ws(ws, ws_bytes, ws::l1_loss_workspace(n))) != WS_OK) return s;
-    const hipError_t e = ws::launch_l1_loss(images, targets, n, dL_dimages, d_loss, ws, static_cast<hipStream_t>(stream));
+    const hipError_t e = ws::launch_l1_loss(images, targets, n, total, dL_dimages, d_loss, ws,
+                                          static_cast<hipStream_t>(stream));
     return hip_status(e, "ws_l1_loss launch");
 }
 

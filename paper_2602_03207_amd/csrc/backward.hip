@@ -277,7 +277,12 @@ struct PreBwdArgs {
     KOpts o;
     BwdWs w;
     GradPtrs out;
+    const int32_t* d_status;
 };
+
+// A gradient value written out: stored, or added to the caller's value with
+// WS_FLAG_ACCUMULATE_GRADS.
+__device__ __forceinline__ void put_grad(float* p, float v, bool acc) { *p = acc ? *p + v : v; }
 
 // Derivatives of the rotation matrix of a unit quaternion (w, x, y, z):
 // returns sum_ij G_ij dR_ij/dq_c for c = w, x, y, z.
@@ -299,7 +304,7 @@ template <int DEG>
 __global__ __launch_bounds__(128) void k_preprocess_bwd_geo(PreBwdArgs a) {
     const int64_t i = int64_t(blockIdx.x) * 128 + threadIdx.x;
     const int64_t n = a.g.n;
-    if (i >= n) return;
+    if (i >= n || *a.d_status != 0) return;
     float gm[3] = {0.f, 0.f, 0.f}, gls[3] = {0.f, 0.f, 0.f}, gq[4] = {0.f, 0.f, 0.f, 0.f}, glogit = 0.f;
     for (int32_t v = 0; v < a.n_views; ++v) {
         const int64_t vi = int64_t(v) * n + i;
@@ -390,14 +395,15 @@ __global__ __launch_bounds__(128) void k_preprocess_bwd_geo(PreBwdArgs a) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) gm[c] += cam.R[0 * 3 + c] * gpx + cam.R[1 * 3 + c] * gpy + cam.R[2 * 3 + c] * gpz;
     }
+    const bool acc = (a.o.flags & WS_FLAG_ACCUMULATE_GRADS) != 0;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        a.out.means[c * n + i] = gm[c];
-        a.out.log_scales[c * n + i] = gls[c];
+        put_grad(&a.out.means[c * n + i], gm[c], acc);
+        put_grad(&a.out.log_scales[c * n + i], gls[c], acc);
     }
 #pragma unroll
-    for (int c = 0; c < 4; ++c) a.out.quats[c * n + i] = gq[c];
-    a.out.logits[i] = glogit;
+    for (int c = 0; c < 4; ++c) put_grad(&a.out.quats[c * n + i], gq[c], acc);
+    put_grad(&a.out.logits[i], glogit, acc);
 }
 
 
@@ -412,7 +418,7 @@ template <int DEG>
 __global__ __launch_bounds__(128) void k_preprocess_bwd_sh(PreBwdArgs a) {
     const int64_t i = int64_t(blockIdx.x) * 128 + threadIdx.x;
     const int64_t n = a.g.n;
-    if (i >= n) return;
+    if (i >= n || *a.d_status != 0) return;
     constexpr int K = (DEG + 1) * (DEG + 1);
     float gm[3] = {0.f, 0.f, 0.f};
     float gsh[3 * K];
@@ -462,8 +468,9 @@ __global__ __launch_bounds__(128) void k_preprocess_bwd_sh(PreBwdArgs a) {
     }
 #pragma unroll
     for (int c = 0; c < 3; ++c) a.out.means[c * n + i] += gm[c];
+    const bool acc = (a.o.flags & WS_FLAG_ACCUMULATE_GRADS) != 0;
 #pragma unroll
-    for (int k = 0; k < 3 * K; ++k) a.out.sh[int64_t(k) * n + i] = gsh[k];
+    for (int k = 0; k < 3 * K; ++k) put_grad(&a.out.sh[int64_t(k) * n + i], gsh[k], acc);
 }
 
 template <int TW, int TH>
@@ -512,6 +519,7 @@ hipError_t launch_render_backward(const GaussPtrs& g, const ws_camera* d_cams, i
     pa.o = o;
     pa.w = w;
     pa.out = grads;
+    pa.d_status = d_status;
     const dim3 grid(uint32_t((g.n + 127) / 128));
     timing_begin(WS_KERNEL_PREPROCESS_BWD, stream);
     // geometry first (writes the mean gradient), then colour (adds to it)

@@ -1,5 +1,6 @@
 // L1 photometric loss and its gradient, reduced in a fixed order so that the
-// loss value is identical on every run.
+// loss value is identical on every run.  The mean is taken over `total`
+// elements (the whole batch), of which one call sees n.
 #include "ws_internal.h"
 
 namespace ws {
@@ -9,15 +10,14 @@ constexpr int kLossThreads = 256;
 constexpr int kLossBlocks = 1024;
 
 __global__ __launch_bounds__(kLossThreads) void k_l1_partial(const float* __restrict__ img,
-                                                             const float* __restrict__ tgt, int64_t n,
+                                                             const float* __restrict__ tgt, int64_t n, float inv_total,
                                                              float* __restrict__ dL, double* __restrict__ partial) {
     __shared__ double s_part[kLossThreads / kWave];
-    const float inv_n = float(1.0 / double(n));
     double acc = 0.0;
     const int64_t stride = int64_t(gridDim.x) * kLossThreads;
     for (int64_t i = int64_t(blockIdx.x) * kLossThreads + threadIdx.x; i < n; i += stride) {
         const float d = img[i] - tgt[i];
-        dL[i] = d > 0.f ? inv_n : (d < 0.f ? -inv_n : 0.f);
+        dL[i] = d > 0.f ? inv_total : (d < 0.f ? -inv_total : 0.f);
         acc += double(fabsf(d));
     }
     acc = wave_sum(acc);
@@ -30,7 +30,7 @@ __global__ __launch_bounds__(kLossThreads) void k_l1_partial(const float* __rest
     }
 }
 
-__global__ __launch_bounds__(kLossThreads) void k_l1_final(const double* __restrict__ partial, int nb, int64_t n,
+__global__ __launch_bounds__(kLossThreads) void k_l1_final(const double* __restrict__ partial, int nb, int64_t total,
                                                            float* __restrict__ loss) {
     __shared__ double s_part[kLossThreads / kWave];
     double acc = 0.0;
@@ -41,7 +41,7 @@ __global__ __launch_bounds__(kLossThreads) void k_l1_final(const double* __restr
     if (threadIdx.x == 0) {
         double s = 0.0;
         for (int w = 0; w < kLossThreads / kWave; ++w) s += s_part[w];
-        *loss = float(s / double(n));
+        *loss = float(s / double(total));
     }
 }
 
@@ -52,12 +52,14 @@ size_t l1_loss_workspace(int64_t n) {
     return align_up(kLossBlocks * sizeof(double));
 }
 
-hipError_t launch_l1_loss(const float* images, const float* targets, int64_t n, float* dL, float* d_loss, void* ws,
-                          hipStream_t stream) {
+hipError_t launch_l1_loss(const float* images, const float* targets, int64_t n, int64_t total, float* dL,
+                          float* d_loss, void* ws, hipStream_t stream) {
     double* partial = static_cast<double*>(ws);
-    hipLaunchKernelGGL(k_l1_partial, dim3(kLossBlocks), dim3(kLossThreads), 0, stream, images, targets, n, dL,
-                       partial);
-    hipLaunchKernelGGL(k_l1_final, dim3(1), dim3(kLossThreads), 0, stream, partial, kLossBlocks, n, d_loss);
+    // 1 / total rounded once from fp64, the value every gradient element takes
+    const float inv_total = float(1.0 / double(total));
+    hipLaunchKernelGGL(k_l1_partial, dim3(kLossBlocks), dim3(kLossThreads), 0, stream, images, targets, n, inv_total,
+                       dL, partial);
+    hipLaunchKernelGGL(k_l1_final, dim3(1), dim3(kLossThreads), 0, stream, partial, kLossBlocks, total, d_loss);
     return hipGetLastError();
 }
 

@@ -280,8 +280,8 @@ hipError_t launch_render_backward(const GaussPtrs& g, const ws_camera* d_cams, i
 size_t render_backward_workspace(int64_t n, int32_t n_views);
 
 // loss.hip
-hipError_t launch_l1_loss(const float* images, const float* targets, int64_t n, float* dL, float* d_loss, void* ws,
-                          hipStream_t stream);
+hipError_t launch_l1_loss(const float* images, const float* targets, int64_t n, int64_t total, float* dL,
+                          float* d_loss, void* ws, hipStream_t stream);
 size_t l1_loss_workspace(int64_t n);
 
 // Benchmark timing hooks (defined in api.hip): no-ops unless ws_timing_start

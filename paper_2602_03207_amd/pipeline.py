@@ -209,7 +209,12 @@ class Renderer:
 
     # ------------------------------------------------------- sequences
     def forward(self, g: GaussianTensors, stream=None) -> int:
-        """Plain path: returns the pair count M (read back once per frame)."""
+        """Plain path: returns the pair count M (read back once per frame).
+
+        The device status word is read after the pre-processing (with M) and
+        again after the render, so a sort or render that did not complete (an
+        expired bounded wait) raises WsError instead of leaving stale images.
+        """
         self.d_status.zero_()
         self.preprocess(g, stream)
         m = int(self.d_num_pairs.item())
@@ -222,6 +227,7 @@ class Renderer:
         if m > 0:
             self.sort(m, stream=stream)
         self.render(m, stream)
+        self._check_status()
         return m
 
     def forward_capacity(self, g: GaussianTensors, stream=None):
@@ -231,10 +237,14 @@ class Renderer:
         self.sort(self.capacity, device_count=True, stream=stream)
         self.render(self.capacity, stream)
 
-    def backward(self, g: GaussianTensors, dL_dimages: torch.Tensor, grads=None, stream=None):
+    def backward(self, g: GaussianTensors, dL_dimages: torch.Tensor, grads=None, stream=None, accumulate=False,
+                 check=False):
         """Parameter gradients of the last forward for dL/dimages (same layout as self.images).
 
-        Returns a dict of tensors shaped like the parameters; `grads` may supply them.
+        Returns a dict of tensors shaped like the parameters; `grads` may supply them.  With `accumulate` the
+        library adds the gradients to `grads` (WS_FLAG_ACCUMULATE_GRADS) instead of overwriting them.  If the
+        forward's status word is set, the library writes nothing; `check` reads it afterwards (a host
+        synchronisation) and raises WsError.
         """
         if grads is None:
             grads = dict(means=torch.empty_like(g.means), log_scales=torch.empty_like(g.log_scales),
@@ -243,8 +253,14 @@ class Renderer:
         need = B.ws_render_backward_workspace_size(g.n, self.n_views)
         ws = self.ws_bwd.get(need)
         gs = B.make_grads(grads["means"], grads["log_scales"], grads["quats"], grads["opacity_logits"], grads["sh"])
-        B.ws_render_backward(g.struct(), self.cam_arr, self.d_cams, self.n_views, self.opts, self.splats, self.lists,
+        opts = self.opts
+        if accumulate:
+            opts = B.ws_options.from_buffer_copy(self.opts)
+            opts.flags |= B.WS_FLAG_ACCUMULATE_GRADS
+        B.ws_render_backward(g.struct(), self.cam_arr, self.d_cams, self.n_views, opts, self.splats, self.lists,
                              self.tile_ranges, dL_dimages, self.d_status, gs, ws, ws.numel(), stream)
+        if check:
+            self._check_status()
         return grads
 
     def _check_status(self):

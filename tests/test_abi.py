@@ -113,6 +113,35 @@ def _err(lib):
     return lib.ws_last_error().decode()
 
 
+def test_l1_loss_rejects_bad_arguments_on_the_host(lib):
+    vp = C.c_void_p
+    a, b, c, d, ws = vp(0x100000), vp(0x200000), vp(0x300000), vp(0x400000), vp(0x500000)
+    need = lib.ws_l1_loss_workspace_size(100)
+    # the batch's element count may not be below the call's
+    st = lib.ws_l1_loss(a, b, 100, 99, c, d, ws, need, None)
+    assert st == B.WS_ERR_INVALID_ARGUMENT and "total" in _err(lib)
+    assert lib.ws_l1_loss(a, b, 100, -1, c, d, ws, need, None) == B.WS_ERR_INVALID_ARGUMENT
+    assert lib.ws_l1_loss(a, b, 0, 0, c, d, ws, need, None) == B.WS_ERR_INVALID_ARGUMENT
+    assert lib.ws_l1_loss(a, None, 100, 0, c, d, ws, need, None) == B.WS_ERR_INVALID_ARGUMENT
+    assert lib.ws_l1_loss(a, b, 100, 0, c, d, ws, need - 1, None) == B.WS_ERR_WORKSPACE_TOO_SMALL
+
+
+def test_unknown_flags_are_rejected_and_accumulate_is_known(lib):
+    vp = C.c_void_p
+    g = B.ws_gaussians()
+    g.n = 0
+    cams = (B.ws_camera * 1)(_cam(64, 64))
+    # the options pass validation with the accumulate flag: the call fails later, on the capacity
+    o = _opts(flags=B.WS_FLAG_ACCUMULATE_GRADS)
+    st = lib.ws_preprocess(C.byref(g), cams, vp(0x100000), 1, C.byref(o), None, None, None, None, -1,
+                           vp(0x200000), vp(0x300000), vp(0x400000), 1 << 20, None)
+    assert st == B.WS_ERR_INVALID_ARGUMENT and "capacity" in _err(lib)
+    o.flags = 1 << 20
+    st = lib.ws_preprocess(C.byref(g), cams, vp(0x100000), 1, C.byref(o), None, None, None, None, -1,
+                           vp(0x200000), vp(0x300000), vp(0x400000), 1 << 20, None)
+    assert st == B.WS_ERR_INVALID_ARGUMENT and "flag" in _err(lib)
+
+
 def test_sort_rejects_bad_arguments_on_the_host(lib):
     vp = C.c_void_p
     a, b, c, d = vp(0x100000), vp(0x200000), vp(0x300000), vp(0x400000)

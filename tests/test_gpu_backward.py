@@ -33,7 +33,10 @@ def _oracle_grads(scene, cams, dL_views, ropts):
     return tot
 
 
-def _compare(got, want, rel=1e-3, elem_frac=0.999):
+def _compare(got, want, rel=1e-3, elem_frac=0.999, outlier_rel=1e-2):
+    """Reading A24: per tensor ||g - g*|| / ||g*|| <= rel; per element |g - g*| <= rel * max(|g*|, rms g*) on at
+    least elem_frac of the elements, and every element within outlier_rel of that scale (the remaining elements
+    are those of splats with a decision near its threshold at some pixel, where fp32 and fp64 may differ)."""
     for k in NAMES:
         g, w = got[k].reshape(-1), want[k].reshape(-1)
         nrm = np.linalg.norm(w)
@@ -43,8 +46,13 @@ def _compare(got, want, rel=1e-3, elem_frac=0.999):
         err = np.linalg.norm(g - w) / nrm
         assert err <= rel, f"{k}: relative error {err:.2e}"
         scale = np.maximum(np.abs(w), np.sqrt(np.mean(w * w)))
-        ok = np.abs(g - w) <= rel * scale
+        ratio = np.abs(g - w) / scale
+        ok = ratio <= rel
+        worst = int(np.argmax(ratio))
+        print(f"{k}: norm error {err:.2e}, {np.count_nonzero(~ok)} of {ok.size} elements above {rel:g}, worst "
+              f"element {worst}: {ratio[worst]:.2e} of its scale (gpu {g[worst]:.6e}, oracle {w[worst]:.6e})")
         assert ok.mean() >= elem_frac, f"{k}: {np.count_nonzero(~ok)} of {ok.size} elements off"
+        assert ratio[worst] <= outlier_rel, f"{k}: element {worst} off by {ratio[worst]:.2e} of its scale"
 
 
 def test_backward_fd_scene_matches_oracle():

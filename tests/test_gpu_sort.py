@@ -101,3 +101,56 @@ def test_sort_oracle_key_buffer_1m_scene():
     for rb in (8, 6):
         got_k, got_v = _gpu_sort(keys, vals, 0, end_bit, rb)
         assert np.array_equal(got_k, want_k) and np.array_equal(got_v, want_v), rb
+
+
+@pytest.mark.slow
+def test_sort_oracle_key_buffer_6m_scene_both_key_widths():
+    """The oracle's pair buffer of the 6M-Gaussian 4K view (about 49 M pairs, 12 011 sort tiles of 4096 pairs:
+    the digit tables of its passes take the three-level scan), bit-exact against std::stable_sort and identical
+    run to run: the 64-bit (tile | depth) sort over the tile and depth bits, and the depth-first variant (pairs
+    stably ordered by depth first, then 32-bit tile keys sorted by ws_sort32 on the tile bits)."""
+    import torch
+    from paper_2602_03207_amd import binding as B
+    scene, cam = scenegen.c3()
+    keys, vals = oracle.emit(scene, cam, oracle.Options(sh_degree=3))
+    n = keys.size
+    assert 40_000_000 <= n <= 60_000_000
+    tile_bits = int(np.ceil(np.log2(240 * 135)))
+    end_bit = 32 + tile_bits
+    sort_tiles = -(-n // 4096)
+    # the digit table (radix x tiles) of an 8-bit pass is scanned in blocks of 1024 entries: more than 1024
+    # blocks take the three-level schedule
+    assert 256 * sort_tiles > 1024 * 1024
+    want_k, want_v = oracle.stable_sort(keys, vals, 0, end_bit)
+    print(f"6M scene: {n} pairs, {sort_tiles} sort tiles", flush=True)
+    runs = [_gpu_sort(keys, vals, 0, end_bit, 8) for _ in range(2)]
+    for got_k, got_v in runs:
+        assert np.array_equal(got_k, want_k) and np.array_equal(got_v, want_v)
+    del runs
+    # depth-first: the stable depth order of the emitted pairs, then the tile bits alone as 32-bit keys
+    dk, dv = oracle.stable_sort(keys, vals, 0, 32)
+    del keys, vals
+    tiles32 = (dk >> np.uint64(32)).astype(np.uint32)
+    del dk
+    want_t = (want_k >> np.uint64(32)).astype(np.uint32)
+    del want_k
+    kin = torch.from_numpy(tiles32.view(np.int32)).cuda()
+    vin = torch.from_numpy(dv.view(np.int32)).cuda()
+    outs = []
+    for rb in (8, 8, 5):
+        kout = torch.full((n,), -1, dtype=torch.int32, device="cuda")
+        vout = torch.full((n,), -1, dtype=torch.int32, device="cuda")
+        d_status = torch.zeros(1, dtype=torch.int32, device="cuda")
+        need = B.ws_sort32_workspace_size(n, 0, tile_bits, rb)
+        ws = torch.empty(need + 256, dtype=torch.uint8, device="cuda")
+        print(f"ws_sort32 of {n} tile keys, radix {rb}", flush=True)
+        B.ws_sort32(kin, vin, kout, vout, n, None, d_status, 0, tile_bits, rb, ws, ws.numel())
+        torch.cuda.synchronize()
+        assert int(d_status.item()) == 0
+        outs.append((kout.cpu().numpy().view(np.uint32), vout.cpu().numpy().view(np.uint32)))
+        del kout, vout, ws
+    for got_k, got_v in outs:
+        # the same lists as the full-key sort (reading A28) ...
+        assert np.array_equal(got_k, want_t) and np.array_equal(got_v, want_v)
+    # ... and identical bits run to run
+    assert np.array_equal(outs[0][1], outs[1][1])
