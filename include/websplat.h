@@ -220,6 +220,20 @@ ws_status ws_sort(const uint64_t* keys_in, const uint32_t* values_in, uint64_t* 
                   int64_t n, const int64_t* d_n, const int32_t* d_status, int32_t begin_bit, int32_t end_bit,
                   int32_t radix_bits, void* ws, size_t ws_bytes, void* stream);
 
+/* ws_sort without a workspace, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation).  Same contract and kernels as ws_sort, for n <= 2^20 pairs (n
+ * is the capacity when d_n != NULL); larger n returns WS_ERR_INVALID_ARGUMENT
+ * with a message.  Its scratch memory is a 24 MiB device array inside the
+ * library, one per GPU, held until the process ends; the call allocates
+ * nothing (no hipMalloc, no hipFree).  Every call on a GPU uses that GPU's one
+ * array, so calls that overlap in time on one GPU (different streams or
+ * threads) race: serialise them.  The first call on a device looks the
+ * array's address up (once per device). */
+ws_status ws_sort_noalloc(const uint64_t* keys_in, const uint32_t* values_in, uint64_t* keys_out,
+                          uint32_t* values_out, int64_t n, const int64_t* d_n, const int32_t* d_status,
+                          int32_t begin_bit, int32_t end_bit, int32_t radix_bits, void* stream);
+
 /* ws_sort on 32-bit keys (Sec. 3.3.2), e.g. the tile ids of WS_FLAG_KEYS32 or
  * fp32 depth bits: same contract, 0 <= begin_bit < end_bit <= 32. */
 ws_status ws_sort32(const uint32_t* keys_in, const uint32_t* values_in, uint32_t* keys_out, uint32_t* values_out,

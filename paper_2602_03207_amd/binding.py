@@ -37,7 +37,7 @@ EXPORTED = [
     "ws_render", "ws_render_backward", "ws_l1_loss", "ws_l1_loss_workspace_size", "ws_graph_begin", "ws_graph_end",
     "ws_graph_launch", "ws_graph_destroy", "ws_last_error", "ws_status_string", "ws_version", "ws_timing_start",
     "ws_timing_stop", "ws_total_bins", "ws_expand_bins_workspace_size", "ws_expand_bins", "ws_sort32",
-    "ws_sort32_workspace_size",
+    "ws_sort32_workspace_size", "ws_sort_noalloc",
 ]
 
 KERNELS = {"preprocess": 0, "scan_emit": 1, "sort_hist": 2, "sort_pass": 3, "ranges": 4, "render": 5,
@@ -115,6 +115,7 @@ def load():
                                   vp, vp, sz, vp]
     lib.ws_sort.argtypes = [vp, vp, vp, vp, i64, vp, vp, i32, i32, i32, vp, sz, vp]
     lib.ws_sort32.argtypes = [vp, vp, vp, vp, i64, vp, vp, i32, i32, i32, vp, sz, vp]
+    lib.ws_sort_noalloc.argtypes = [vp, vp, vp, vp, i64, vp, vp, i32, i32, i32, vp]
     lib.ws_render.argtypes = [vp, i64, P(ws_camera), vp, i32, P(ws_options), vp, vp, i64, vp, vp, vp, vp, vp, sz,
                               vp]
     lib.ws_render_backward.argtypes = [P(ws_gaussians), P(ws_camera), vp, i32, P(ws_options), vp, vp, vp, vp, vp,
@@ -130,7 +131,8 @@ def load():
     lib.ws_version.restype = i32
     lib.ws_timing_start.argtypes = [i32]
     lib.ws_timing_stop.argtypes = [P(C.c_double), P(C.c_int64)]
-    for name in ("ws_timing_start", "ws_timing_stop", "ws_preprocess", "ws_sort", "ws_sort32", "ws_expand_bins",
+    for name in ("ws_timing_start", "ws_timing_stop", "ws_preprocess", "ws_sort", "ws_sort32", "ws_sort_noalloc",
+                 "ws_expand_bins",
                  "ws_render",
                  "ws_render_backward", "ws_l1_loss", "ws_graph_begin",
                  "ws_graph_end", "ws_graph_launch", "ws_graph_destroy"):
@@ -277,6 +279,12 @@ def ws_sort32(keys_in, values_in, keys_out, values_out, n, d_n, d_status, begin_
               ws_bytes, stream=None):
     _check(load().ws_sort32(_ptr(keys_in), _ptr(values_in), _ptr(keys_out), _ptr(values_out), n, _ptr(d_n),
                             _ptr(d_status), begin_bit, end_bit, radix_bits, _ptr(ws), ws_bytes, _stream(stream)))
+
+
+def ws_sort_noalloc(keys_in, values_in, keys_out, values_out, n, d_n, d_status, begin_bit, end_bit, radix_bits,
+                    stream=None):
+    _check(load().ws_sort_noalloc(_ptr(keys_in), _ptr(values_in), _ptr(keys_out), _ptr(values_out), n, _ptr(d_n),
+                                  _ptr(d_status), begin_bit, end_bit, radix_bits, _stream(stream)))
 
 
 def ws_expand_bins(splats, n, cams, d_cams, n_views, opt, keys, values, capacity, d_num_pairs, d_status, tile_values,

@@ -10,7 +10,7 @@ import time
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libwebsplat.so")
-SOURCES = ["api.hip", "preprocess.hip", "sort.hip", "render.hip", "backward.hip", "loss.hip"]
+SOURCES = ["api.hip", "preprocess.hip", "sort.hip", "render.hip", "backward.hip", "loss.hip", "noalloc.hip"]
 ARCH = "gfx950"
 
 

@@ -359,6 +359,22 @@ ws_status ws_sort32(const uint32_t* keys_in, const uint32_t* values_in, uint32_t
                         radix_bits, ws, ws_bytes, stream);
 }
 
+ws_status ws_sort_noalloc(const uint64_t* keys_in, const uint32_t* values_in, uint64_t* keys_out,
+                          uint32_t* values_out, int64_t n, const int64_t* d_n, const int32_t* d_status,
+                          int32_t begin_bit, int32_t end_bit, int32_t radix_bits, void* stream) {
+    if (n < 0 || n > ws::kStaticScratchMaxPairs)
+        return fail(WS_ERR_INVALID_ARGUMENT,
+                    "ws_sort_noalloc: n = %lld exceeds the static scratch's maximum of %lld pairs (use ws_sort)",
+                    (long long)n, (long long)ws::kStaticScratchMaxPairs);
+    if (n == 0) return WS_OK;
+    void* scratch = nullptr;
+    const hipError_t e = ws::static_scratch(&scratch);
+    if (e != hipSuccess) return hip_status(e, "ws_sort_noalloc: static scratch");
+    // the same validation and kernels as ws_sort, with the static scratch as the workspace
+    return sort_checked("ws_sort_noalloc", keys_in, values_in, keys_out, values_out, n, d_n, d_status, begin_bit,
+                        end_bit, radix_bits, scratch, ws::kStaticScratchBytes, stream);
+}
+
 ws_status ws_render(const ws_splat* splats, int64_t n, const ws_camera* cams, const ws_camera* d_cams,
                     int32_t n_views, const ws_options* opt, const void* keys, const uint32_t* values,
                     int64_t capacity, const int64_t* d_num_pairs, const int32_t* d_status, uint32_t* tile_ranges,

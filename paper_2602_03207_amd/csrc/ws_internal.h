@@ -289,6 +289,13 @@ size_t l1_loss_workspace(int64_t n);
 void timing_begin(int kernel, hipStream_t stream);
 void timing_end(int kernel, hipStream_t stream);
 
+// noalloc.hip: the allocation-free sort's scratch, a file-scope device array
+// of kStaticScratchBytes per GPU.  static_scratch() returns its device address
+// on the current device (looked up once per device).
+constexpr int64_t kStaticScratchMaxPairs = int64_t(1) << 20;
+constexpr size_t kStaticScratchBytes = size_t(24) << 20;
+hipError_t static_scratch(void** ptr);
+
 // Round a byte count up to the workspace alignment.
 inline size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 
