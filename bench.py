@@ -242,6 +242,48 @@ def bench_ablations(res, frames=10):
     return out
 
 
+def bench_packed(res, frames=20):
+    """Sec. 3.2's packed render inputs (WS_FLAG_PACKED: fp16 ellipse axes and RGBA8 colour and opacity in
+    32-byte records instead of 48) on the tuned 1080p frame: frame and render times beside the full-precision
+    records, and what the quantisation does to the image."""
+    import torch
+    from paper_2602_03207_amd import binding as B
+    from paper_2602_03207_amd.batched import BatchedForward
+    from paper_2602_03207_amd.pipeline import Renderer
+    g, cam, opts = res["g"], res["cam"], res["opts"]
+    stream = torch.cuda.current_stream()
+    out, imgs = {}, {}
+    for name, extra in (("full", 0), ("packed", B.WS_FLAG_PACKED)):
+        o = B.ws_options.from_buffer_copy(opts)
+        o.flags = opts.flags | extra
+        bf = BatchedForward([cam], o, g)
+        bf.capture()
+        for _ in range(3):
+            bf.replay()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(frames)]
+        for a, b in ev:
+            a.record(bf.stream)
+            bf.replay()
+            b.record(bf.stream)
+        bf.stream.synchronize()
+        bf.check()
+        imgs[name] = bf.r.images.clone()
+        bf.close()
+        r = Renderer([cam], o)
+        r.forward(g, stream)
+        kt = kernel_times(lambda: r.forward(g, stream), ["preprocess", "render"])
+        out[name] = {"record_bytes": B.PACKED_SPLAT_BYTES if extra else B.SPLAT_BYTES,
+                     "frame_ms": round(statistics.median(a.elapsed_time(b) for a, b in ev), 4),
+                     "preprocess_ms": round(kt["preprocess"]["avg_ms"], 4),
+                     "render_ms": round(kt["render"]["avg_ms"], 4)}
+        del r
+    d = (imgs["packed"] - imgs["full"]).abs()
+    out["image_vs_full"] = {"max_abs_diff": round(float(d.max().item()), 5),
+                            "mean_abs_diff": float(d.mean().item()),
+                            "note": "the packing clamps colours to [0, 1] and quantises opacity, colour and the ellipse"}
+    return out
+
+
 def bench_depth_sort(res, iters=20):
     """The paper's own sort workload (Sec. 3.3.2): a stable sort of the visible splats' fp32 depth
     keys of the 1080p frame (32 bits, 4 x 8-bit passes) through ws_sort32, keys already in HBM."""
@@ -667,6 +709,8 @@ def main():
     if not args.no_ablations:
         log("leg: ablations -RADIUS and -CULL (Sec. 4.4)")
         line["ablations"] = bench_ablations(res)
+    log("leg: packed render inputs (Sec. 3.2)")
+    line["packed_records"] = bench_packed(res)
     if not args.no_batched:
         log("leg: batched vs plain fwd+bwd (8 views, 1920x1080)")
         line["batched_fwd_bwd"] = bench_batched(args)

@@ -91,6 +91,11 @@ typedef struct ws_camera {
                                         emission order already is the depth order); ws_sort32 on bits
                                         [0, end_bit - 32) then gives the same lists; ws_render and
                                         ws_expand_bins read such keys */
+#define WS_FLAG_PACKED          64u  /* packed render inputs (Sec. 3.2): ws_preprocess writes ws_splat_packed
+                                        records (32 bytes: fp16 ellipse axes, RGBA8 colour and opacity)
+                                        where `splats` is passed, and ws_expand_bins / ws_render read them;
+                                        colours are clamped to [0, 1] and opacity, colour and the ellipse are
+                                        quantised.  Forward only: ws_render_backward rejects the flag. */
 #define WS_FLAG_ACCUMULATE_GRADS 32u  /* ws_render_backward: add the gradients to `grads` instead of
                                          overwriting them (a batch rendered by several calls, e.g. one view
                                          each, then sums its gradients in the library) */
@@ -141,6 +146,25 @@ typedef struct ws_splat {
     uint16_t rect[4];    /* inclusive pixel rectangle x0, x1, y0, y1 (the culling AABB, clipped) */
 } ws_splat;
 
+/* The packed record of WS_FLAG_PACKED, 32 bytes, 16-byte aligned (Sec. 3.2
+ * packs the ellipse axes as fp16 pairs and colour plus opacity as RGBA8).
+ * Let Sigma' = [[a, b], [b, c]] be the projected covariance with eigenvalues
+ * l1 >= l2 and unit eigenvector v1 = (x, y) of l1 (from (l1 - c, b) when
+ * a >= c, else (b, l1 - a); (1, 0) when Sigma' is a multiple of I) and
+ * v2 = (-y, x).  The axes are sqrt(l1) v1 and sqrt(l2) v2, each component
+ * rounded to IEEE fp16 (nearest even).  The renderer uses the quantised
+ * ellipse Sigma'_q = axis1 axis1^T + axis2 axis2^T, whose determinant is
+ * (axis1 x axis2)^2, and its inverse as the conic.  r, g, b =
+ * floor(255 min(1, colour) + 1/2), a = floor(255 sigma + 1/2); colour and
+ * sigma are these bytes / 255.  Valid only where tiles_touched != 0. */
+typedef struct ws_splat_packed {
+    float mean2d[2];     /* projected centre, pixels */
+    uint16_t axes[4];    /* fp16 bits: axis1.x, axis1.y, axis2.x, axis2.y (pixels) */
+    uint8_t rgba[4];
+    float depth;         /* camera-space z (fp32), as in ws_splat */
+    uint16_t rect[4];    /* inclusive pixel rectangle x0, x1, y0, y1, as in ws_splat */
+} ws_splat_packed;
+
 typedef struct ws_gaussian_grads {  /* same shapes as ws_gaussians; overwritten, not accumulated */
     float* means;
     float* log_scales;
@@ -187,7 +211,7 @@ int64_t ws_total_image_floats(const ws_camera* cams, int32_t n_views);
  *   g           Gaussians (device arrays, see the layout above)
  *   cams        host array of n_views cameras (read during the call, for sizes)
  *   d_cams      device copy of the same n_views cameras (read by the kernels)
- *   splats      out [n_views][n] ws_splat
+ *   splats      out [n_views][n] ws_splat (ws_splat_packed with WS_FLAG_PACKED)
  *   tiles_touched out [n_views][n] uint32: tiles (bins, with bins larger than
  *               one tile) covered by the splat, 0 if culled
  *   keys, values out [capacity]: pair j = ((global tile or bin id) << 32 | fp32
@@ -246,7 +270,8 @@ ws_status ws_sort32(const uint32_t* keys_in, const uint32_t* values_in, uint32_t
  * key order; every tile of the bin keeps, in that order, the pairs whose pixel
  * rectangle meets the tile.  The result is the same ids in the same order as
  * the tile's run of pairs when the keys name tiles.
- *   splats        [n_views][n] from ws_preprocess (their pixel rectangles decide)
+ *   splats        [n_views][n] from ws_preprocess (their pixel rectangles decide;
+ *                 ws_splat_packed records with WS_FLAG_PACKED)
  *   keys, values  pairs from ws_sort over the bin bits (ws_sort32 with
  *                 WS_FLAG_KEYS32); count = min(*d_num_pairs, capacity)
  *   tile_values   out [tile_capacity] uint32: every tile's list of Gaussian ids.
@@ -264,7 +289,8 @@ ws_status ws_expand_bins(const ws_splat* splats, int64_t n, const ws_camera* cam
                          size_t ws_bytes, void* stream);
 
 /* Tile ranges and front-to-back compositing (Eq. 2, Eq. 4).
- *   splats        [n_views][n] from ws_preprocess
+ *   splats        [n_views][n] from ws_preprocess (ws_splat_packed records with
+ *                 WS_FLAG_PACKED: the ellipse, colour and opacity they quantise)
  *   keys, values  tile-sorted pairs from ws_sort (uint64_t keys) or ws_sort32
  *                 (uint32_t keys, WS_FLAG_KEYS32); count = min(*d_num_pairs, capacity).
  *                 keys = NULL: tile_ranges is an input instead (from

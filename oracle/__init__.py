@@ -285,13 +285,54 @@ def composite(mean2d, conic, opacity, rgb, pix_rect, cam, opts: Options, vals, r
     return out
 
 
-def render(scene, cam, opts: Options, mode="tiled", mask=None, outcomes=False) -> dict:
+def ellipse_axes(cov2d):
+    """Principal axes of the projected ellipses Sigma' = [[a, b], [b, c]] (cov2d rows a, b, c; det > 0): sqrt(l1) v1
+    and sqrt(l2) v2 with l1 >= l2 the eigenvalues, v1 the unit eigenvector of l1 taken from (l1 - c, b) when
+    a >= c and else from (b, l1 - a), and v2 = v1 turned by +90 degrees (the axes Sec. 3.2 stores in fp16).
+    Returns [4, n]: axis1.x, axis1.y, axis2.x, axis2.y."""
+    a, b, c = (np.asarray(x, np.float64) for x in cov2d)
+    det = a * c - b * b
+    hd = 0.5 * (a - c)
+    l1 = 0.5 * (a + c) + np.sqrt(hd * hd + b * b)
+    l2 = det / l1
+    vx = np.where(a >= c, l1 - c, b)
+    vy = np.where(a >= c, b, l1 - a)
+    nv = np.sqrt(vx * vx + vy * vy)
+    safe = nv > 0
+    vx = np.where(safe, vx / np.where(safe, nv, 1.0), 1.0)
+    vy = np.where(safe, vy / np.where(safe, nv, 1.0), 0.0)
+    s1, s2 = np.sqrt(l1), np.sqrt(l2)
+    return np.stack([s1 * vx, s1 * vy, -s2 * vy, s2 * vx])
+
+
+def pack_quantise(proj):
+    """Sec. 3.2's packed render inputs, as the renderer then sees them: the ellipse axes rounded to IEEE fp16
+    (nearest even), the ellipse rebuilt as axis1 axis1^T + axis2 axis2^T (determinant: the squared cross product
+    of the axes) and inverted into the conic; colour clamped to [0, 1] and opacity, each stored as
+    floor(255 x + 1/2) / 255 (RGBA8).  Returns (conic [3, n], opacity [n], rgb [3, n]) in fp64; rows of culled
+    splats are left as they are."""
+    vis = proj["status"] == 0
+    cov = np.where(vis[None], proj["cov2d"], np.array([[1.0], [0.0], [1.0]]))
+    ax = ellipse_axes(cov).astype(np.float16).astype(np.float64)
+    a1x, a1y, a2x, a2y = ax
+    s00, s01, s11 = a1x * a1x + a2x * a2x, a1x * a1y + a2x * a2y, a1y * a1y + a2y * a2y
+    det = (a1x * a2y - a1y * a2x) ** 2
+    conic = np.where(vis[None], np.stack([s11 / det, -s01 / det, s00 / det]), proj["conic"])
+    q = lambda x: np.floor(255.0 * x + 0.5) / 255.0  # noqa: E731
+    opacity = np.where(vis, q(np.asarray(proj["opacity"], np.float64)), proj["opacity"])
+    rgb = np.where(vis[None], q(np.minimum(np.asarray(proj["rgb"], np.float64), 1.0)), proj["rgb"])
+    return conic, opacity, rgb
+
+
+def render(scene, cam, opts: Options, mode="tiled", mask=None, outcomes=False, packed=False) -> dict:
     """Whole forward path for one view.
 
     mode="tiled": preprocess, emit, stable sort, tile ranges, composite (the
     pipeline's own steps).  mode="brute": every validly projected Gaussian at
     every pixel in (fp32 depth bits, id) order, no culling (the definition).
     outcomes=True (tiled mode) attaches composite_outcomes() as out["outcomes"].
+    packed=True (tiled mode) composites the packed render inputs of Sec. 3.2 (pack_quantise): the same pairs and
+    pixel rectangles, the quantised ellipse, colour and opacity.
     """
     _check_opts(scene, opts)
     if mode == "brute":
@@ -309,8 +350,9 @@ def render(scene, cam, opts: Options, mode="tiled", mask=None, outcomes=False) -
     skeys, svals = stable_sort(keys, vals)
     tx, ty = tiles_xy(cam, opts)
     ranges = tile_ranges(skeys, tx * ty)
-    out = composite(proj["mean2d"], proj["conic"], proj["opacity"], proj["rgb"], proj["pix_rect"], cam, opts,
-                    svals, ranges, 0, mask, outcomes=outcomes)
+    conic, opacity, rgb = pack_quantise(proj) if packed else (proj["conic"], proj["opacity"], proj["rgb"])
+    out = composite(proj["mean2d"], conic, opacity, rgb, proj["pix_rect"], cam, opts, svals, ranges, 0, mask,
+                    outcomes=outcomes)
     out.update(proj=proj, keys=keys, vals=vals, sorted_keys=skeys, sorted_vals=svals, ranges=ranges)
     return out
 

@@ -30,6 +30,7 @@ WS_FLAG_ORDERED_RENDER = 4
 WS_FLAG_DEPTH_FIRST = 8
 WS_FLAG_KEYS32 = 16
 WS_FLAG_ACCUMULATE_GRADS = 32
+WS_FLAG_PACKED = 64
 
 EXPORTED = [
     "ws_preprocess_workspace_size", "ws_sort_workspace_size", "ws_render_workspace_size",
@@ -74,6 +75,7 @@ class ws_gaussian_grads(C.Structure):
 
 
 SPLAT_BYTES = 48
+PACKED_SPLAT_BYTES = 32
 CAMERA_BYTES = C.sizeof(ws_camera)
 
 _lib = None

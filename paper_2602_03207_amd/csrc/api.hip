@@ -49,7 +49,7 @@ ws_status check_options(const ws_options* o) {
         if (b != 0 && b != 1 && b != 2 && b != 4 && b != 8)
             return fail(WS_ERR_INVALID_ARGUMENT, "bin_x / bin_y must be 1, 2, 4 or 8 (0 reads as 1), got %d", b);
     if (o->flags & ~(WS_FLAG_FIXED_3SIGMA | WS_FLAG_NO_VIEWPORT_CULL | WS_FLAG_ORDERED_RENDER | WS_FLAG_DEPTH_FIRST |
-                     WS_FLAG_KEYS32 | WS_FLAG_ACCUMULATE_GRADS))
+                     WS_FLAG_KEYS32 | WS_FLAG_ACCUMULATE_GRADS | WS_FLAG_PACKED))
         return fail(WS_ERR_INVALID_ARGUMENT, "unknown flag bits 0x%x", o->flags);
     if ((o->flags & WS_FLAG_KEYS32) && !(o->flags & WS_FLAG_DEPTH_FIRST))
         return fail(WS_ERR_INVALID_ARGUMENT, "WS_FLAG_KEYS32 needs WS_FLAG_DEPTH_FIRST (the keys carry no depth)");
@@ -444,6 +444,8 @@ ws_status ws_render_backward(const ws_gaussians* g, const ws_camera* cams, const
     if (!grads || (g->n > 0 && (!grads->means || !grads->log_scales || !grads->quats || !grads->opacity_logits ||
                                 !grads->sh)))
         return fail(WS_ERR_INVALID_ARGUMENT, "a gradient array is NULL");
+    if (opt->flags & WS_FLAG_PACKED)
+        return fail(WS_ERR_UNSUPPORTED, "ws_render_backward needs full-precision ws_splat records (no WS_FLAG_PACKED)");
     if (!tile_ranges || !dL_dimages || !d_status) return fail(WS_ERR_INVALID_ARGUMENT, "tile_ranges / dL_dimages / d_status is NULL");
     if (g->n > 0 && (!splats || !values)) return fail(WS_ERR_INVALID_ARGUMENT, "splats / values is NULL");
     if (g->n * int64_t(n_views) > kMaxGaussians) return fail(WS_ERR_INVALID_ARGUMENT, "n * n_views must be < 2^31");

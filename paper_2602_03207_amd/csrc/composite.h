@@ -59,6 +59,44 @@ __device__ __forceinline__ StagedSplat stage_splat(const ws_splat* __restrict__ 
     return s;
 }
 
+// The same from a 32-byte packed record (ws_splat_packed; `recs` addresses
+// the view's records in float4s): the conic is the inverse of the quantised
+// ellipse axis1 axis1^T + axis2 axis2^T, whose determinant is the squared
+// cross product of the axes; colour and opacity are the bytes / 255.
+__device__ __forceinline__ StagedSplat stage_splat_packed(const float4* __restrict__ recs, uint32_t id) {
+    const float4 r0 = recs[2 * int64_t(id)], r1 = recs[2 * int64_t(id) + 1];
+    const uint32_t a01 = __float_as_uint(r0.z), a23 = __float_as_uint(r0.w);
+    const float a1x = float(__builtin_bit_cast(_Float16, uint16_t(a01 & 0xffffu)));
+    const float a1y = float(__builtin_bit_cast(_Float16, uint16_t(a01 >> 16)));
+    const float a2x = float(__builtin_bit_cast(_Float16, uint16_t(a23 & 0xffffu)));
+    const float a2y = float(__builtin_bit_cast(_Float16, uint16_t(a23 >> 16)));
+    const float s00 = fmaf(a1x, a1x, a2x * a2x), s01 = fmaf(a1x, a1y, a2x * a2y), s11 = fmaf(a1y, a1y, a2y * a2y);
+    const float cross = fmaf(a1x, a2y, -a1y * a2x);
+    const float idet = 1.f / (cross * cross);
+    const uint32_t rgba = __float_as_uint(r1.x);
+    StagedSplat s;
+    s.u = r0.x;
+    s.v = r0.y;
+    s.qa = -0.5f * kLog2e * (s11 * idet);
+    s.qb = -kLog2e * (-s01 * idet);
+    s.qc = -0.5f * kLog2e * (s00 * idet);
+    s.ls = __log2f(float(rgba >> 24) / 255.f);
+    s.r = float(rgba & 0xffu) / 255.f;
+    s.g = float((rgba >> 8) & 0xffu) / 255.f;
+    s.b = float((rgba >> 16) & 0xffu) / 255.f;
+    const uint32_t rx = __float_as_uint(r1.z), ry = __float_as_uint(r1.w);
+    const uint32_t x0 = rx & 0xffffu, x1 = rx >> 16, y0 = ry & 0xffffu, y1 = ry >> 16;
+    if (x1 >= x0 && y1 >= y0) {
+        s.rxy = pack_xy(int(x0), int(y0));
+        s.rwh = pack_xy(int(x1 - x0), int(y1 - y0));
+    } else {
+        s.rxy = 0xffffffffu;
+        s.rwh = 0u;
+    }
+    s.id = id;
+    return s;
+}
+
 // A splat that covers no pixel: used for out-of-range ids.
 __device__ __forceinline__ StagedSplat empty_splat() {
     StagedSplat s{};

@@ -104,12 +104,24 @@ __global__ __launch_bounds__(kPreThreads) void k_preprocess(GaussPtrs g, const w
     const int64_t vi = int64_t(v) * g.n + i;
     tiles_touched[vi] = vis ? st.tiles : 0u;
     if (!vis) return;
-    float4* rec = reinterpret_cast<float4*>(splats + vi);
     const uint32_t r01 = uint32_t(st.rect[0]) | (uint32_t(st.rect[1]) << 16);
     const uint32_t r23 = uint32_t(st.rect[2]) | (uint32_t(st.rect[3]) << 16);
-    rec[0] = make_float4(st.u, st.v, st.A, st.B);
-    rec[1] = make_float4(st.C, st.sigma, st.rgb[0], st.rgb[1]);
-    rec[2] = make_float4(st.rgb[2], st.z32, __uint_as_float(r01), __uint_as_float(r23));
+    if (o.flags & WS_FLAG_PACKED) {  // 32-byte ws_splat_packed records
+        float ax[4];
+        ellipse_axes(st.a, st.b, st.c, st.det, ax);
+        const uint32_t a01 = half_bits(ax[0]) | (half_bits(ax[1]) << 16);
+        const uint32_t a23 = half_bits(ax[2]) | (half_bits(ax[3]) << 16);
+        const uint32_t rgba = unorm8(fminf(st.rgb[0], 1.f)) | (unorm8(fminf(st.rgb[1], 1.f)) << 8) |
+                              (unorm8(fminf(st.rgb[2], 1.f)) << 16) | (unorm8(st.sigma) << 24);
+        float4* rec = reinterpret_cast<float4*>(splats) + 2 * vi;
+        rec[0] = make_float4(st.u, st.v, __uint_as_float(a01), __uint_as_float(a23));
+        rec[1] = make_float4(__uint_as_float(rgba), st.z32, __uint_as_float(r01), __uint_as_float(r23));
+    } else {
+        float4* rec = reinterpret_cast<float4*>(splats + vi);
+        rec[0] = make_float4(st.u, st.v, st.A, st.B);
+        rec[1] = make_float4(st.C, st.sigma, st.rgb[0], st.rgb[1]);
+        rec[2] = make_float4(st.rgb[2], st.z32, __uint_as_float(r01), __uint_as_float(r23));
+    }
     // a dense copy of the depth, so that the compaction reads it coalesced
     // rather than one word out of every 48-byte record
     if (depth) depth[vi] = __float_as_uint(st.z32);
@@ -159,7 +171,8 @@ struct CountStore {
 };
 
 struct EmitArgs {
-    const ws_splat* splats;
+    const float4* splats;  // records of rec_f4 float4s; float4 rec_tail of each holds (., depth, rect01, rect23)
+    int32_t rec_f4, rec_tail;
     const ws_camera* cams;
     int32_t n_views;
     const uint32_t* list;
@@ -271,7 +284,7 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(EmitArgs a) {
         const bool in = ent < nvis && int64_t(start) < p1;
         if (in) {
             const int64_t view = int64_t(idx / uint32_t(a.n));  // V n < 2^32
-            const float4 r2 = reinterpret_cast<const float4*>(a.splats + idx)[2];
+            const float4 r2 = a.splats[int64_t(idx) * a.rec_f4 + a.rec_tail];
             const uint32_t r01 = __float_as_uint(r2.z), r23 = __float_as_uint(r2.w);
             uint32_t tbase, tilesx;
             if (one_view) {
@@ -419,7 +432,11 @@ hipError_t launch_preprocess(const GaussPtrs& g, const ws_camera* d_cams, int32_
     launch_scan<uint64_t, kCountItems>(CountLoad{tiles_touched, list}, CountStore{pw.offsets, pw.first_entry, pw.emit_blocks},
                           ents, pw.d_nvis, d_status, pw.scan_b, reinterpret_cast<uint64_t*>(d_num_pairs), stream, true);
     EmitArgs ea;
-    ea.splats = splats;
+    // the record's last float4 holds (., depth, rect01, rect23) in both layouts
+    const bool packed = (o.flags & WS_FLAG_PACKED) != 0;
+    ea.splats = reinterpret_cast<const float4*>(splats);
+    ea.rec_f4 = packed ? 2 : 3;
+    ea.rec_tail = packed ? 1 : 2;
     ea.cams = d_cams;
     ea.n_views = n_views;
     ea.list = list;

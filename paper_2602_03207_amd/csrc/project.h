@@ -282,4 +282,41 @@ __device__ __forceinline__ bool compute_projection(const GaussPtrs& g, int64_t i
     return true;
 }
 
+// ---- packed records (WS_FLAG_PACKED; Sec. 3.2's fp16 ellipse axes and RGBA8
+// colour and opacity)
+
+// The principal axes of Sigma' = [[a, b], [b, c]] (det = ac - b^2 > 0):
+// sqrt(l1) v1 and sqrt(l2) v2 with l1 >= l2 its eigenvalues, v1 the unit
+// eigenvector of l1 taken from (l1 - c, b) when a >= c, else (b, l1 - a)
+// (the larger of the two null-space vectors of Sigma' - l1 I), v2 = v1
+// turned by +90 degrees; l2 = det / l1 avoids the cancellation of mid - r.
+__device__ __forceinline__ void ellipse_axes(float a, float b, float c, float det, float* ax) {
+    const float hd = 0.5f * (a - c);
+    const float r = sqrtf(fmaf(hd, hd, b * b));
+    const float l1 = 0.5f * (a + c) + r;
+    const float l2 = det / l1;
+    float vx = a >= c ? l1 - c : b, vy = a >= c ? b : l1 - a;
+    const float nv = sqrtf(fmaf(vx, vx, vy * vy));
+    if (nv > 0.f) {
+        vx /= nv;
+        vy /= nv;
+    } else {
+        vx = 1.f;
+        vy = 0.f;
+    }
+    const float s1 = sqrtf(l1), s2 = sqrtf(l2);
+    ax[0] = s1 * vx;
+    ax[1] = s1 * vy;
+    ax[2] = -s2 * vy;
+    ax[3] = s2 * vx;
+}
+
+// IEEE fp16 bits of x, rounded to nearest even.
+__device__ __forceinline__ uint32_t half_bits(float x) {
+    return uint32_t(__builtin_bit_cast(uint16_t, static_cast<_Float16>(x)));
+}
+
+// floor(255 x + 1/2) for x in [0, 1].
+__device__ __forceinline__ uint32_t unorm8(float x) { return uint32_t(floorf(fmaf(x, 255.f, 0.5f))); }
+
 }  // namespace ws

@@ -162,7 +162,8 @@ constexpr int kExpandItems = 4;
 constexpr int kExpandWaves = kExpandThreads / kWave;
 
 struct ExpandArgs {
-    const ws_splat* splats;
+    const uint2* splats;  // records of rec_u2 uint2s; uint2 rect_u2 of each is (x0 | x1 << 16, y0 | y1 << 16)
+    int32_t rec_u2, rect_u2;
     int64_t n;
     const ws_camera* cams;
     int32_t n_views;
@@ -211,7 +212,7 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand(ExpandArgs a) {
     const int64_t tile = toff + int64_t(ty) * txn + tx;
     const uint32_t bs = a.bin_ranges[2 * bin], be = a.bin_ranges[2 * bin + 1];
     const uint32_t base = (bs << kl) + k * (be - bs);
-    const ws_splat* vs = a.splats + int64_t(v) * a.n;
+    const uint2* vs = a.splats + int64_t(v) * a.n * a.rec_u2;
     const uint32_t lane = lane_id();
     const int wave = threadIdx.x / kWave;
     uint32_t count = 0;
@@ -228,8 +229,8 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand(ExpandArgs a) {
         for (int j = 0; j < kExpandItems; ++j) {
             keep[j] = false;
             if (id[j] < uint64_t(a.n)) {
-                // words 10 and 11 of the record: x0 | x1 << 16, y0 | y1 << 16
-                const uint2 r = reinterpret_cast<const uint2*>(vs + id[j])[5];
+                // the record's rectangle words: x0 | x1 << 16, y0 | y1 << 16
+                const uint2 r = vs[int64_t(id[j]) * a.rec_u2 + a.rect_u2];
                 const int32_t tx0 = int32_t((r.x & 0xffffu) >> a.tws), tx1 = int32_t((r.x >> 16) >> a.tws);
                 const int32_t ty0 = int32_t((r.y & 0xffffu) >> a.ths), ty1 = int32_t((r.y >> 16) >> a.ths);
                 keep[j] = tx0 <= tx && tx <= tx1 && ty0 <= ty && ty <= ty1;
@@ -353,7 +354,8 @@ __device__ __forceinline__ void stage_batch(const RenderArgs& a, const ws_splat*
     if (idx < end) {
         const uint32_t id = a.values[idx];
         if (id < uint64_t(a.n)) {
-            s = stage_splat(vsplats, id);
+            s = (a.o.flags & WS_FLAG_PACKED) ? stage_splat_packed(reinterpret_cast<const float4*>(vsplats), id)
+                                             : stage_splat(vsplats, id);
             valid = true;
         }
         s_batch[threadIdx.x] = s;
@@ -370,7 +372,11 @@ __device__ __forceinline__ void render_tile(const RenderArgs& a, int64_t g, Stag
     quadrant_pixel<TW>(ti.x0, ti.y0, &px, &py);
     const bool inside = px < ti.W && py < ti.H;
     const uint32_t start = a.ranges[2 * g], end = a.ranges[2 * g + 1];
-    const ws_splat* vsplats = a.splats + int64_t(ti.view) * a.n;
+    // the view's records: 48-byte ws_splat, or 32-byte ws_splat_packed (addressed in float4s)
+    const ws_splat* vsplats = (a.o.flags & WS_FLAG_PACKED)
+                                  ? reinterpret_cast<const ws_splat*>(reinterpret_cast<const float4*>(a.splats) +
+                                                                      2 * int64_t(ti.view) * a.n)
+                                  : a.splats + int64_t(ti.view) * a.n;
     const uint64_t* my_masks = s_masks + (threadIdx.x / kWave) * NW;
     PixelState ps;
     ps.init(px, py);
@@ -548,7 +554,10 @@ hipError_t launch_expand(const ws_splat* splats, int64_t n, const ws_camera* d_c
     const uint32_t rgrid = uint32_t(std::min<int64_t>(std::max<int64_t>((capacity + rchunk - 1) / rchunk, 1), 4096));
     launch_ranges(o, keys, capacity, d_num_pairs, d_status, bin_ranges, total_bins, rgrid, stream);
     ExpandArgs ea;
-    ea.splats = splats;
+    const bool packed = (o.flags & WS_FLAG_PACKED) != 0;
+    ea.splats = reinterpret_cast<const uint2*>(splats);
+    ea.rec_u2 = packed ? 4 : 6;   // 32- or 48-byte records
+    ea.rect_u2 = packed ? 3 : 5;  // words 6-7 or 10-11
     ea.n = std::max<int64_t>(n, 1);
     ea.cams = d_cams;
     ea.n_views = n_views;

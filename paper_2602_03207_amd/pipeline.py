@@ -118,7 +118,9 @@ class Renderer:
             return
         self.n = n
         v = self.n_views
-        self.splats = torch.empty((v * max(n, 1), 12), dtype=torch.float32, device=self.device)
+        # 48-byte ws_splat records, or 32-byte ws_splat_packed ones (WS_FLAG_PACKED)
+        words = (B.PACKED_SPLAT_BYTES if self.packed else B.SPLAT_BYTES) // 4
+        self.splats = torch.empty((v * max(n, 1), words), dtype=torch.float32, device=self.device)
         self.tiles_touched = torch.empty(v * max(n, 1), dtype=torch.int32, device=self.device)
 
     def _ensure_capacity(self, cap):
@@ -138,6 +140,11 @@ class Renderer:
     def keys32(self) -> bool:
         """Keys are 32-bit tile (bin) ids (WS_FLAG_KEYS32)."""
         return bool(self.opts.flags & B.WS_FLAG_KEYS32)
+
+    @property
+    def packed(self) -> bool:
+        """Render inputs packed into 32-byte records (WS_FLAG_PACKED; forward only)."""
+        return bool(self.opts.flags & B.WS_FLAG_PACKED)
 
     @property
     def per_bin(self) -> int:

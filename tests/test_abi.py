@@ -126,6 +126,19 @@ def test_l1_loss_rejects_bad_arguments_on_the_host(lib):
     assert lib.ws_l1_loss(a, b, 100, 0, c, d, ws, need - 1, None) == B.WS_ERR_WORKSPACE_TOO_SMALL
 
 
+def test_backward_rejects_packed_records(lib):
+    vp = C.c_void_p
+    g = B.ws_gaussians()
+    g.n = 10
+    g.means = g.log_scales = g.quats = g.opacity_logits = g.sh = 0x100000
+    grads = B.make_grads(0x200000, 0x200000, 0x200000, 0x200000, 0x200000)
+    cams = (B.ws_camera * 1)(_cam(64, 64))
+    o = _opts(flags=B.WS_FLAG_PACKED)
+    st = lib.ws_render_backward(C.byref(g), cams, vp(0x300000), 1, C.byref(o), vp(0x400000), vp(0x500000),
+                                vp(0x600000), vp(0x700000), vp(0x800000), C.byref(grads), vp(0x900000), 1 << 30, None)
+    assert st == B.WS_ERR_UNSUPPORTED and "PACKED" in _err(lib)
+
+
 def test_unknown_flags_are_rejected_and_accumulate_is_known(lib):
     vp = C.c_void_p
     g = B.ws_gaussians()

@@ -691,3 +691,42 @@ def test_p18_l1_loss_hand_computed():
         e[i] = 1e-7
         fd = (oracle.l1_loss_grad(a + e, b)[0] - oracle.l1_loss_grad(a - e, b)[0]) / 2e-7
         assert abs(fd - ga[i]) < 1e-9
+
+
+def test_p19_packed_ellipse_axes_and_bytes():
+    """Sec. 3.2's packing as the oracle models it: the axes of [[a, b], [b, c]] rebuild it exactly, are orthogonal
+    and ordered; hand-computed axes of two ellipses; the byte quantisation of colour and opacity."""
+    rng = np.random.default_rng(19)
+    n = 500
+    s1 = np.exp(rng.uniform(-1, 5, n))
+    s2 = s1 * np.exp(-rng.uniform(0, 5, n))
+    th = rng.uniform(0, np.pi, n)
+    c_, s_ = np.cos(th), np.sin(th)
+    a = c_ * c_ * s1 * s1 + s_ * s_ * s2 * s2
+    c = s_ * s_ * s1 * s1 + c_ * c_ * s2 * s2
+    b = c_ * s_ * (s1 * s1 - s2 * s2)
+    ax = oracle.ellipse_axes(np.stack([a, b, c]))
+    a1, a2 = ax[:2], ax[2:]
+    rebuilt = np.stack([a1[0] ** 2 + a2[0] ** 2, a1[0] * a1[1] + a2[0] * a2[1], a1[1] ** 2 + a2[1] ** 2])
+    assert np.allclose(rebuilt, np.stack([a, b, c]), rtol=1e-10, atol=1e-10 * s1 * s1)
+    assert np.all(np.abs((a1 * a2).sum(0)) <= 1e-10 * s1 * s1)
+    n1, n2 = np.hypot(*a1), np.hypot(*a2)
+    assert np.allclose(n1, s1, rtol=1e-9) and np.allclose(n2, s2, rtol=1e-6)
+    # diag(4, 1): axes (2, 0) and (0, 1); [[2, 1], [1, 2]]: l1 = 3 along (1, 1)/sqrt 2, l2 = 1 along (-1, 1)/sqrt 2
+    got = oracle.ellipse_axes(np.array([[4.0, 2.0], [0.0, 1.0], [1.0, 2.0]]))
+    r = math.sqrt(0.5)
+    assert np.allclose(got[:, 0], [2, 0, 0, 1]) and np.allclose(got[:, 1], [math.sqrt(3) * r, math.sqrt(3) * r, -r, r])
+    # a > c with b < 0 and a < c: the eigenvector equation holds for axis1
+    for cov in ([5.0, -2.0, 1.0], [1.0, 0.7, 3.0]):
+        A = np.array([[cov[0], cov[1]], [cov[1], cov[2]]])
+        g = oracle.ellipse_axes(np.array(cov).reshape(3, 1))[:, 0]
+        lam = np.linalg.eigvalsh(A)[1]
+        assert np.allclose(A @ g[:2], lam * g[:2], rtol=1e-12)
+    # bytes: floor(255 x + 1/2) / 255, colours clamped at 1
+    proj = dict(status=np.zeros(4, np.int8), cov2d=np.tile([[2.0], [0.0], [2.0]], (1, 4)), conic=np.zeros((3, 4)),
+                opacity=np.array([1 / 255, 0.5, 0.99, 1.0]), rgb=np.array([[0.0, 0.5, 1.3, 0.2 / 255]] * 3))
+    conic, op, rgb = oracle.pack_quantise(proj)
+    assert np.array_equal(op * 255, [1, 128, 252, 255])
+    assert np.array_equal(rgb[0] * 255, [0, 128, 255, 0])
+    # the axes (sqrt 2, 0), (0, sqrt 2) in fp16: sqrt 2 rounds to 1.4140625, the conic is its inverse square
+    assert np.array_equal(conic[:, 0], [1 / 1.4140625 ** 2, 0.0, 1 / 1.4140625 ** 2])
