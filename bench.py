@@ -584,23 +584,93 @@ def bench_small(args, frames=200):
             "images_equal_plain": same}
 
 
+def host_cpu():
+    """CPU model and the cores this process may use on the host that runs it."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    usable = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return {"model": model, "logical_cpus": os.cpu_count(), "usable_cpus": usable}
+
+
 def cpu_baseline(args):
-    """fp64 oracle (single thread) on a bounded sample: whole frames of the 1M-Gaussian 1080p view."""
+    """The fp64 oracle on the host's cores, on bounded samples of the benchmark workloads: whole frames of the
+    1M-Gaussian 1080p view on one thread (`value`) and on every usable core (the oracle's loops over Gaussians,
+    tiles and pixel rows; the sort stays std::stable_sort on one thread), frames of the 10K-Gaussian 256x256
+    view, std::stable_sort of the 1080p and 4K pair buffers, and one forward+backward 1080p training view."""
+    import numpy as np
+
     import oracle
     import scenegen
+    host = host_cpu()
+    cores = max(1, int(host["usable_cpus"] or 1))
+
+    def timed(fn, runs):
+        ts = []
+        for _ in range(runs):
+            t0 = time.perf_counter()
+            fn()
+            ts.append(time.perf_counter() - t0)
+        return statistics.median(ts), ts
+
     scene, cam = scenegen.c2()
     opts = oracle.Options(sh_degree=3)
+    oracle.set_threads(1)
     frames = 0
     t0 = time.perf_counter()
     while True:
         oracle.render(scene, cam, opts)
         frames += 1
-        if time.perf_counter() - t0 > args.cpu_seconds or frames >= 4:
+        if time.perf_counter() - t0 > args.cpu_seconds or frames >= 2:
             break
     dt = time.perf_counter() - t0
-    return {"value": round(frames / dt, 5), "unit": "frames/s", "cores": 1, "kind": "oracle",
-            "sample": f"{frames} full frame(s) of the 1M-Gaussian 1920x1080 view (preprocess, emission, "
-                      f"std::stable_sort, compositing), fp64, one thread, {dt:.1f} s"}
+    out = {"value": round(frames / dt, 5), "unit": "frames/s", "cores": 1, "kind": "oracle",
+           "sample": f"{frames} full frame(s) of the 1M-Gaussian 1920x1080 view (preprocess, emission, "
+                     f"std::stable_sort, compositing), fp64, one thread, {dt:.1f} s",
+           "host": host}
+    # every usable core
+    oracle.set_threads(cores)
+    med, _ = timed(lambda: oracle.render(scene, cam, opts), 3)
+    out["all_cores"] = {"threads": cores, "frames_per_s": round(1.0 / med, 4), "frame_s_median_of_3": round(med, 3),
+                        "speedup_vs_one_thread": round((1.0 / med) / (frames / dt), 2),
+                        "note": "OpenMP over Gaussians, tiles and pixel rows; std::stable_sort on one thread"}
+    # std::stable_sort of the 1080p pair buffer (16x16 tiles, Gaussian order, tile and depth bits)
+    keys, vals = oracle.emit(scene, cam, opts)
+    end_bit = 32 + int(np.ceil(np.log2(120 * 68)))
+    oracle.set_threads(1)
+    med, _ = timed(lambda: oracle.stable_sort(keys, vals, 0, end_bit), 3)
+    out["stable_sort_c2"] = {"pairs": int(keys.size), "bits": end_bit, "s_median_of_3": round(med, 4),
+                             "keys_per_s": round(keys.size / med, 1)}
+    del keys, vals
+    # the 10K-Gaussian 256x256 frame, one thread
+    s1, c1 = scenegen.c1()
+    med, _ = timed(lambda: oracle.render(s1, c1, oracle.Options()), 20)
+    out["c1_one_thread"] = {"frames_per_s": round(1.0 / med, 3), "frame_s_median_of_20": round(med, 4)}
+    # one forward+backward training view (1M Gaussians, 1920x1080, L1 gradient), one thread
+    s5, cams5, _ = scenegen.c5(n_views=1)
+    img = oracle.forward_backward(s5, cams5[0], opts)["image"]
+    dL = np.sign(np.random.default_rng(0).standard_normal(img.shape)) / img.size
+    med, _ = timed(lambda: oracle.forward_backward(s5, cams5[0], opts, dL), 1)
+    out["c5_fwd_bwd_one_thread"] = {"views_per_s": round(1.0 / med, 4), "view_s": round(med, 3)}
+    del s5, img, dL
+    # std::stable_sort of the 4K pair buffer (6M Gaussians, about 49 M pairs), one run
+    s3, c3 = scenegen.c3()
+    oracle.set_threads(cores)
+    keys, vals = oracle.emit(s3, c3, opts)
+    del s3
+    oracle.set_threads(1)
+    end_bit = 32 + int(np.ceil(np.log2(240 * 135)))
+    med, _ = timed(lambda: oracle.stable_sort(keys, vals, 0, end_bit), 1)
+    out["stable_sort_c3"] = {"pairs": int(keys.size), "bits": end_bit, "s_one_run": round(med, 3),
+                             "keys_per_s": round(keys.size / med, 1)}
+    oracle.set_threads(cores)
+    return out
 
 
 def main():

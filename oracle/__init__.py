@@ -3,7 +3,10 @@
 TEST INFRASTRUCTURE ONLY: the tests, the smoke entry point and the
 CPU-baseline leg of the benchmark use this package; the GPU library never
 does, and the two share no code.  The arithmetic lives in oracle.cpp (plain
-C++17, fp64, single-threaded); this module only marshals numpy arrays.
+C++17, fp64); this module only marshals numpy arrays.  The library is built
+with OpenMP: its loops over independent Gaussians, tiles and pixel rows run on
+set_threads() host threads (OMP_NUM_THREADS by default) and give the same bits
+for any thread count; the sort is std::stable_sort on one thread.
 
 Every input is widened from the caller's values to fp64 before the call, so a
 GPU run fed the same fp32 arrays sees exactly the same numbers.
@@ -41,7 +44,7 @@ def build(verbose=False, sanitize=None):
         cmd = ["g++", "-O1", "-g", "-std=c++17", "-Wall", "-Wextra", "-fsanitize=address,undefined",
                "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer", "-shared", "-fPIC", "-o", out, _SRC]
     else:
-        cmd = ["g++", "-O2", "-std=c++17", "-Wall", "-Wextra", "-shared", "-fPIC", "-o", out, _SRC]
+        cmd = ["g++", "-O2", "-std=c++17", "-Wall", "-Wextra", "-fopenmp", "-shared", "-fPIC", "-o", out, _SRC]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)
@@ -71,6 +74,8 @@ def _load():
                                            P(C.c_int64), i64, P(C.c_uint8), i32, i64, P(C.c_int64), P(C.c_int32),
                                            d, d]
     lib.orc_composite_outcomes.restype = i64
+    lib.orc_set_threads.argtypes = [i32]
+    lib.orc_max_threads.restype = i32
     lib.orc_sh_basis.argtypes = [d, i32, d]
     lib.orc_quat_to_rotmat.argtypes = [d, d]
     _lib = lib
@@ -378,6 +383,15 @@ def forward_backward(scene, cam, opts: Options, dL_dimage=None):
                                  _dp(grads["means"]), _dp(grads["log_scales"]), _dp(grads["quats"]),
                                  _dp(grads["opacity_logits"]), _dp(grads["sh"]), _dp(splat_grad))
     return dict(image=image, grads=grads, splat_grad=splat_grad, hash=int(h))
+
+
+def set_threads(k: int) -> None:
+    """Host threads of the oracle's loops over independent items (results do not depend on it)."""
+    _load().orc_set_threads(int(k))
+
+
+def max_threads() -> int:
+    return int(_load().orc_max_threads())
 
 
 def sh_basis(direction, degree=3):

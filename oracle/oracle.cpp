@@ -25,6 +25,11 @@
 // decisions) are listed in the design notes of the repository; the code
 // states each one where it is used.
 //
+// Threads: loops over independent items (Gaussians, tiles, pixel rows) may
+// run on several host threads (OpenMP); every item is computed by the same
+// code, so the results do not depend on the thread count.  The sort is
+// std::stable_sort on one thread.
+//
 // Precision: every quantity is computed in fp64 from the caller's values.
 // The only fp32 step is the depth key, which the method defines as the bits
 // of the fp32 depth.
@@ -40,11 +45,15 @@
 // fp32 implementation; its primary outcome is composite_pixel's result.
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
 #include <numeric>
 #include <vector>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 namespace {
 
@@ -466,8 +475,13 @@ void composite_pixel_adjoint(const std::vector<Contrib>& cs, double T_final,
 }
 
 // Projected splat of every Gaussian for a view, plus decision records.
+// Loops over independent items (Gaussians, tiles, pixel rows) carry OpenMP
+// work-sharing pragmas: with an OpenMP build and more than one thread they run
+// on several host cores and give the same bits, each item being computed by
+// the same code whatever thread runs it; without OpenMP they are plain loops.
 void project_all(const GaussArrays& g, const Camera& cam, const Options& opt, std::vector<Projected<double>>& out) {
     out.resize(size_t(g.n));
+#pragma omp parallel for schedule(static, 4096)
     for (int64_t i = 0; i < g.n; ++i) out[size_t(i)] = project_one(g, i, cam, opt);
 }
 
@@ -751,29 +765,30 @@ int orc_composite(int64_t n, const double* mean2d, const double* conic, const do
                                   pix_rect[i], pix_rect[n + i], pix_rect[2 * n + i], pix_rect[3 * n + i]};
     const int32_t W = cam->width, H = cam->height;
     const int32_t tx_n = (W + opt->tile_w - 1) / opt->tile_w, ty_n = (H + opt->tile_h - 1) / opt->tile_h;
-    std::vector<int64_t> ids;
-    for (int32_t ty = 0; ty < ty_n; ++ty)
-        for (int32_t tx = 0; tx < tx_n; ++tx) {
-            const int64_t tile = tile_offset + int64_t(ty) * tx_n + tx;
-            const int64_t s = ranges[2 * tile], e = ranges[2 * tile + 1];
-            ids.resize(size_t(e - s));
-            for (int64_t j = s; j < e; ++j) ids[size_t(j - s)] = vals[j];
-            for (int32_t py = ty * opt->tile_h; py < std::min(H, (ty + 1) * opt->tile_h); ++py)
-                for (int32_t px = tx * opt->tile_w; px < std::min(W, (tx + 1) * opt->tile_w); ++px) {
-                    const int64_t pix = int64_t(py) * W + px;
-                    if (mask && !mask[pix]) continue;
-                    PixelResult r = composite_pixel(px, py, ids.data(), int64_t(ids.size()),
-                                                    [&](int64_t id) -> const PixelSplat& { return S[size_t(id)]; },
-                                                    *opt, nullptr);
-                    if (out->rgb) for (int ch = 0; ch < 3; ++ch) out->rgb[int64_t(ch) * H * W + pix] = r.rgb[ch];
-                    if (out->T) out->T[pix] = r.T;
-                    if (out->n_eval) out->n_eval[pix] = r.n_eval;
-                    if (out->n_contrib) out->n_contrib[pix] = r.n_contrib;
-                    if (out->alpha_margin) out->alpha_margin[pix] = r.alpha_margin;
-                    if (out->t_margin) out->t_margin[pix] = r.t_margin;
-                    if (out->hash) out->hash[pix] = r.hash;
-                }
-        }
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t t = 0; t < int64_t(tx_n) * ty_n; ++t) {
+        std::vector<int64_t> ids;
+        const int32_t ty = int32_t(t / tx_n), tx = int32_t(t % tx_n);
+        const int64_t tile = tile_offset + int64_t(ty) * tx_n + tx;
+        const int64_t s = ranges[2 * tile], e = ranges[2 * tile + 1];
+        ids.resize(size_t(e - s));
+        for (int64_t j = s; j < e; ++j) ids[size_t(j - s)] = vals[j];
+        for (int32_t py = ty * opt->tile_h; py < std::min(H, (ty + 1) * opt->tile_h); ++py)
+            for (int32_t px = tx * opt->tile_w; px < std::min(W, (tx + 1) * opt->tile_w); ++px) {
+                const int64_t pix = int64_t(py) * W + px;
+                if (mask && !mask[pix]) continue;
+                PixelResult r = composite_pixel(px, py, ids.data(), int64_t(ids.size()),
+                                                [&](int64_t id) -> const PixelSplat& { return S[size_t(id)]; },
+                                                *opt, nullptr);
+                if (out->rgb) for (int ch = 0; ch < 3; ++ch) out->rgb[int64_t(ch) * H * W + pix] = r.rgb[ch];
+                if (out->T) out->T[pix] = r.T;
+                if (out->n_eval) out->n_eval[pix] = r.n_eval;
+                if (out->n_contrib) out->n_contrib[pix] = r.n_contrib;
+                if (out->alpha_margin) out->alpha_margin[pix] = r.alpha_margin;
+                if (out->t_margin) out->t_margin[pix] = r.t_margin;
+                if (out->hash) out->hash[pix] = r.hash;
+            }
+    }
     (void)n_pairs;
     return 0;
 }
@@ -802,6 +817,7 @@ int orc_render_brute(int64_t n, const double* means, const double* log_scales, c
     std::vector<PixelSplat> S = splats_of(P);
     const int32_t W = cam->width, H = cam->height;
     for (auto& s : S) { s.x0 = 0; s.x1 = W - 1; s.y0 = 0; s.y1 = H - 1; }  // no rectangle test
+#pragma omp parallel for schedule(dynamic, 1)
     for (int32_t py = 0; py < H; ++py)
         for (int32_t px = 0; px < W; ++px) {
             const int64_t pix = int64_t(py) * W + px;
@@ -928,48 +944,71 @@ int64_t orc_composite_outcomes(int64_t n, const double* mean2d, const double* co
     for (size_t i = 0; i < S.size(); ++i) E[i] = splat_error(S[i], *opt);
     const int32_t W = cam->width, H = cam->height;
     const int32_t tx_n = (W + opt->tile_w - 1) / opt->tile_w, ty_n = (H + opt->tile_h - 1) / opt->tile_h;
-    std::vector<int64_t> ids;
-    int64_t found = 0;
-    for (int32_t ty = 0; ty < ty_n; ++ty)
-        for (int32_t tx = 0; tx < tx_n; ++tx) {
-            const int64_t tile = tile_offset + int64_t(ty) * tx_n + tx;
-            const int64_t s0 = ranges[2 * tile], e0 = ranges[2 * tile + 1];
-            ids.resize(size_t(e0 - s0));
-            double maxc = std::max({std::fabs(opt->bg[0]), std::fabs(opt->bg[1]), std::fabs(opt->bg[2])});
-            for (int64_t j = s0; j < e0; ++j) {
-                ids[size_t(j - s0)] = vals[j];
-                for (int ch = 0; ch < 3; ++ch) maxc = std::max(maxc, std::fabs(S[vals[j]].rgb[ch]));
+    struct Found {
+        int64_t pix;
+        int32_t n_out;
+        double bound;
+        std::vector<double> rgb;
+    };
+    const int64_t n_tiles = int64_t(tx_n) * ty_n;
+    std::vector<std::vector<Found>> per_tile(static_cast<size_t>(n_tiles));
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t t = 0; t < n_tiles; ++t) {
+        std::vector<int64_t> ids;
+        const int32_t ty = int32_t(t / tx_n), tx = int32_t(t % tx_n);
+        const int64_t tile = tile_offset + int64_t(ty) * tx_n + tx;
+        const int64_t s0 = ranges[2 * tile], e0 = ranges[2 * tile + 1];
+        ids.resize(size_t(e0 - s0));
+        double maxc = std::max({std::fabs(opt->bg[0]), std::fabs(opt->bg[1]), std::fabs(opt->bg[2])});
+        for (int64_t j = s0; j < e0; ++j) {
+            ids[size_t(j - s0)] = vals[j];
+            for (int ch = 0; ch < 3; ++ch) maxc = std::max(maxc, std::fabs(S[vals[j]].rgb[ch]));
+        }
+        for (int32_t py = ty * opt->tile_h; py < std::min(H, (ty + 1) * opt->tile_h); ++py)
+            for (int32_t px = tx * opt->tile_w; px < std::min(W, (tx + 1) * opt->tile_w); ++px) {
+                const int64_t p = int64_t(py) * W + px;
+                if (mask && !mask[p]) continue;
+                OutcomeSearch o;
+                o.S = &S;
+                o.E = &E;
+                o.ids = ids.data();
+                o.count = int64_t(ids.size());
+                o.opt = opt;
+                o.px = px;
+                o.py = py;
+                o.pcx = px + 0.5;
+                o.pcy = py + 0.5;
+                o.max_out = size_t(std::max(max_out, 1));
+                const double C0[3] = {0.0, 0.0, 0.0};
+                o.run(0, 1.0, C0, 0.0);
+                if (!o.uncertain) continue;
+                per_tile[size_t(t)].push_back(
+                    Found{p, o.capped ? 0 : int32_t(o.out.size() / 3), o.first_T * maxc, o.out});
             }
-            for (int32_t py = ty * opt->tile_h; py < std::min(H, (ty + 1) * opt->tile_h); ++py)
-                for (int32_t px = tx * opt->tile_w; px < std::min(W, (tx + 1) * opt->tile_w); ++px) {
-                    const int64_t p = int64_t(py) * W + px;
-                    if (mask && !mask[p]) continue;
-                    OutcomeSearch o;
-                    o.S = &S;
-                    o.E = &E;
-                    o.ids = ids.data();
-                    o.count = int64_t(ids.size());
-                    o.opt = opt;
-                    o.px = px;
-                    o.py = py;
-                    o.pcx = px + 0.5;
-                    o.pcy = py + 0.5;
-                    o.max_out = size_t(std::max(max_out, 1));
-                    const double C0[3] = {0.0, 0.0, 0.0};
-                    o.run(0, 1.0, C0, 0.0);
-                    if (!o.uncertain) continue;
-                    if (found < cap) {
-                        pix[found] = p;
-                        const size_t k = o.out.size() / 3;
-                        n_out[found] = o.capped ? 0 : int32_t(k);
-                        for (size_t q = 0; q < o.out.size(); ++q) out_rgb[size_t(found) * size_t(max_out) * 3 + q] = o.out[q];
-                        bound[found] = o.first_T * maxc;
-                    }
-                    ++found;
-                }
+    }
+    // in tile order, as a single-threaded run lists them
+    int64_t found = 0;
+    for (const auto& list : per_tile)
+        for (const Found& f : list) {
+            if (found < cap) {
+                pix[found] = f.pix;
+                n_out[found] = f.n_out;
+                for (size_t q = 0; q < f.rgb.size(); ++q) out_rgb[size_t(found) * size_t(max_out) * 3 + q] = f.rgb[q];
+                bound[found] = f.bound;
+            }
+            ++found;
         }
     return found;
 }
+
+// Threads of the OpenMP work-sharing loops (1 without OpenMP).
+#ifdef _OPENMP
+void orc_set_threads(int32_t k) { omp_set_num_threads(k > 0 ? k : 1); }
+int32_t orc_max_threads(void) { return omp_get_max_threads(); }
+#else
+void orc_set_threads(int32_t k) { (void)k; }
+int32_t orc_max_threads(void) { return 1; }
+#endif
 
 // Building blocks exposed for the pins.
 void orc_sh_basis(const double* dir, int32_t degree, double* out) {

@@ -251,9 +251,9 @@ def test_render_c2_in_the_benchmark_configuration():
 
 
 @pytest.mark.slow
-def test_render_c3_sampled_pixels():
-    """The 6M-Gaussian 4K frame (the large-scene workload): pair count against the oracle's and 4000
-    sampled pixels against the oracle compositing just those pixels."""
+def test_render_c3_full_frame():
+    """The 6M-Gaussian 4K frame (the large-scene workload): pair count against the oracle's and every one of
+    its 8.3 M pixels against the oracle's image (the oracle's loops over tiles run on the host's cores)."""
     import torch
     from paper_2602_03207_amd import binding as B
     from paper_2602_03207_amd.pipeline import GaussianTensors, Renderer
@@ -267,11 +267,10 @@ def test_render_c3_sampled_pixels():
     ro = oracle_options(sh_degree=3)
     m_ref = oracle.pair_count(scene, cam, ro)
     assert abs(r.num_pairs - m_ref) <= 1e-4 * m_ref, (r.num_pairs, m_ref)  # rectangle bounds at a margin
-    rng = np.random.default_rng(31)
-    mask = np.zeros((cam.height, cam.width), np.uint8)
-    mask.reshape(-1)[rng.choice(cam.height * cam.width, 4000, replace=False)] = 1
-    ref = oracle.render(scene, cam, ro, mask=mask, outcomes=True)
-    worst, frac = assert_image_parity(img, ref, sel=mask.astype(bool))
+    print("C3: oracle render of the full frame", flush=True)
+    ref = oracle.render(scene, cam, ro, outcomes=True)
+    worst, frac = assert_image_parity(img, ref)
+    del ref
     # the fastest 4K layout (16x16 tiles in 4x2 bins, 32-bit keys, device-sized sequence): the same image
     m_gpu = r.num_pairs
     del r
@@ -283,15 +282,15 @@ def test_render_c3_sampled_pixels():
     torch.cuda.synchronize()
     assert rb.status() == 0
     assert np.array_equal(rb.image(0).cpu().numpy().view(np.uint32), img.view(np.uint32))
-    print(f"C3 sampled: worst {worst:.2e}, flagged {frac:.2e}, M gpu {m_gpu} oracle {m_ref}")
+    print(f"C3: worst {worst:.2e}, several outcomes on {frac:.2e} of pixels, M gpu {m_gpu} oracle {m_ref}")
 
 
 @pytest.mark.slow
-def test_render_c4_all_views_one_launch_sampled_pixels():
+def test_render_c4_all_views_one_launch():
     """The 64-view workload of uneven resolution rendered as one batched call in the layouts the multi-view
     benchmark's autotuner picks among (here 16x16 tiles in 4x2 bins with 32-bit keys and one workgroup per
-    tile, and 32x16 tiles with the persistent ordered render): three views of different sizes, 2000 sampled
-    pixels each, against the oracle compositing just those pixels; both layouts give identical images."""
+    tile, and 32x16 tiles with the persistent ordered render): one view of each size, every pixel against the
+    oracle's image of that view; both layouts give identical images of all 64 views."""
     import torch
     from paper_2602_03207_amd import binding as B
     from paper_2602_03207_amd.pipeline import GaussianTensors, Renderer
@@ -307,15 +306,12 @@ def test_render_c4_all_views_one_launch_sampled_pixels():
     sizes = {}
     for v, c in enumerate(cams):
         sizes.setdefault((c.width, c.height), v)
-    rng = np.random.default_rng(41)
     ro = oracle_options(sh_degree=3)
     for v in sorted(sizes.values()):
         cam = cams[v]
         img = r.image(v).cpu().numpy()
-        mask = np.zeros((cam.height, cam.width), np.uint8)
-        mask.reshape(-1)[rng.choice(cam.height * cam.width, 2000, replace=False)] = 1
-        ref = oracle.render(scene, cam, ro, mask=mask, outcomes=True)
-        worst, frac = assert_image_parity(img, ref, sel=mask.astype(bool))
+        ref = oracle.render(scene, cam, ro, outcomes=True)
+        worst, frac = assert_image_parity(img, ref)
         print(f"C4 view {v} ({cam.width}x{cam.height}): worst {worst:.2e}, flagged {frac:.2e}")
     images = r.images.clone()
     del r

@@ -730,3 +730,28 @@ def test_p19_packed_ellipse_axes_and_bytes():
     assert np.array_equal(rgb[0] * 255, [0, 128, 255, 0])
     # the axes (sqrt 2, 0), (0, sqrt 2) in fp16: sqrt 2 rounds to 1.4140625, the conic is its inverse square
     assert np.array_equal(conic[:, 0], [1 / 1.4140625 ** 2, 0.0, 1 / 1.4140625 ** 2])
+
+
+def test_p20_results_do_not_depend_on_the_thread_count():
+    """The oracle's loops over independent Gaussians, tiles and pixel rows give the same bits on 1 and on 4
+    host threads: tiled and brute compositing, decision outcomes, emission and gradients."""
+    sc = _tiny_scene(77, n=600, spread=1.0, deg=1)
+    cam = scenegen.look_at([0.3, -0.2, -2.5], [0, 0, 0], 72, 56)
+    opts = oracle.Options(sh_degree=1)
+    runs = []
+    n0 = oracle.max_threads()
+    for k in (1, 4):
+        oracle.set_threads(k)
+        t = oracle.render(sc, cam, opts, outcomes=True)
+        b = oracle.render(sc, cam, opts, mode="brute")
+        fb = oracle.forward_backward(sc, cam, opts, np.ones((3, cam.height, cam.width)))
+        runs.append((t, b, fb))
+    oracle.set_threads(n0)
+    (t1, b1, f1), (t4, b4, f4) = runs
+    for key in ("rgb", "T", "n_eval", "hash"):
+        assert np.array_equal(t1[key], t4[key]) and np.array_equal(b1[key], b4[key]), key
+    assert np.array_equal(t1["keys"], t4["keys"]) and np.array_equal(t1["sorted_vals"], t4["sorted_vals"])
+    for key in ("pix", "n_out", "rgb", "bound"):
+        assert np.array_equal(t1["outcomes"][key], t4["outcomes"][key]), key
+    for key in f1["grads"]:
+        assert np.array_equal(f1["grads"][key], f4["grads"][key]), key
