@@ -25,6 +25,9 @@ def compile_flags():
         # never emit packed fp32 arithmetic (v_pk_*_f32)
         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
         "-munsafe-fp-atomics",
+        # atomics stay as written: the optimizer's wave-level rewrite of atomics to one (uniform) address
+        # adds a read-lane loop and lane counting in front of adds that a single lane makes
+        "-mllvm", "-amdgpu-atomic-optimizer-strategy=None",
         f"-I{os.path.join(HERE, '..', 'include')}",
     ]
 

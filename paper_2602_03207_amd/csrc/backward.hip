@@ -11,9 +11,12 @@
 //        dL/dalpha_k = dL/dC . (c_k T_k - R_k / (1 - alpha_k))
 //     and, unless alpha was clamped, dL/dsigma = dL/dalpha exp(power) and
 //     dL/dpower = dL/dalpha * alpha with the derivatives of the power in the
-//     centre and the conic.  The nine per-splat sums of a staged batch are
-//     reduced across the wave (shuffles) and across the workgroup (LDS
-//     atomics), then added to device memory with one atomic per value.
+//     centre and the conic.  Per (pixel, splat) the pass forms nine values:
+//     the moments dL/dpower * (1, dx, dy, dx^2, dx dy, dy^2) and the colour
+//     gradient; their per-splat sums over a staged batch are reduced across
+//     the wave (lane swaps and DPP) and across the workgroup (LDS atomics),
+//     turned into dL/d(centre, conic, sigma) with the splat's conic once, and
+//     added to device memory with one atomic per value.
 // k_bwd_clear           zeroes the per-(view, splat) gradient buffer.
 // k_preprocess_bwd_geo  one thread per Gaussian, summing over the views: the
 //     chain through the conic inverse, the EWA covariance, the Jacobian
@@ -214,7 +217,6 @@ __global__ __launch_bounds__(TW * TH) void k_render_bwd(BwdArgs a) {
             if (cmask == 0) continue;
             const bool contrib = lane_in(cmask);
             const bool unclamped = lane_in(cmask & wave_ballot(!(araw > bk.alpha_max)));
-            const RawConic& q = s_conic[t];
             // 1 - alpha >= 1 - alpha_max > 0; the hardware reciprocal (about
             // 1 ulp) keeps the back-to-front recovery of T well inside the
             // gradient tolerance
@@ -225,13 +227,16 @@ __global__ __launch_bounds__(TW * TH) void k_render_bwd(BwdArgs a) {
             // dL/dalpha = dL/dC . (c_k T_k - R_k / (1 - alpha)); zero through the clamp
             const float dLda = Tk * Dc - inv * SR;
             const float gp = unclamped ? dLda * araw : 0.f;  // dL/dpower
+            // moments of dL/dpower over the splat's pixels; the conic and 1/sigma,
+            // constant per splat, are applied once to their sums (flush below)
             float gv[kNG];
-            gv[0] = -gp * (q.A * dx + q.B * dy);
-            gv[1] = -gp * (q.C * dy + q.B * dx);
-            gv[2] = -0.5f * gp * dx * dx;
-            gv[3] = -gp * dx * dy;
-            gv[4] = -0.5f * gp * dy * dy;
-            gv[5] = gp * q.inv_sigma;  // dL/dsigma = dL/dalpha exp(power)
+            const float gdx = gp * dx, gdy = gp * dy;
+            gv[0] = gdx;
+            gv[1] = gdy;
+            gv[2] = gdx * dx;
+            gv[3] = gdx * dy;
+            gv[4] = gdy * dy;
+            gv[5] = gp;
             gv[6] = dLdC[0] * w;
             gv[7] = dLdC[1] * w;
             gv[8] = dLdC[2] * w;
@@ -259,11 +264,26 @@ __global__ __launch_bounds__(TW * TH) void k_render_bwd(BwdArgs a) {
             if (j < bend) {
                 const uint32_t id = s_batch[threadIdx.x].id;
                 if (id < uint64_t(a.n)) {
+                    // from the moments S0..S5 of dL/dpower (with dx = u - px, dy = v - py):
+                    //   dL/du = -(A S0 + B S1), dL/dv = -(B S0 + C S1),
+                    //   dL/dA = -S2 / 2, dL/dB = -S3, dL/dC = -S4 / 2, dL/dsigma = S5 / sigma
+                    const RawConic q = s_conic[threadIdx.x];
+                    float m[kNG];
 #pragma unroll
-                    for (int k = 0; k < kNG; ++k) {
-                        const float v = s_acc[k][threadIdx.x];
-                        if (v != 0.f) atomicAdd(&a.w.sg[int64_t(k) * a.w.vn + vbase + id], v);
-                    }
+                    for (int k = 0; k < kNG; ++k) m[k] = s_acc[k][threadIdx.x];
+                    float g[kNG];
+                    g[0] = -fmaf(q.A, m[0], q.B * m[1]);
+                    g[1] = -fmaf(q.B, m[0], q.C * m[1]);
+                    g[2] = -0.5f * m[2];
+                    g[3] = -m[3];
+                    g[4] = -0.5f * m[4];
+                    g[5] = m[5] * q.inv_sigma;
+                    g[6] = m[6];
+                    g[7] = m[7];
+                    g[8] = m[8];
+#pragma unroll
+                    for (int k = 0; k < kNG; ++k)
+                        if (g[k] != 0.f) atomicAdd(&a.w.sg[int64_t(k) * a.w.vn + vbase + id], g[k]);
                 }
             }
         }
