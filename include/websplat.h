@@ -220,9 +220,10 @@ int64_t ws_total_image_floats(const ws_camera* cams, int32_t n_views);
  *               keys is uint64_t[capacity], or uint32_t[capacity] holding the
  *               tile (bin) id alone with WS_FLAG_KEYS32
  *   d_num_pairs out device int64: the number of pairs M (also when M > capacity)
- *   d_status    in/out device int32; set to WS_ERR_CAPACITY when M > capacity
- *               (pairs beyond capacity are not written).  The caller zeroes it
- *               before the first call of a frame.
+ *   d_status    in/out device int32: the frame's status word.  The call's first
+ *               kernel sets it to 0 (a frame starts clean); it is set to
+ *               WS_ERR_CAPACITY when M > capacity (pairs beyond capacity are not
+ *               written), and the later calls of the frame report into it.
  * Culls (no pair): sigma < alpha_min, p.z <= near_z, non-finite parameters or
  * zero quaternion, and a pixel rectangle that contains no pixel centre. */
 ws_status ws_preprocess(const ws_gaussians* g, const ws_camera* cams, const ws_camera* d_cams, int32_t n_views,

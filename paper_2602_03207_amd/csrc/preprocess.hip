@@ -43,6 +43,8 @@ constexpr int kEmitSlots = kEmitThreads;               // entries loaded per rou
 // dependent loads).
 constexpr int kCompactItems = 16;
 constexpr int kCountItems = 8;
+// The depth sort of depth-first emission: 31 key bits in 4 passes of 8 bits.
+constexpr int kDepthPasses = 4, kDepthRadixBits = 8, kDepthRadix = 1 << kDepthRadixBits;
 
 struct PreprocessWs {
     uint32_t* list_a;       // [V n] visible entries in index order
@@ -82,7 +84,7 @@ size_t layout(void* ws, int64_t n, int32_t n_views, int64_t capacity, bool depth
         p.depth = reinterpret_cast<uint32_t*>(take(size_t(ents) * 4));
         p.dkey_a = reinterpret_cast<uint32_t*>(take(size_t(ents) * 4));
         p.dkey_b = reinterpret_cast<uint32_t*>(take(size_t(ents) * 4));
-        p.sort_ws = take(sort_workspace(ents, 0, 31, 8, true, 4));
+        p.sort_ws = take(sort_workspace(ents, 0, 31, kDepthRadixBits, true, 4));
     }
     if (out) *out = p;
     return off;
@@ -95,7 +97,7 @@ __global__ __launch_bounds__(kPreThreads) void k_preprocess(GaussPtrs g, const w
                                                            uint32_t* __restrict__ depth, ClearList clr) {
     const int32_t v = blockIdx.y;
     const int64_t i = int64_t(blockIdx.x) * kPreThreads + threadIdx.x;
-    // the look-back words of the scans and of the depth sort that follow
+    // the look-back words of the scans and of the depth sort that follow, and the status word
     clear_words(clr, int64_t(v) * gridDim.x * kPreThreads + i, int64_t(gridDim.x) * gridDim.y * kPreThreads);
     if (i >= g.n) return;
     const ws_camera& cam = cams[v];
@@ -147,6 +149,171 @@ struct CompactStore {
         if (dkeys) dkeys[pos] = it.depth;
     }
 };
+
+// ---- depth-first compaction: one kernel lists the visible entries with their
+// depth keys and prepares the depth sort that follows.  Block b takes `rounds`
+// consecutive chunks of 4096 entries (16 per thread, wave-striped; enough
+// rounds that at most kCompactMaxBlocks blocks cover the input), counts their
+// visible entries and finds its offset by the decoupled look-back of scan.h
+// (block b waits only for lower blocks, which each XCD starts first; bounded
+// wait; the look-back's latency grows with the block count, hence the cap),
+// then writes the list entries and depth keys (with several rounds the
+// entries are read again, from the cache, for the writes).  On the way it
+// counts the depth digits of its visible entries for every pass of the depth
+// sort (LDS, then one global add per non-zero bin) and zeroes the sort's
+// look-back words of the sort tiles its entries land in, so the sort needs no
+// histogram launch.
+constexpr int kCompactThreads = 256;
+constexpr int kCompactBlock = kCompactThreads * kCompactItems;
+constexpr int kCompactWaves = kCompactThreads / kWave;
+constexpr int64_t kCompactMaxBlocks = 1024;
+constexpr int kCompactMaxRounds = 64;
+
+struct CompactArgs {
+    const uint32_t* tiles_touched;
+    const uint32_t* depth;
+    uint32_t* list;
+    uint32_t* dkeys;
+    int64_t total;
+    int32_t rounds;  // chunks of kCompactBlock entries per block
+    uint64_t* look;  // [blocks] look-back words, zeroed by k_preprocess
+    int64_t* d_nvis;
+    int32_t* d_status;
+    SortHistWords sw;  // the depth sort's histograms (zeroed by k_preprocess) and look-back words
+};
+
+inline int32_t compact_rounds(int64_t total) {
+    const int64_t chunks = (std::max<int64_t>(total, 1) + kCompactBlock - 1) / kCompactBlock;
+    return int32_t(std::min<int64_t>((chunks + kCompactMaxBlocks - 1) / kCompactMaxBlocks, kCompactMaxRounds));
+}
+inline int64_t compact_blocks_of(int64_t total) {
+    const int64_t per = int64_t(kCompactBlock) * compact_rounds(total);
+    return (std::max<int64_t>(total, 1) + per - 1) / per;
+}
+
+// Loads one chunk's visibility flags and depth keys (16 per thread).
+__device__ __forceinline__ void compact_load(const CompactArgs& a, int64_t wbase, uint32_t* tt, uint32_t* dk) {
+#pragma unroll
+    for (int j = 0; j < kCompactItems; ++j) {
+        const int64_t i = wbase + j * kWave;
+        const int64_t ic = i < a.total ? i : a.total - 1;
+        tt[j] = a.tiles_touched[ic];
+        dk[j] = a.depth[ic];
+    }
+#pragma unroll
+    for (int j = 0; j < kCompactItems; ++j) tt[j] = (wbase + j * kWave < a.total && tt[j] != 0u) ? 1u : 0u;
+}
+
+template <bool MULTI>
+__global__ __launch_bounds__(kCompactThreads) void k_compact(CompactArgs a) {
+    constexpr int kPerWave = kCompactItems * kWave;
+    constexpr int bins = kDepthPasses * kDepthRadix;
+    __shared__ uint32_t s_hist[bins];
+    __shared__ uint32_t s_cnt[kCompactMaxRounds * kCompactWaves];  // visible entries per (round, wave)
+    __shared__ uint64_t s_excl;
+    if (*a.d_status != 0) return;
+    const int64_t per_block = int64_t(kCompactBlock) * a.rounds;
+    const int64_t nb = (a.total + per_block - 1) / per_block;
+    if (int64_t(blockIdx.x) >= nb) return;
+    const int64_t b = blockIdx.x;
+    for (int k = threadIdx.x; k < bins; k += kCompactThreads) s_hist[k] = 0;
+    const int wave = threadIdx.x / kWave;
+    const uint32_t lane = lane_id();
+    __syncthreads();  // the histogram's zeroing before the adds
+    uint32_t tt[kCompactItems], dk[kCompactItems];
+    const int rounds = MULTI ? a.rounds : 1;
+    for (int r = 0; r < rounds; ++r) {
+        const int64_t wbase = b * per_block + int64_t(r) * kCompactBlock + int64_t(wave) * kPerWave + lane;
+        compact_load(a, wbase, tt, dk);
+        uint32_t cnt = 0;
+#pragma unroll
+        for (int j = 0; j < kCompactItems; ++j) {
+            cnt += uint32_t(__popcll(__ballot(tt[j] != 0u)));
+            // depth digits of every pass (bit 31 of a positive depth is 0)
+            if (tt[j]) {
+#pragma unroll
+                for (int p = 0; p < kDepthPasses; ++p)
+                    atomicAdd(&s_hist[p * kDepthRadix + ((dk[j] >> (p * kDepthRadixBits)) & (kDepthRadix - 1))], 1u);
+            }
+        }
+        if (lane == 0) s_cnt[r * kCompactWaves + wave] = cnt;
+    }
+    __syncthreads();
+    uint64_t block_sum = 0;
+    for (int k = 0; k < rounds * kCompactWaves; ++k) block_sum += s_cnt[k];
+    if (wave == 0) {
+        if (lane == 0) store_agent(&a.look[b], (b == 0 ? kScanInc : kScanAgg) | block_sum);
+        uint64_t excl = 0;
+        if (b > 0) {
+            int64_t k = b - 1;  // lane l reads predecessor k - l
+            uint32_t spins = 0;
+            while (true) {
+                const int64_t kk = k - int64_t(lane);
+                uint64_t st = kk >= 0 ? load_agent(&a.look[kk]) : kScanInc;
+                uint64_t need = 0, incm = 0;
+                while (true) {
+                    incm = __ballot((st >> 62) == 2);
+                    const uint64_t zero = __ballot((st >> 62) == 0);
+                    need = incm ? ((incm & (~incm + 1)) << 1) - 1 : ~uint64_t(0);
+                    if ((zero & need) == 0) break;
+                    if (++spins > kSpinLimit) {
+                        if (lane == 0) atomicExch(a.d_status, int32_t(WS_ERR_SPIN_LIMIT));
+                        need = 0;
+                        incm = 1;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                    if ((st >> 62) == 0) st = load_agent(&a.look[kk]);
+                }
+                const uint64_t part = ((need >> lane) & 1) ? (st & kScanVal) : 0;
+                excl += wave_sum(part);
+                if (incm) break;
+                k -= kWave;
+            }
+            if (lane == 0) store_agent(&a.look[b], kScanInc | (excl + block_sum));
+        }
+        if (lane == 0) {
+            s_excl = excl;
+            if (b == nb - 1) *a.d_nvis = int64_t(excl + block_sum);
+        }
+    }
+    __syncthreads();
+    uint64_t off = s_excl;
+    for (int r = 0; r < rounds; ++r) {
+        uint64_t woff = 0, rsum = 0;
+        for (int w = 0; w < kCompactWaves; ++w) {
+            const uint32_t c = s_cnt[r * kCompactWaves + w];
+            woff += w < wave ? c : 0u;
+            rsum += c;
+        }
+        const int64_t wbase = b * per_block + int64_t(r) * kCompactBlock + int64_t(wave) * kPerWave + lane;
+        if (MULTI) compact_load(a, wbase, tt, dk);  // again, from the cache
+        uint64_t pos = off + woff;
+#pragma unroll
+        for (int j = 0; j < kCompactItems; ++j) {
+            const uint64_t m = __ballot(tt[j] != 0u);
+            if (tt[j]) {
+                const uint64_t q = pos + lanes_below(m);
+                a.list[q] = uint32_t(wbase + j * kWave);
+                a.dkeys[q] = dk[j];
+            }
+            pos += uint64_t(__popcll(m));
+        }
+        off += rsum;
+    }
+    for (int k = threadIdx.x; k < bins; k += kCompactThreads)
+        if (s_hist[k]) atomicAdd(&a.sw.hist[k], s_hist[k]);
+    // the depth sort's look-back words of the sort tiles this block's entries land in
+    if (block_sum > 0) {
+        const int64_t t0 = int64_t(s_excl) / a.sw.tile, t1 = int64_t(s_excl + block_sum - 1) / a.sw.tile;
+        const uint32_t words = uint32_t(t1 - t0 + 1) * kDepthRadix;  // per pass, a few tiles
+#pragma unroll
+        for (int p = 0; p < kDepthPasses; ++p) {
+            uint32_t* st = a.sw.status + (int64_t(p) * a.sw.max_tiles + t0) * kDepthRadix;
+            for (uint32_t w = threadIdx.x; w < words; w += kCompactThreads) st[w] = 0u;
+        }
+    }
+}
 
 // ---- counts: prefix sum of the listed entries' tile counts
 struct CountLoad {
@@ -398,9 +565,13 @@ hipError_t launch_preprocess(const GaussPtrs& g, const ws_camera* d_cams, int32_
     const uint32_t gx = uint32_t(std::max<int64_t>((g.n + kPreThreads - 1) / kPreThreads, 1));
     const int64_t ents = std::max<int64_t>(pw.total, 1);
     ClearList clr;
-    clr.add(pw.scan_a, scan_sync_words(pw.total, kCompactItems));
-    if (depth_first) sort_sync_words(pw.sort_ws, ents, 0, 31, 8, true, 4, &clr);
+    // depth-first: k_compact's look-back words (one 64-bit word per block); otherwise those of the scan
+    const int64_t compact_blocks = compact_blocks_of(ents);
+    clr.add(pw.scan_a, depth_first ? 2 * compact_blocks : scan_sync_words(pw.total, kCompactItems));
+    if (depth_first) sort_sync_words(pw.sort_ws, ents, 0, 31, kDepthRadixBits, true, 4, &clr);
     clr.add(pw.scan_b, scan_sync_words(ents, kCountItems));
+    // a frame starts with a clean status word (no kernel of this launch reads it)
+    clr.add(d_status, 1);
     timing_begin(WS_KERNEL_PREPROCESS, stream);
     switch (o.sh_degree) {
         case 0: hipLaunchKernelGGL(k_preprocess<0>, dim3(gx, n_views), dim3(kPreThreads), 0, stream, g, d_cams, o,
@@ -415,18 +586,37 @@ hipError_t launch_preprocess(const GaussPtrs& g, const ws_camera* d_cams, int32_
     timing_end(WS_KERNEL_PREPROCESS, stream);
 
     timing_begin(WS_KERNEL_SCAN_EMIT, stream);
-    // compaction of the visible entries (count to d_nvis)
-    launch_scan<uint64_t, kCompactItems>(FlagLoad{tiles_touched, pw.depth}, CompactStore{pw.list_a, depth_first ? pw.dkey_a : nullptr},
-                          pw.total, nullptr, d_status, pw.scan_a, reinterpret_cast<uint64_t*>(pw.d_nvis), stream,
-                          true);
     const uint32_t* list = pw.list_a;
     if (depth_first) {
+        // compaction of the visible entries with their depth keys (count to d_nvis), which also
+        // prepares the depth sort: its digit histograms and look-back words
+        CompactArgs ca;
+        ca.tiles_touched = tiles_touched;
+        ca.depth = pw.depth;
+        ca.list = pw.list_a;
+        ca.dkeys = pw.dkey_a;
+        ca.total = ents;
+        ca.rounds = compact_rounds(ents);
+        ca.look = static_cast<uint64_t*>(pw.scan_a);
+        ca.d_nvis = pw.d_nvis;
+        ca.d_status = d_status;
+        ca.sw = sort_hist_words(pw.sort_ws, ents, 0, 31, kDepthRadixBits, true, 4);
+        if (ca.sw.passes != kDepthPasses || ca.sw.radix != kDepthRadix) std::abort();  // a programming error
+        if (ca.rounds > 1)
+            hipLaunchKernelGGL(k_compact<true>, dim3(uint32_t(compact_blocks)), dim3(kCompactThreads), 0, stream, ca);
+        else
+            hipLaunchKernelGGL(k_compact<false>, dim3(uint32_t(compact_blocks)), dim3(kCompactThreads), 0, stream, ca);
         // stable sort of the visible entries by depth: positive fp32 bits order like the values
         // the visible entries are typically a small fraction of all (view, Gaussian) entries
         const hipError_t e = launch_sort(pw.dkey_a, pw.list_a, pw.dkey_b, pw.list_b, ents, pw.d_nvis, d_status, 0, 31,
-                                         8, pw.sort_ws, stream, false, true, true);
+                                         kDepthRadixBits, pw.sort_ws, stream, false, true, true, true);
         if (e != hipSuccess) return e;
         list = pw.list_b;
+    } else {
+        // compaction of the visible entries (count to d_nvis)
+        launch_scan<uint64_t, kCompactItems>(FlagLoad{tiles_touched, nullptr}, CompactStore{pw.list_a, nullptr},
+                                             pw.total, nullptr, d_status, pw.scan_a,
+                                             reinterpret_cast<uint64_t*>(pw.d_nvis), stream, true);
     }
     // pair offsets of the listed entries (total to d_num_pairs)
     launch_scan<uint64_t, kCountItems>(CountLoad{tiles_touched, list}, CountStore{pw.offsets, pw.first_entry, pw.emit_blocks},

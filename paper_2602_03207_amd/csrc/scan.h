@@ -4,10 +4,11 @@
 //  * one pass (up to kOnePassMaxBlocks blocks): every block scans its items in
 //    registers, publishes its sum, reads its predecessors' published sums
 //    (a decoupled look-back: one wave reads 64 predecessors per round trip
-//    and stops at the first inclusive prefix) and writes its results.  Blocks
-//    take an atomic ticket, so a block only waits for blocks that have
-//    started, and the wait is bounded (WS_ERR_SPIN_LIMIT on expiry).  One
-//    read of the items, two launches (clearing the published sums, the pass).
+//    and stops at the first inclusive prefix) and writes its results.  Block
+//    b scans chunk b: each XCD starts its workgroups in index order, so a
+//    block only waits for blocks that have been started, and the wait is
+//    bounded (WS_ERR_SPIN_LIMIT on expiry).  One read of the items, two
+//    launches (clearing the published sums, the pass).
 //  * wait-free (larger inputs): the hierarchical scan of the paper's sort stage
 //    (Sec. 3.3.2) -- reduce, one-workgroup scan of the block sums, down-sweep
 //    -- each level one dispatch, no workgroup ever waits for another.
@@ -170,7 +171,6 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_onepass(Loader ld, Writer
     constexpr int kPerWave = ITEMS * kWave;
     __shared__ T s_wave[kScanThreads / kWave];
     __shared__ T s_excl;
-    __shared__ uint32_t s_block;
     if (d_status && *d_status != 0) return;
     const int64_t n = scan_count(cap, d_n);
     const int64_t nb = (n + (kScanThreads * ITEMS) - 1) / (kScanThreads * ITEMS);
@@ -178,11 +178,10 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_onepass(Loader ld, Writer
         if (blockIdx.x == 0 && threadIdx.x == 0 && total_out) *total_out = T(0);
         return;
     }
-    // blocks past the live ones leave before taking a ticket
+    // blocks past the live ones leave at once
     if (int64_t(blockIdx.x) >= nb) return;
-    if (threadIdx.x == 0) s_block = atomicAdd(ticket, 1u);
-    __syncthreads();
-    const int64_t b = s_block;
+    (void)ticket;
+    const int64_t b = blockIdx.x;
     const int wave = threadIdx.x / kWave;
     const uint32_t lane = lane_id();
     const int64_t wbase = b * (kScanThreads * ITEMS) + int64_t(wave) * kPerWave + lane;

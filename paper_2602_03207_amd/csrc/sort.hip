@@ -17,10 +17,12 @@
 //  * look-back (small inputs, up to kSmallSortMax pairs, or inputs whose
 //    device count is known to be far below the capacity): base_d from one
 //    histogram of all passes (k_sort_hist), prefix_wg by a decoupled look-back
-//    over per-tile counts published in device memory.  Tiles take an atomic
-//    ticket, so a tile only waits for tiles that have started, and the wait is
-//    bounded (WS_ERR_SPIN_LIMIT on expiry).  One read and one write per pair
-//    and pass, and one launch per pass.
+//    over per-tile counts published in device memory.  Up to kLookbackGrid
+//    tiles, workgroup b sorts tile b (each XCD starts its workgroups in index
+//    order, so a tile only waits for tiles that have been started); more
+//    tiles are taken through an atomic ticket by as many workgroups.  The wait
+//    is bounded (WS_ERR_SPIN_LIMIT on expiry).  One read and one write per
+//    pair and pass, and one launch per pass.
 //  * wait-free (large inputs, where the ticket's round trip in front of every
 //    tile's loads and the histogram's extra read cost more than they save):
 //    per pass, k_upsweep counts each tile's digits into a digit-major table
@@ -473,6 +475,7 @@ struct PassArgs {
     const uint32_t* hist;  // [radix] of this pass
     uint32_t* status;      // [max_tiles][2^B] of this pass
     uint32_t* ticket;
+    bool direct;  // one workgroup per tile (no ticket)
 };
 
 template <int B, int ITEMS, typename K>
@@ -556,11 +559,17 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_pass(PassArgs<K> a) {
     if (a.d_status && *a.d_status != 0) return;
     const int64_t n = device_count(a.cap, a.d_n);
     const int64_t ntiles = (n + kTile - 1) / kTile;
-    // Workgroups past the live tiles leave before taking a ticket.  The others
-    // take tickets until they run past the live tiles; each tile goes to one
-    // workgroup, and a workgroup only ever waits for tiles with smaller
-    // tickets, which running workgroups hold.
+    // Workgroups past the live tiles leave at once.
     if (int64_t(blockIdx.x) >= ntiles) return;
+    if (a.direct) {  // the grid covers every tile: workgroup b sorts tile b
+        clear_whist(sm);
+        __syncthreads();
+        sort_tile_lookback<B, ITEMS, K>(sm, a, n, int64_t(blockIdx.x));
+        return;
+    }
+    // The others take tickets until they run past the live tiles; each tile
+    // goes to one workgroup, and a workgroup only ever waits for tiles with
+    // smaller tickets, which running workgroups hold.
     while (true) {
         if (threadIdx.x == 0) sm.tile = atomicAdd(a.ticket, 1u);
         clear_whist(sm);
@@ -595,9 +604,12 @@ void run_pass(const PassLaunch<K>& c) {
                               c.L->table_scan, static_cast<uint32_t*>(nullptr), c.stream, true);
         hipLaunchKernelGGL((k_downsweep<B, ITEMS, K>), dim3(grid), dim3(kSortThreads), 0, c.stream, c.da);
     } else {
-        // workgroups loop over tickets, so the grid need not cover every tile
+        // up to kLookbackGrid tiles one workgroup each, otherwise workgroups
+        // loop over tickets, so the grid need not cover every tile
         const uint32_t lgrid = uint32_t(std::min<int64_t>(c.L->max_tiles, kLookbackGrid));
-        hipLaunchKernelGGL((k_sort_pass<B, ITEMS, K>), dim3(lgrid), dim3(kSortThreads), 0, c.stream, c.pa);
+        PassArgs<K> pa = c.pa;
+        pa.direct = c.L->max_tiles <= kLookbackGrid;
+        hipLaunchKernelGGL((k_sort_pass<B, ITEMS, K>), dim3(lgrid), dim3(kSortThreads), 0, c.stream, pa);
     }
 }
 
@@ -629,17 +641,33 @@ void sort_sync_words(void* ws, int64_t capacity, int32_t begin_bit, int32_t end_
     if (!L.wait_free) c->add(L.hist, int64_t(L.passes) * (L.radix + 1));  // histograms, then tickets
 }
 
+SortHistWords sort_hist_words(void* ws, int64_t capacity, int32_t begin_bit, int32_t end_bit, int32_t radix_bits,
+                              bool sparse, int key_bytes) {
+    SortLayout L;
+    plan(ws, capacity, begin_bit, end_bit, radix_bits, sparse, key_bytes, &L);
+    SortHistWords w{};
+    if (L.wait_free) return w;
+    w.hist = L.hist;
+    w.status = L.status;
+    w.max_tiles = L.max_tiles;
+    w.passes = L.passes;
+    w.radix = L.radix;
+    w.r = L.r;
+    w.tile = kSortThreads * L.items;
+    return w;
+}
+
 namespace {
 
 template <typename K>
 hipError_t launch_sort_t(const K* kin, const uint32_t* vin, K* kout, uint32_t* vout, int64_t n, const int64_t* d_n,
                          const int32_t* d_status, int32_t begin_bit, int32_t end_bit, int32_t radix_bits, void* ws,
-                         hipStream_t stream, bool timed, bool sparse, bool precleared) {
+                         hipStream_t stream, bool timed, bool sparse, bool precleared, bool hist_ready) {
     SortLayout L;
     plan(ws, n, begin_bit, end_bit, radix_bits, sparse, int(sizeof(K)), &L);
     K* alt_keys = static_cast<K*>(L.alt_keys);
     const int hist_id = timed ? WS_KERNEL_SORT_HIST : -1, pass_id = timed ? WS_KERNEL_SORT_PASS : -1;
-    if (!L.wait_free) {
+    if (!L.wait_free && !hist_ready) {
         if (!precleared)
             hipLaunchKernelGGL(k_sort_init, dim3(1), dim3(256), 0, stream, L.hist, L.passes * L.radix, L.tickets,
                                L.passes);
@@ -704,16 +732,18 @@ hipError_t launch_sort_t(const K* kin, const uint32_t* vin, K* kout, uint32_t* v
 
 hipError_t launch_sort(const uint64_t* kin, const uint32_t* vin, uint64_t* kout, uint32_t* vout, int64_t n,
                        const int64_t* d_n, const int32_t* d_status, int32_t begin_bit, int32_t end_bit,
-                       int32_t radix_bits, void* ws, hipStream_t stream, bool timed, bool sparse, bool precleared) {
+                       int32_t radix_bits, void* ws, hipStream_t stream, bool timed, bool sparse, bool precleared,
+                       bool hist_ready) {
     return launch_sort_t<uint64_t>(kin, vin, kout, vout, n, d_n, d_status, begin_bit, end_bit, radix_bits, ws, stream,
-                                   timed, sparse, precleared);
+                                   timed, sparse, precleared, hist_ready);
 }
 
 hipError_t launch_sort(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout, int64_t n,
                        const int64_t* d_n, const int32_t* d_status, int32_t begin_bit, int32_t end_bit,
-                       int32_t radix_bits, void* ws, hipStream_t stream, bool timed, bool sparse, bool precleared) {
+                       int32_t radix_bits, void* ws, hipStream_t stream, bool timed, bool sparse, bool precleared,
+                       bool hist_ready) {
     return launch_sort_t<uint32_t>(kin, vin, kout, vout, n, d_n, d_status, begin_bit, end_bit, radix_bits, ws, stream,
-                                   timed, sparse, precleared);
+                                   timed, sparse, precleared, hist_ready);
 }
 
 }  // namespace ws

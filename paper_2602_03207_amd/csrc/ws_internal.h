@@ -245,20 +245,36 @@ size_t preprocess_workspace(int64_t n, int32_t n_views, int64_t capacity, uint32
 // `precleared`: an earlier kernel of the stream zeroed the words that
 // sort_sync_words lists, so the sort launches no clearing kernel.
 // The two overloads sort 64-bit and 32-bit keys; key_bytes below is 8 or 4.
+// `hist_ready`: an earlier kernel filled the histograms and cleared the
+// look-back words listed by sort_hist_words (look-back schedule only).
 hipError_t launch_sort(const uint64_t* kin, const uint32_t* vin, uint64_t* kout, uint32_t* vout, int64_t n,
                        const int64_t* d_n, const int32_t* d_status, int32_t begin_bit, int32_t end_bit,
                        int32_t radix_bits, void* ws, hipStream_t stream, bool timed = true, bool sparse = false,
-                       bool precleared = false);
+                       bool precleared = false, bool hist_ready = false);
 hipError_t launch_sort(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout, int64_t n,
                        const int64_t* d_n, const int32_t* d_status, int32_t begin_bit, int32_t end_bit,
                        int32_t radix_bits, void* ws, hipStream_t stream, bool timed = true, bool sparse = false,
-                       bool precleared = false);
+                       bool precleared = false, bool hist_ready = false);
 size_t sort_workspace(int64_t capacity, int32_t begin_bit, int32_t end_bit, int32_t radix_bits, bool sparse = false,
                       int key_bytes = 8);
 // Adds to `c` the words of a sort with these arguments that must be zero when
 // it starts (none for the wait-free schedule, whose passes clear their own).
 void sort_sync_words(void* ws, int64_t capacity, int32_t begin_bit, int32_t end_bit, int32_t radix_bits, bool sparse,
                      int key_bytes, ClearList* c);
+// The digit histograms and look-back words of a look-back (sparse or small)
+// sort with these arguments, for a kernel that produces the sort's input and
+// fills them on the way (launch_sort with hist_ready then skips its histogram
+// kernel): hist [passes][radix] (zero when the producer starts, then the digit
+// counts of every pass), status [passes][max_tiles][radix] (the words of every
+// tile holding input zeroed by the producer), tiles of `tile` pairs.
+struct SortHistWords {
+    uint32_t* hist;
+    uint32_t* status;
+    int64_t max_tiles;
+    int passes, radix, r, tile;
+};
+SortHistWords sort_hist_words(void* ws, int64_t capacity, int32_t begin_bit, int32_t end_bit, int32_t radix_bits,
+                              bool sparse, int key_bytes);
 
 // render.hip
 hipError_t launch_render(const ws_splat* splats, int64_t n, const ws_camera* d_cams, int32_t n_views,

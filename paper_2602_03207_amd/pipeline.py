@@ -222,12 +222,10 @@ class Renderer:
         again after the render, so a sort or render that did not complete (an
         expired bounded wait) raises WsError instead of leaving stale images.
         """
-        self.d_status.zero_()
-        self.preprocess(g, stream)
+        self.preprocess(g, stream)  # resets the status word
         m = int(self.d_num_pairs.item())
         if m > self.capacity:
             self._ensure_capacity(int(m * 1.2) + 1024)
-            self.d_status.zero_()
             self.preprocess(g, stream)
         self._check_status()
         self.num_pairs = m
@@ -239,8 +237,7 @@ class Renderer:
 
     def forward_capacity(self, g: GaussianTensors, stream=None):
         """Device-sized path (no host synchronisation); capacity must already cover M."""
-        self.d_status.zero_()
-        self.preprocess(g, stream)
+        self.preprocess(g, stream)  # resets the status word
         self.sort(self.capacity, device_count=True, stream=stream)
         self.render(self.capacity, stream)
 
