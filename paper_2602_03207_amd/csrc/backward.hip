@@ -160,6 +160,11 @@ __global__ __launch_bounds__(TW * TH) void k_render_bwd(BwdArgs a) {
     __syncthreads();
     const int32_t maxlast = s_maxlast;
     if (maxlast < 0) return;  // nothing composited in this tile
+    // this wave's last contributor: its walk skips the entries behind it
+    int32_t wlast = ps.last;
+#pragma unroll
+    for (int s = 32; s >= 1; s >>= 1) wlast = max(wlast, __shfl_xor(wlast, s, kWave));
+    wlast = __builtin_amdgcn_readfirstlane(wlast);
 
     // ---- pass 2: back to front from the last contributor
     float dLdC[3] = {0.f, 0.f, 0.f};
@@ -199,6 +204,7 @@ __global__ __launch_bounds__(TW * TH) void k_render_bwd(BwdArgs a) {
         // back to front over the staged splats that meet this wave's quadrant
         MaskWalk<NW, false> walk;
         walk.init(my_masks);
+        walk.keep_up_to(wlast - bstart);
         for (int t = walk.next(); t >= 0; t = walk.next()) {
             const int32_t j = bstart + t;
             const StagedSplat& s = s_batch[t];

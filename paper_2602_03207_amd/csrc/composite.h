@@ -354,6 +354,14 @@ struct MaskWalk {
         for (int w = 0; w < NW; ++w) mk[w] = uniform_u64(quadrant_masks[w]);
         sw = Forward ? 0 : NW - 1;
     }
+    // Drops the entries past batch position `lim` (< 0: every entry).
+    __device__ __forceinline__ void keep_up_to(int lim) {
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            const int hi = lim - w * kWave;  // last kept bit of this mask
+            mk[w] = hi < 0 ? 0 : (hi >= kWave - 1 ? mk[w] : mk[w] & ((uint64_t(2) << hi) - 1));
+        }
+    }
     __device__ __forceinline__ int next() {
         constexpr int kCur = Forward ? 0 : NW - 1;
         while (mk[kCur] == 0) {
