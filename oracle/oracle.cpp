@@ -609,17 +609,19 @@ struct OutcomeSearch {
         double C[3] = {Cin[0], Cin[1], Cin[2]};
         for (; j < count; ++j) {
             const PixelSplat& s = (*S)[size_t(ids[j])];
-            // a pixel more than one pixel outside the rectangle is far from the
-            // alpha_min ellipse, which the rectangle bounds exactly
-            if (px < s.x0 - 1 || px > s.x1 + 1 || py < s.y0 - 1 || py > s.y1 + 1) continue;
             const bool in_rect = !(px < s.x0 || px > s.x1 || py < s.y0 || py > s.y1);
             const double dx = s.u - pcx, dy = s.v - pcy;
             const double power = -0.5 * (s.A * dx * dx + s.C * dy * dy) - s.B * dx * dy;
-            const double alpha_raw = s.sigma * std::exp(power);
-            const double alpha = std::min(opt->alpha_max, alpha_raw);
             const SplatError& se = (*E)[size_t(ids[j])];
             const double ea = s.sigma > 0.0 ? alpha_log_error(s, se, dx, dy, power) : 0.0;
             const double la = se.ln_sigma_rel + power;
+            // Outside the rectangle the rule never composites (reading A27);
+            // an fp32 evaluation that tests alpha alone takes the splat there
+            // only where its alpha test is within reach, the one case the
+            // enumeration below follows.
+            if (!in_rect && !(std::fabs(la) <= ea)) continue;
+            const double alpha_raw = s.sigma * std::exp(power);
+            const double alpha = std::min(opt->alpha_max, alpha_raw);
             const bool take_here = in_rect && alpha >= opt->alpha_min;
             if (std::fabs(la) <= ea && alpha_raw > 0.0) {  // the alpha test within reach: both choices valid
                 mark(T);

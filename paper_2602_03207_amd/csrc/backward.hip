@@ -113,7 +113,8 @@ __device__ __forceinline__ void wave_sum9(float (&v)[kNG], float* q0, float* q1,
     *q2 = row_sum(p8 + z1);
 }
 
-template <int TW, int TH>
+// RECT: the rectangle test of the forward (see blend_one), in both passes.
+template <int TW, int TH, bool RECT>
 __global__ __launch_bounds__(TW * TH) void k_render_bwd(BwdArgs a) {
     constexpr int NT = TW * TH, NW = NT / kWave;
     __shared__ StagedSplat s_batch[NT];
@@ -153,7 +154,7 @@ __global__ __launch_bounds__(TW * TH) void k_render_bwd(BwdArgs a) {
         }
         stage_quadrant_masks<TW, TH>(s, valid, ti.x0, ti.y0, bk.log2_amin, s_masks);
         __syncthreads();
-        composite_batch<NW>(ps, active, s_batch, my_masks, int32_t(b0 - start), bk);
+        composite_batch<NW, RECT>(ps, active, s_batch, my_masks, int32_t(b0 - start), bk);
     }
     __syncthreads();
     if (ps.last >= 0) atomicMax(&s_maxlast, ps.last);
@@ -218,7 +219,7 @@ __global__ __launch_bounds__(TW * TH) void k_render_bwd(BwdArgs a) {
             const float alpha = __builtin_amdgcn_fmed3f(araw, 0.f, bk.alpha_max);
             // the lane decisions as lane masks (ballots of the comparisons, as in
             // the forward), applied with inverse ballots: no per-lane branches
-            const uint64_t cmask = wave_ballot(j <= last) & wave_ballot(in_rect(s, pix)) &
+            const uint64_t cmask = wave_ballot(j <= last) & (RECT ? wave_ballot(in_rect(s, pix)) : ~uint64_t(0)) &
                                    wave_ballot(!(alpha < bk.alpha_min));
             if (cmask == 0) continue;
             const bool contrib = lane_in(cmask);
@@ -501,7 +502,10 @@ __global__ __launch_bounds__(128) void k_preprocess_bwd_sh(PreBwdArgs a) {
 
 template <int TW, int TH>
 void launch_bwd_t(const BwdArgs& ba, int64_t tiles, hipStream_t stream) {
-    hipLaunchKernelGGL((k_render_bwd<TW, TH>), dim3(uint32_t(tiles)), dim3(TW * TH), 0, stream, ba);
+    if (ba.o.flags & WS_FLAG_FIXED_3SIGMA)
+        hipLaunchKernelGGL((k_render_bwd<TW, TH, true>), dim3(uint32_t(tiles)), dim3(TW * TH), 0, stream, ba);
+    else
+        hipLaunchKernelGGL((k_render_bwd<TW, TH, false>), dim3(uint32_t(tiles)), dim3(TW * TH), 0, stream, ba);
 }
 
 }  // namespace

@@ -194,9 +194,19 @@ __device__ __forceinline__ bool lane_in(uint64_t mask) { return __builtin_amdgcn
 // masks too (ballots of the comparisons) and applied with lane_in().  A splat
 // that no active lane's rectangle holds changes nothing (all its masks are
 // empty), so it needs no separate test.
+//
+// RECT: test the pixel against the splat's rectangle.  With the opacity-aware
+// extent the rectangle is the bounding box of the ellipse where alpha reaches
+// alpha_min (Sec. 3.4), so a pixel outside it has alpha < alpha_min and the
+// alpha test alone rejects it; only a pixel whose alpha lies within the fp32
+// rounding of alpha_min can decide differently, which is one of the pixel's
+// correct fp32 results either way.  The fixed 3-sigma extent can be smaller
+// than that ellipse, and the ellipse of a packed record (axes rounded to fp16)
+// can reach past it: both need the test.
+template <bool RECT>
 __device__ __forceinline__ void blend_one(PixelState& ps, uint64_t& active, const StagedSplat& s, int32_t idx,
                                           const BlendConsts& k) {
-    const uint64_t inr = active & wave_ballot(in_rect(s, ps.pxy));
+    const uint64_t inr = RECT ? active & wave_ballot(in_rect(s, ps.pxy)) : active;
     const float dx = s.u - ps.pcx, dy = s.v - ps.pcy;
     // min(alpha_max, sigma e^power) as one clamp: the raw value is never negative
     const float alpha = __builtin_amdgcn_fmed3f(raw_alpha(s, dx, dy), 0.f, k.alpha_max);
@@ -388,7 +398,7 @@ struct MaskWalk {
 // all records read from LDS before the first is blended.  The wave leaves once all
 // its lanes have stopped (`active` empty); a splat blended after that changes
 // nothing.
-template <int NW>
+template <int NW, bool RECT>
 __device__ __forceinline__ void composite_batch(PixelState& ps, uint64_t& active, const StagedSplat* batch,
                                                 const uint64_t* quadrant_masks, int32_t idx0, const BlendConsts& k) {
     if (active == 0) return;
@@ -413,18 +423,18 @@ __device__ __forceinline__ void composite_batch(PixelState& ps, uint64_t& active
                 const int j3 = __builtin_ctzll(m);
                 m &= m - 1;
                 const StagedSplat s1 = wb[j1], s2 = wb[j2], s3 = wb[j3];
-                blend_one(ps, active, s0, wi + j0, k);
-                blend_one(ps, active, s1, wi + j1, k);
-                blend_one(ps, active, s2, wi + j2, k);
-                blend_one(ps, active, s3, wi + j3, k);
+                blend_one<RECT>(ps, active, s0, wi + j0, k);
+                blend_one<RECT>(ps, active, s1, wi + j1, k);
+                blend_one<RECT>(ps, active, s2, wi + j2, k);
+                blend_one<RECT>(ps, active, s3, wi + j3, k);
             } else if (left >= 2) {
                 const int j1 = __builtin_ctzll(m);
                 m &= m - 1;
                 const StagedSplat s1 = wb[j1];
-                blend_one(ps, active, s0, wi + j0, k);
-                blend_one(ps, active, s1, wi + j1, k);
+                blend_one<RECT>(ps, active, s0, wi + j0, k);
+                blend_one<RECT>(ps, active, s1, wi + j1, k);
             } else {
-                blend_one(ps, active, s0, wi + j0, k);
+                blend_one<RECT>(ps, active, s0, wi + j0, k);
             }
             if (active == 0) return;
         }

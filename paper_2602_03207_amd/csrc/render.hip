@@ -363,8 +363,8 @@ __device__ __forceinline__ void stage_batch(const RenderArgs& a, const ws_splat*
     stage_quadrant_masks<TW, TH>(s, valid, x0, y0, log2_amin, s_masks);
 }
 
-// Composites global tile g into the images.
-template <int TW, int TH>
+// Composites global tile g into the images (RECT: see blend_one).
+template <int TW, int TH, bool RECT>
 __device__ __forceinline__ void render_tile(const RenderArgs& a, int64_t g, StagedSplat* s_batch, uint64_t* s_masks) {
     constexpr int NT = TW * TH, NW = NT / kWave;
     const TileInfo ti = locate_tile(a.cams, a.n_views, g, TW, TH);
@@ -386,7 +386,7 @@ __device__ __forceinline__ void render_tile(const RenderArgs& a, int64_t g, Stag
         if (__syncthreads_count(!lane_in(active)) == NT) break;
         stage_batch<TW, TH>(a, vsplats, b0, end, ti.x0, ti.y0, bk.log2_amin, s_batch, s_masks);
         __syncthreads();
-        composite_batch<NW>(ps, active, s_batch, my_masks, int32_t(b0 - start), bk);
+        composite_batch<NW, RECT>(ps, active, s_batch, my_masks, int32_t(b0 - start), bk);
     }
     if (inside) {
         float* img = a.images + ti.img_off;
@@ -398,13 +398,13 @@ __device__ __forceinline__ void render_tile(const RenderArgs& a, int64_t g, Stag
     }
 }
 
-template <int TW, int TH>
+template <int TW, int TH, bool RECT>
 __global__ __launch_bounds__(TW * TH) void k_render(RenderArgs a) {
     constexpr int NW = TW * TH / kWave;
     __shared__ StagedSplat s_batch[TW * TH];
     __shared__ uint64_t s_masks[NW * NW];
     if (*a.d_status != 0) return;
-    render_tile<TW, TH>(a, blockIdx.x, s_batch, s_masks);
+    render_tile<TW, TH, RECT>(a, blockIdx.x, s_batch, s_masks);
 }
 
 // ---- ordered, persistent render
@@ -455,7 +455,7 @@ __global__ __launch_bounds__(256) void k_tile_order(const uint32_t* ranges, int6
 
 // Every workgroup takes list positions from *queue until they run past the
 // end; each take advances the counter, so every workgroup leaves.
-template <int TW, int TH>
+template <int TW, int TH, bool RECT>
 __global__ __launch_bounds__(TW * TH) void k_render_queue(RenderArgs a, const uint32_t* order, uint32_t* queue) {
     constexpr int NW = TW * TH / kWave;
     __shared__ StagedSplat s_batch[TW * TH];
@@ -468,7 +468,7 @@ __global__ __launch_bounds__(TW * TH) void k_render_queue(RenderArgs a, const ui
         const uint32_t q = s_q;
         __syncthreads();
         if (int64_t(q) >= a.total_tiles) break;
-        render_tile<TW, TH>(a, order[q], s_batch, s_masks);
+        render_tile<TW, TH, RECT>(a, order[q], s_batch, s_masks);
     }
 }
 
@@ -501,14 +501,14 @@ __global__ void k_order_clear(uint32_t* words, int count) {
 }
 
 // Resident workgroups of k_render_queue on the current device (cached per device).
-template <int TW, int TH>
+template <int TW, int TH, bool RECT>
 uint32_t persistent_grid() {
     static int cached[64] = {0};
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
     if (cached[dev] == 0) {
         int per_cu = 0, cus = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_render_queue<TW, TH>, TW * TH, 0) != hipSuccess ||
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_render_queue<TW, TH, RECT>, TW * TH, 0) != hipSuccess ||
             per_cu < 1)
             per_cu = 1;
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 1;
@@ -529,15 +529,24 @@ void launch_ranges(const KOpts& o, const void* keys, int64_t capacity, const int
                            o.cell_mask());
 }
 
-template <int TW, int TH>
-void launch_render_t(const RenderArgs& ra, const OrderWs* ow, hipStream_t stream) {
+template <int TW, int TH, bool RECT>
+void launch_render_rt(const RenderArgs& ra, const OrderWs* ow, hipStream_t stream) {
     if (!ow) {
-        hipLaunchKernelGGL((k_render<TW, TH>), dim3(uint32_t(ra.total_tiles)), dim3(TW * TH), 0, stream, ra);
+        hipLaunchKernelGGL((k_render<TW, TH, RECT>), dim3(uint32_t(ra.total_tiles)), dim3(TW * TH), 0, stream, ra);
         return;
     }
-    const uint32_t grid = uint32_t(std::min<int64_t>(persistent_grid<TW, TH>(), ra.total_tiles));
-    hipLaunchKernelGGL((k_render_queue<TW, TH>), dim3(grid), dim3(TW * TH), 0, stream, ra,
+    const uint32_t grid = uint32_t(std::min<int64_t>(persistent_grid<TW, TH, RECT>(), ra.total_tiles));
+    hipLaunchKernelGGL((k_render_queue<TW, TH, RECT>), dim3(grid), dim3(TW * TH), 0, stream, ra,
                        static_cast<const uint32_t*>(ow->order), ow->queue);
+}
+
+// The rectangle test is needed only where the ellipse the render evaluates
+// may reach beyond the rectangle: the fixed 3-sigma extent, and packed records
+// (the rectangle bounds the ellipse before its axes are rounded to fp16).
+template <int TW, int TH>
+void launch_render_t(const RenderArgs& ra, const OrderWs* ow, hipStream_t stream) {
+    if (ra.o.flags & (WS_FLAG_FIXED_3SIGMA | WS_FLAG_PACKED)) launch_render_rt<TW, TH, true>(ra, ow, stream);
+    else launch_render_rt<TW, TH, false>(ra, ow, stream);
 }
 
 }  // namespace
