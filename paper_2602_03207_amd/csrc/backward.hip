@@ -73,10 +73,11 @@ struct RawConic {
 // swap pairs up values (v0, v1), (v2, v3), ... and one add leaves each value's
 // half-sums in one half of the wave; the 16-lane swap pairs up those and one
 // add leaves each value's quarter-sums in one row; DPP permutes inside rows
-// then sum each row.  Results, in every lane of the row: q0 holds v0, v2, v1,
-// v3 in rows 0, 1, 2, 3; q1 holds v4, v6, v5, v7; q2 holds v8 in row 0.  Every
-// step is a VALU operation on all 64 lanes (the callers run with all lanes
-// active); no LDS traffic.
+// then sum each row.  The ninth value has no partner: it is summed per row and
+// then across rows by the two row broadcasts.  Results, in every lane of the
+// row: q0 holds v0, v2, v1, v3 in rows 0, 1, 2, 3; q1 holds v4, v6, v5, v7;
+// q2 holds v8 in row 3.  Every step is a VALU operation on all 64 lanes (the
+// callers run with all lanes active); no LDS traffic.
 __device__ __forceinline__ void swap32(float& a, float& b) {
     // both operands are read and written (the swap builtin of this compiler
     // returns the first register twice); two wait states on either side
@@ -98,19 +99,24 @@ __device__ __forceinline__ float row_sum(float v) {
     return v;
 }
 __device__ __forceinline__ void wave_sum9(float (&v)[kNG], float* q0, float* q1, float* q2) {
-    float z0 = 0.f, z1 = 0.f;
     swap32(v[0], v[1]);
     swap32(v[2], v[3]);
     swap32(v[4], v[5]);
     swap32(v[6], v[7]);
-    swap32(v[8], z0);
-    float p01 = v[0] + v[1], p23 = v[2] + v[3], p45 = v[4] + v[5], p67 = v[6] + v[7], p8 = v[8] + z0;
+    float p01 = v[0] + v[1], p23 = v[2] + v[3], p45 = v[4] + v[5], p67 = v[6] + v[7];
     swap16(p01, p23);
     swap16(p45, p67);
-    swap16(p8, z1);
-    *q0 = row_sum(p01 + p23);
-    *q1 = row_sum(p45 + p67);
-    *q2 = row_sum(p8 + z1);
+    // row_bcast:15 adds the last lane of each row to the next row (row 0 has no
+    // source and adds 0), row_bcast:31 adds lane 31 to rows 2 and 3: row 3
+    // then holds r3 + r2 + (r1 + r0); rows 0-2 hold partial sums nobody reads
+    float s0 = row_sum(p01 + p23), s1 = row_sum(p45 + p67), s2 = dpp_add<0x143>(dpp_add<0x142>(row_sum(v[8])));
+    // complete the sums in every lane here: left to itself the compiler moves
+    // the last add of each into the row leaders' branch, which turns one DPP
+    // add into a zeroed register, a DPP move and an add
+    asm volatile("" : "+v"(s0), "+v"(s1), "+v"(s2));
+    *q0 = s0;
+    *q1 = s1;
+    *q2 = s2;
 }
 
 // RECT: the rectangle test of the forward (see blend_one), in both passes.
@@ -261,7 +267,7 @@ __global__ __launch_bounds__(TW * TH) void k_render_bwd(BwdArgs a) {
                     const int k0 = row == 1 ? 2 : (row == 2 ? 1 : row);  // rows hold v0, v2, v1, v3
                     atomicAdd(&s_acc[k0][t], q0);
                     atomicAdd(&s_acc[4 + k0][t], q1);
-                    if (row == 0) atomicAdd(&s_acc[8][t], q2);
+                    if (row == 3) atomicAdd(&s_acc[8][t], q2);
                 }
             }
         }
