@@ -569,7 +569,7 @@ hipError_t launch_preprocess(const GaussPtrs& g, const ws_camera* d_cams, int32_
     const int64_t compact_blocks = compact_blocks_of(ents);
     clr.add(pw.scan_a, depth_first ? 2 * compact_blocks : scan_sync_words(pw.total, kCompactItems));
     if (depth_first) sort_sync_words(pw.sort_ws, ents, 0, 31, kDepthRadixBits, true, 4, &clr);
-    clr.add(pw.scan_b, scan_sync_words(ents, kCountItems));
+    clr.add(pw.scan_b, scan_sync_words(ents, kCountItems, true));
     // a frame starts with a clean status word (no kernel of this launch reads it)
     clr.add(d_status, 1);
     timing_begin(WS_KERNEL_PREPROCESS, stream);
@@ -620,7 +620,8 @@ hipError_t launch_preprocess(const GaussPtrs& g, const ws_camera* d_cams, int32_
     }
     // pair offsets of the listed entries (total to d_num_pairs)
     launch_scan<uint64_t, kCountItems>(CountLoad{tiles_touched, list}, CountStore{pw.offsets, pw.first_entry, pw.emit_blocks},
-                          ents, pw.d_nvis, d_status, pw.scan_b, reinterpret_cast<uint64_t*>(d_num_pairs), stream, true);
+                          ents, pw.d_nvis, d_status, pw.scan_b, reinterpret_cast<uint64_t*>(d_num_pairs), stream, true,
+                          true);
     EmitArgs ea;
     // the record's last float4 holds (., depth, rect01, rect23) in both layouts
     const bool packed = (o.flags & WS_FLAG_PACKED) != 0;

@@ -1,17 +1,22 @@
 // Device-wide exclusive prefix sums.
 //
 // Two schedules, chosen by the number of blocks:
-//  * one pass (up to kOnePassMaxBlocks blocks): every block scans its items in
+//  * one pass (up to kOnePassMaxBlocks blocks, or any number for a sparse
+//    scan, whose live count read from device memory is typically far below
+//    the capacity the grid is sized for): every block scans its items in
 //    registers, publishes its sum, reads its predecessors' published sums
 //    (a decoupled look-back: one wave reads 64 predecessors per round trip
 //    and stops at the first inclusive prefix) and writes its results.  Block
-//    b scans chunk b: each XCD starts its workgroups in index order, so a
-//    block only waits for blocks that have been started, and the wait is
-//    bounded (WS_ERR_SPIN_LIMIT on expiry).  One read of the items, two
-//    launches (clearing the published sums, the pass).
-//  * wait-free (larger inputs): the hierarchical scan of the paper's sort stage
-//    (Sec. 3.3.2) -- reduce, one-workgroup scan of the block sums, down-sweep
-//    -- each level one dispatch, no workgroup ever waits for another.
+//    b scans chunk b and waits only for blocks with smaller indices; the
+//    smallest unfinished block is always running, since each XCD starts its
+//    workgroups in index order (its resources can only be held by blocks with
+//    smaller indices, which have finished).  The wait is bounded
+//    (WS_ERR_SPIN_LIMIT on expiry).  One read of the items, two launches
+//    (clearing the published sums, the pass).
+//  * wait-free (larger dense inputs): the hierarchical scan of the paper's sort
+//    stage (Sec. 3.3.2) -- reduce, one-workgroup scan of the block sums,
+//    down-sweep -- each level one dispatch, no workgroup ever waits for
+//    another.
 //
 // Loader:  using Item = ...;                    what the writer needs of item i
 //          __device__ Item operator()(int64_t i) const      (0 <= i < n)
@@ -159,15 +164,14 @@ constexpr uint64_t kScanInc = uint64_t(2) << 62;
 constexpr uint64_t kScanVal = (uint64_t(1) << 62) - 1;
 
 template <int Threads>
-__global__ __launch_bounds__(Threads) void k_scan_clear(uint64_t* status, int64_t nb, uint32_t* ticket) {
+__global__ __launch_bounds__(Threads) void k_scan_clear(uint64_t* status, int64_t nb) {
     for (int64_t i = threadIdx.x; i < nb; i += Threads) status[i] = 0;
-    if (threadIdx.x == 0) *ticket = 0;
 }
 
 template <class T, int ITEMS, class Loader, class Writer>
 __global__ __launch_bounds__(kScanThreads) void k_scan_onepass(Loader ld, Writer wr, int64_t cap, const int64_t* d_n,
                                                                const int32_t* d_status, uint64_t* status,
-                                                               uint32_t* ticket, T* total_out) {
+                                                               T* total_out) {
     constexpr int kPerWave = ITEMS * kWave;
     __shared__ T s_wave[kScanThreads / kWave];
     __shared__ T s_excl;
@@ -180,7 +184,6 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_onepass(Loader ld, Writer
     }
     // blocks past the live ones leave at once
     if (int64_t(blockIdx.x) >= nb) return;
-    (void)ticket;
     const int64_t b = blockIdx.x;
     const int wave = threadIdx.x / kWave;
     const uint32_t lane = lane_id();
@@ -259,32 +262,36 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_onepass(Loader ld, Writer
 // Workspace of one scan over up to `cap` items (either schedule), bytes.
 inline size_t scan_workspace(int64_t cap, int items = kScanItems) {
     const int64_t nb = scan_blocks(cap, items);
-    return align_up(size_t(nb) * 8) + align_up(8);
+    return align_up(size_t(nb) * 8);
 }
+
+inline bool scan_one_pass(int64_t nb, bool sparse) { return sparse || nb <= kOnePassMaxBlocks; }
 
 // Words at the start of the workspace that must be zero when a one-pass scan
 // (the schedule taken when a status word is given) starts; 0 for the
 // three-level schedule, which needs none.
-inline int64_t scan_sync_words(int64_t cap, int items = kScanItems) {
+inline int64_t scan_sync_words(int64_t cap, int items = kScanItems, bool sparse = false) {
     const int64_t nb = scan_blocks(cap, items);
-    return nb <= kOnePassMaxBlocks ? int64_t(align_up(size_t(nb) * 8) + 4) / 4 : 0;
+    return scan_one_pass(nb, sparse) ? 2 * nb : 0;
 }
 
 // Scans up to `cap` items (the count read from d_n when given).  `ws` holds
 // scan_workspace(cap, ITEMS) bytes; `d_status` (may be null) is also the word
 // a bounded wait that expires reports into.  With `precleared` an earlier
-// kernel of the stream zeroed the scan_sync_words(cap, ITEMS) words at `ws`.
+// kernel of the stream zeroed the scan_sync_words(cap, ITEMS, sparse) words at
+// `ws`.  `sparse`: the live count (d_n) is typically far below `cap`, so the
+// one-pass schedule is taken at any capacity (its blocks past the live ones
+// leave at once).
 template <class T, int ITEMS = kScanItems, class Loader, class Writer>
 void launch_scan(const Loader& ld, const Writer& wr, int64_t cap, const int64_t* d_n, const int32_t* d_status,
-                 void* ws, T* total_out, hipStream_t stream, bool precleared = false) {
+                 void* ws, T* total_out, hipStream_t stream, bool precleared = false, bool sparse = false) {
     const int64_t nb = scan_blocks(cap, ITEMS);
     char* base = static_cast<char*>(ws);
-    if (nb <= kOnePassMaxBlocks && d_status) {
+    if (scan_one_pass(nb, sparse) && d_status) {
         uint64_t* status = reinterpret_cast<uint64_t*>(base);
-        uint32_t* ticket = reinterpret_cast<uint32_t*>(base + align_up(size_t(nb) * 8));
-        if (!precleared) hipLaunchKernelGGL(k_scan_clear<256>, dim3(1), dim3(256), 0, stream, status, nb, ticket);
+        if (!precleared) hipLaunchKernelGGL(k_scan_clear<256>, dim3(1), dim3(256), 0, stream, status, nb);
         hipLaunchKernelGGL((k_scan_onepass<T, ITEMS, Loader, Writer>), dim3(uint32_t(nb)), dim3(kScanThreads), 0, stream, ld,
-                           wr, cap, d_n, d_status, status, ticket, total_out);
+                           wr, cap, d_n, d_status, status, total_out);
         return;
     }
     T* partials = reinterpret_cast<T*>(base);

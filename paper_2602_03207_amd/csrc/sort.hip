@@ -17,14 +17,16 @@
 //  * look-back (small inputs, up to kSmallSortMax pairs, or inputs whose
 //    device count is known to be far below the capacity): base_d from one
 //    histogram of all passes (k_sort_hist), prefix_wg by a decoupled look-back
-//    over per-tile counts published in device memory.  Up to kLookbackGrid
-//    tiles, workgroup b sorts tile b (each XCD starts its workgroups in index
-//    order, so a tile only waits for tiles that have been started); more
-//    tiles are taken through an atomic ticket by as many workgroups.  The wait
-//    is bounded (WS_ERR_SPIN_LIMIT on expiry).  One read and one write per
-//    pair and pass, and one launch per pass.
-//  * wait-free (large inputs, where the ticket's round trip in front of every
-//    tile's loads and the histogram's extra read cost more than they save):
+//    over per-tile counts published in device memory.  Workgroup b sorts tile
+//    b, and the grid covers every tile the capacity can hold (workgroups past
+//    the live tiles leave at once).  A tile waits only for tiles with smaller
+//    indices, and the smallest unfinished tile is always running: each XCD
+//    starts its workgroups in index order, so its resources can only be held
+//    by tiles with smaller indices, which have finished.  The wait is bounded
+//    (WS_ERR_SPIN_LIMIT on expiry).  One read and one write per pair and pass,
+//    and one launch per pass.
+//  * wait-free (large inputs, where the look-back chain in front of every
+//    tile's writes and the histogram's extra read cost more than they save):
 //    per pass, k_upsweep counts each tile's digits into a digit-major table
 //    [digit][tile]; one exclusive scan of that table (the hierarchical scan of
 //    scan.h) yields base_d + prefix_wg for every (digit, tile) at once;
@@ -47,7 +49,6 @@ constexpr int kHistThreads = 256;
 constexpr int kMaxBins = 2048;  // passes * radix over every radix width
 constexpr int kLook = 16;       // predecessor tiles read at once by the look-back
 constexpr int kTableItems = 4;  // items per thread of the digit table's prefix sum
-constexpr int64_t kLookbackGrid = 1024;  // workgroups of a look-back pass at most
 constexpr uint32_t kStAgg = 1u << 30;
 constexpr uint32_t kStInc = 2u << 30;
 constexpr uint32_t kStMask = (1u << 30) - 1;
@@ -57,7 +58,6 @@ struct SortLayout {
     uint32_t* alt_vals;
     uint32_t* hist;      // look-back: [passes][radix]
     uint32_t* status;    // look-back: [passes][max_tiles][radix]
-    uint32_t* tickets;   // look-back: [passes]
     uint32_t* table;     // wait-free: [radix][max_tiles]
     void* table_scan;    // wait-free: workspace of the table's prefix sum
     int64_t max_tiles;
@@ -94,9 +94,7 @@ size_t plan(void* ws, int64_t capacity, int begin_bit, int end_bit, int radix_bi
         L.table = reinterpret_cast<uint32_t*>(take(size_t(entries) * 4));
         L.table_scan = take(scan_workspace(entries, kTableItems));
     } else {
-        // histograms and tickets side by side: one region to clear
-        L.hist = reinterpret_cast<uint32_t*>(take(size_t(L.passes) * (L.radix + 1) * 4));
-        L.tickets = L.hist ? L.hist + L.passes * L.radix : nullptr;
+        L.hist = reinterpret_cast<uint32_t*>(take(size_t(L.passes) * L.radix * 4));
         L.status = reinterpret_cast<uint32_t*>(take(size_t(L.passes) * L.max_tiles * L.radix * 4));
     }
     if (out) *out = L;
@@ -124,7 +122,6 @@ struct TileSmem {
     uint32_t tile_off[kRadix];
     uint32_t global[kRadix];
     uint32_t scan[kSortWaves + 1];
-    uint32_t tile;
 };
 
 template <int B, typename K>
@@ -394,9 +391,8 @@ struct TableStore {
 
 // ------------------------------------------------ look-back schedule
 
-__global__ void k_sort_init(uint32_t* hist, int bins, uint32_t* tickets, int passes) {
+__global__ void k_sort_init(uint32_t* hist, int bins) {
     for (int i = threadIdx.x; i < bins; i += blockDim.x) hist[i] = 0;
-    for (int i = threadIdx.x; i < passes; i += blockDim.x) tickets[i] = 0;
 }
 
 template <typename K>
@@ -474,8 +470,6 @@ struct PassArgs {
     int shift;
     const uint32_t* hist;  // [radix] of this pass
     uint32_t* status;      // [max_tiles][2^B] of this pass
-    uint32_t* ticket;
-    bool direct;  // one workgroup per tile (no ticket)
 };
 
 template <int B, int ITEMS, typename K>
@@ -559,26 +553,11 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_pass(PassArgs<K> a) {
     if (a.d_status && *a.d_status != 0) return;
     const int64_t n = device_count(a.cap, a.d_n);
     const int64_t ntiles = (n + kTile - 1) / kTile;
-    // Workgroups past the live tiles leave at once.
+    // Workgroups past the live tiles leave at once; workgroup b sorts tile b.
     if (int64_t(blockIdx.x) >= ntiles) return;
-    if (a.direct) {  // the grid covers every tile: workgroup b sorts tile b
-        clear_whist(sm);
-        __syncthreads();
-        sort_tile_lookback<B, ITEMS, K>(sm, a, n, int64_t(blockIdx.x));
-        return;
-    }
-    // The others take tickets until they run past the live tiles; each tile
-    // goes to one workgroup, and a workgroup only ever waits for tiles with
-    // smaller tickets, which running workgroups hold.
-    while (true) {
-        if (threadIdx.x == 0) sm.tile = atomicAdd(a.ticket, 1u);
-        clear_whist(sm);
-        __syncthreads();
-        const int64_t tile = sm.tile;
-        if (tile >= ntiles) return;
-        sort_tile_lookback<B, ITEMS, K>(sm, a, n, tile);
-        __syncthreads();  // the tile's LDS is reused by the next ticket
-    }
+    clear_whist(sm);
+    __syncthreads();
+    sort_tile_lookback<B, ITEMS, K>(sm, a, n, int64_t(blockIdx.x));
 }
 
 // ------------------------------------------------ dispatch
@@ -604,12 +583,7 @@ void run_pass(const PassLaunch<K>& c) {
                               c.L->table_scan, static_cast<uint32_t*>(nullptr), c.stream, true);
         hipLaunchKernelGGL((k_downsweep<B, ITEMS, K>), dim3(grid), dim3(kSortThreads), 0, c.stream, c.da);
     } else {
-        // up to kLookbackGrid tiles one workgroup each, otherwise workgroups
-        // loop over tickets, so the grid need not cover every tile
-        const uint32_t lgrid = uint32_t(std::min<int64_t>(c.L->max_tiles, kLookbackGrid));
-        PassArgs<K> pa = c.pa;
-        pa.direct = c.L->max_tiles <= kLookbackGrid;
-        hipLaunchKernelGGL((k_sort_pass<B, ITEMS, K>), dim3(lgrid), dim3(kSortThreads), 0, c.stream, pa);
+        hipLaunchKernelGGL((k_sort_pass<B, ITEMS, K>), dim3(grid), dim3(kSortThreads), 0, c.stream, c.pa);
     }
 }
 
@@ -638,7 +612,7 @@ void sort_sync_words(void* ws, int64_t capacity, int32_t begin_bit, int32_t end_
                      int key_bytes, ClearList* c) {
     SortLayout L;
     plan(ws, capacity, begin_bit, end_bit, radix_bits, sparse, key_bytes, &L);
-    if (!L.wait_free) c->add(L.hist, int64_t(L.passes) * (L.radix + 1));  // histograms, then tickets
+    if (!L.wait_free) c->add(L.hist, int64_t(L.passes) * L.radix);
 }
 
 SortHistWords sort_hist_words(void* ws, int64_t capacity, int32_t begin_bit, int32_t end_bit, int32_t radix_bits,
@@ -669,8 +643,7 @@ hipError_t launch_sort_t(const K* kin, const uint32_t* vin, K* kout, uint32_t* v
     const int hist_id = timed ? WS_KERNEL_SORT_HIST : -1, pass_id = timed ? WS_KERNEL_SORT_PASS : -1;
     if (!L.wait_free && !hist_ready) {
         if (!precleared)
-            hipLaunchKernelGGL(k_sort_init, dim3(1), dim3(256), 0, stream, L.hist, L.passes * L.radix, L.tickets,
-                               L.passes);
+            hipLaunchKernelGGL(k_sort_init, dim3(1), dim3(256), 0, stream, L.hist, L.passes * L.radix);
         HistArgs<K> h;
         h.keys = kin;
         h.cap = n;
@@ -719,7 +692,6 @@ hipError_t launch_sort_t(const K* kin, const uint32_t* vin, K* kout, uint32_t* v
         c.pa.shift = shift;
         c.pa.hist = L.wait_free ? nullptr : L.hist + p * L.radix;
         c.pa.status = L.wait_free ? nullptr : L.status + int64_t(p) * L.max_tiles * L.radix;
-        c.pa.ticket = L.wait_free ? nullptr : L.tickets + p;
         timing_begin(pass_id, stream);
         if (L.items == kItemsSmall) run_pass_bits<kItemsSmall, K>(c, bits);
         else run_pass_bits<kItemsLarge, K>(c, bits);

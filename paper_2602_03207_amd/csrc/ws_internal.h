@@ -134,7 +134,7 @@ __device__ __forceinline__ void store_agent(uint32_t* p, uint32_t v) {
 // many polls gives up and reports WS_ERR_SPIN_LIMIT instead of hanging.
 constexpr uint32_t kSpinLimit = 1u << 22;
 
-// Synchronisation words (look-back flags, tickets, global histograms) must be
+// Synchronisation words (look-back flags, global histograms) must be
 // zero when the kernel that uses them starts.  Instead of a clearing launch of
 // its own (a few microseconds each, most of it the dependency between
 // back-to-back launches), an earlier kernel of the same stream that does not
