@@ -103,7 +103,7 @@ typedef struct ws_camera {
 typedef struct ws_options {
     int32_t tile_w, tile_h;   /* 16x16 (default), 8x8, 16x8 or 32x16 pixels */
     int32_t sh_degree;        /* 0..3 */
-    int32_t radix_bits;       /* ws_sort digit width 1..8; 0 = library default (8) */
+    int32_t radix_bits;       /* ws_sort digit width 1..10; 0 = library default (8) */
     uint32_t flags;           /* WS_FLAG_* */
     float near_z;             /* cull p.z <= near_z (default 0.2) */
     float lowpass;            /* added to both diagonal entries of the 2D covariance (0.3 px^2) */
@@ -239,8 +239,11 @@ ws_status ws_preprocess(const ws_gaussians* g, const ws_camera* cams, const ws_c
  *   n          number of pairs, or the capacity when d_n != NULL
  *   d_n        optional device int64 count (clamped to n), for device-sized sorts
  *   d_status   optional device status word: if non-zero on entry nothing is done
- * 0 <= begin_bit < end_bit <= 64; n < 2^30.  With radix_bits r the sort runs
- * ceil((end_bit - begin_bit) / r) passes. */
+ * 0 <= begin_bit < end_bit <= 64; n < 2^30; 0 <= radix_bits <= 10 (0: 8).
+ * With radix_bits r the sort runs ceil((end_bit - begin_bit) / r) passes; for
+ * inputs of up to 2^20 pairs (the look-back schedule) r is first narrowed
+ * until the histograms of all passes hold at most 2048 bins (the result is the
+ * same stable order at any r). */
 ws_status ws_sort(const uint64_t* keys_in, const uint32_t* values_in, uint64_t* keys_out, uint32_t* values_out,
                   int64_t n, const int64_t* d_n, const int32_t* d_status, int32_t begin_bit, int32_t end_bit,
                   int32_t radix_bits, void* ws, size_t ws_bytes, void* stream);

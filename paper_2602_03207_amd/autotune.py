@@ -29,7 +29,7 @@ from . import binding as B
 from .pipeline import GaussianTensors, Renderer
 
 TILES = ((16, 16), (8, 8), (16, 8), (32, 16))
-RADIX_BITS = (4, 5, 6, 7, 8)
+RADIX_BITS = (5, 6, 7, 8, 9, 10)
 BINS = ((1, 1),)  # bins of tiles searched by default: none (pass e.g. ((1, 1), (2, 2), (4, 2)))
 ORDERED = (None,)  # render schedules searched by default: the one in the options (pass (False, True) for both)
 

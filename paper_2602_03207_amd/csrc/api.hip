@@ -43,8 +43,8 @@ ws_status check_options(const ws_options* o) {
                               o->tile_w, o->tile_h);
     if (o->sh_degree < 0 || o->sh_degree > 3)
         return fail(WS_ERR_UNSUPPORTED, "sh_degree %d not supported (0..3)", o->sh_degree);
-    if (o->radix_bits < 0 || o->radix_bits > 8)
-        return fail(WS_ERR_INVALID_ARGUMENT, "radix_bits %d out of range (0..8)", o->radix_bits);
+    if (o->radix_bits < 0 || o->radix_bits > ws::kMaxRadixBits)
+        return fail(WS_ERR_INVALID_ARGUMENT, "radix_bits %d out of range (0..%d)", o->radix_bits, ws::kMaxRadixBits);
     for (const int32_t b : {o->bin_x, o->bin_y})
         if (b != 0 && b != 1 && b != 2 && b != 4 && b != 8)
             return fail(WS_ERR_INVALID_ARGUMENT, "bin_x / bin_y must be 1, 2, 4 or 8 (0 reads as 1), got %d", b);
@@ -237,13 +237,15 @@ size_t ws_preprocess_workspace_size(int64_t n, int32_t n_views, int64_t capacity
 }
 
 size_t ws_sort_workspace_size(int64_t capacity, int32_t begin_bit, int32_t end_bit, int32_t radix_bits) {
-    if (capacity < 0 || begin_bit < 0 || end_bit > 64 || begin_bit >= end_bit || radix_bits < 0 || radix_bits > 8)
+    if (capacity < 0 || begin_bit < 0 || end_bit > 64 || begin_bit >= end_bit || radix_bits < 0 ||
+        radix_bits > ws::kMaxRadixBits)
         return 0;
     return ws::sort_workspace(capacity, begin_bit, end_bit, radix_bits, false, 8);
 }
 
 size_t ws_sort32_workspace_size(int64_t capacity, int32_t begin_bit, int32_t end_bit, int32_t radix_bits) {
-    if (capacity < 0 || begin_bit < 0 || end_bit > 32 || begin_bit >= end_bit || radix_bits < 0 || radix_bits > 8)
+    if (capacity < 0 || begin_bit < 0 || end_bit > 32 || begin_bit >= end_bit || radix_bits < 0 ||
+        radix_bits > ws::kMaxRadixBits)
         return 0;
     return ws::sort_workspace(capacity, begin_bit, end_bit, radix_bits, false, 4);
 }
@@ -325,8 +327,9 @@ ws_status sort_checked(const char* name, const K* keys_in, const uint32_t* value
     if (begin_bit < 0 || end_bit > kBits || begin_bit >= end_bit)
         return fail(WS_ERR_INVALID_ARGUMENT, "%s: need 0 <= begin_bit < end_bit <= %d (got %d, %d)", name, kBits,
                     begin_bit, end_bit);
-    if (radix_bits < 0 || radix_bits > 8)
-        return fail(WS_ERR_INVALID_ARGUMENT, "%s: radix_bits %d out of range", name, radix_bits);
+    if (radix_bits < 0 || radix_bits > ws::kMaxRadixBits)
+        return fail(WS_ERR_INVALID_ARGUMENT, "%s: radix_bits %d out of range (0..%d)", name, radix_bits,
+                    ws::kMaxRadixBits);
     if (n == 0) return WS_OK;
     if (!keys_in || !values_in || !keys_out || !values_out)
         return fail(WS_ERR_INVALID_ARGUMENT, "%s: a key/value pointer is NULL", name);

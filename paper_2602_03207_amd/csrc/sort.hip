@@ -46,7 +46,7 @@ constexpr int kItemsLarge = 16;              // 4096-pair tiles
 constexpr int kItemsSmall = 4;               // 1024-pair tiles
 constexpr int64_t kSmallSortMax = 1 << 20;   // capacities up to this use small tiles
 constexpr int kHistThreads = 256;
-constexpr int kMaxBins = 2048;  // passes * radix over every radix width
+constexpr int kMaxBins = 2048;  // passes * radix of the look-back schedule's histograms, at most
 constexpr int kLook = 16;       // predecessor tiles read at once by the look-back
 constexpr int kTableItems = 4;  // items per thread of the digit table's prefix sum
 constexpr uint32_t kStAgg = 1u << 30;
@@ -74,6 +74,13 @@ size_t plan(void* ws, int64_t capacity, int begin_bit, int end_bit, int radix_bi
     L.radix = 1 << L.r;
     L.passes = (end_bit - begin_bit + L.r - 1) / L.r;
     const bool small = sparse || capacity <= kSmallSortMax;
+    // the look-back schedule's histograms of all passes fit kMaxBins: a wider
+    // digit than that allows is narrowed (the order is the same at any width)
+    while (small && L.r > 1 && L.passes * L.radix > kMaxBins) {
+        --L.r;
+        L.radix = 1 << L.r;
+        L.passes = (end_bit - begin_bit + L.r - 1) / L.r;
+    }
     L.items = small ? kItemsSmall : kItemsLarge;
     const int64_t tile = int64_t(kSortThreads) * L.items;
     L.max_tiles = std::max<int64_t>((capacity + tile - 1) / tile, 1);
@@ -129,13 +136,37 @@ __device__ __forceinline__ uint32_t digit_of(K k, int shift) {
     return uint32_t(k >> shift) & ((1u << B) - 1u);
 }
 
+// Per-digit work is spread over the workgroup in blocks: thread t owns digits
+// t * DPT ... t * DPT + DPT - 1 (DPT = 1 up to 8-bit digits, where threads
+// t >= 2^B own none), so a thread's digits are consecutive in digit order.
+template <int B>
+constexpr int digits_per_thread() {
+    return (1 << B) > kSortThreads ? (1 << B) / kSortThreads : 1;
+}
+
+// Exclusive prefix over digit order of per-digit values held DPT per thread.
+template <int DPT>
+__device__ __forceinline__ void digit_exclusive_scan(const uint32_t (&v)[DPT], uint32_t (&ex)[DPT], uint32_t* scratch) {
+    uint32_t s = 0;
+#pragma unroll
+    for (int i = 0; i < DPT; ++i) {
+        ex[i] = s;
+        s += v[i];
+    }
+    uint32_t total;
+    const uint32_t base = block_exclusive_scan<kSortThreads>(s, scratch, &total);
+#pragma unroll
+    for (int i = 0; i < DPT; ++i) ex[i] += base;
+}
+
 // Loads the tile and computes, for every item, its rank among the equal
 // digits of its wave.  On return whist[w][d] holds the exclusive prefix over
-// waves of digit d's count and *cnt_out (threads t < 2^B) the tile's count of
-// digit t.  whist must be zero on entry.
+// waves of digit d's count and cnt_out[i] the tile's count of this thread's
+// digit i (zero for digits past 2^B).  whist must be zero on entry.
 template <int B, int ITEMS, typename K>
 __device__ __forceinline__ void load_and_rank(TileSmem<B, ITEMS, K>& sm, const K* kin, int64_t n, int64_t tile,
-                                              int shift, K* key, uint32_t* rank, uint32_t* cnt_out) {
+                                              int shift, K* key, uint32_t* rank,
+                                              uint32_t (&cnt_out)[digits_per_thread<B>()]) {
     constexpr int kTile = kSortThreads * ITEMS;
     const int wave = threadIdx.x / kWave;
     const uint32_t lane = lane_id();
@@ -183,17 +214,21 @@ __device__ __forceinline__ void load_and_rank(TileSmem<B, ITEMS, K>& sm, const K
     }
     __syncthreads();
     // per digit: exclusive prefix over the waves, and the tile's count
-    const int t = threadIdx.x;
-    uint32_t c = 0;
-    if (t < (1 << B)) {
+    constexpr int DPT = digits_per_thread<B>();
 #pragma unroll
-        for (int w = 0; w < kSortWaves; ++w) {
-            const uint32_t x = sm.whist[w][t];
-            sm.whist[w][t] = c;
-            c += x;
+    for (int i = 0; i < DPT; ++i) {
+        const int d = int(threadIdx.x) * DPT + i;
+        uint32_t c = 0;
+        if (d < (1 << B)) {
+#pragma unroll
+            for (int w = 0; w < kSortWaves; ++w) {
+                const uint32_t x = sm.whist[w][d];
+                sm.whist[w][d] = c;
+                c += x;
+            }
         }
+        cnt_out[i] = c;
     }
-    *cnt_out = c;
 }
 
 // Reordering of a ranked tile by digit through LDS, so that global writes are
@@ -359,18 +394,23 @@ __global__ __launch_bounds__(kSortThreads) void k_downsweep(DownArgs<K> a) {
     const int64_t tile = xcd_contiguous(blockIdx.x, uint32_t(ntiles));
     clear_whist(sm);
     __syncthreads();
+    constexpr int DPT = digits_per_thread<B>();
     K key[ITEMS];
     uint32_t rank[ITEMS];
-    uint32_t cnt;
-    load_and_rank<B, ITEMS, K>(sm, a.kin, n, tile, a.shift, key, rank, &cnt);
+    uint32_t cnt[DPT];
+    load_and_rank<B, ITEMS, K>(sm, a.kin, n, tile, a.shift, key, rank, cnt);
     // the values are in flight during the scan and the staging of the keys
     uint32_t val[ITEMS];
     load_vals<ITEMS>(a.vin, n, tile, val);
-    uint32_t total;
-    const uint32_t toff = block_exclusive_scan<kSortThreads>(cnt, sm.scan, &total);
-    if (threadIdx.x < (1 << B)) {
-        sm.tile_off[threadIdx.x] = toff;
-        sm.global[threadIdx.x] = a.table[int64_t(threadIdx.x) * a.max_tiles + tile];
+    uint32_t toff[DPT];
+    digit_exclusive_scan<DPT>(cnt, toff, sm.scan);
+#pragma unroll
+    for (int i = 0; i < DPT; ++i) {
+        const int d = int(threadIdx.x) * DPT + i;
+        if (d < (1 << B)) {
+            sm.tile_off[d] = toff[i];
+            sm.global[d] = a.table[int64_t(d) * a.max_tiles + tile];
+        }
     }
     __syncthreads();
     stage_keys<B, ITEMS, K>(sm, n, tile, a.shift, key, rank);
@@ -476,23 +516,37 @@ template <int B, int ITEMS, typename K>
 __device__ __forceinline__ void sort_tile_lookback(TileSmem<B, ITEMS, K>& sm, const PassArgs<K>& a, int64_t n,
                                                    int64_t tile) {
     constexpr int RADIX = 1 << B;
+    constexpr int DPT = digits_per_thread<B>();
     K key[ITEMS];
     uint32_t rank[ITEMS];
-    uint32_t cnt;
-    load_and_rank<B, ITEMS, K>(sm, a.kin, n, tile, a.shift, key, rank, &cnt);
-    const int t = threadIdx.x;
-    if (t < RADIX) store_agent(&a.status[tile * RADIX + t], (tile == 0 ? kStInc : kStAgg) | cnt);
-    uint32_t total;
-    const uint32_t toff = block_exclusive_scan<kSortThreads>(cnt, sm.scan, &total);
-    const uint32_t hv = t < RADIX ? a.hist[t] : 0u;
-    const uint32_t dbase = block_exclusive_scan<kSortThreads>(hv, sm.scan, &total);
-    if (t < RADIX) sm.tile_off[t] = toff;
+    uint32_t cnt[DPT];
+    load_and_rank<B, ITEMS, K>(sm, a.kin, n, tile, a.shift, key, rank, cnt);
+#pragma unroll
+    for (int i = 0; i < DPT; ++i) {
+        const int d = int(threadIdx.x) * DPT + i;
+        if (d < RADIX) store_agent(&a.status[tile * RADIX + d], (tile == 0 ? kStInc : kStAgg) | cnt[i]);
+    }
+    uint32_t toff[DPT], hv[DPT], dbase[DPT];
+    digit_exclusive_scan<DPT>(cnt, toff, sm.scan);
+#pragma unroll
+    for (int i = 0; i < DPT; ++i) {
+        const int d = int(threadIdx.x) * DPT + i;
+        hv[i] = d < RADIX ? a.hist[d] : 0u;
+    }
+    digit_exclusive_scan<DPT>(hv, dbase, sm.scan);
+#pragma unroll
+    for (int i = 0; i < DPT; ++i) {
+        const int d = int(threadIdx.x) * DPT + i;
+        if (d < RADIX) sm.tile_off[d] = toff[i];
+    }
     __syncthreads();
     // the keys wait in LDS (and the values are in flight) during the look-back
     stage_keys<B, ITEMS, K>(sm, n, tile, a.shift, key, rank);
     uint32_t val[ITEMS];
     load_vals<ITEMS>(a.vin, n, tile, val);
-    if (t < RADIX) {
+    for (int i = 0; i < DPT; ++i) {
+        const int t = int(threadIdx.x) * DPT + i;  // the digit
+        if (t >= RADIX) break;
         uint32_t excl = 0;
         if (tile > 0) {
             // Look back over windows of kLook predecessors with all loads in
@@ -538,9 +592,9 @@ __device__ __forceinline__ void sort_tile_lookback(TileSmem<B, ITEMS, K>& sm, co
                 }
                 k -= kLook;
             }
-            store_agent(&a.status[tile * RADIX + t], kStInc | (excl + cnt));
+            store_agent(&a.status[tile * RADIX + t], kStInc | (excl + cnt[i]));
         }
-        sm.global[t] = dbase + excl;
+        sm.global[t] = dbase[i] + excl;
     }
     __syncthreads();
     flush_tile<B, ITEMS, K>(sm, n, tile, a.shift, rank, val, a.kout, a.vout);
@@ -597,7 +651,9 @@ void run_pass_bits(const PassLaunch<K>& c, int bits) {
         case 5: run_pass<5, ITEMS, K>(c); break;
         case 6: run_pass<6, ITEMS, K>(c); break;
         case 7: run_pass<7, ITEMS, K>(c); break;
-        default: run_pass<8, ITEMS, K>(c); break;
+        case 8: run_pass<8, ITEMS, K>(c); break;
+        case 9: run_pass<9, ITEMS, K>(c); break;
+        default: run_pass<10, ITEMS, K>(c); break;
     }
 }
 

@@ -130,6 +130,9 @@ __device__ __forceinline__ void store_agent(uint32_t* p, uint32_t v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Widest digit of a radix sort pass (bits).
+constexpr int kMaxRadixBits = 10;
+
 // Bounded waits: a look-back that has not seen its predecessor after this
 // many polls gives up and reports WS_ERR_SPIN_LIMIT instead of hanging.
 constexpr uint32_t kSpinLimit = 1u << 22;

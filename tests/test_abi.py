@@ -165,7 +165,9 @@ def test_sort_rejects_bad_arguments_on_the_host(lib):
     # end beyond 64
     assert lib.ws_sort(a, b, c, d, 10, None, None, 0, 65, 8, ws, 1 << 20, None) == B.WS_ERR_INVALID_ARGUMENT
     # radix width out of range
-    assert lib.ws_sort(a, b, c, d, 10, None, None, 0, 32, 9, ws, 1 << 20, None) == B.WS_ERR_INVALID_ARGUMENT
+    assert lib.ws_sort(a, b, c, d, 10, None, None, 0, 32, 11, ws, 1 << 20, None) == B.WS_ERR_INVALID_ARGUMENT
+    assert lib.ws_sort(a, b, c, d, 10, None, None, 0, 32, -1, ws, 1 << 20, None) == B.WS_ERR_INVALID_ARGUMENT
+    assert lib.ws_sort_workspace_size(1000, 0, 32, 11) == 0 and lib.ws_sort_workspace_size(1000, 0, 32, 10) > 0
     # too many pairs
     assert lib.ws_sort(a, b, c, d, 1 << 30, None, None, 0, 32, 8, ws, 1 << 40, None) == B.WS_ERR_INVALID_ARGUMENT
     # output overlapping the input
@@ -204,7 +206,7 @@ def test_preprocess_and_render_reject_bad_options_on_the_host(lib):
     bad = [
         dict(tile_w=12, tile_h=12),
         dict(sh_degree=4),
-        dict(radix_bits=9),
+        dict(radix_bits=11),
         dict(flags=1 << 12),
         dict(near_z=0.0),
         dict(alpha_min=0.0),

@@ -68,7 +68,7 @@ def test_sort32_bit_exact(bits):
         assert np.array_equal(got_k, want_k), (name, bits)
 
 
-@pytest.mark.parametrize("radix_bits", [1, 3, 4, 5, 6, 7, 8])
+@pytest.mark.parametrize("radix_bits", [1, 3, 4, 5, 6, 7, 8, 9, 10])
 def test_sort32_every_radix_width(radix_bits):
     rng = np.random.default_rng(100 + radix_bits)
     keys = rng.integers(0, 2**32, 60_001, dtype=np.uint64).astype(np.uint32)
@@ -84,9 +84,14 @@ def test_sort32_large_schedule_and_device_count():
     keys = rng.integers(0, 1 << 15, 1_500_001, dtype=np.uint64).astype(np.uint32)
     vals = np.arange(keys.size, dtype=np.uint32)
     want_k, want_v = _oracle_sort32(keys, vals, 0, 15)
-    for cap, dc in ((keys.size, False), (2_000_000, True)):
-        got_k, got_v = _gpu_sort32(keys, vals, 0, 15, radix_bits=8, capacity=cap, device_count=dc)
+    for cap, dc, rb in ((keys.size, False, 8), (2_000_000, True, 8), (keys.size, False, 10), (2_000_000, True, 9)):
+        got_k, got_v = _gpu_sort32(keys, vals, 0, 15, radix_bits=rb, capacity=cap, device_count=dc)
         assert np.array_equal(got_k, want_k) and np.array_equal(got_v, want_v)
+    # the frame's case: 9-10 bits of bin ids sorted in one pass of the look-back schedule
+    bins = rng.integers(0, 1 << 10, 700_001, dtype=np.uint64).astype(np.uint32)
+    want_k, want_v = _oracle_sort32(bins, vals[:bins.size], 0, 10)
+    got_k, got_v = _gpu_sort32(bins, vals[:bins.size], 0, 10, radix_bits=10, capacity=900_000, device_count=True)
+    assert np.array_equal(got_k, want_k) and np.array_equal(got_v, want_v)
     small = keys[:123_457].copy()
     want_k, want_v = _oracle_sort32(small, vals[:small.size], 0, 15)
     outs = [_gpu_sort32(small, vals[:small.size], 0, 15, capacity=300_000, device_count=True) for _ in range(3)]

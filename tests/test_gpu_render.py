@@ -234,7 +234,7 @@ def test_render_c2_in_the_benchmark_configuration():
     g = GaussianTensors.from_scene(scene)
     ref = oracle.render(scene, cam, oracle_options(sh_degree=3), outcomes=True)
     flags = B.WS_FLAG_DEPTH_FIRST | B.WS_FLAG_KEYS32
-    for tile, bins, rb in (((16, 16), (4, 2), 7), ((16, 16), (2, 2), 6), ((32, 16), (1, 1), 6)):
+    for tile, bins, rb in (((16, 16), (4, 2), 9), ((16, 16), (2, 2), 6), ((32, 16), (4, 4), 8), ((32, 16), (1, 1), 6)):
         print(f"C2 benchmark layout: tile {tile} bins {bins} radix {rb}", flush=True)
         opts = gpu_options(sh_degree=3, tile_w=tile[0], tile_h=tile[1], radix_bits=rb, flags=flags, bin_x=bins[0],
                            bin_y=bins[1])

@@ -65,6 +65,26 @@ def test_sort_every_radix_width(radix_bits):
     assert np.array_equal(got_k, want_k) and np.array_equal(got_v, want_v)
 
 
+@pytest.mark.parametrize("bits,radix_bits,n,capacity", [
+    ((0, 20), 10, 200_003, None),        # look-back schedule, two 10-bit passes
+    ((5, 32), 9, 150_001, None),         # look-back, three 9-bit passes
+    ((0, 32), 10, 150_001, None),        # look-back: 10 bits narrowed until the histograms fit
+    ((0, 30), 10, 1_500_001, None),      # wait-free schedule, three 10-bit passes
+    ((32, 51), 10, 1_200_001, 1_600_000),  # wait-free, device-sized, a 10-bit and a 9-bit pass
+])
+def test_sort_wide_digits(bits, radix_bits, n, capacity):
+    """Digits wider than the 256 threads of a sort tile (9 and 10 bits: several digits per thread in the
+    per-digit scans and look-backs) on both schedules, bit-exact against std::stable_sort."""
+    rng = np.random.default_rng(radix_bits * 1000 + bits[0])
+    keys = rng.integers(0, 2**63, n, dtype=np.uint64)
+    keys[::7] = keys[3]  # runs of equal keys: stability
+    vals = np.arange(n, dtype=np.uint32)
+    want_k, want_v = oracle.stable_sort(keys, vals, *bits)
+    got_k, got_v = _gpu_sort(keys, vals, *bits, radix_bits=radix_bits, capacity=capacity,
+                             device_count=capacity is not None)
+    assert np.array_equal(got_v, want_v) and np.array_equal(got_k, want_k)
+
+
 def test_sort_device_count_and_repeatability():
     rng = np.random.default_rng(9)
     keys = rng.integers(0, 2**40, 123_457, dtype=np.uint64)
