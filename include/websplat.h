@@ -327,6 +327,31 @@ ws_status ws_render_backward(const ws_gaussians* g, const ws_camera* cams, const
                              const int32_t* d_status, ws_gaussian_grads* grads, void* ws, size_t ws_bytes,
                              void* stream);
 
+/* The compositing adjoint of the L1 photometric loss, for the training step:
+ * the result of ws_l1_loss over these views' images followed by
+ * ws_render_backward with its dL/dimages, without that gradient image.  The
+ * adjoint forms each pixel's dL/dC = sign(images - targets) / total (sign(0) =
+ * 0, 1 / total rounded once from fp64, as ws_l1_loss) from the two images,
+ * and every tile sums |images - targets| over its pixels.
+ *   images    the forward's images of these views (ws_render's output)
+ *   targets   same layout
+ *   total     element count the mean is taken over: 0 means the views'
+ *             3 * sum(W * H); a larger count for a batch split over calls
+ *   d_loss    out, device float: sum |images - targets| / total (per-tile fp64
+ *             sums reduced in a fixed order, rounded once: identical bits run
+ *             to run; it may differ from ws_l1_loss's value in the last bit,
+ *             which sums in another order)
+ * Every other argument, the gradients written and the status handling are
+ * those of ws_render_backward; with d_status non-zero *d_loss is not written.
+ * ws: ws_render_backward_l1_workspace_size bytes. */
+ws_status ws_render_backward_l1(const ws_gaussians* g, const ws_camera* cams, const ws_camera* d_cams,
+                                int32_t n_views, const ws_options* opt, const ws_splat* splats,
+                                const uint32_t* values, const uint32_t* tile_ranges, const float* images,
+                                const float* targets, int64_t total, float* d_loss, const int32_t* d_status,
+                                ws_gaussian_grads* grads, void* ws, size_t ws_bytes, void* stream);
+size_t ws_render_backward_l1_workspace_size(int64_t n, const ws_camera* cams, int32_t n_views,
+                                           const ws_options* opt);
+
 /* L1 photometric loss of the multi-view training step (the mean over every
  * image element of the batch).  Over the n floats of this call:
  *   *d_loss    = sum |images - targets| / total

@@ -2,8 +2,9 @@
 
 `BatchedStep` runs, for V cameras of uneven resolution at once:
     preprocess (all views) -> sort (device-sized) -> render (all tiles of all
-    views) -> L1 loss against the targets -> backward (all views, gradients
-    summed over views)
+    views) -> backward of the L1 loss against the targets (all views, the loss
+    and its gradient formed inside the compositing adjoint, gradients summed
+    over views)
 without any host synchronisation, so the whole sequence is captured once with
 ws_graph_begin / ws_graph_end and replayed with ws_graph_launch.  Pair buffers
 are sized from a measured frame with headroom; a replay that would need more
@@ -42,11 +43,8 @@ class BatchedStep:
         with torch.cuda.stream(self.stream):
             m = self.r.forward(g, stream=self.stream)  # measure M once, eagerly
             self.r._ensure_capacity(int(m * headroom) + 4096)
-        self.dL = torch.empty_like(self.r.images)
         self.loss = torch.zeros(1, dtype=torch.float32, device=device)
         self.grads = _zero_grads(g)
-        self.ws_loss = torch.empty(max(B.ws_l1_loss_workspace_size(self.r.image_floats), 256), dtype=torch.uint8,
-                                   device=device)
         self.graph = None
         # one eager step sizes every workspace before any capture
         self.step_eager()
@@ -56,9 +54,8 @@ class BatchedStep:
         s = self.stream
         with torch.cuda.stream(s):
             self.r.forward_capacity(self.g, stream=s)
-            B.ws_l1_loss(self.r.images, self.targets, self.r.image_floats, 0, self.dL, self.loss, self.ws_loss,
-                         self.ws_loss.numel(), s)
-            self.r.backward(self.g, self.dL, grads=self.grads, stream=s)
+            # the L1 loss and its gradient are formed inside the compositing adjoint
+            self.r.backward_l1(self.g, self.targets, self.loss, grads=self.grads, stream=s)
 
     def capture(self):
         s = self.stream

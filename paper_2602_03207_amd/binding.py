@@ -38,7 +38,7 @@ EXPORTED = [
     "ws_render", "ws_render_backward", "ws_l1_loss", "ws_l1_loss_workspace_size", "ws_graph_begin", "ws_graph_end",
     "ws_graph_launch", "ws_graph_destroy", "ws_last_error", "ws_status_string", "ws_version", "ws_timing_start",
     "ws_timing_stop", "ws_total_bins", "ws_expand_bins_workspace_size", "ws_expand_bins", "ws_sort32",
-    "ws_sort32_workspace_size", "ws_sort_noalloc",
+    "ws_sort32_workspace_size", "ws_sort_noalloc", "ws_render_backward_l1", "ws_render_backward_l1_workspace_size",
 ]
 
 KERNELS = {"preprocess": 0, "scan_emit": 1, "sort_hist": 2, "sort_pass": 3, "ranges": 4, "render": 5,
@@ -122,6 +122,10 @@ def load():
                               vp]
     lib.ws_render_backward.argtypes = [P(ws_gaussians), P(ws_camera), vp, i32, P(ws_options), vp, vp, vp, vp, vp,
                                        P(ws_gaussian_grads), vp, sz, vp]
+    lib.ws_render_backward_l1.argtypes = [P(ws_gaussians), P(ws_camera), vp, i32, P(ws_options), vp, vp, vp, vp, vp,
+                                          i64, vp, vp, P(ws_gaussian_grads), vp, sz, vp]
+    lib.ws_render_backward_l1_workspace_size.argtypes = [i64, P(ws_camera), i32, P(ws_options)]
+    lib.ws_render_backward_l1_workspace_size.restype = sz
     lib.ws_l1_loss.argtypes = [vp, vp, i64, i64, vp, vp, vp, sz, vp]
     lib.ws_graph_begin.argtypes = [vp]
     lib.ws_graph_end.argtypes = [vp, P(vp)]
@@ -242,6 +246,10 @@ def ws_render_backward_workspace_size(n, n_views):
     return load().ws_render_backward_workspace_size(n, n_views)
 
 
+def ws_render_backward_l1_workspace_size(n, cams, n_views, opt):
+    return load().ws_render_backward_l1_workspace_size(n, cams, n_views, C.byref(opt))
+
+
 def ws_l1_loss_workspace_size(n):
     return load().ws_l1_loss_workspace_size(n)
 
@@ -308,6 +316,14 @@ def ws_render_backward(g, cams, d_cams, n_views, opt, splats, values, tile_range
     _check(load().ws_render_backward(C.byref(g), cams, _ptr(d_cams), n_views, C.byref(opt), _ptr(splats),
                                      _ptr(values), _ptr(tile_ranges), _ptr(dL_dimages), _ptr(d_status),
                                      C.byref(grads), _ptr(ws), ws_bytes, _stream(stream)))
+
+
+def ws_render_backward_l1(g, cams, d_cams, n_views, opt, splats, values, tile_ranges, images, targets, total, d_loss,
+                          d_status, grads, ws, ws_bytes, stream=None):
+    _check(load().ws_render_backward_l1(C.byref(g), cams, _ptr(d_cams), n_views, C.byref(opt), _ptr(splats),
+                                        _ptr(values), _ptr(tile_ranges), _ptr(images), _ptr(targets), total,
+                                        _ptr(d_loss), _ptr(d_status), C.byref(grads), _ptr(ws), ws_bytes,
+                                        _stream(stream)))
 
 
 def ws_l1_loss(images, targets, n, total, dL_dimages, d_loss, ws, ws_bytes, stream=None):

@@ -283,6 +283,12 @@ size_t ws_render_backward_workspace_size(int64_t n, int32_t n_views) {
     return ws::render_backward_workspace(n, n_views);
 }
 
+size_t ws_render_backward_l1_workspace_size(int64_t n, const ws_camera* cams, int32_t n_views,
+                                           const ws_options* opt) {
+    if (n < 0 || n_views < 1 || !cams || !opt) return 0;
+    return ws::render_backward_l1_workspace(n, n_views, total_tiles_of(cams, n_views, opt->tile_w, opt->tile_h));
+}
+
 size_t ws_l1_loss_workspace_size(int64_t n) {
     if (n < 0) return 0;
     return ws::l1_loss_workspace(n);
@@ -435,25 +441,33 @@ ws_status ws_expand_bins(const ws_splat* splats, int64_t n, const ws_camera* cam
     return hip_status(e, "ws_expand_bins launch");
 }
 
-ws_status ws_render_backward(const ws_gaussians* g, const ws_camera* cams, const ws_camera* d_cams,
-                             int32_t n_views, const ws_options* opt, const ws_splat* splats,
-                             const uint32_t* values, const uint32_t* tile_ranges, const float* dL_dimages,
-                             const int32_t* d_status, ws_gaussian_grads* grads, void* ws, size_t ws_bytes,
-                             void* stream) {
+extern "C++" {
+namespace {
+
+// The checks and the launch shared by ws_render_backward and ws_render_backward_l1.
+ws_status render_backward_checked(const char* name, const ws_gaussians* g, const ws_camera* cams,
+                                  const ws_camera* d_cams, int32_t n_views, const ws_options* opt,
+                                  const ws_splat* splats, const uint32_t* values, const uint32_t* tile_ranges,
+                                  const float* dL_dimages, const ws::L1Loss* l1, const int32_t* d_status,
+                                  ws_gaussian_grads* grads, void* ws, size_t ws_bytes, void* stream) {
     ws_status s;
     if ((s = check_gaussians(g)) != WS_OK) return s;
     if ((s = check_cameras(cams, d_cams, n_views)) != WS_OK) return s;
     if ((s = check_options(opt)) != WS_OK) return s;
     if (!grads || (g->n > 0 && (!grads->means || !grads->log_scales || !grads->quats || !grads->opacity_logits ||
                                 !grads->sh)))
-        return fail(WS_ERR_INVALID_ARGUMENT, "a gradient array is NULL");
+        return fail(WS_ERR_INVALID_ARGUMENT, "%s: a gradient array is NULL", name);
     if (opt->flags & WS_FLAG_PACKED)
-        return fail(WS_ERR_UNSUPPORTED, "ws_render_backward needs full-precision ws_splat records (no WS_FLAG_PACKED)");
-    if (!tile_ranges || !dL_dimages || !d_status) return fail(WS_ERR_INVALID_ARGUMENT, "tile_ranges / dL_dimages / d_status is NULL");
-    if (g->n > 0 && (!splats || !values)) return fail(WS_ERR_INVALID_ARGUMENT, "splats / values is NULL");
-    if (g->n * int64_t(n_views) > kMaxGaussians) return fail(WS_ERR_INVALID_ARGUMENT, "n * n_views must be < 2^31");
-    if ((s = check_ws(ws, ws_bytes, ws::render_backward_workspace(g->n, n_views))) != WS_OK) return s;
+        return fail(WS_ERR_UNSUPPORTED, "%s needs full-precision ws_splat records (no WS_FLAG_PACKED)", name);
+    if (!tile_ranges || !d_status) return fail(WS_ERR_INVALID_ARGUMENT, "%s: tile_ranges / d_status is NULL", name);
+    if (!l1 && !dL_dimages) return fail(WS_ERR_INVALID_ARGUMENT, "%s: dL_dimages is NULL", name);
+    if (g->n > 0 && (!splats || !values)) return fail(WS_ERR_INVALID_ARGUMENT, "%s: splats / values is NULL", name);
+    if (g->n * int64_t(n_views) > kMaxGaussians)
+        return fail(WS_ERR_INVALID_ARGUMENT, "%s: n * n_views must be < 2^31", name);
     const int64_t tiles = total_tiles_of(cams, n_views, opt->tile_w, opt->tile_h);
+    const size_t need =
+        l1 ? ws::render_backward_l1_workspace(g->n, n_views, tiles) : ws::render_backward_workspace(g->n, n_views);
+    if ((s = check_ws(ws, ws_bytes, need)) != WS_OK) return s;
     ws::GradPtrs gp;
     gp.means = grads->means;
     gp.log_scales = grads->log_scales;
@@ -462,8 +476,39 @@ ws_status ws_render_backward(const ws_gaussians* g, const ws_camera* cams, const
     gp.sh = grads->sh;
     const hipError_t e = ws::launch_render_backward(gauss_ptrs(g), d_cams, n_views, tiles, ws::to_kopts(*opt), splats,
                                                     values, tile_ranges, dL_dimages, d_status, gp, ws,
-                                                    static_cast<hipStream_t>(stream));
-    return hip_status(e, "ws_render_backward launch");
+                                                    static_cast<hipStream_t>(stream), l1);
+    return hip_status(e, name);
+}
+
+}  // namespace
+}  // extern "C++"
+
+ws_status ws_render_backward(const ws_gaussians* g, const ws_camera* cams, const ws_camera* d_cams,
+                             int32_t n_views, const ws_options* opt, const ws_splat* splats,
+                             const uint32_t* values, const uint32_t* tile_ranges, const float* dL_dimages,
+                             const int32_t* d_status, ws_gaussian_grads* grads, void* ws, size_t ws_bytes,
+                             void* stream) {
+    return render_backward_checked("ws_render_backward", g, cams, d_cams, n_views, opt, splats, values, tile_ranges,
+                                   dL_dimages, nullptr, d_status, grads, ws, ws_bytes, stream);
+}
+
+ws_status ws_render_backward_l1(const ws_gaussians* g, const ws_camera* cams, const ws_camera* d_cams,
+                                int32_t n_views, const ws_options* opt, const ws_splat* splats,
+                                const uint32_t* values, const uint32_t* tile_ranges, const float* images,
+                                const float* targets, int64_t total, float* d_loss, const int32_t* d_status,
+                                ws_gaussian_grads* grads, void* ws, size_t ws_bytes, void* stream) {
+    if (!cams || n_views < 1) return fail(WS_ERR_INVALID_ARGUMENT, "ws_render_backward_l1: no cameras");
+    int64_t elems = 0;
+    for (int32_t v = 0; v < n_views; ++v) elems += 3 * int64_t(cams[v].width) * cams[v].height;
+    if (total == 0) total = elems;
+    if (total < elems)
+        return fail(WS_ERR_INVALID_ARGUMENT, "ws_render_backward_l1: total (%lld) must be 0 or >= the views' %lld "
+                    "elements", (long long)total, (long long)elems);
+    if (!images || !targets || !d_loss)
+        return fail(WS_ERR_INVALID_ARGUMENT, "ws_render_backward_l1: images / targets / d_loss is NULL");
+    const ws::L1Loss l1{images, targets, total, d_loss};
+    return render_backward_checked("ws_render_backward_l1", g, cams, d_cams, n_views, opt, splats, values,
+                                   tile_ranges, nullptr, &l1, d_status, grads, ws, ws_bytes, stream);
 }
 
 ws_status ws_l1_loss(const float* images, const float* targets, int64_t n, int64_t total, float* dL_dimages,

@@ -17,6 +17,10 @@
 //     the wave (lane swaps and DPP) and across the workgroup (LDS atomics),
 //     turned into dL/d(centre, conic, sigma) with the splat's conic once, and
 //     added to device memory with one atomic per value.
+//     With the L1 loss (L1Args.images set), dL/dC is formed in the kernel as
+//     sign(image - target) / total instead of read from a gradient image, and
+//     each tile writes the sum of |image - target| over its pixels (fp64, fixed
+//     order) for k_l1_final.
 // k_bwd_clear           zeroes the per-(view, splat) gradient buffer.
 // k_preprocess_bwd_geo  one thread per Gaussian, summing over the views: the
 //     chain through the conic inverse, the EWA covariance, the Jacobian
@@ -51,6 +55,14 @@ __global__ void k_bwd_clear(float* p, int64_t count) {
     for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < count; i += stride) p[i] = 0.f;
 }
 
+// The L1 loss inside the compositing adjoint (images == nullptr: dL is read).
+struct L1Args {
+    const float* images;
+    const float* targets;
+    float inv_total;  // 1 / total rounded once from fp64, as ws_l1_loss
+    double* partial;  // [total_tiles] sums of |image - target| per tile
+};
+
 struct BwdArgs {
     const ws_splat* splats;
     int64_t n;
@@ -59,6 +71,7 @@ struct BwdArgs {
     const uint32_t* values;
     const uint32_t* ranges;
     const float* dL;
+    L1Args l1;
     const int32_t* d_status;
     BwdWs w;
     KOpts o;
@@ -128,12 +141,26 @@ __global__ __launch_bounds__(TW * TH) void k_render_bwd(BwdArgs a) {
     __shared__ float s_acc[kNG][NT];
     __shared__ uint64_t s_masks[NW * NW];
     __shared__ int32_t s_maxlast;
+    __shared__ double s_l1[NW];
     if (*a.d_status != 0) return;
     const int64_t g = blockIdx.x;
     const TileInfo ti = locate_tile(a.cams, a.n_views, g, TW, TH);
     int px, py;
     quadrant_pixel<TW>(ti.x0, ti.y0, &px, &py);
     const bool inside = px < ti.W && py < ti.H;
+    // L1: the pixel's image and target values, loaded now and used after pass 1
+    // (their latency overlaps pass 1's first staging loads)
+    const bool l1 = a.l1.images != nullptr;
+    float l1_img[3] = {0.f, 0.f, 0.f}, l1_tgt[3] = {0.f, 0.f, 0.f};
+    if (l1 && inside) {
+        const int64_t plane = int64_t(ti.W) * ti.H;
+        const int64_t p = ti.img_off + int64_t(py) * ti.W + px;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            l1_img[c] = a.l1.images[p + c * plane];
+            l1_tgt[c] = a.l1.targets[p + c * plane];
+        }
+    }
     const uint64_t* my_masks = s_masks + (threadIdx.x / kWave) * NW;
     const uint32_t start = a.ranges[2 * g], end = a.ranges[2 * g + 1];
     const ws_splat* vsplats = a.splats + int64_t(ti.view) * a.n;
@@ -162,8 +189,26 @@ __global__ __launch_bounds__(TW * TH) void k_render_bwd(BwdArgs a) {
         __syncthreads();
         composite_batch<NW, RECT>(ps, active, s_batch, my_masks, int32_t(b0 - start), bk);
     }
+    float dLdC[3] = {0.f, 0.f, 0.f};
+    if (l1) {
+        // the L1 loss of this tile's pixels: its gradient and the tile's sum of |image - target|
+        double part = 0.0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const float d = l1_img[c] - l1_tgt[c];  // 0 for lanes without a pixel
+            dLdC[c] = d > 0.f ? a.l1.inv_total : (d < 0.f ? -a.l1.inv_total : 0.f);
+            part += double(fabsf(d));
+        }
+        part = wave_sum(part);
+        if (lane_id() == 0) s_l1[threadIdx.x / kWave] = part;
+    }
     __syncthreads();
     if (ps.last >= 0) atomicMax(&s_maxlast, ps.last);
+    if (l1 && threadIdx.x == 0) {
+        double s = 0.0;
+        for (int w = 0; w < NW; ++w) s += s_l1[w];
+        a.l1.partial[g] = s;
+    }
     __syncthreads();
     const int32_t maxlast = s_maxlast;
     if (maxlast < 0) return;  // nothing composited in this tile
@@ -174,8 +219,7 @@ __global__ __launch_bounds__(TW * TH) void k_render_bwd(BwdArgs a) {
     wlast = __builtin_amdgcn_readfirstlane(wlast);
 
     // ---- pass 2: back to front from the last contributor
-    float dLdC[3] = {0.f, 0.f, 0.f};
-    if (inside) {
+    if (!a.l1.images && inside) {
         const int64_t plane = int64_t(ti.W) * ti.H;
         const int64_t p = ti.img_off + int64_t(py) * ti.W + px;
         dLdC[0] = a.dL[p];
@@ -520,15 +564,23 @@ size_t render_backward_workspace(int64_t n, int32_t n_views) {
     return align_up(size_t(kNG) * size_t(std::max<int64_t>(n, 1)) * n_views * sizeof(float));
 }
 
+size_t render_backward_l1_workspace(int64_t n, int32_t n_views, int64_t total_tiles) {
+    return render_backward_workspace(n, n_views) + align_up(size_t(std::max<int64_t>(total_tiles, 1)) * sizeof(double));
+}
+
 hipError_t launch_render_backward(const GaussPtrs& g, const ws_camera* d_cams, int32_t n_views,
                                   int64_t total_tiles, const KOpts& o, const ws_splat* splats,
                                   const uint32_t* values, const uint32_t* tile_ranges, const float* dL_dimages,
-                                  const int32_t* d_status, const GradPtrs& grads, void* ws, hipStream_t stream) {
+                                  const int32_t* d_status, const GradPtrs& grads, void* ws, hipStream_t stream,
+                                  const L1Loss* l1) {
     BwdWs w = carve_bwd(ws, g.n, n_views);
+    double* l1_part = l1 ? reinterpret_cast<double*>(static_cast<char*>(ws) + render_backward_workspace(g.n, n_views))
+                         : nullptr;
     const int64_t count = int64_t(kNG) * w.vn;
     const uint32_t cgrid = uint32_t(std::min<int64_t>(std::max<int64_t>((count + 255) / 256, 1), 8192));
     hipLaunchKernelGGL(k_bwd_clear, dim3(cgrid), dim3(256), 0, stream, w.sg, count);
-    if (g.n == 0) return hipGetLastError();
+    // with no Gaussians only the loss remains (every tile list is empty)
+    if (g.n == 0 && !l1) return hipGetLastError();
     if (total_tiles > 0) {
         BwdArgs ba;
         ba.splats = splats;
@@ -538,6 +590,8 @@ hipError_t launch_render_backward(const GaussPtrs& g, const ws_camera* d_cams, i
         ba.values = values;
         ba.ranges = tile_ranges;
         ba.dL = dL_dimages;
+        ba.l1 = L1Args{nullptr, nullptr, 0.f, nullptr};
+        if (l1) ba.l1 = L1Args{l1->images, l1->targets, float(1.0 / double(l1->total)), l1_part};
         ba.d_status = d_status;
         ba.w = w;
         ba.o = o;
@@ -547,7 +601,9 @@ hipError_t launch_render_backward(const GaussPtrs& g, const ws_camera* d_cams, i
         else if (o.tile_w == 16 && o.tile_h == 8) launch_bwd_t<16, 8>(ba, total_tiles, stream);
         else launch_bwd_t<32, 16>(ba, total_tiles, stream);
         timing_end(WS_KERNEL_RENDER_BWD, stream);
+        if (l1) launch_l1_final(l1_part, total_tiles, l1->total, d_status, l1->d_loss, stream);
     }
+    if (g.n == 0) return hipGetLastError();
     PreBwdArgs pa;
     pa.g = g;
     pa.cams = d_cams;

@@ -267,6 +267,32 @@ class Renderer:
             self._check_status()
         return grads
 
+    def backward_l1(self, g: GaussianTensors, targets: torch.Tensor, loss: torch.Tensor, total=0, grads=None,
+                    stream=None, accumulate=False, check=False):
+        """Parameter gradients of the L1 loss of the last forward's images against `targets` (same layout as
+        self.images), and the loss into `loss` (a one-float device tensor): ws_render_backward_l1, which forms
+        dL/dimages inside the compositing adjoint.  `total` as in ws_l1_loss (0: this renderer's image
+        elements); the other arguments as in backward()."""
+        if grads is None:
+            grads = dict(means=torch.empty_like(g.means), log_scales=torch.empty_like(g.log_scales),
+                         quats=torch.empty_like(g.quats), opacity_logits=torch.empty_like(g.opacity_logits),
+                         sh=torch.empty_like(g.sh))
+        if targets.numel() != self.image_floats or not targets.is_contiguous():
+            raise ValueError("targets must be a contiguous tensor shaped like the images")
+        need = B.ws_render_backward_l1_workspace_size(g.n, self.cam_arr, self.n_views, self.opts)
+        ws = self.ws_bwd.get(need)
+        gs = B.make_grads(grads["means"], grads["log_scales"], grads["quats"], grads["opacity_logits"], grads["sh"])
+        opts = self.opts
+        if accumulate:
+            opts = B.ws_options.from_buffer_copy(self.opts)
+            opts.flags |= B.WS_FLAG_ACCUMULATE_GRADS
+        B.ws_render_backward_l1(g.struct(), self.cam_arr, self.d_cams, self.n_views, opts, self.splats, self.lists,
+                                self.tile_ranges, self.images, targets, total, loss, self.d_status, gs, ws,
+                                ws.numel(), stream)
+        if check:
+            self._check_status()
+        return grads
+
     def _check_status(self):
         st = int(self.d_status.item())
         if st != 0:

@@ -139,6 +139,35 @@ def test_backward_rejects_packed_records(lib):
     assert st == B.WS_ERR_UNSUPPORTED and "PACKED" in _err(lib)
 
 
+def test_fused_l1_backward_rejects_bad_arguments_on_the_host(lib):
+    vp = C.c_void_p
+    g = B.ws_gaussians()
+    g.n = 0
+    grads = B.make_grads(0x200000, 0x200000, 0x200000, 0x200000, 0x200000)
+    cams = (B.ws_camera * 2)(_cam(64, 48), _cam(32, 16))
+    o = _opts()
+    elems = 3 * (64 * 48 + 32 * 16)
+    need = lib.ws_render_backward_l1_workspace_size(0, cams, 2, C.byref(o))
+    # the per-tile loss sums come on top of the plain backward's workspace
+    assert need >= lib.ws_render_backward_workspace_size(0, 2) + 8 * lib.ws_total_tiles(cams, 2, C.byref(o))
+    assert lib.ws_render_backward_l1_workspace_size(-1, cams, 2, C.byref(o)) == 0
+
+    def call(images=0x610000, targets=0x620000, total=0, loss=0x630000, ws_bytes=need):
+        return lib.ws_render_backward_l1(C.byref(g), cams, vp(0x300000), 2, C.byref(o), vp(0x400000),
+                                         vp(0x500000), vp(0x600000), vp(images) if images else None,
+                                         vp(targets) if targets else None, total, vp(loss) if loss else None,
+                                         vp(0x800000), C.byref(grads), vp(0x900000), ws_bytes, None)
+
+    st = call(total=elems - 1)
+    assert st == B.WS_ERR_INVALID_ARGUMENT and "total" in _err(lib)
+    assert call(images=0) == B.WS_ERR_INVALID_ARGUMENT
+    assert call(targets=0) == B.WS_ERR_INVALID_ARGUMENT
+    assert call(loss=0) == B.WS_ERR_INVALID_ARGUMENT
+    assert call(ws_bytes=need - 1) == B.WS_ERR_WORKSPACE_TOO_SMALL
+    o.flags = B.WS_FLAG_PACKED
+    assert call() == B.WS_ERR_UNSUPPORTED
+
+
 def test_unknown_flags_are_rejected_and_accumulate_is_known(lib):
     vp = C.c_void_p
     g = B.ws_gaussians()
