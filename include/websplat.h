@@ -313,19 +313,21 @@ ws_status ws_render(const ws_splat* splats, int64_t n, const ws_camera* cams, co
 /* Reverse mode of ws_render and ws_preprocess.  Given dL/dimages (same
  * layout as images), writes dL/d(parameters) summed over the views into
  * `grads` (overwritten).  The compositing adjoint recomputes each tile front
- * to back to find every pixel's final transmittance and last contributor,
- * then walks back to front; no per-pixel state is stored by the forward.
- * Discrete decisions (culls, skips, early stop, clamps) take the derivative
- * of the branch taken.  values / tile_ranges are the lists ws_render read
- * (with bins larger than one tile: ws_expand_bins' tile_values / tile_ranges).
- * With WS_FLAG_ACCUMULATE_GRADS in opt->flags the gradients are added to
- * `grads` instead.  d_status: the forward's status word; if it is non-zero
- * (the forward did not complete) no kernel writes anything, `grads` included. */
+ * to back with the forward's arithmetic and decisions, and takes the colour
+ * behind each splat from the forward's output `images` (its final colour
+ * minus what the splats up to that one composited); the forward stores no
+ * per-pixel state.  Discrete decisions (culls, skips, early stop, clamps) take
+ * the derivative of the branch taken.  values / tile_ranges are the lists
+ * ws_render read (with bins larger than one tile: ws_expand_bins' tile_values
+ * / tile_ranges); images is ws_render's output for them.  With
+ * WS_FLAG_ACCUMULATE_GRADS in opt->flags the gradients are added to `grads`
+ * instead.  d_status: the forward's status word; if it is non-zero (the
+ * forward did not complete) no kernel writes anything, `grads` included. */
 ws_status ws_render_backward(const ws_gaussians* g, const ws_camera* cams, const ws_camera* d_cams,
                              int32_t n_views, const ws_options* opt, const ws_splat* splats,
-                             const uint32_t* values, const uint32_t* tile_ranges, const float* dL_dimages,
-                             const int32_t* d_status, ws_gaussian_grads* grads, void* ws, size_t ws_bytes,
-                             void* stream);
+                             const uint32_t* values, const uint32_t* tile_ranges, const float* images,
+                             const float* dL_dimages, const int32_t* d_status, ws_gaussian_grads* grads, void* ws,
+                             size_t ws_bytes, void* stream);
 
 /* The compositing adjoint of the L1 photometric loss, for the training step:
  * the result of ws_l1_loss over these views' images followed by

@@ -121,7 +121,7 @@ def load():
     lib.ws_render.argtypes = [vp, i64, P(ws_camera), vp, i32, P(ws_options), vp, vp, i64, vp, vp, vp, vp, vp, sz,
                               vp]
     lib.ws_render_backward.argtypes = [P(ws_gaussians), P(ws_camera), vp, i32, P(ws_options), vp, vp, vp, vp, vp,
-                                       P(ws_gaussian_grads), vp, sz, vp]
+                                       vp, P(ws_gaussian_grads), vp, sz, vp]
     lib.ws_render_backward_l1.argtypes = [P(ws_gaussians), P(ws_camera), vp, i32, P(ws_options), vp, vp, vp, vp, vp,
                                           i64, vp, vp, P(ws_gaussian_grads), vp, sz, vp]
     lib.ws_render_backward_l1_workspace_size.argtypes = [i64, P(ws_camera), i32, P(ws_options)]
@@ -311,10 +311,10 @@ def ws_render(splats, n, cams, d_cams, n_views, opt, keys, values, capacity, d_n
                             ws_bytes, _stream(stream)))
 
 
-def ws_render_backward(g, cams, d_cams, n_views, opt, splats, values, tile_ranges, dL_dimages, d_status, grads, ws,
-                       ws_bytes, stream=None):
+def ws_render_backward(g, cams, d_cams, n_views, opt, splats, values, tile_ranges, images, dL_dimages, d_status,
+                       grads, ws, ws_bytes, stream=None):
     _check(load().ws_render_backward(C.byref(g), cams, _ptr(d_cams), n_views, C.byref(opt), _ptr(splats),
-                                     _ptr(values), _ptr(tile_ranges), _ptr(dL_dimages), _ptr(d_status),
+                                     _ptr(values), _ptr(tile_ranges), _ptr(images), _ptr(dL_dimages), _ptr(d_status),
                                      C.byref(grads), _ptr(ws), ws_bytes, _stream(stream)))
 
 

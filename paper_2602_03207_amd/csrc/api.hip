@@ -448,7 +448,8 @@ namespace {
 ws_status render_backward_checked(const char* name, const ws_gaussians* g, const ws_camera* cams,
                                   const ws_camera* d_cams, int32_t n_views, const ws_options* opt,
                                   const ws_splat* splats, const uint32_t* values, const uint32_t* tile_ranges,
-                                  const float* dL_dimages, const ws::L1Loss* l1, const int32_t* d_status,
+                                  const float* images, const float* dL_dimages, const ws::L1Loss* l1,
+                                  const int32_t* d_status,
                                   ws_gaussian_grads* grads, void* ws, size_t ws_bytes, void* stream) {
     ws_status s;
     if ((s = check_gaussians(g)) != WS_OK) return s;
@@ -459,7 +460,8 @@ ws_status render_backward_checked(const char* name, const ws_gaussians* g, const
         return fail(WS_ERR_INVALID_ARGUMENT, "%s: a gradient array is NULL", name);
     if (opt->flags & WS_FLAG_PACKED)
         return fail(WS_ERR_UNSUPPORTED, "%s needs full-precision ws_splat records (no WS_FLAG_PACKED)", name);
-    if (!tile_ranges || !d_status) return fail(WS_ERR_INVALID_ARGUMENT, "%s: tile_ranges / d_status is NULL", name);
+    if (!tile_ranges || !images || !d_status)
+        return fail(WS_ERR_INVALID_ARGUMENT, "%s: tile_ranges / images / d_status is NULL", name);
     if (!l1 && !dL_dimages) return fail(WS_ERR_INVALID_ARGUMENT, "%s: dL_dimages is NULL", name);
     if (g->n > 0 && (!splats || !values)) return fail(WS_ERR_INVALID_ARGUMENT, "%s: splats / values is NULL", name);
     if (g->n * int64_t(n_views) > kMaxGaussians)
@@ -475,7 +477,7 @@ ws_status render_backward_checked(const char* name, const ws_gaussians* g, const
     gp.logits = grads->opacity_logits;
     gp.sh = grads->sh;
     const hipError_t e = ws::launch_render_backward(gauss_ptrs(g), d_cams, n_views, tiles, ws::to_kopts(*opt), splats,
-                                                    values, tile_ranges, dL_dimages, d_status, gp, ws,
+                                                    values, tile_ranges, images, dL_dimages, d_status, gp, ws,
                                                     static_cast<hipStream_t>(stream), l1);
     return hip_status(e, name);
 }
@@ -485,11 +487,11 @@ ws_status render_backward_checked(const char* name, const ws_gaussians* g, const
 
 ws_status ws_render_backward(const ws_gaussians* g, const ws_camera* cams, const ws_camera* d_cams,
                              int32_t n_views, const ws_options* opt, const ws_splat* splats,
-                             const uint32_t* values, const uint32_t* tile_ranges, const float* dL_dimages,
-                             const int32_t* d_status, ws_gaussian_grads* grads, void* ws, size_t ws_bytes,
-                             void* stream) {
+                             const uint32_t* values, const uint32_t* tile_ranges, const float* images,
+                             const float* dL_dimages, const int32_t* d_status, ws_gaussian_grads* grads, void* ws,
+                             size_t ws_bytes, void* stream) {
     return render_backward_checked("ws_render_backward", g, cams, d_cams, n_views, opt, splats, values, tile_ranges,
-                                   dL_dimages, nullptr, d_status, grads, ws, ws_bytes, stream);
+                                   images, dL_dimages, nullptr, d_status, grads, ws, ws_bytes, stream);
 }
 
 ws_status ws_render_backward_l1(const ws_gaussians* g, const ws_camera* cams, const ws_camera* d_cams,
@@ -506,9 +508,9 @@ ws_status ws_render_backward_l1(const ws_gaussians* g, const ws_camera* cams, co
                     "elements", (long long)total, (long long)elems);
     if (!images || !targets || !d_loss)
         return fail(WS_ERR_INVALID_ARGUMENT, "ws_render_backward_l1: images / targets / d_loss is NULL");
-    const ws::L1Loss l1{images, targets, total, d_loss};
+    const ws::L1Loss l1{targets, total, d_loss};
     return render_backward_checked("ws_render_backward_l1", g, cams, d_cams, n_views, opt, splats, values,
-                                   tile_ranges, nullptr, &l1, d_status, grads, ws, ws_bytes, stream);
+                                   tile_ranges, images, nullptr, &l1, d_status, grads, ws, ws_bytes, stream);
 }
 
 ws_status ws_l1_loss(const float* images, const float* targets, int64_t n, int64_t total, float* dL_dimages,

@@ -1,14 +1,15 @@
 // Reverse mode of the render path.
 //
-// k_render_bwd<TW, TH>  per tile, no stored per-pixel state: pass 1 walks the
+// k_render_bwd<TW, TH>  per tile, no stored per-pixel state: one pass walks the
 //     tile's list front to back exactly as the forward does (same staged
-//     arithmetic, same decisions) to get each pixel's final transmittance and
-//     the list index of its last contributor; pass 2 walks back to front from
-//     there, recovering T_k = T_{k+1} / (1 - alpha_k) (alpha <= alpha_max < 1)
-//     and the suffix colour R_k = sum_{i>k} c_i alpha_i T_i + bg T_final, and
-//     forms for each contributor
-//        dL/dc_k     = alpha_k T_k dL/dC
+//     arithmetic, same decisions, so T_k is the forward's transmittance) and
+//     forms for each splat a pixel takes
+//        dL/dc_k     = w_k dL/dC              (w_k = T_k - T_{k+1}, the forward's weight)
 //        dL/dalpha_k = dL/dC . (c_k T_k - R_k / (1 - alpha_k))
+//     with R_k = sum_{i>k} c_i w_i + bg T_final, the colour behind splat k,
+//     taken as C - sum_{i<=k} c_i w_i from the pixel's forward output C
+//     (background included): dL/dC . R_k = dL/dC . C - P_k with P_k the running
+//     sum of (dL/dC . c_i) w_i
 //     and, unless alpha was clamped, dL/dsigma = dL/dalpha exp(power) and
 //     dL/dpower = dL/dalpha * alpha with the derivatives of the power in the
 //     centre and the conic.  Per (pixel, splat) the pass forms nine values:
@@ -55,9 +56,8 @@ __global__ void k_bwd_clear(float* p, int64_t count) {
     for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < count; i += stride) p[i] = 0.f;
 }
 
-// The L1 loss inside the compositing adjoint (images == nullptr: dL is read).
+// The L1 loss inside the compositing adjoint (targets == nullptr: dL is read).
 struct L1Args {
-    const float* images;
     const float* targets;
     float inv_total;  // 1 / total rounded once from fp64, as ws_l1_loss
     double* partial;  // [total_tiles] sums of |image - target| per tile
@@ -70,6 +70,7 @@ struct BwdArgs {
     int32_t n_views;
     const uint32_t* values;
     const uint32_t* ranges;
+    const float* images;  // the forward's images
     const float* dL;
     L1Args l1;
     const int32_t* d_status;
@@ -132,7 +133,7 @@ __device__ __forceinline__ void wave_sum9(float (&v)[kNG], float* q0, float* q1,
     *q2 = s2;
 }
 
-// RECT: the rectangle test of the forward (see blend_one), in both passes.
+// RECT: the rectangle test of the forward (see blend_one).
 template <int TW, int TH, bool RECT>
 __global__ __launch_bounds__(TW * TH) void k_render_bwd(BwdArgs a) {
     constexpr int NT = TW * TH, NW = NT / kWave;
@@ -140,7 +141,6 @@ __global__ __launch_bounds__(TW * TH) void k_render_bwd(BwdArgs a) {
     __shared__ RawConic s_conic[NT];
     __shared__ float s_acc[kNG][NT];
     __shared__ uint64_t s_masks[NW * NW];
-    __shared__ int32_t s_maxlast;
     __shared__ double s_l1[NW];
     if (*a.d_status != 0) return;
     const int64_t g = blockIdx.x;
@@ -148,99 +148,46 @@ __global__ __launch_bounds__(TW * TH) void k_render_bwd(BwdArgs a) {
     int px, py;
     quadrant_pixel<TW>(ti.x0, ti.y0, &px, &py);
     const bool inside = px < ti.W && py < ti.H;
-    // L1: the pixel's image and target values, loaded now and used after pass 1
-    // (their latency overlaps pass 1's first staging loads)
-    const bool l1 = a.l1.images != nullptr;
-    float l1_img[3] = {0.f, 0.f, 0.f}, l1_tgt[3] = {0.f, 0.f, 0.f};
-    if (l1 && inside) {
+    const bool l1 = a.l1.targets != nullptr;
+    // per pixel: the forward's colour C (background included) and dL/dC, given
+    // or, with the L1 loss, sign(C - target) / total.  The loads are issued
+    // here and used after the first batch is staged, so their latency overlaps
+    // the staging's.
+    float img[3] = {0.f, 0.f, 0.f}, aux[3] = {0.f, 0.f, 0.f};  // aux: the target, or dL/dC
+    if (inside) {
         const int64_t plane = int64_t(ti.W) * ti.H;
         const int64_t p = ti.img_off + int64_t(py) * ti.W + px;
+        const float* src = l1 ? a.l1.targets : a.dL;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-            l1_img[c] = a.l1.images[p + c * plane];
-            l1_tgt[c] = a.l1.targets[p + c * plane];
+            img[c] = a.images[p + c * plane];
+            aux[c] = src[p + c * plane];
         }
     }
+    float dLdC[3] = {0.f, 0.f, 0.f};
+    float SC = 0.f;  // dL/dC . C: dL/dC . R_k = SC - P_k, P_k = dL/dC . (colour composited up to splat k)
+    bool ready = false;
     const uint64_t* my_masks = s_masks + (threadIdx.x / kWave) * NW;
     const uint32_t start = a.ranges[2 * g], end = a.ranges[2 * g + 1];
     const ws_splat* vsplats = a.splats + int64_t(ti.view) * a.n;
     const int64_t vbase = int64_t(ti.view) * a.n;
-
-    // ---- pass 1: front to back, as in the forward
-    PixelState ps;
-    ps.init(px, py);
-    uint64_t active = wave_ballot(inside);  // lanes whose pixel is still compositing
-    const BlendConsts bk(a.o);
-    if (threadIdx.x == 0) s_maxlast = -1;
-    for (uint32_t b0 = start; b0 < end; b0 += NT) {
-        if (__syncthreads_count(!lane_in(active)) == NT) break;
-        const uint32_t idx = b0 + threadIdx.x;
-        StagedSplat s = empty_splat();
-        bool valid = false;
-        if (idx < end) {
-            const uint32_t id = a.values[idx];
-            if (id < uint64_t(a.n)) {
-                s = stage_splat(vsplats, id);
-                valid = true;
-            }
-            s_batch[threadIdx.x] = s;
-        }
-        stage_quadrant_masks<TW, TH>(s, valid, ti.x0, ti.y0, bk.log2_amin, s_masks);
-        __syncthreads();
-        composite_batch<NW, RECT>(ps, active, s_batch, my_masks, int32_t(b0 - start), bk);
-    }
-    float dLdC[3] = {0.f, 0.f, 0.f};
-    if (l1) {
-        // the L1 loss of this tile's pixels: its gradient and the tile's sum of |image - target|
-        double part = 0.0;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const float d = l1_img[c] - l1_tgt[c];  // 0 for lanes without a pixel
-            dLdC[c] = d > 0.f ? a.l1.inv_total : (d < 0.f ? -a.l1.inv_total : 0.f);
-            part += double(fabsf(d));
-        }
-        part = wave_sum(part);
-        if (lane_id() == 0) s_l1[threadIdx.x / kWave] = part;
-    }
-    __syncthreads();
-    if (ps.last >= 0) atomicMax(&s_maxlast, ps.last);
-    if (l1 && threadIdx.x == 0) {
-        double s = 0.0;
-        for (int w = 0; w < NW; ++w) s += s_l1[w];
-        a.l1.partial[g] = s;
-    }
-    __syncthreads();
-    const int32_t maxlast = s_maxlast;
-    if (maxlast < 0) return;  // nothing composited in this tile
-    // this wave's last contributor: its walk skips the entries behind it
-    int32_t wlast = ps.last;
-#pragma unroll
-    for (int s = 32; s >= 1; s >>= 1) wlast = max(wlast, __shfl_xor(wlast, s, kWave));
-    wlast = __builtin_amdgcn_readfirstlane(wlast);
-
-    // ---- pass 2: back to front from the last contributor
-    if (!a.l1.images && inside) {
-        const int64_t plane = int64_t(ti.W) * ti.H;
-        const int64_t p = ti.img_off + int64_t(py) * ti.W + px;
-        dLdC[0] = a.dL[p];
-        dLdC[1] = a.dL[p + plane];
-        dLdC[2] = a.dL[p + 2 * plane];
-    }
-    float T = ps.T;
-    // dL/dC . R_k, R_k the suffix colour behind splat k (background included)
-    float SR = (dLdC[0] * a.o.bg[0] + dLdC[1] * a.o.bg[1] + dLdC[2] * a.o.bg[2]) * T;
-    const int32_t last = ps.last;
     const float pcx = float(px) + 0.5f, pcy = float(py) + 0.5f;
     const uint32_t pix = inside ? pack_xy(px, py) : kNoPixel;
-    for (int32_t bend = maxlast + 1; bend > 0; bend -= NT) {
-        const int32_t bstart = bend - NT > 0 ? bend - NT : 0;
-        __syncthreads();
+    const BlendConsts bk(a.o);
+    float T = 1.f, P = 0.f;
+    uint64_t active = wave_ballot(inside);  // lanes whose pixel is still compositing
+
+    // One pass front to back over the tile's list, replaying the forward's
+    // decisions with its arithmetic (so T_k is the forward's transmittance),
+    // and forming the adjoint of every splat a pixel takes.
+    for (uint32_t b0 = start; b0 < end; b0 += NT) {
+        if (__syncthreads_count(!lane_in(active)) == NT) break;
         {
-            const int32_t j = bstart + int32_t(threadIdx.x);
+            const uint32_t idx = b0 + threadIdx.x;
             StagedSplat s = empty_splat();
             bool valid = false;
-            if (j < bend) {
-                const uint32_t id = a.values[start + uint32_t(j)];
+            if (idx < end) {
+                const uint32_t id = a.values[idx];
                 valid = id < uint64_t(a.n);
                 if (valid) s = stage_splat(vsplats, id);
                 s_batch[threadIdx.x] = s;
@@ -252,73 +199,82 @@ __global__ __launch_bounds__(TW * TH) void k_render_bwd(BwdArgs a) {
             stage_quadrant_masks<TW, TH>(s, valid, ti.x0, ti.y0, bk.log2_amin, s_masks);
         }
         __syncthreads();
-        // back to front over the staged splats that meet this wave's quadrant
-        MaskWalk<NW, false> walk;
-        walk.init(my_masks);
-        walk.keep_up_to(wlast - bstart);
-        for (int t = walk.next(); t >= 0; t = walk.next()) {
-            const int32_t j = bstart + t;
-            const StagedSplat& s = s_batch[t];
-            // The forward's alpha (same evaluation, same skip decision), then
-            // every lane evaluates the adjoint without branches: a lane that
-            // does not take the splat gets zero weights, so its sums and state
-            // stay unchanged (nested per-lane branches cost more in moves and
-            // mask bookkeeping than the arithmetic they skip).
-            const float dx = s.u - pcx, dy = s.v - pcy;
-            const float araw = raw_alpha(s, dx, dy);
-            const float alpha = __builtin_amdgcn_fmed3f(araw, 0.f, bk.alpha_max);
-            // the lane decisions as lane masks (ballots of the comparisons, as in
-            // the forward), applied with inverse ballots: no per-lane branches
-            const uint64_t cmask = wave_ballot(j <= last) & (RECT ? wave_ballot(in_rect(s, pix)) : ~uint64_t(0)) &
-                                   wave_ballot(!(alpha < bk.alpha_min));
-            if (cmask == 0) continue;
-            const bool contrib = lane_in(cmask);
-            const bool unclamped = lane_in(cmask & wave_ballot(!(araw > bk.alpha_max)));
-            // 1 - alpha >= 1 - alpha_max > 0; the hardware reciprocal (about
-            // 1 ulp) keeps the back-to-front recovery of T well inside the
-            // gradient tolerance
-            const float inv = __builtin_amdgcn_rcpf(1.f - alpha);
-            const float Tk = T * inv;
-            const float w = contrib ? alpha * Tk : 0.f;
-            const float Dc = dLdC[0] * s.r + dLdC[1] * s.g + dLdC[2] * s.b;  // dL/dC . c_k
-            // dL/dalpha = dL/dC . (c_k T_k - R_k / (1 - alpha)); zero through the clamp
-            const float dLda = Tk * Dc - inv * SR;
-            const float gp = unclamped ? dLda * araw : 0.f;  // dL/dpower
-            // moments of dL/dpower over the splat's pixels; the conic and 1/sigma,
-            // constant per splat, are applied once to their sums (flush below)
-            float gv[kNG];
-            const float gdx = gp * dx, gdy = gp * dy;
-            gv[0] = gdx;
-            gv[1] = gdy;
-            gv[2] = gdx * dx;
-            gv[3] = gdx * dy;
-            gv[4] = gdy * dy;
-            gv[5] = gp;
-            gv[6] = dLdC[0] * w;
-            gv[7] = dLdC[1] * w;
-            gv[8] = dLdC[2] * w;
-            SR = fmaf(Dc, w, SR);
-            T = contrib ? Tk : T;
-            {
-                float q0, q1, q2;
-                wave_sum9(gv, &q0, &q1, &q2);
-                // the first lane of each row adds its row's values (distinct addresses);
-                // some lane contributes, so the sums are rarely zero and are added
-                // without a test (adding +0 changes no sum)
-                const uint32_t lane = lane_id();
-                if ((lane & 15) == 0) {
-                    const int row = int(lane >> 4);
-                    const int k0 = row == 1 ? 2 : (row == 2 ? 1 : row);  // rows hold v0, v2, v1, v3
-                    atomicAdd(&s_acc[k0][t], q0);
-                    atomicAdd(&s_acc[4 + k0][t], q1);
-                    if (row == 3) atomicAdd(&s_acc[8][t], q2);
+        if (!ready) {
+            ready = true;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const float d = img[c] - aux[c];
+                dLdC[c] = l1 ? (d > 0.f ? a.l1.inv_total : (d < 0.f ? -a.l1.inv_total : 0.f)) : aux[c];
+            }
+            SC = fmaf(dLdC[0], img[0], fmaf(dLdC[1], img[1], dLdC[2] * img[2]));
+        }
+        if (active != 0) {
+            // front to back over the staged splats that meet this wave's quadrant
+            MaskWalk<NW, true> walk;
+            walk.init(my_masks);
+            for (int t = walk.next(); t >= 0; t = walk.next()) {
+                const StagedSplat& s = s_batch[t];
+                // the forward's evaluation and decisions (blend_one), as lane masks
+                const float dx = s.u - pcx, dy = s.v - pcy;
+                const float araw = raw_alpha(s, dx, dy);
+                const float alpha = __builtin_amdgcn_fmed3f(araw, 0.f, bk.alpha_max);
+                const float Tn = fmaf(-T, alpha, T);
+                const uint64_t hit = (RECT ? active & wave_ballot(in_rect(s, pix)) : active) &
+                                     wave_ballot(!(alpha < bk.alpha_min));
+                const uint64_t stop = hit & wave_ballot(Tn < bk.t_min);
+                const uint64_t take_m = hit & ~stop;
+                active &= ~stop;
+                if (take_m != 0) {
+                    // every lane evaluates the adjoint without branches: a lane
+                    // that does not take the splat gets zero weights, so its sums
+                    // and state stay unchanged
+                    const bool take = lane_in(take_m);
+                    const bool unclamped = lane_in(take_m & wave_ballot(!(araw > bk.alpha_max)));
+                    const float T1 = take ? Tn : T;
+                    const float w = T - T1;  // the forward's weight of splat k
+                    const float Dc = fmaf(dLdC[0], s.r, fmaf(dLdC[1], s.g, dLdC[2] * s.b));  // dL/dC . c_k
+                    P = fmaf(Dc, w, P);
+                    // 1 - alpha >= 1 - alpha_max > 0 (hardware reciprocal, about 1 ulp)
+                    const float inv = __builtin_amdgcn_rcpf(1.f - alpha);
+                    // dL/dalpha = dL/dC . (c_k T_k - R_k / (1 - alpha)); zero through the clamp
+                    const float dLda = fmaf(T, Dc, -(SC - P) * inv);
+                    const float gp = unclamped ? dLda * araw : 0.f;  // dL/dpower
+                    // moments of dL/dpower over the splat's pixels; the conic and
+                    // 1/sigma, constant per splat, are applied once to their sums
+                    // (flush below)
+                    float gv[kNG];
+                    const float gdx = gp * dx, gdy = gp * dy;
+                    gv[0] = gdx;
+                    gv[1] = gdy;
+                    gv[2] = gdx * dx;
+                    gv[3] = gdx * dy;
+                    gv[4] = gdy * dy;
+                    gv[5] = gp;
+                    gv[6] = dLdC[0] * w;
+                    gv[7] = dLdC[1] * w;
+                    gv[8] = dLdC[2] * w;
+                    T = T1;
+                    float q0, q1, q2;
+                    wave_sum9(gv, &q0, &q1, &q2);
+                    // the first lane of each row adds its row's values (distinct
+                    // addresses); some lane contributes, so the sums are rarely
+                    // zero and are added without a test (adding +0 changes no sum)
+                    const uint32_t lane = lane_id();
+                    if ((lane & 15) == 0) {
+                        const int row = int(lane >> 4);
+                        const int k0 = row == 1 ? 2 : (row == 2 ? 1 : row);  // rows hold v0, v2, v1, v3
+                        atomicAdd(&s_acc[k0][t], q0);
+                        atomicAdd(&s_acc[4 + k0][t], q1);
+                        if (row == 3) atomicAdd(&s_acc[8][t], q2);
+                    }
                 }
+                if (active == 0) break;
             }
         }
         __syncthreads();
         {
-            const int32_t j = bstart + int32_t(threadIdx.x);
-            if (j < bend) {
+            const uint32_t idx = b0 + threadIdx.x;
+            if (idx < end) {
                 const uint32_t id = s_batch[threadIdx.x].id;
                 if (id < uint64_t(a.n)) {
                     // from the moments S0..S5 of dL/dpower (with dx = u - px, dy = v - py):
@@ -328,21 +284,35 @@ __global__ __launch_bounds__(TW * TH) void k_render_bwd(BwdArgs a) {
                     float m[kNG];
 #pragma unroll
                     for (int k = 0; k < kNG; ++k) m[k] = s_acc[k][threadIdx.x];
-                    float g[kNG];
-                    g[0] = -fmaf(q.A, m[0], q.B * m[1]);
-                    g[1] = -fmaf(q.B, m[0], q.C * m[1]);
-                    g[2] = -0.5f * m[2];
-                    g[3] = -m[3];
-                    g[4] = -0.5f * m[4];
-                    g[5] = m[5] * q.inv_sigma;
-                    g[6] = m[6];
-                    g[7] = m[7];
-                    g[8] = m[8];
+                    float gg[kNG];
+                    gg[0] = -fmaf(q.A, m[0], q.B * m[1]);
+                    gg[1] = -fmaf(q.B, m[0], q.C * m[1]);
+                    gg[2] = -0.5f * m[2];
+                    gg[3] = -m[3];
+                    gg[4] = -0.5f * m[4];
+                    gg[5] = m[5] * q.inv_sigma;
+                    gg[6] = m[6];
+                    gg[7] = m[7];
+                    gg[8] = m[8];
 #pragma unroll
                     for (int k = 0; k < kNG; ++k)
-                        if (g[k] != 0.f) atomicAdd(&a.w.sg[int64_t(k) * a.w.vn + vbase + id], g[k]);
+                        if (gg[k] != 0.f) atomicAdd(&a.w.sg[int64_t(k) * a.w.vn + vbase + id], gg[k]);
                 }
             }
+        }
+    }
+    if (l1) {
+        // the tile's sum of |image - target| (lanes without a pixel hold zeros)
+        double part = 0.0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) part += double(fabsf(img[c] - aux[c]));
+        part = wave_sum(part);
+        if (lane_id() == 0) s_l1[threadIdx.x / kWave] = part;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double sum = 0.0;
+            for (int w = 0; w < NW; ++w) sum += s_l1[w];
+            a.l1.partial[g] = sum;
         }
     }
 }
@@ -570,9 +540,9 @@ size_t render_backward_l1_workspace(int64_t n, int32_t n_views, int64_t total_ti
 
 hipError_t launch_render_backward(const GaussPtrs& g, const ws_camera* d_cams, int32_t n_views,
                                   int64_t total_tiles, const KOpts& o, const ws_splat* splats,
-                                  const uint32_t* values, const uint32_t* tile_ranges, const float* dL_dimages,
-                                  const int32_t* d_status, const GradPtrs& grads, void* ws, hipStream_t stream,
-                                  const L1Loss* l1) {
+                                  const uint32_t* values, const uint32_t* tile_ranges, const float* images,
+                                  const float* dL_dimages, const int32_t* d_status, const GradPtrs& grads, void* ws,
+                                  hipStream_t stream, const L1Loss* l1) {
     BwdWs w = carve_bwd(ws, g.n, n_views);
     double* l1_part = l1 ? reinterpret_cast<double*>(static_cast<char*>(ws) + render_backward_workspace(g.n, n_views))
                          : nullptr;
@@ -589,9 +559,10 @@ hipError_t launch_render_backward(const GaussPtrs& g, const ws_camera* d_cams, i
         ba.n_views = n_views;
         ba.values = values;
         ba.ranges = tile_ranges;
+        ba.images = images;
         ba.dL = dL_dimages;
-        ba.l1 = L1Args{nullptr, nullptr, 0.f, nullptr};
-        if (l1) ba.l1 = L1Args{l1->images, l1->targets, float(1.0 / double(l1->total)), l1_part};
+        ba.l1 = L1Args{nullptr, 0.f, nullptr};
+        if (l1) ba.l1 = L1Args{l1->targets, float(1.0 / double(l1->total)), l1_part};
         ba.d_status = d_status;
         ba.w = w;
         ba.o = o;

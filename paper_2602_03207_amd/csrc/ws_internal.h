@@ -294,16 +294,15 @@ hipError_t launch_expand(const ws_splat* splats, int64_t n, const ws_camera* d_c
 // backward.hip
 // The L1 loss formed inside the compositing adjoint (ws_render_backward_l1).
 struct L1Loss {
-    const float* images;
     const float* targets;
     int64_t total;  // elements the mean is taken over
     float* d_loss;
 };
 hipError_t launch_render_backward(const GaussPtrs& g, const ws_camera* d_cams, int32_t n_views,
                                   int64_t total_tiles, const KOpts& o, const ws_splat* splats,
-                                  const uint32_t* values, const uint32_t* tile_ranges, const float* dL_dimages,
-                                  const int32_t* d_status, const GradPtrs& grads, void* ws, hipStream_t stream,
-                                  const L1Loss* l1 = nullptr);
+                                  const uint32_t* values, const uint32_t* tile_ranges, const float* images,
+                                  const float* dL_dimages, const int32_t* d_status, const GradPtrs& grads, void* ws,
+                                  hipStream_t stream, const L1Loss* l1 = nullptr);
 size_t render_backward_l1_workspace(int64_t n, int32_t n_views, int64_t total_tiles);
 // *loss = sum of partial[0..nb) / total in a fixed order; nothing when *d_status != 0 (d_status may be null).
 void launch_l1_final(const double* partial, int64_t nb, int64_t total, const int32_t* d_status, float* loss,

@@ -262,7 +262,7 @@ class Renderer:
             opts = B.ws_options.from_buffer_copy(self.opts)
             opts.flags |= B.WS_FLAG_ACCUMULATE_GRADS
         B.ws_render_backward(g.struct(), self.cam_arr, self.d_cams, self.n_views, opts, self.splats, self.lists,
-                             self.tile_ranges, dL_dimages, self.d_status, gs, ws, ws.numel(), stream)
+                             self.tile_ranges, self.images, dL_dimages, self.d_status, gs, ws, ws.numel(), stream)
         if check:
             self._check_status()
         return grads

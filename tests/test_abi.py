@@ -135,7 +135,8 @@ def test_backward_rejects_packed_records(lib):
     cams = (B.ws_camera * 1)(_cam(64, 64))
     o = _opts(flags=B.WS_FLAG_PACKED)
     st = lib.ws_render_backward(C.byref(g), cams, vp(0x300000), 1, C.byref(o), vp(0x400000), vp(0x500000),
-                                vp(0x600000), vp(0x700000), vp(0x800000), C.byref(grads), vp(0x900000), 1 << 30, None)
+                                vp(0x600000), vp(0x650000), vp(0x700000), vp(0x800000), C.byref(grads), vp(0x900000),
+                                1 << 30, None)
     assert st == B.WS_ERR_UNSUPPORTED and "PACKED" in _err(lib)
 
 
