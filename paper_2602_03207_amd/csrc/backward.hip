@@ -137,9 +137,12 @@ __device__ __forceinline__ void wave_sum9(float (&v)[kNG], float* q0, float* q1,
 template <int TW, int TH, bool RECT>
 __global__ __launch_bounds__(TW * TH) void k_render_bwd(BwdArgs a) {
     constexpr int NT = TW * TH, NW = NT / kWave;
-    __shared__ StagedSplat s_batch[NT];
-    __shared__ RawConic s_conic[NT];
-    __shared__ float s_acc[kNG][NT];
+    // batches of NB = NT / 2 list entries: half the LDS of one entry per
+    // thread, so more workgroups are resident to hide the adjoint's latencies
+    constexpr int NB = NT / 2;
+    __shared__ StagedSplat s_batch[NB];
+    __shared__ RawConic s_conic[NB];
+    __shared__ float s_acc[kNG][NB];
     __shared__ uint64_t s_masks[NW * NW];
     __shared__ double s_l1[NW];
     if (*a.d_status != 0) return;
@@ -180,13 +183,13 @@ __global__ __launch_bounds__(TW * TH) void k_render_bwd(BwdArgs a) {
     // One pass front to back over the tile's list, replaying the forward's
     // decisions with its arithmetic (so T_k is the forward's transmittance),
     // and forming the adjoint of every splat a pixel takes.
-    for (uint32_t b0 = start; b0 < end; b0 += NT) {
+    for (uint32_t b0 = start; b0 < end; b0 += NB) {
         if (__syncthreads_count(!lane_in(active)) == NT) break;
         {
             const uint32_t idx = b0 + threadIdx.x;
             StagedSplat s = empty_splat();
             bool valid = false;
-            if (idx < end) {
+            if (threadIdx.x < NB && idx < end) {
                 const uint32_t id = a.values[idx];
                 valid = id < uint64_t(a.n);
                 if (valid) s = stage_splat(vsplats, id);
@@ -194,8 +197,10 @@ __global__ __launch_bounds__(TW * TH) void k_render_bwd(BwdArgs a) {
                 const float* rec = reinterpret_cast<const float*>(vsplats + (valid ? id : 0));
                 s_conic[threadIdx.x] = RawConic{rec[2], rec[3], rec[4], 1.f / rec[5]};
             }
+            if (threadIdx.x < NB) {
 #pragma unroll
-            for (int k = 0; k < kNG; ++k) s_acc[k][threadIdx.x] = 0.f;
+                for (int k = 0; k < kNG; ++k) s_acc[k][threadIdx.x] = 0.f;
+            }
             stage_quadrant_masks<TW, TH>(s, valid, ti.x0, ti.y0, bk.log2_amin, s_masks);
         }
         __syncthreads();
@@ -274,7 +279,7 @@ __global__ __launch_bounds__(TW * TH) void k_render_bwd(BwdArgs a) {
         __syncthreads();
         {
             const uint32_t idx = b0 + threadIdx.x;
-            if (idx < end) {
+            if (threadIdx.x < NB && idx < end) {
                 const uint32_t id = s_batch[threadIdx.x].id;
                 if (id < uint64_t(a.n)) {
                     // from the moments S0..S5 of dL/dpower (with dx = u - px, dy = v - py):
