@@ -320,7 +320,8 @@ def measured_traffic(dom, tile):
     """HBM bytes per launch of the dominant kernel from the committed counter summary, or None when the
     summary covers another kernel or the kernel's sources changed since the counters were taken."""
     import hashlib
-    names = {"render": f"k_render<{tile[0]}, {tile[1]}>"}
+    # the frame's flags (opacity-aware extent, full records) select the render without the rectangle test
+    names = {"render": f"k_render<{tile[0]}, {tile[1]}, false>"}
     if dom not in names or not os.path.exists(TRAFFIC_FILE):
         return None
     fields = {}
