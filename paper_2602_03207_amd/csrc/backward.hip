@@ -15,9 +15,10 @@
 //     centre and the conic.  Per (pixel, splat) the pass forms nine values:
 //     the moments dL/dpower * (1, dx, dy, dx^2, dx dy, dy^2) and the colour
 //     gradient; their per-splat sums over a staged batch are reduced across
-//     the wave (lane swaps and DPP) and across the workgroup (LDS atomics),
-//     turned into dL/d(centre, conic, sigma) with the splat's conic once, and
-//     added to device memory with one atomic per value.
+//     the wave (lane swaps and DPP), stored per wave in LDS, added over the
+//     waves in a fixed order, turned into dL/d(centre, conic, sigma) with the
+//     splat's conic once, and added to device memory with one atomic per
+//     value.
 //     With the L1 loss (L1Args.images set), dL/dC is formed in the kernel as
 //     sign(image - target) / total instead of read from a gradient image, and
 //     each tile writes the sum of |image - target| over its pixels (fp64, fixed
@@ -38,9 +39,17 @@ namespace ws {
 namespace {
 
 constexpr int kNG = 9;  // u, v, A, B, C, sigma, r, g, b
+// One 64-byte record of gradients per (view, splat): the nine values, then
+// seven unused floats.  A wave adds a splat's nine values with one atomic
+// instruction whose lanes address one cache line, which the memory system
+// serves as one request; nine arrays would take nine.
+constexpr int kRec = 16;
+#ifndef WS_BWD_SUMS
+#define WS_BWD_SUMS 256
+#endif
 
 struct BwdWs {
-    float* sg;   // [kNG][V * n] per-(view, splat) gradients
+    float* sg;   // [V * n][kRec] per-(view, splat) gradients
     int64_t vn;  // V * n
 };
 
@@ -51,9 +60,10 @@ BwdWs carve_bwd(void* ws, int64_t n, int32_t n_views) {
     return b;
 }
 
-__global__ void k_bwd_clear(float* p, int64_t count) {
+__global__ void k_bwd_clear(float4* p, int64_t count) {
     const int64_t stride = int64_t(gridDim.x) * blockDim.x;
-    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < count; i += stride) p[i] = 0.f;
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < count; i += stride)
+        p[i] = make_float4(0.f, 0.f, 0.f, 0.f);
 }
 
 // The L1 loss inside the compositing adjoint (targets == nullptr: dL is read).
@@ -83,15 +93,19 @@ struct RawConic {
 };
 
 // Sums over the 64 lanes of a wave of the nine per-splat gradient values,
-// transposed so that the work halves at every cross-row step: the 32-lane
-// swap pairs up values (v0, v1), (v2, v3), ... and one add leaves each value's
-// half-sums in one half of the wave; the 16-lane swap pairs up those and one
-// add leaves each value's quarter-sums in one row; DPP permutes inside rows
-// then sum each row.  The ninth value has no partner: it is summed per row and
-// then across rows by the two row broadcasts.  Results, in every lane of the
-// row: q0 holds v0, v2, v1, v3 in rows 0, 1, 2, 3; q1 holds v4, v6, v5, v7;
-// q2 holds v8 in row 3.  Every step is a VALU operation on all 64 lanes (the
-// callers run with all lanes active); no LDS traffic.
+// transposed so that the work halves at every step: the 32-lane swap pairs up
+// values (v0, v1), (v2, v3), ... and one add leaves each value's half-sums in
+// one half of the wave; the 16-lane swap pairs up those and one add leaves each
+// value's quarter-sums in one row (rows 0-3 hold v0, v2, v1, v3 in one
+// register and v4, v6, v5, v7 in the other); two DPP adds limited to lane banks
+// fold the two registers into one, the first value in lanes 0-7 of each row
+// and the second in lanes 8-15; three DPP adds inside each half-row finish the
+// sums.  The ninth value has no partner: the same three DPP adds and an 8-lane
+// rotation sum it over each row, and two row broadcasts add the rows.
+// Result: lane 8h + 16r (h = 0, 1; r = 0..3) holds the sum of value
+// 4h + (0, 2, 1, 3)[r] in *q, and every lane of row 3 the sum of v8 in *q8.
+// Every step is a VALU operation on all 64 lanes (the callers run with all
+// lanes active); no LDS traffic.
 __device__ __forceinline__ void swap32(float& a, float& b) {
     // both operands are read and written (the swap builtin of this compiler
     // returns the first register twice); two wait states on either side
@@ -105,14 +119,29 @@ __device__ __forceinline__ float dpp_add(float v) {
     const int moved = __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xf, 0xf, false);
     return v + __builtin_bit_cast(float, moved);
 }
-__device__ __forceinline__ float row_sum(float v) {
-    v = dpp_add<0xb1>(v);   // quad_perm [1, 0, 3, 2]: pairs
-    v = dpp_add<0x4e>(v);   // quad_perm [2, 3, 0, 1]: quads
-    v = dpp_add<0x124>(v);  // row_ror 4
-    v = dpp_add<0x128>(v);  // row_ror 8: every lane holds its row's sum
+// Lanes 0-7 of each row: x + x rotated by 8 lanes (the sum of x over lanes i
+// and i + 8); lanes 8-15: the same of y.  Each add writes only its two lane
+// banks; a DPP source needs two wait states after the VALU write of it, and
+// the result as well before the next DPP reads it.
+__device__ __forceinline__ float fold_halves(float x, float y) {
+    float z;
+    asm volatile(
+        "s_nop 1\n\t"
+        "v_add_f32_dpp %0, %1, %1 row_ror:8 row_mask:0xf bank_mask:0x3\n\t"
+        "v_add_f32_dpp %0, %2, %2 row_ror:8 row_mask:0xf bank_mask:0xc\n\t"
+        "s_nop 1"
+        : "=&v"(z)
+        : "v"(x), "v"(y));
+    return z;
+}
+// The sum over each 8-lane half of a row, in all its lanes.
+__device__ __forceinline__ float half_row_sum(float v) {
+    v = dpp_add<0x141>(v);  // row_half_mirror: lanes i and 7 - i
+    v = dpp_add<0x4e>(v);   // quad_perm [2, 3, 0, 1]
+    v = dpp_add<0xb1>(v);   // quad_perm [1, 0, 3, 2]
     return v;
 }
-__device__ __forceinline__ void wave_sum9(float (&v)[kNG], float* q0, float* q1, float* q2) {
+__device__ __forceinline__ void wave_sum9(float (&v)[kNG], float* q, float* q8) {
     swap32(v[0], v[1]);
     swap32(v[2], v[3]);
     swap32(v[4], v[5]);
@@ -120,29 +149,37 @@ __device__ __forceinline__ void wave_sum9(float (&v)[kNG], float* q0, float* q1,
     float p01 = v[0] + v[1], p23 = v[2] + v[3], p45 = v[4] + v[5], p67 = v[6] + v[7];
     swap16(p01, p23);
     swap16(p45, p67);
-    // row_bcast:15 adds the last lane of each row to the next row (row 0 has no
-    // source and adds 0), row_bcast:31 adds lane 31 to rows 2 and 3: row 3
-    // then holds r3 + r2 + (r1 + r0); rows 0-2 hold partial sums nobody reads
-    float s0 = row_sum(p01 + p23), s1 = row_sum(p45 + p67), s2 = dpp_add<0x143>(dpp_add<0x142>(row_sum(v[8])));
+    // v8 opaque: otherwise the compiler folds its product into the first DPP
+    // add as a zeroed register, a DPP move and a multiply-add
+    asm volatile("" : "+v"(v[8]));
+    // v8: the sum over each row (half-rows and one 8-lane rotation), then
+    // row_bcast:15 adds the last lane of each row to the next row (row 0 has
+    // no source and adds 0) and row_bcast:31 adds lane 31 to rows 2 and 3:
+    // row 3 then holds r3 + r2 + (r1 + r0)
+    float s = half_row_sum(fold_halves(p01 + p23, p45 + p67));
+    float s8 = dpp_add<0x143>(dpp_add<0x142>(dpp_add<0x128>(half_row_sum(v[8]))));
     // complete the sums in every lane here: left to itself the compiler moves
-    // the last add of each into the row leaders' branch, which turns one DPP
-    // add into a zeroed register, a DPP move and an add
-    asm volatile("" : "+v"(s0), "+v"(s1), "+v"(s2));
-    *q0 = s0;
-    *q1 = s1;
-    *q2 = s2;
+    // the last add of each into the leaders' branch, which turns one DPP add
+    // into a zeroed register, a DPP move and an add
+    asm volatile("" : "+v"(s), "+v"(s8));
+    *q = s;
+    *q8 = s8;
 }
 
 // RECT: the rectangle test of the forward (see blend_one).
 template <int TW, int TH, bool RECT>
-__global__ __launch_bounds__(TW * TH) void k_render_bwd(BwdArgs a) {
+__global__ __launch_bounds__(TW * TH, 8) void k_render_bwd(BwdArgs a) {
     constexpr int NT = TW * TH, NW = NT / kWave;
-    // batches of NB = NT / 2 list entries: half the LDS of one entry per
-    // thread, so more workgroups are resident to hide the adjoint's latencies
-    constexpr int NB = NT / 2;
+    // batches of NB list entries: at most half a tile's threads, and at most
+    // WS_BWD_SUMS (wave, entry) pairs of per-wave sums
+    constexpr int NB = NT / 2 < WS_BWD_SUMS / NW ? NT / 2 : WS_BWD_SUMS / NW;
     __shared__ StagedSplat s_batch[NB];
     __shared__ RawConic s_conic[NB];
-    __shared__ float s_acc[kNG][NB];
+    // per wave and batch entry the wave's nine sums, [wave][entry][9]: each
+    // wave writes its own (a plain store, no LDS atomics), the flush adds the
+    // waves' sums in a fixed order
+    __shared__ float4 s_sums4[NW * NB * kNG / 4];
+    float* const s_sums = reinterpret_cast<float*>(s_sums4);
     __shared__ uint64_t s_masks[NW * NW];
     __shared__ double s_l1[NW];
     if (*a.d_status != 0) return;
@@ -153,9 +190,8 @@ __global__ __launch_bounds__(TW * TH) void k_render_bwd(BwdArgs a) {
     const bool inside = px < ti.W && py < ti.H;
     const bool l1 = a.l1.targets != nullptr;
     // per pixel: the forward's colour C (background included) and dL/dC, given
-    // or, with the L1 loss, sign(C - target) / total.  The loads are issued
-    // here and used after the first batch is staged, so their latency overlaps
-    // the staging's.
+    // or, with the L1 loss, sign(C - target) / total (and |C - target| for the
+    // tile's loss sum).
     float img[3] = {0.f, 0.f, 0.f}, aux[3] = {0.f, 0.f, 0.f};  // aux: the target, or dL/dC
     if (inside) {
         const int64_t plane = int64_t(ti.W) * ti.H;
@@ -167,9 +203,16 @@ __global__ __launch_bounds__(TW * TH) void k_render_bwd(BwdArgs a) {
             aux[c] = src[p + c * plane];
         }
     }
-    float dLdC[3] = {0.f, 0.f, 0.f};
-    float SC = 0.f;  // dL/dC . C: dL/dC . R_k = SC - P_k, P_k = dL/dC . (colour composited up to splat k)
-    bool ready = false;
+    float dLdC[3];
+    double part = 0.0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const float d = img[c] - aux[c];
+        dLdC[c] = l1 ? (d > 0.f ? a.l1.inv_total : (d < 0.f ? -a.l1.inv_total : 0.f)) : aux[c];
+        part += double(fabsf(d));
+    }
+    // dL/dC . C: dL/dC . R_k = SC - P_k, P_k = dL/dC . (colour composited up to splat k)
+    const float SC = fmaf(dLdC[0], img[0], fmaf(dLdC[1], img[1], dLdC[2] * img[2]));
     const uint64_t* my_masks = s_masks + (threadIdx.x / kWave) * NW;
     const uint32_t start = a.ranges[2 * g], end = a.ranges[2 * g + 1];
     const ws_splat* vsplats = a.splats + int64_t(ti.view) * a.n;
@@ -197,28 +240,24 @@ __global__ __launch_bounds__(TW * TH) void k_render_bwd(BwdArgs a) {
                 const float* rec = reinterpret_cast<const float*>(vsplats + (valid ? id : 0));
                 s_conic[threadIdx.x] = RawConic{rec[2], rec[3], rec[4], 1.f / rec[5]};
             }
-            if (threadIdx.x < NB) {
-#pragma unroll
-                for (int k = 0; k < kNG; ++k) s_acc[k][threadIdx.x] = 0.f;
-            }
+            for (int i = threadIdx.x; i < NW * NB * kNG / 4; i += NT) s_sums4[i] = make_float4(0.f, 0.f, 0.f, 0.f);
             stage_quadrant_masks<TW, TH>(s, valid, ti.x0, ti.y0, bk.log2_amin, s_masks);
         }
         __syncthreads();
-        if (!ready) {
-            ready = true;
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                const float d = img[c] - aux[c];
-                dLdC[c] = l1 ? (d > 0.f ? a.l1.inv_total : (d < 0.f ? -a.l1.inv_total : 0.f)) : aux[c];
-            }
-            SC = fmaf(dLdC[0], img[0], fmaf(dLdC[1], img[1], dLdC[2] * img[2]));
-        }
         if (active != 0) {
             // front to back over the staged splats that meet this wave's quadrant
             MaskWalk<NW, true> walk;
             walk.init(my_masks);
+            // The wave's nine sums of a splat are stored by nine lanes: the
+            // first lane of each half-row stores its value's sum (rows hold
+            // v0, v2, v1, v3, plus 4 in the second half-row), lane 49 that of v8.
+            const uint32_t lane = lane_id();
+            const bool leader = (lane & 7) == 0, lane49 = lane == 49;
+            const int row = int(lane >> 4);
+            const int kq = lane49 ? 8 : (row == 1 ? 2 : (row == 2 ? 1 : row)) + int(lane & 8) / 2;
+            float* const my_sums = s_sums + (threadIdx.x / kWave) * NB * kNG + kq;
             for (int t = walk.next(); t >= 0; t = walk.next()) {
-                const StagedSplat& s = s_batch[t];
+                const StagedSplat s = s_batch[t];
                 // the forward's evaluation and decisions (blend_one), as lane masks
                 const float dx = s.u - pcx, dy = s.v - pcy;
                 const float araw = raw_alpha(s, dx, dy);
@@ -259,58 +298,51 @@ __global__ __launch_bounds__(TW * TH) void k_render_bwd(BwdArgs a) {
                     gv[7] = dLdC[1] * w;
                     gv[8] = dLdC[2] * w;
                     T = T1;
-                    float q0, q1, q2;
-                    wave_sum9(gv, &q0, &q1, &q2);
-                    // the first lane of each row adds its row's values (distinct
-                    // addresses); some lane contributes, so the sums are rarely
-                    // zero and are added without a test (adding +0 changes no sum)
-                    const uint32_t lane = lane_id();
-                    if ((lane & 15) == 0) {
-                        const int row = int(lane >> 4);
-                        const int k0 = row == 1 ? 2 : (row == 2 ? 1 : row);  // rows hold v0, v2, v1, v3
-                        atomicAdd(&s_acc[k0][t], q0);
-                        atomicAdd(&s_acc[4 + k0][t], q1);
-                        if (row == 3) atomicAdd(&s_acc[8][t], q2);
-                    }
+                    float q, q8;
+                    wave_sum9(gv, &q, &q8);
+                    if (leader || lane49) my_sums[t * kNG] = lane49 ? q8 : q;
                 }
                 if (active == 0) break;
             }
         }
         __syncthreads();
-        {
-            const uint32_t idx = b0 + threadIdx.x;
-            if (threadIdx.x < NB && idx < end) {
-                const uint32_t id = s_batch[threadIdx.x].id;
-                if (id < uint64_t(a.n)) {
-                    // from the moments S0..S5 of dL/dpower (with dx = u - px, dy = v - py):
-                    //   dL/du = -(A S0 + B S1), dL/dv = -(B S0 + C S1),
-                    //   dL/dA = -S2 / 2, dL/dB = -S3, dL/dC = -S4 / 2, dL/dsigma = S5 / sigma
-                    const RawConic q = s_conic[threadIdx.x];
-                    float m[kNG];
+        // One lane per (entry, value), sixteen lanes per entry: value k of the
+        // entry's gradient record, from the waves' sums added in wave order.
+        // From the moments S0..S5 of dL/dpower (with dx = u - px, dy = v - py):
+        //   dL/du = -(A S0 + B S1), dL/dv = -(B S0 + C S1),
+        //   dL/dA = -S2 / 2, dL/dB = -S3, dL/dC = -S4 / 2, dL/dsigma = S5 / sigma
+        for (int i = threadIdx.x; i < NB * kRec; i += NT) {
+            const int t = i / kRec, k = i % kRec;
+            if (k >= kNG || b0 + uint32_t(t) >= end) continue;
+            const uint32_t id = s_batch[t].id;
+            if (id >= uint64_t(a.n)) continue;
+            const float* sums = s_sums + t * kNG;
+            float mk = 0.f, mo = 0.f;  // S_k, and for k < 2 S_(1-k)
 #pragma unroll
-                    for (int k = 0; k < kNG; ++k) m[k] = s_acc[k][threadIdx.x];
-                    float gg[kNG];
-                    gg[0] = -fmaf(q.A, m[0], q.B * m[1]);
-                    gg[1] = -fmaf(q.B, m[0], q.C * m[1]);
-                    gg[2] = -0.5f * m[2];
-                    gg[3] = -m[3];
-                    gg[4] = -0.5f * m[4];
-                    gg[5] = m[5] * q.inv_sigma;
-                    gg[6] = m[6];
-                    gg[7] = m[7];
-                    gg[8] = m[8];
+            for (int w = 0; w < NW; ++w) mk += sums[w * NB * kNG + k];
+            if (k < 2) {
 #pragma unroll
-                    for (int k = 0; k < kNG; ++k)
-                        if (gg[k] != 0.f) atomicAdd(&a.w.sg[int64_t(k) * a.w.vn + vbase + id], gg[k]);
-                }
+                for (int w = 0; w < NW; ++w) mo += sums[w * NB * kNG + (1 - k)];
             }
+            const RawConic q = s_conic[t];
+            float gg;
+            if (k == 0)
+                gg = -fmaf(q.A, mk, q.B * mo);
+            else if (k == 1)
+                gg = -fmaf(q.B, mo, q.C * mk);
+            else if (k == 2 || k == 4)
+                gg = -0.5f * mk;
+            else if (k == 3)
+                gg = -mk;
+            else if (k == 5)
+                gg = mk * q.inv_sigma;
+            else
+                gg = mk;
+            if (gg != 0.f) atomicAdd(&a.w.sg[(vbase + id) * kRec + k], gg);
         }
     }
     if (l1) {
         // the tile's sum of |image - target| (lanes without a pixel hold zeros)
-        double part = 0.0;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) part += double(fabsf(img[c] - aux[c]));
         part = wave_sum(part);
         if (lane_id() == 0) s_l1[threadIdx.x / kWave] = part;
         __syncthreads();
@@ -360,13 +392,12 @@ __global__ __launch_bounds__(128) void k_preprocess_bwd_geo(PreBwdArgs a) {
     float gm[3] = {0.f, 0.f, 0.f}, gls[3] = {0.f, 0.f, 0.f}, gq[4] = {0.f, 0.f, 0.f, 0.f}, glogit = 0.f;
     for (int32_t v = 0; v < a.n_views; ++v) {
         const int64_t vi = int64_t(v) * n + i;
-        float gs[6];
+        const float4* rec = reinterpret_cast<const float4*>(a.w.sg + vi * kRec);
+        const float4 r0 = rec[0], r1 = rec[1];
+        const float gs[6] = {r0.x, r0.y, r0.z, r0.w, r1.x, r1.y};
         bool any = false;
 #pragma unroll
-        for (int k = 0; k < 6; ++k) {
-            gs[k] = a.w.sg[int64_t(k) * a.w.vn + vi];
-            any = any || gs[k] != 0.f;
-        }
+        for (int k = 0; k < 6; ++k) any = any || gs[k] != 0.f;
         if (!any) continue;
         const ws_camera& cam = a.cams[v];
         ProjState st;
@@ -479,9 +510,9 @@ __global__ __launch_bounds__(128) void k_preprocess_bwd_sh(PreBwdArgs a) {
     const float mx = a.g.means[i], my = a.g.means[n + i], mz = a.g.means[2 * n + i];
     for (int32_t v = 0; v < a.n_views; ++v) {
         const int64_t vi = int64_t(v) * n + i;
-        float gcol[3];
-#pragma unroll
-        for (int ch = 0; ch < 3; ++ch) gcol[ch] = a.w.sg[int64_t(6 + ch) * a.w.vn + vi];
+        const float* rec = a.w.sg + vi * kRec;
+        const float2 rg = *reinterpret_cast<const float2*>(rec + 6);
+        const float gcol[3] = {rg.x, rg.y, rec[8]};
         if (gcol[0] == 0.f && gcol[1] == 0.f && gcol[2] == 0.f) continue;
         const ws_camera& cam = a.cams[v];
         // the forward's view direction and colour (same arithmetic)
@@ -536,7 +567,7 @@ void launch_bwd_t(const BwdArgs& ba, int64_t tiles, hipStream_t stream) {
 }  // namespace
 
 size_t render_backward_workspace(int64_t n, int32_t n_views) {
-    return align_up(size_t(kNG) * size_t(std::max<int64_t>(n, 1)) * n_views * sizeof(float));
+    return align_up(size_t(kRec) * size_t(std::max<int64_t>(n, 1)) * n_views * sizeof(float));
 }
 
 size_t render_backward_l1_workspace(int64_t n, int32_t n_views, int64_t total_tiles) {
@@ -551,9 +582,9 @@ hipError_t launch_render_backward(const GaussPtrs& g, const ws_camera* d_cams, i
     BwdWs w = carve_bwd(ws, g.n, n_views);
     double* l1_part = l1 ? reinterpret_cast<double*>(static_cast<char*>(ws) + render_backward_workspace(g.n, n_views))
                          : nullptr;
-    const int64_t count = int64_t(kNG) * w.vn;
+    const int64_t count = int64_t(kRec / 4) * w.vn;  // float4s
     const uint32_t cgrid = uint32_t(std::min<int64_t>(std::max<int64_t>((count + 255) / 256, 1), 8192));
-    hipLaunchKernelGGL(k_bwd_clear, dim3(cgrid), dim3(256), 0, stream, w.sg, count);
+    hipLaunchKernelGGL(k_bwd_clear, dim3(cgrid), dim3(256), 0, stream, reinterpret_cast<float4*>(w.sg), count);
     // with no Gaussians only the loss remains (every tile list is empty)
     if (g.n == 0 && !l1) return hipGetLastError();
     if (total_tiles > 0) {
