@@ -322,10 +322,15 @@ ws_status ws_render(const ws_splat* splats, int64_t n, const ws_camera* cams, co
  * / tile_ranges); images is ws_render's output for them.  With
  * WS_FLAG_ACCUMULATE_GRADS in opt->flags the gradients are added to `grads`
  * instead.  d_status: the forward's status word; if it is non-zero (the
- * forward did not complete) no kernel writes anything, `grads` included. */
+ * forward did not complete) no kernel writes anything, `grads` included.
+ *   tiles_touched  ws_preprocess's [n_views][n] counts for these splats, or
+ *                  NULL.  The adjoint keeps one 64-byte gradient record per
+ *                  (view, Gaussian) in ws; with the counts it clears and reads
+ *                  only the records of entries with a non-zero count (the
+ *                  only ones a tile list can hold), with NULL every record. */
 ws_status ws_render_backward(const ws_gaussians* g, const ws_camera* cams, const ws_camera* d_cams,
                              int32_t n_views, const ws_options* opt, const ws_splat* splats,
-                             const uint32_t* values, const uint32_t* tile_ranges, const float* images,
+                             const uint32_t* tiles_touched, const uint32_t* values, const uint32_t* tile_ranges, const float* images,
                              const float* dL_dimages, const int32_t* d_status, ws_gaussian_grads* grads, void* ws,
                              size_t ws_bytes, void* stream);
 
@@ -348,7 +353,7 @@ ws_status ws_render_backward(const ws_gaussians* g, const ws_camera* cams, const
  * ws: ws_render_backward_l1_workspace_size bytes. */
 ws_status ws_render_backward_l1(const ws_gaussians* g, const ws_camera* cams, const ws_camera* d_cams,
                                 int32_t n_views, const ws_options* opt, const ws_splat* splats,
-                                const uint32_t* values, const uint32_t* tile_ranges, const float* images,
+                                const uint32_t* tiles_touched, const uint32_t* values, const uint32_t* tile_ranges, const float* images,
                                 const float* targets, int64_t total, float* d_loss, const int32_t* d_status,
                                 ws_gaussian_grads* grads, void* ws, size_t ws_bytes, void* stream);
 size_t ws_render_backward_l1_workspace_size(int64_t n, const ws_camera* cams, int32_t n_views,

@@ -121,9 +121,9 @@ def load():
     lib.ws_render.argtypes = [vp, i64, P(ws_camera), vp, i32, P(ws_options), vp, vp, i64, vp, vp, vp, vp, vp, sz,
                               vp]
     lib.ws_render_backward.argtypes = [P(ws_gaussians), P(ws_camera), vp, i32, P(ws_options), vp, vp, vp, vp, vp,
-                                       vp, P(ws_gaussian_grads), vp, sz, vp]
+                                       vp, vp, P(ws_gaussian_grads), vp, sz, vp]
     lib.ws_render_backward_l1.argtypes = [P(ws_gaussians), P(ws_camera), vp, i32, P(ws_options), vp, vp, vp, vp, vp,
-                                          i64, vp, vp, P(ws_gaussian_grads), vp, sz, vp]
+                                          vp, i64, vp, vp, P(ws_gaussian_grads), vp, sz, vp]
     lib.ws_render_backward_l1_workspace_size.argtypes = [i64, P(ws_camera), i32, P(ws_options)]
     lib.ws_render_backward_l1_workspace_size.restype = sz
     lib.ws_l1_loss.argtypes = [vp, vp, i64, i64, vp, vp, vp, sz, vp]
@@ -311,17 +311,17 @@ def ws_render(splats, n, cams, d_cams, n_views, opt, keys, values, capacity, d_n
                             ws_bytes, _stream(stream)))
 
 
-def ws_render_backward(g, cams, d_cams, n_views, opt, splats, values, tile_ranges, images, dL_dimages, d_status,
-                       grads, ws, ws_bytes, stream=None):
+def ws_render_backward(g, cams, d_cams, n_views, opt, splats, tiles_touched, values, tile_ranges, images,
+                       dL_dimages, d_status, grads, ws, ws_bytes, stream=None):
     _check(load().ws_render_backward(C.byref(g), cams, _ptr(d_cams), n_views, C.byref(opt), _ptr(splats),
-                                     _ptr(values), _ptr(tile_ranges), _ptr(images), _ptr(dL_dimages), _ptr(d_status),
+                                     _ptr(tiles_touched), _ptr(values), _ptr(tile_ranges), _ptr(images), _ptr(dL_dimages), _ptr(d_status),
                                      C.byref(grads), _ptr(ws), ws_bytes, _stream(stream)))
 
 
-def ws_render_backward_l1(g, cams, d_cams, n_views, opt, splats, values, tile_ranges, images, targets, total, d_loss,
-                          d_status, grads, ws, ws_bytes, stream=None):
+def ws_render_backward_l1(g, cams, d_cams, n_views, opt, splats, tiles_touched, values, tile_ranges, images,
+                          targets, total, d_loss, d_status, grads, ws, ws_bytes, stream=None):
     _check(load().ws_render_backward_l1(C.byref(g), cams, _ptr(d_cams), n_views, C.byref(opt), _ptr(splats),
-                                        _ptr(values), _ptr(tile_ranges), _ptr(images), _ptr(targets), total,
+                                        _ptr(tiles_touched), _ptr(values), _ptr(tile_ranges), _ptr(images), _ptr(targets), total,
                                         _ptr(d_loss), _ptr(d_status), C.byref(grads), _ptr(ws), ws_bytes,
                                         _stream(stream)))
 

@@ -447,8 +447,9 @@ namespace {
 // The checks and the launch shared by ws_render_backward and ws_render_backward_l1.
 ws_status render_backward_checked(const char* name, const ws_gaussians* g, const ws_camera* cams,
                                   const ws_camera* d_cams, int32_t n_views, const ws_options* opt,
-                                  const ws_splat* splats, const uint32_t* values, const uint32_t* tile_ranges,
-                                  const float* images, const float* dL_dimages, const ws::L1Loss* l1,
+                                  const ws_splat* splats, const uint32_t* tiles_touched, const uint32_t* values,
+                                  const uint32_t* tile_ranges, const float* images, const float* dL_dimages,
+                                  const ws::L1Loss* l1,
                                   const int32_t* d_status,
                                   ws_gaussian_grads* grads, void* ws, size_t ws_bytes, void* stream) {
     ws_status s;
@@ -477,7 +478,7 @@ ws_status render_backward_checked(const char* name, const ws_gaussians* g, const
     gp.logits = grads->opacity_logits;
     gp.sh = grads->sh;
     const hipError_t e = ws::launch_render_backward(gauss_ptrs(g), d_cams, n_views, tiles, ws::to_kopts(*opt), splats,
-                                                    values, tile_ranges, images, dL_dimages, d_status, gp, ws,
+                                                    tiles_touched, values, tile_ranges, images, dL_dimages, d_status, gp, ws,
                                                     static_cast<hipStream_t>(stream), l1);
     return hip_status(e, name);
 }
@@ -487,16 +488,16 @@ ws_status render_backward_checked(const char* name, const ws_gaussians* g, const
 
 ws_status ws_render_backward(const ws_gaussians* g, const ws_camera* cams, const ws_camera* d_cams,
                              int32_t n_views, const ws_options* opt, const ws_splat* splats,
-                             const uint32_t* values, const uint32_t* tile_ranges, const float* images,
-                             const float* dL_dimages, const int32_t* d_status, ws_gaussian_grads* grads, void* ws,
-                             size_t ws_bytes, void* stream) {
-    return render_backward_checked("ws_render_backward", g, cams, d_cams, n_views, opt, splats, values, tile_ranges,
-                                   images, dL_dimages, nullptr, d_status, grads, ws, ws_bytes, stream);
+                             const uint32_t* tiles_touched, const uint32_t* values, const uint32_t* tile_ranges,
+                             const float* images, const float* dL_dimages, const int32_t* d_status,
+                             ws_gaussian_grads* grads, void* ws, size_t ws_bytes, void* stream) {
+    return render_backward_checked("ws_render_backward", g, cams, d_cams, n_views, opt, splats, tiles_touched, values,
+                                   tile_ranges, images, dL_dimages, nullptr, d_status, grads, ws, ws_bytes, stream);
 }
 
 ws_status ws_render_backward_l1(const ws_gaussians* g, const ws_camera* cams, const ws_camera* d_cams,
                                 int32_t n_views, const ws_options* opt, const ws_splat* splats,
-                                const uint32_t* values, const uint32_t* tile_ranges, const float* images,
+                                const uint32_t* tiles_touched, const uint32_t* values, const uint32_t* tile_ranges, const float* images,
                                 const float* targets, int64_t total, float* d_loss, const int32_t* d_status,
                                 ws_gaussian_grads* grads, void* ws, size_t ws_bytes, void* stream) {
     if (!cams || n_views < 1) return fail(WS_ERR_INVALID_ARGUMENT, "ws_render_backward_l1: no cameras");
@@ -509,8 +510,8 @@ ws_status ws_render_backward_l1(const ws_gaussians* g, const ws_camera* cams, co
     if (!images || !targets || !d_loss)
         return fail(WS_ERR_INVALID_ARGUMENT, "ws_render_backward_l1: images / targets / d_loss is NULL");
     const ws::L1Loss l1{targets, total, d_loss};
-    return render_backward_checked("ws_render_backward_l1", g, cams, d_cams, n_views, opt, splats, values,
-                                   tile_ranges, images, nullptr, &l1, d_status, grads, ws, ws_bytes, stream);
+    return render_backward_checked("ws_render_backward_l1", g, cams, d_cams, n_views, opt, splats, tiles_touched,
+                                   values, tile_ranges, images, nullptr, &l1, d_status, grads, ws, ws_bytes, stream);
 }
 
 ws_status ws_l1_loss(const float* images, const float* targets, int64_t n, int64_t total, float* dL_dimages,

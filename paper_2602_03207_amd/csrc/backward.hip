@@ -60,10 +60,12 @@ BwdWs carve_bwd(void* ws, int64_t n, int32_t n_views) {
     return b;
 }
 
-__global__ void k_bwd_clear(float4* p, int64_t count) {
+// Zeroes the gradient records (count float4s, kRec / 4 per record), only
+// those of entries with a non-zero tile count when `touched` is given.
+__global__ void k_bwd_clear(float4* p, int64_t count, const uint32_t* touched) {
     const int64_t stride = int64_t(gridDim.x) * blockDim.x;
     for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < count; i += stride)
-        p[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (!touched || touched[i / (kRec / 4)] != 0u) p[i] = make_float4(0.f, 0.f, 0.f, 0.f);
 }
 
 // The L1 loss inside the compositing adjoint (targets == nullptr: dL is read).
@@ -360,6 +362,7 @@ struct PreBwdArgs {
     int32_t n_views;
     KOpts o;
     BwdWs w;
+    const uint32_t* touched;  // [V][n] tile counts, or nullptr: every record was cleared
     GradPtrs out;
     const int32_t* d_status;
 };
@@ -392,6 +395,7 @@ __global__ __launch_bounds__(128) void k_preprocess_bwd_geo(PreBwdArgs a) {
     float gm[3] = {0.f, 0.f, 0.f}, gls[3] = {0.f, 0.f, 0.f}, gq[4] = {0.f, 0.f, 0.f, 0.f}, glogit = 0.f;
     for (int32_t v = 0; v < a.n_views; ++v) {
         const int64_t vi = int64_t(v) * n + i;
+        if (a.touched && a.touched[vi] == 0u) continue;  // in no tile list: no gradient, record not cleared
         const float4* rec = reinterpret_cast<const float4*>(a.w.sg + vi * kRec);
         const float4 r0 = rec[0], r1 = rec[1];
         const float gs[6] = {r0.x, r0.y, r0.z, r0.w, r1.x, r1.y};
@@ -510,6 +514,7 @@ __global__ __launch_bounds__(128) void k_preprocess_bwd_sh(PreBwdArgs a) {
     const float mx = a.g.means[i], my = a.g.means[n + i], mz = a.g.means[2 * n + i];
     for (int32_t v = 0; v < a.n_views; ++v) {
         const int64_t vi = int64_t(v) * n + i;
+        if (a.touched && a.touched[vi] == 0u) continue;
         const float* rec = a.w.sg + vi * kRec;
         const float2 rg = *reinterpret_cast<const float2*>(rec + 6);
         const float gcol[3] = {rg.x, rg.y, rec[8]};
@@ -576,15 +581,16 @@ size_t render_backward_l1_workspace(int64_t n, int32_t n_views, int64_t total_ti
 
 hipError_t launch_render_backward(const GaussPtrs& g, const ws_camera* d_cams, int32_t n_views,
                                   int64_t total_tiles, const KOpts& o, const ws_splat* splats,
-                                  const uint32_t* values, const uint32_t* tile_ranges, const float* images,
-                                  const float* dL_dimages, const int32_t* d_status, const GradPtrs& grads, void* ws,
-                                  hipStream_t stream, const L1Loss* l1) {
+                                  const uint32_t* tiles_touched, const uint32_t* values, const uint32_t* tile_ranges,
+                                  const float* images, const float* dL_dimages, const int32_t* d_status,
+                                  const GradPtrs& grads, void* ws, hipStream_t stream, const L1Loss* l1) {
     BwdWs w = carve_bwd(ws, g.n, n_views);
     double* l1_part = l1 ? reinterpret_cast<double*>(static_cast<char*>(ws) + render_backward_workspace(g.n, n_views))
                          : nullptr;
     const int64_t count = int64_t(kRec / 4) * w.vn;  // float4s
     const uint32_t cgrid = uint32_t(std::min<int64_t>(std::max<int64_t>((count + 255) / 256, 1), 8192));
-    hipLaunchKernelGGL(k_bwd_clear, dim3(cgrid), dim3(256), 0, stream, reinterpret_cast<float4*>(w.sg), count);
+    hipLaunchKernelGGL(k_bwd_clear, dim3(cgrid), dim3(256), 0, stream, reinterpret_cast<float4*>(w.sg), count,
+                       tiles_touched);
     // with no Gaussians only the loss remains (every tile list is empty)
     if (g.n == 0 && !l1) return hipGetLastError();
     if (total_tiles > 0) {
@@ -617,6 +623,7 @@ hipError_t launch_render_backward(const GaussPtrs& g, const ws_camera* d_cams, i
     pa.n_views = n_views;
     pa.o = o;
     pa.w = w;
+    pa.touched = tiles_touched;
     pa.out = grads;
     pa.d_status = d_status;
     const dim3 grid(uint32_t((g.n + 127) / 128));

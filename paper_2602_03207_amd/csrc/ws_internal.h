@@ -300,7 +300,7 @@ struct L1Loss {
 };
 hipError_t launch_render_backward(const GaussPtrs& g, const ws_camera* d_cams, int32_t n_views,
                                   int64_t total_tiles, const KOpts& o, const ws_splat* splats,
-                                  const uint32_t* values, const uint32_t* tile_ranges, const float* images,
+                                  const uint32_t* tiles_touched, const uint32_t* values, const uint32_t* tile_ranges, const float* images,
                                   const float* dL_dimages, const int32_t* d_status, const GradPtrs& grads, void* ws,
                                   hipStream_t stream, const L1Loss* l1 = nullptr);
 size_t render_backward_l1_workspace(int64_t n, int32_t n_views, int64_t total_tiles);

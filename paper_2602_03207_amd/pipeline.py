@@ -261,8 +261,9 @@ class Renderer:
         if accumulate:
             opts = B.ws_options.from_buffer_copy(self.opts)
             opts.flags |= B.WS_FLAG_ACCUMULATE_GRADS
-        B.ws_render_backward(g.struct(), self.cam_arr, self.d_cams, self.n_views, opts, self.splats, self.lists,
-                             self.tile_ranges, self.images, dL_dimages, self.d_status, gs, ws, ws.numel(), stream)
+        B.ws_render_backward(g.struct(), self.cam_arr, self.d_cams, self.n_views, opts, self.splats,
+                             self.tiles_touched, self.lists, self.tile_ranges, self.images, dL_dimages, self.d_status,
+                             gs, ws, ws.numel(), stream)
         if check:
             self._check_status()
         return grads
@@ -286,9 +287,9 @@ class Renderer:
         if accumulate:
             opts = B.ws_options.from_buffer_copy(self.opts)
             opts.flags |= B.WS_FLAG_ACCUMULATE_GRADS
-        B.ws_render_backward_l1(g.struct(), self.cam_arr, self.d_cams, self.n_views, opts, self.splats, self.lists,
-                                self.tile_ranges, self.images, targets, total, loss, self.d_status, gs, ws,
-                                ws.numel(), stream)
+        B.ws_render_backward_l1(g.struct(), self.cam_arr, self.d_cams, self.n_views, opts, self.splats,
+                                self.tiles_touched, self.lists, self.tile_ranges, self.images, targets, total, loss,
+                                self.d_status, gs, ws, ws.numel(), stream)
         if check:
             self._check_status()
         return grads

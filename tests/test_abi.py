@@ -134,7 +134,7 @@ def test_backward_rejects_packed_records(lib):
     grads = B.make_grads(0x200000, 0x200000, 0x200000, 0x200000, 0x200000)
     cams = (B.ws_camera * 1)(_cam(64, 64))
     o = _opts(flags=B.WS_FLAG_PACKED)
-    st = lib.ws_render_backward(C.byref(g), cams, vp(0x300000), 1, C.byref(o), vp(0x400000), vp(0x500000),
+    st = lib.ws_render_backward(C.byref(g), cams, vp(0x300000), 1, C.byref(o), vp(0x400000), None, vp(0x500000),
                                 vp(0x600000), vp(0x650000), vp(0x700000), vp(0x800000), C.byref(grads), vp(0x900000),
                                 1 << 30, None)
     assert st == B.WS_ERR_UNSUPPORTED and "PACKED" in _err(lib)
@@ -154,7 +154,7 @@ def test_fused_l1_backward_rejects_bad_arguments_on_the_host(lib):
     assert lib.ws_render_backward_l1_workspace_size(-1, cams, 2, C.byref(o)) == 0
 
     def call(images=0x610000, targets=0x620000, total=0, loss=0x630000, ws_bytes=need):
-        return lib.ws_render_backward_l1(C.byref(g), cams, vp(0x300000), 2, C.byref(o), vp(0x400000),
+        return lib.ws_render_backward_l1(C.byref(g), cams, vp(0x300000), 2, C.byref(o), vp(0x400000), None,
                                          vp(0x500000), vp(0x600000), vp(images) if images else None,
                                          vp(targets) if targets else None, total, vp(loss) if loss else None,
                                          vp(0x800000), C.byref(grads), vp(0x900000), ws_bytes, None)

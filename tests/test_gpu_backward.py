@@ -125,6 +125,42 @@ def test_backward_binned_32bit_keys_match_oracle(bins):
     _compare(got, want)
 
 
+def test_backward_tile_counts_gate_the_gradient_records():
+    """With ws_preprocess's tile counts the adjoint clears and reads only the gradient records of entries in
+    some tile list; without them (NULL) every record.  Both start from a workspace of NaN bytes: the records
+    the counts skip are never read, and both calls give the same gradients (up to the order of the float
+    atomics) as the oracle."""
+    import torch
+    from paper_2602_03207_amd import binding as B
+    from paper_2602_03207_amd.pipeline import GaussianTensors, Renderer
+    scene = scenegen.random_scene(2500, 8, log_scale_mu=-3.0, logit_sd=2.0, sh_degree=1, dc_sd=0.5, rest_sd=0.2)
+    cams = [scenegen.look_at([0.3, -0.2, -3.0], [0, 0, 0], 128, 96), scenegen.look_at([2.0, 0.5, -2.0], [0, 0, 0], 77, 61)]
+    rng = np.random.default_rng(6)
+    dLs = [rng.standard_normal((3, c.height, c.width)).astype(np.float32) for c in cams]
+    r = Renderer(cams, gpu_options(sh_degree=1))
+    g = GaussianTensors.from_scene(scene)
+    r.forward(g)
+    assert int((r.tiles_touched[:len(cams) * g.n] == 0).sum()) > 0  # some entries are culled
+    dL = torch.as_tensor(np.concatenate([d.reshape(-1) for d in dLs])).cuda()
+    need = B.ws_render_backward_workspace_size(g.n, len(cams))
+    out = []
+    for touched in (r.tiles_touched, None):
+        ws = torch.full((need + 256,), 0xFF, dtype=torch.uint8, device="cuda")
+        off = (-ws.data_ptr()) % 256
+        ws = ws[off:off + need]
+        grads = {k: torch.zeros_like(getattr(g, k)) for k in NAMES}
+        gs = B.make_grads(grads["means"], grads["log_scales"], grads["quats"], grads["opacity_logits"], grads["sh"])
+        B.ws_render_backward(g.struct(), r.cam_arr, r.d_cams, r.n_views, r.opts, r.splats, touched, r.lists,
+                             r.tile_ranges, r.images, dL, r.d_status, gs, ws, need)
+        torch.cuda.synchronize()
+        assert r.status() == 0
+        out.append({k: grads[k].cpu().numpy().astype(np.float64) for k in NAMES})
+    for k in NAMES:
+        assert np.isfinite(out[0][k]).all() and np.isfinite(out[1][k]).all(), k
+        np.testing.assert_allclose(out[0][k], out[1][k], rtol=1e-4, atol=1e-6 * np.abs(out[1][k]).max(), err_msg=k)
+    _compare(out[0], _oracle_grads(scene, cams, dLs, oracle_options(sh_degree=1)))
+
+
 def test_autograd_function_matches_backward_call():
     import torch
     from paper_2602_03207_amd.autograd import render_gaussians
