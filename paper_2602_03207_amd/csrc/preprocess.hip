@@ -90,15 +90,23 @@ size_t layout(void* ws, int64_t n, int32_t n_views, int64_t capacity, bool depth
     return off;
 }
 
+// Workgroup order: the grid holds gx8 blocks of Gaussians (gx rounded up to a
+// multiple of 8) for each of the V views.  Workgroups are dealt to the 8 XCDs
+// in turn, so workgroup p runs on XCD p % 8; its (block, view) is chosen so
+// that each XCD takes the V views of one block one after the other (block
+// p % 8 + 8 (j / V), view j % V, j = p / 8): a block's parameters are then
+// read from memory once and served to its other views by that XCD's L2.
 template <int DEG>
 __global__ __launch_bounds__(kPreThreads) void k_preprocess(GaussPtrs g, const ws_camera* __restrict__ cams, KOpts o,
-                                                           ws_splat* __restrict__ splats,
+                                                           int32_t n_views, ws_splat* __restrict__ splats,
                                                            uint32_t* __restrict__ tiles_touched,
                                                            uint32_t* __restrict__ depth, ClearList clr) {
-    const int32_t v = blockIdx.y;
-    const int64_t i = int64_t(blockIdx.x) * kPreThreads + threadIdx.x;
+    const uint32_t j = blockIdx.x >> 3;
+    const int32_t v = int32_t(j % uint32_t(n_views));
+    const int64_t blk = int64_t(blockIdx.x & 7u) + 8 * int64_t(j / uint32_t(n_views));
+    const int64_t i = blk * kPreThreads + threadIdx.x;
     // the look-back words of the scans and of the depth sort that follow, and the status word
-    clear_words(clr, int64_t(v) * gridDim.x * kPreThreads + i, int64_t(gridDim.x) * gridDim.y * kPreThreads);
+    clear_words(clr, int64_t(blockIdx.x) * kPreThreads + threadIdx.x, int64_t(gridDim.x) * kPreThreads);
     if (i >= g.n) return;
     const ws_camera& cam = cams[v];
     ProjState st;
@@ -573,14 +581,15 @@ hipError_t launch_preprocess(const GaussPtrs& g, const ws_camera* d_cams, int32_
     // a frame starts with a clean status word (no kernel of this launch reads it)
     clr.add(d_status, 1);
     timing_begin(WS_KERNEL_PREPROCESS, stream);
+    const dim3 pgrid(uint32_t((gx + 7) / 8 * 8) * uint32_t(n_views));
     switch (o.sh_degree) {
-        case 0: hipLaunchKernelGGL(k_preprocess<0>, dim3(gx, n_views), dim3(kPreThreads), 0, stream, g, d_cams, o,
+        case 0: hipLaunchKernelGGL(k_preprocess<0>, pgrid, dim3(kPreThreads), 0, stream, g, d_cams, o, n_views,
                                    splats, tiles_touched, pw.depth, clr); break;
-        case 1: hipLaunchKernelGGL(k_preprocess<1>, dim3(gx, n_views), dim3(kPreThreads), 0, stream, g, d_cams, o,
+        case 1: hipLaunchKernelGGL(k_preprocess<1>, pgrid, dim3(kPreThreads), 0, stream, g, d_cams, o, n_views,
                                    splats, tiles_touched, pw.depth, clr); break;
-        case 2: hipLaunchKernelGGL(k_preprocess<2>, dim3(gx, n_views), dim3(kPreThreads), 0, stream, g, d_cams, o,
+        case 2: hipLaunchKernelGGL(k_preprocess<2>, pgrid, dim3(kPreThreads), 0, stream, g, d_cams, o, n_views,
                                    splats, tiles_touched, pw.depth, clr); break;
-        default: hipLaunchKernelGGL(k_preprocess<3>, dim3(gx, n_views), dim3(kPreThreads), 0, stream, g, d_cams, o,
+        default: hipLaunchKernelGGL(k_preprocess<3>, pgrid, dim3(kPreThreads), 0, stream, g, d_cams, o, n_views,
                                     splats, tiles_touched, pw.depth, clr); break;
     }
     timing_end(WS_KERNEL_PREPROCESS, stream);
