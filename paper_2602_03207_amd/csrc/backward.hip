@@ -44,9 +44,10 @@ constexpr int kNG = 9;  // u, v, A, B, C, sigma, r, g, b
 // instruction whose lanes address one cache line, which the memory system
 // serves as one request; nine arrays would take nine.
 constexpr int kRec = 16;
-#ifndef WS_BWD_SUMS
-#define WS_BWD_SUMS 256
-#endif
+// (wave, entry) pairs of per-wave sums a batch holds: 64 entries per batch of
+// a 16x16 tile (128 needed 18 KB of LDS per workgroup, six per CU, and 32
+// doubled the batches; both were slower)
+constexpr int kBwdSums = 256;
 
 struct BwdWs {
     float* sg;   // [V * n][kRec] per-(view, splat) gradients
@@ -161,8 +162,8 @@ __device__ __forceinline__ void wave_sum9(float (&v)[kNG], float* q, float* q8) 
     float s = half_row_sum(fold_halves(p01 + p23, p45 + p67));
     float s8 = dpp_add<0x143>(dpp_add<0x142>(dpp_add<0x128>(half_row_sum(v[8]))));
     // complete the sums in every lane here: left to itself the compiler moves
-    // the last add of each into the leaders' branch, which turns one DPP add
-    // into a zeroed register, a DPP move and an add
+    // the last add of each into the storing lanes' branch, which turns one DPP
+    // add into a zeroed register, a DPP move and an add
     asm volatile("" : "+v"(s), "+v"(s8));
     *q = s;
     *q8 = s8;
@@ -173,8 +174,8 @@ template <int TW, int TH, bool RECT>
 __global__ __launch_bounds__(TW * TH, 8) void k_render_bwd(BwdArgs a) {
     constexpr int NT = TW * TH, NW = NT / kWave;
     // batches of NB list entries: at most half a tile's threads, and at most
-    // WS_BWD_SUMS (wave, entry) pairs of per-wave sums
-    constexpr int NB = NT / 2 < WS_BWD_SUMS / NW ? NT / 2 : WS_BWD_SUMS / NW;
+    // kBwdSums (wave, entry) pairs of per-wave sums
+    constexpr int NB = NT / 2 < kBwdSums / NW ? NT / 2 : kBwdSums / NW;
     __shared__ StagedSplat s_batch[NB];
     __shared__ RawConic s_conic[NB];
     // per wave and batch entry the wave's nine sums, [wave][entry][9]: each
