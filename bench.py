@@ -604,7 +604,8 @@ def cpu_baseline(args):
     """The fp64 oracle on the host's cores, on bounded samples of the benchmark workloads: whole frames of the
     1M-Gaussian 1080p view on one thread (`value`) and on every usable core (the oracle's loops over Gaussians,
     tiles and pixel rows; the sort stays std::stable_sort on one thread), frames of the 10K-Gaussian 256x256
-    view, std::stable_sort of the 1080p and 4K pair buffers, and one forward+backward 1080p training view."""
+    view, std::stable_sort of the 1080p and 4K pair buffers and of the 1080p view's visible depths, and one
+    forward+backward 1080p training view."""
     import numpy as np
 
     import oracle
@@ -648,7 +649,14 @@ def cpu_baseline(args):
     med, _ = timed(lambda: oracle.stable_sort(keys, vals, 0, end_bit), 3)
     out["stable_sort_c2"] = {"pairs": int(keys.size), "bits": end_bit, "s_median_of_3": round(med, 4),
                              "keys_per_s": round(keys.size / med, 1)}
-    del keys, vals
+    # the paper's sort workload on the CPU: std::stable_sort of the visible splats' fp32 depth keys (index
+    # order, as the GPU's depth_sort leg sorts them): each visible Gaussian's first pair carries its depth
+    ids, first = np.unique(vals, return_index=True)
+    dk = keys[first] & np.uint64(0xFFFFFFFF)
+    med, _ = timed(lambda: oracle.stable_sort(dk, ids, 0, 32), 5)
+    out["stable_sort_depth_c2"] = {"keys": int(dk.size), "bits": 32, "s_median_of_5": round(med, 5),
+                                   "keys_per_s": round(dk.size / med, 1)}
+    del keys, vals, ids, first, dk
     # the 10K-Gaussian 256x256 frame, one thread
     s1, c1 = scenegen.c1()
     med, _ = timed(lambda: oracle.render(s1, c1, oracle.Options()), 20)
