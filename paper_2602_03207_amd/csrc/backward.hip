@@ -530,11 +530,23 @@ __global__ __launch_bounds__(128) void k_preprocess_bwd_sh(PreBwdArgs a) {
         dz *= idn;
         float Y[16];
         sh_eval_basis(dx, dy, dz, DEG, Y);
+        // the coefficients, read by walking one pointer down the rows: the
+        // pointer is opaque to the compiler, so it does not hoist the 3K row
+        // addresses out of the loop (3K 64-bit addresses held in registers
+        // halved the kernel's resident waves)
+        const float* p = a.g.sh + i;
+        asm volatile("" : "+v"(p));
+        float shc[3 * K];
+#pragma unroll
+        for (int k = 0; k < 3 * K; ++k) {
+            shc[k] = *p;
+            p += n;
+        }
         float col[3] = {0.5f, 0.5f, 0.5f};
 #pragma unroll
         for (int k = 0; k < K; ++k) {
 #pragma unroll
-            for (int ch = 0; ch < 3; ++ch) col[ch] = fmaf(a.g.sh[(int64_t(k) * 3 + ch) * n + i], Y[k], col[ch]);
+            for (int ch = 0; ch < 3; ++ch) col[ch] = fmaf(shc[k * 3 + ch], Y[k], col[ch]);
         }
         float wsh[16];
 #pragma unroll
@@ -545,7 +557,7 @@ __global__ __launch_bounds__(128) void k_preprocess_bwd_sh(PreBwdArgs a) {
 #pragma unroll
             for (int k = 0; k < K; ++k) {
                 gsh[k * 3 + ch] = fmaf(gc, Y[k], gsh[k * 3 + ch]);
-                wsh[k] = fmaf(gc, a.g.sh[(int64_t(k) * 3 + ch) * n + i], wsh[k]);
+                wsh[k] = fmaf(gc, shc[k * 3 + ch], wsh[k]);
             }
         }
         float gdx, gdy, gdz;
