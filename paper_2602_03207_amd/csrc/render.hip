@@ -273,7 +273,7 @@ __global__ __launch_bounds__(kExpandThreads) void k_expand(ExpandArgs a) {
 // HBM about once), keeps the pairs whose coverage bit w is set and compacts
 // them in order with a ballot per item: no LDS and no barrier.  Waves of tiles
 // past the view's right or bottom edge leave at once.
-constexpr int kExpandBinItems = 8;
+constexpr int kExpandBinItems = 16;
 
 template <typename K>
 __global__ __launch_bounds__(1024) void k_expand_bin(ExpandArgs a, int64_t bins) {
