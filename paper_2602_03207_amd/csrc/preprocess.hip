@@ -9,9 +9,10 @@
 //               entry's fp32 depth bits are written too and the list is then
 //               stably sorted by depth.
 // counts        prefix sum of the listed entries' tile counts: each entry's
-//               first pair, the total M, and for every 2048-pair block of the
+//               first pair, the total M, and for every emission block of the
 //               output the entry that owns its first pair.
-// k_emit        one workgroup per 2048 pairs, in rounds of up to 256 entries:
+// k_emit        one workgroup per block of 512, 1024 or 2048 pairs (by the
+//               pair capacity), in rounds of up to 256 entries:
 //               loads the entries that cover the round's pairs, finds each
 //               pair's owner by marking the entry starts in LDS and taking a
 //               running maximum, and writes key = (tile << 32) | depth bits
@@ -34,9 +35,14 @@ namespace {
 
 constexpr int kPreThreads = 256;
 constexpr int kEmitThreads = 256;
-constexpr int kEmitItems = 8;
-constexpr int kEmitPairs = kEmitThreads * kEmitItems;  // pairs per emission workgroup
-constexpr int kEmitSlots = kEmitThreads;               // entries loaded per round
+constexpr int kEmitSlots = kEmitThreads;  // entries loaded per round
+// Pairs per emission workgroup: kEmitThreads x (2, 4 or 8) by the pair
+// capacity.  Small frames (a 1080p view's 1.1 M bin pairs) spread over more
+// workgroups; large ones (49 M pairs at 4K) keep 2 048-pair blocks, where
+// smaller blocks cost more in per-block overhead than they gain.
+inline int emit_items_for(int64_t capacity) {
+    return capacity <= (int64_t(1) << 21) ? 2 : (capacity <= (int64_t(1) << 23) ? 4 : 8);
+}
 // Items per thread of the two prefix sums: the visibility flags of every
 // entry (large blocks, a short look-back) and the tile counts of the listed
 // entries (smaller blocks: few entries are listed and each count takes two
@@ -59,13 +65,16 @@ struct PreprocessWs {
     int64_t* d_nvis;
     void* sort_ws;
     int64_t total, emit_blocks;
+    int32_t emit_items;  // pairs per emission workgroup / kEmitThreads
 };
 
 size_t layout(void* ws, int64_t n, int32_t n_views, int64_t capacity, bool depth_first, PreprocessWs* out) {
     PreprocessWs p{};
     p.total = n * n_views;
     const int64_t ents = std::max<int64_t>(p.total, 1);
-    p.emit_blocks = std::max<int64_t>((capacity + kEmitPairs - 1) / kEmitPairs, 1);
+    p.emit_items = emit_items_for(capacity);
+    const int64_t emit_pairs = int64_t(kEmitThreads) * p.emit_items;
+    p.emit_blocks = std::max<int64_t>((capacity + emit_pairs - 1) / emit_pairs, 1);
     char* base = static_cast<char*>(ws);
     size_t off = 0;
     auto take = [&](size_t bytes) {
@@ -335,12 +344,13 @@ struct CountStore {
     uint32_t* offsets;
     uint32_t* first_entry;
     int64_t emit_blocks;
+    uint32_t emit_pairs;  // pairs per emission block
     __device__ void operator()(int64_t e, uint64_t s, uint64_t cnt) const {
         offsets[e] = uint32_t(s);
         if (cnt == 0) return;
         // every output block whose first pair falls inside [s, s + cnt) starts in entry e
-        const uint64_t b_lo = (s + kEmitPairs - 1) / kEmitPairs;
-        const uint64_t b_hi = (s + cnt - 1) / kEmitPairs;
+        const uint64_t b_lo = (s + emit_pairs - 1) / emit_pairs;
+        const uint64_t b_hi = (s + cnt - 1) / emit_pairs;
         for (uint64_t b = b_lo; b <= b_hi && int64_t(b) < emit_blocks; ++b) first_entry[b] = uint32_t(e);
     }
 };
@@ -398,8 +408,9 @@ __device__ __forceinline__ uint32_t wave_inclusive_max(uint32_t v) {
     return v;
 }
 
-template <bool K32, bool MASK>
+template <bool K32, bool MASK, int EI>
 __global__ __launch_bounds__(kEmitThreads) void k_emit(EmitArgs a) {
+    constexpr int kEmitItems = EI, kEmitPairs = kEmitThreads * EI;
     __shared__ uint32_t s_owner[kEmitPairs];
     __shared__ uint32_t s_start[kEmitSlots];
     __shared__ uint32_t s_gid[kEmitSlots];
@@ -557,6 +568,15 @@ __global__ __launch_bounds__(kEmitThreads) void k_emit(EmitArgs a) {
     }
 }
 
+template <int EI>
+void launch_emit(const EmitArgs& ea, bool k32, bool mask, int64_t blocks, hipStream_t stream) {
+    const dim3 eg(static_cast<uint32_t>(blocks)), eb(kEmitThreads);
+    if (k32 && mask) hipLaunchKernelGGL((k_emit<true, true, EI>), eg, eb, 0, stream, ea);
+    else if (k32) hipLaunchKernelGGL((k_emit<true, false, EI>), eg, eb, 0, stream, ea);
+    else if (mask) hipLaunchKernelGGL((k_emit<false, true, EI>), eg, eb, 0, stream, ea);
+    else hipLaunchKernelGGL((k_emit<false, false, EI>), eg, eb, 0, stream, ea);
+}
+
 }  // namespace
 
 size_t preprocess_workspace(int64_t n, int32_t n_views, int64_t capacity, uint32_t flags) {
@@ -628,7 +648,8 @@ hipError_t launch_preprocess(const GaussPtrs& g, const ws_camera* d_cams, int32_
                                              reinterpret_cast<uint64_t*>(pw.d_nvis), stream, true);
     }
     // pair offsets of the listed entries (total to d_num_pairs)
-    launch_scan<uint64_t, kCountItems>(CountLoad{tiles_touched, list}, CountStore{pw.offsets, pw.first_entry, pw.emit_blocks},
+    launch_scan<uint64_t, kCountItems>(CountLoad{tiles_touched, list}, CountStore{pw.offsets, pw.first_entry, pw.emit_blocks,
+                                                                       uint32_t(kEmitThreads * pw.emit_items)},
                           ents, pw.d_nvis, d_status, pw.scan_b, reinterpret_cast<uint64_t*>(d_num_pairs), stream, true,
                           true);
     EmitArgs ea;
@@ -659,12 +680,12 @@ hipError_t launch_preprocess(const GaussPtrs& g, const ws_camera* d_cams, int32_
     ea.mask_shift = o.mask_shift;
     ea.keys = keys;
     ea.values = values;
-    const dim3 eg(uint32_t(pw.emit_blocks)), eb(kEmitThreads);
     const bool k32 = (o.flags & WS_FLAG_KEYS32) != 0, mask = o.mask_shift >= 0;
-    if (k32 && mask) hipLaunchKernelGGL((k_emit<true, true>), eg, eb, 0, stream, ea);
-    else if (k32) hipLaunchKernelGGL((k_emit<true, false>), eg, eb, 0, stream, ea);
-    else if (mask) hipLaunchKernelGGL((k_emit<false, true>), eg, eb, 0, stream, ea);
-    else hipLaunchKernelGGL((k_emit<false, false>), eg, eb, 0, stream, ea);
+    switch (pw.emit_items) {
+        case 2: launch_emit<2>(ea, k32, mask, pw.emit_blocks, stream); break;
+        case 4: launch_emit<4>(ea, k32, mask, pw.emit_blocks, stream); break;
+        default: launch_emit<8>(ea, k32, mask, pw.emit_blocks, stream); break;
+    }
     timing_end(WS_KERNEL_SCAN_EMIT, stream);
     return hipGetLastError();
 }
