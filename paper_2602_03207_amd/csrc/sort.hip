@@ -11,7 +11,8 @@
 // counters in LDS; the tile is reordered by digit in LDS, keys first and then
 // values through the same buffer, so that global writes are runs of
 // consecutive addresses.  A tile is 256 threads x ITEMS pairs: 4096 pairs for
-// large inputs, 1024 for small ones so that they still spread over the CUs.
+// large inputs, 2048 for mid-sized ones and 1024 for small ones, so that they
+// still spread over the CUs.
 //
 // Two schedules compute base_d + prefix_wg; they give identical bits:
 //  * look-back (small inputs, up to kSmallSortMax pairs, or inputs whose
@@ -43,8 +44,10 @@ namespace {
 constexpr int kSortThreads = 256;
 constexpr int kSortWaves = kSortThreads / kWave;
 constexpr int kItemsLarge = 16;              // 4096-pair tiles
+constexpr int kItemsMid = 8;                 // 2048-pair tiles
 constexpr int kItemsSmall = 4;               // 1024-pair tiles
 constexpr int64_t kSmallSortMax = 1 << 20;   // capacities up to this use small tiles
+constexpr int64_t kMidSortMax = 1 << 23;     // wait-free sorts up to this use 2048-pair tiles
 constexpr int kHistThreads = 256;
 constexpr int kMaxBins = 2048;  // passes * radix of the look-back schedule's histograms, at most
 constexpr int kLook = 16;       // predecessor tiles read at once by the look-back
@@ -81,7 +84,10 @@ size_t plan(void* ws, int64_t capacity, int begin_bit, int end_bit, int radix_bi
         L.radix = 1 << L.r;
         L.passes = (end_bit - begin_bit + L.r - 1) / L.r;
     }
-    L.items = small ? kItemsSmall : kItemsLarge;
+    // wait-free tiles: 2048 pairs up to 8 M pairs of capacity (twice the
+    // workgroups of 4096-pair tiles for a 1080p frame's 1-2 M pairs), 4096
+    // above, where longer digit runs make the scatter's writes whole lines
+    L.items = small ? kItemsSmall : (capacity <= kMidSortMax ? kItemsMid : kItemsLarge);
     const int64_t tile = int64_t(kSortThreads) * L.items;
     L.max_tiles = std::max<int64_t>((capacity + tile - 1) / tile, 1);
     L.wait_free = !small;
@@ -750,6 +756,7 @@ hipError_t launch_sort_t(const K* kin, const uint32_t* vin, K* kout, uint32_t* v
         c.pa.status = L.wait_free ? nullptr : L.status + int64_t(p) * L.max_tiles * L.radix;
         timing_begin(pass_id, stream);
         if (L.items == kItemsSmall) run_pass_bits<kItemsSmall, K>(c, bits);
+        else if (L.items == kItemsMid) run_pass_bits<kItemsMid, K>(c, bits);
         else run_pass_bits<kItemsLarge, K>(c, bits);
         timing_end(pass_id, stream);
     }
