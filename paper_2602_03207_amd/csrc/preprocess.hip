@@ -48,7 +48,7 @@ inline int emit_items_for(int64_t capacity) {
 // entries (smaller blocks: few entries are listed and each count takes two
 // dependent loads).
 constexpr int kCompactItems = 16;
-constexpr int kCountItems = 8;
+constexpr int kCountItems = 4;
 // The depth sort of depth-first emission: 31 key bits in 4 passes of 8 bits.
 constexpr int kDepthPasses = 4, kDepthRadixBits = 8, kDepthRadix = 1 << kDepthRadixBits;
 
