@@ -61,12 +61,14 @@ BwdWs carve_bwd(void* ws, int64_t n, int32_t n_views) {
     return b;
 }
 
-// Zeroes the gradient records (count float4s, kRec / 4 per record), only
-// those of entries with a non-zero tile count when `touched` is given.
-__global__ void k_bwd_clear(float4* p, int64_t count, const uint32_t* touched) {
-    const int64_t stride = int64_t(gridDim.x) * blockDim.x;
-    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < count; i += stride)
-        if (!touched || touched[i / (kRec / 4)] != 0u) p[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+// Zeroes the gradient records (recs of them, kRec / 4 float4s each), only
+// those of entries with a non-zero tile count when `touched` is given: one
+// thread per record reads its count once and writes the whole record.
+__global__ void k_bwd_clear(float4* p, int64_t recs, const uint32_t* touched) {
+    const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (r >= recs || (touched && touched[r] == 0u)) return;
+#pragma unroll
+    for (int k = 0; k < kRec / 4; ++k) p[r * (kRec / 4) + k] = make_float4(0.f, 0.f, 0.f, 0.f);
 }
 
 // The L1 loss inside the compositing adjoint (targets == nullptr: dL is read).
@@ -600,9 +602,8 @@ hipError_t launch_render_backward(const GaussPtrs& g, const ws_camera* d_cams, i
     BwdWs w = carve_bwd(ws, g.n, n_views);
     double* l1_part = l1 ? reinterpret_cast<double*>(static_cast<char*>(ws) + render_backward_workspace(g.n, n_views))
                          : nullptr;
-    const int64_t count = int64_t(kRec / 4) * w.vn;  // float4s
-    const uint32_t cgrid = uint32_t(std::min<int64_t>(std::max<int64_t>((count + 255) / 256, 1), 8192));
-    hipLaunchKernelGGL(k_bwd_clear, dim3(cgrid), dim3(256), 0, stream, reinterpret_cast<float4*>(w.sg), count,
+    const uint32_t cgrid = uint32_t(std::max<int64_t>((w.vn + 255) / 256, 1));
+    hipLaunchKernelGGL(k_bwd_clear, dim3(cgrid), dim3(256), 0, stream, reinterpret_cast<float4*>(w.sg), w.vn,
                        tiles_touched);
     // with no Gaussians only the loss remains (every tile list is empty)
     if (g.n == 0 && !l1) return hipGetLastError();
